@@ -1,0 +1,426 @@
+/*
+ * d3q19_oracle.c -- plain FP64 CPU oracle: D3Q19 BGK lattice Boltzmann with
+ * the on-site velocity boundary condition of Hecht & Harting
+ * (arXiv:0811.4593).
+ *
+ * TEST INFRASTRUCTURE ONLY: called from tests/, __graft_entry__.smoke() and
+ * bench.py's cpu_baseline leg.  Shares nothing with the HIP library.
+ *
+ * Written for reading against the paper, not for speed: populations are kept
+ * in 1-based arrays f[1..19] so that every boundary formula below reads like
+ * the paper's equation it cites.  Readings of passages that are silent,
+ * ambiguous or garbled are marked "Reading:".
+ */
+#include "d3q19_oracle.h"
+
+#include <math.h>
+#include <omp.h>
+#include <stddef.h>
+#include <string.h>
+
+/* Lattice vectors c_i: the columns of the matrix M (Sec. II, eq_deffs).
+ * Entry 0 is unused so that indices match the paper. */
+static const int CX[20] = {0, 1, -1, 0, 0, 0, 0, 1, 1, 1, 1, -1, -1, -1, -1, 0, 0, 0, 0, 0};
+static const int CY[20] = {0, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0};
+static const int CZ[20] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, 1, -1, 0};
+
+/* Lattice weights (eq_weights). */
+static double weight(int i) {
+  if (i <= 6) return 2.0 / 36.0;
+  if (i <= 18) return 1.0 / 36.0;
+  return 12.0 / 36.0;
+}
+
+/* Index i of the lattice vector (cx, cy, cz); 0 if it is not one. */
+static int vector_index(int cx, int cy, int cz) {
+  for (int i = 1; i <= 19; ++i)
+    if (CX[i] == cx && CY[i] == cy && CZ[i] == cz) return i;
+  return 0;
+}
+
+/* Index of the opposite vector, c_{-i} = -c_i. */
+static int opposite(int i) { return vector_index(-CX[i], -CY[i], -CZ[i]); }
+
+static int dot_c(int i, const int n[3]) { return CX[i] * n[0] + CY[i] * n[1] + CZ[i] * n[2]; }
+
+/* Inward unit normal of each face (faces: x=0, x=nx-1, y=0, y=ny-1, z=0, z=nz-1). */
+static const int NORMAL[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+
+void oracle_tables(int c[19][3], double w[19]) {
+  for (int i = 1; i <= 19; ++i) {
+    c[i - 1][0] = CX[i];
+    c[i - 1][1] = CY[i];
+    c[i - 1][2] = CZ[i];
+    w[i - 1] = weight(i);
+  }
+}
+
+/* Second-order equilibrium, c_s^2 = 1/3 (eq_feq):
+ * f_i^eq = w_i rho [1 + c.u/cs^2 + (c.u)^2/(2 cs^4) - u^2/(2 cs^2)]. */
+static void feq_paper(double rho, const double u[3], double feq[20]) {
+  const double cs2 = 1.0 / 3.0;
+  const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  for (int i = 1; i <= 19; ++i) {
+    const double cu = CX[i] * u[0] + CY[i] * u[1] + CZ[i] * u[2];
+    feq[i] = weight(i) * rho * (1.0 + cu / cs2 + cu * cu / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
+  }
+}
+
+void oracle_feq(double rho, const double u[3], double feq[19]) {
+  double e[20];
+  feq_paper(rho, u, e);
+  for (int i = 1; i <= 19; ++i) feq[i - 1] = e[i];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Face rules: Sec. IV (bottom plane, eq_uin, eq_f5, eq_f9-eq_f17, eq_Nx,     */
+/* eq_Ny) and the Appendix (top, left, right, front, back).  In each rule the */
+/* density and the transverse momentum corrections N use known populations */
+/* only (in-plane and outgoing), so the unknowns can be assigned after.      */
+/* ------------------------------------------------------------------------ */
+
+/* z = 0, inward normal +z (Sec. IV). */
+static void face_bottom(double *f, double vx, double vy, double vz) {
+  const double rho = (f[1] + f[2] + f[3] + f[4] + f[7] + f[8] + f[11] + f[12] + f[19] +
+                      2.0 * (f[6] + f[10] + f[14] + f[16] + f[18])) / (1.0 - vz);  /* eq_uin */
+  const double Nzx = 0.5 * (f[1] + f[7] + f[8] - (f[2] + f[11] + f[12])) - rho * vx / 3.0;  /* eq_Nx */
+  const double Nzy = 0.5 * (f[3] + f[7] + f[11] - (f[4] + f[8] + f[12])) - rho * vy / 3.0;  /* eq_Ny */
+  f[5] = f[6] + rho * vz / 3.0;                          /* eq_f5 */
+  f[9] = f[14] + rho / 6.0 * (vz + vx) - Nzx;            /* eq_f9 */
+  f[13] = f[10] + rho / 6.0 * (vz - vx) + Nzx;           /* eq_f13 */
+  f[15] = f[18] + rho / 6.0 * (vz + vy) - Nzy;           /* eq_f15 */
+  f[17] = f[16] + rho / 6.0 * (vz - vy) + Nzy;           /* eq_f17 */
+}
+
+/* z = nz-1, inward normal -z (Appendix, top plane). */
+static void face_top(double *f, double vx, double vy, double vz) {
+  const double rho = (f[1] + f[2] + f[3] + f[4] + f[7] + f[11] + f[12] + f[8] + f[19] +
+                      2.0 * (f[5] + f[9] + f[13] + f[15] + f[17])) / (vz + 1.0);
+  const double Nzx = 0.5 * (f[1] + f[7] + f[8] - (f[2] + f[11] + f[12])) - rho * vx / 3.0;
+  const double Nzy = 0.5 * (f[3] + f[7] + f[11] - (f[4] + f[8] + f[12])) - rho * vy / 3.0;
+  f[6] = f[5] - rho * vz / 3.0;
+  f[10] = f[13] + rho / 6.0 * (-vz + vx) - Nzx;
+  f[14] = f[9] + rho / 6.0 * (-vz - vx) + Nzx;
+  f[16] = f[17] + rho / 6.0 * (-vz + vy) - Nzy;
+  f[18] = f[15] + rho / 6.0 * (-vz - vy) + Nzy;
+}
+
+/* x = 0, inward normal +x (Appendix, left boundary; eq_rhooutx, eq_Nxy, eq_Nxz). */
+static void face_left(double *f, double vx, double vy, double vz) {
+  const double rho = (f[3] + f[4] + f[5] + f[6] + f[15] + f[16] + f[17] + f[18] + f[19] +
+                      2.0 * (f[2] + f[11] + f[12] + f[13] + f[14])) / (1.0 - vx);
+  const double Nxy = 0.5 * (f[3] + f[15] + f[16] - (f[4] + f[17] + f[18])) - rho * vy / 3.0;
+  const double Nxz = 0.5 * (f[5] + f[17] + f[15] - (f[6] + f[16] + f[18])) - rho * vz / 3.0;
+  f[1] = f[2] + rho * vx / 3.0;
+  f[8] = f[11] + rho / 6.0 * (vx - vy) + Nxy;
+  f[7] = f[12] + rho / 6.0 * (vx + vy) - Nxy;
+  f[9] = f[14] + rho / 6.0 * (vx + vz) - Nxz;
+  f[10] = f[13] + rho / 6.0 * (vx - vz) + Nxz;
+}
+
+/* x = nx-1, inward normal -x (Appendix, right boundary; eq_rhoinx). */
+static void face_right(double *f, double vx, double vy, double vz) {
+  const double rho = (f[3] + f[4] + f[5] + f[6] + f[15] + f[16] + f[17] + f[18] + f[19] +
+                      2.0 * (f[1] + f[7] + f[8] + f[9] + f[10])) / (vx + 1.0);
+  const double Nxy = 0.5 * (f[3] + f[15] + f[16] - (f[4] + f[17] + f[18])) - rho * vy / 3.0;
+  const double Nxz = 0.5 * (f[5] + f[17] + f[15] - (f[6] + f[16] + f[18])) - rho * vz / 3.0;
+  f[2] = f[1] - rho * vx / 3.0;
+  f[11] = f[8] + rho / 6.0 * (-vx + vy) - Nxy;
+  f[12] = f[7] + rho / 6.0 * (-vx - vy) + Nxy;
+  f[14] = f[9] + rho / 6.0 * (-vx - vz) + Nxz;
+  f[13] = f[10] + rho / 6.0 * (-vx + vz) - Nxz;
+}
+
+/* y = 0, inward normal +y (Appendix, front boundary; eq_rhoiny, eq_Nyx, eq_Nyz). */
+static void face_front(double *f, double vx, double vy, double vz) {
+  const double rho = (f[1] + f[2] + f[5] + f[6] + f[9] + f[10] + f[13] + f[14] + f[19] +
+                      2.0 * (f[4] + f[8] + f[12] + f[17] + f[18])) / (1.0 - vy);
+  const double Nyx = 0.5 * (f[1] + f[9] + f[10] - (f[2] + f[13] + f[14])) - rho * vx / 3.0;
+  const double Nyz = 0.5 * (f[5] + f[9] + f[13] - (f[6] + f[10] + f[14])) - rho * vz / 3.0;
+  f[3] = f[4] + rho * vy / 3.0;
+  f[7] = f[12] + rho / 6.0 * (vy + vx) - Nyx;
+  f[11] = f[8] + rho / 6.0 * (vy - vx) + Nyx;
+  f[15] = f[18] + rho / 6.0 * (vy + vz) - Nyz;
+  f[16] = f[17] + rho / 6.0 * (vy - vz) + Nyz;
+}
+
+/* y = ny-1, inward normal -y (Appendix, back boundary; eq_rhoouty). */
+static void face_back(double *f, double vx, double vy, double vz) {
+  const double rho = (f[1] + f[2] + f[5] + f[6] + f[9] + f[10] + f[13] + f[14] + f[19] +
+                      2.0 * (f[3] + f[7] + f[11] + f[15] + f[16])) / (vy + 1.0);
+  const double Nyx = 0.5 * (f[1] + f[9] + f[10] - (f[2] + f[13] + f[14])) - rho * vx / 3.0;
+  const double Nyz = 0.5 * (f[5] + f[9] + f[13] - (f[6] + f[10] + f[14])) - rho * vz / 3.0;
+  f[4] = f[3] - rho * vy / 3.0;
+  f[12] = f[7] + rho / 6.0 * (-vy - vx) + Nyx;
+  f[8] = f[11] + rho / 6.0 * (-vy + vx) - Nyx;
+  f[18] = f[15] + rho / 6.0 * (-vy - vz) + Nyz;
+  f[17] = f[16] + rho / 6.0 * (-vy + vz) - Nyz;
+}
+
+static void face_rule_paper(int face, const double v[3], double *f) {
+  switch (face) {
+    case 0: face_left(f, v[0], v[1], v[2]); break;
+    case 1: face_right(f, v[0], v[1], v[2]); break;
+    case 2: face_front(f, v[0], v[1], v[2]); break;
+    case 3: face_back(f, v[0], v[1], v[2]); break;
+    case 4: face_bottom(f, v[0], v[1], v[2]); break;
+    case 5: face_top(f, v[0], v[1], v[2]); break;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Edge rule, no-slip (Sec. V: eq_Nxzy, eq_edge, eq_buried).                 */
+/* n1, n2: inward normals of the two planes meeting at the edge.            */
+/* ------------------------------------------------------------------------ */
+static void edge_rule_paper(const int n1[3], const int n2[3], double *f) {
+  /* Edge direction n1 x n2. */
+  const int e[3] = {n1[1] * n2[2] - n1[2] * n2[1], n1[2] * n2[0] - n1[0] * n2[2],
+                    n1[0] * n2[1] - n1[1] * n2[0]};
+  int bounced[20] = {0};
+  int buried[20] = {0};
+  /* Buried link: c = +-(n1 - n2); its opposite also points out of the domain. */
+  buried[vector_index(n1[0] - n2[0], n1[1] - n2[1], n1[2] - n2[2])] = 1;
+  buried[vector_index(n2[0] - n1[0], n2[1] - n1[1], n2[2] - n1[2])] = 1;
+
+  /* Step 1: bounce back every population whose source lies outside the
+   * domain (c.n1 > 0 or c.n2 > 0), buried links excepted. */
+  for (int i = 1; i <= 18; ++i) {
+    const int unknown = dot_c(i, n1) > 0 || dot_c(i, n2) > 0;
+    if (unknown && !buried[i]) {
+      f[i] = f[opposite(i)];
+      bounced[i] = 1;
+    }
+  }
+
+  /* Step 2: transverse momentum correction along the edge (eq_Nxzy):
+   * N = (f_{+e} - f_{-e}) / 4, spread over the four bounced populations with
+   * c.e != 0.  Reading: the correction is subtracted, N (c.e), so that the
+   * momentum along the edge vanishes ("to ensure no-slip"); adding it as the
+   * text literally says would double that momentum instead. */
+  const double N = 0.25 * (f[vector_index(e[0], e[1], e[2])] - f[vector_index(-e[0], -e[1], -e[2])]);
+  for (int i = 1; i <= 18; ++i)
+    if (bounced[i] && dot_c(i, e) != 0) f[i] -= N * dot_c(i, e);
+
+  /* Step 3: buried links and rest population (eq_buried).  Reading of the
+   * bracket: 1 - (1 - |c.(n1 x n2)|)(1 - |c.(n1+n2)|/|c|^2), which is 0 for
+   * the buried pair and 1 for the other 16 moving populations (6 of weight
+   * 2/36 and 10 of weight 1/36, 22/36 in all). */
+  const int s[3] = {n1[0] + n2[0], n1[1] + n2[1], n1[2] + n2[2]};
+  double sum = 0.0;
+  for (int i = 1; i <= 18; ++i) {
+    const double c2 = (double)(CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i]);
+    const double bracket = 1.0 - (1.0 - fabs((double)dot_c(i, e))) * (1.0 - fabs((double)dot_c(i, s) / c2));
+    if (bracket != 0.0) sum += f[i] * bracket; /* a zero bracket drops the (unknown) term */
+  }
+  const double fb = sum / 22.0;
+  for (int i = 1; i <= 18; ++i)
+    if (buried[i]) f[i] = fb;
+  f[19] = 12.0 * fb; /* w_19 / w_7 = 12 */
+}
+
+/* ------------------------------------------------------------------------ */
+/* Corner rule, no-slip (Sec. V, eq_corner).                                 */
+/* ------------------------------------------------------------------------ */
+static void corner_rule_paper(const int n1[3], const int n2[3], const int n3[3], double *f) {
+  const int s[3] = {n1[0] + n2[0] + n3[0], n1[1] + n2[1] + n3[1], n1[2] + n2[2] + n3[2]};
+  /* Bounce back the populations coming from outside whose opposite is known;
+   * the six buried vectors are those with c.(n1+n2+n3) = 0. */
+  for (int i = 1; i <= 18; ++i) {
+    const int unknown = dot_c(i, n1) > 0 || dot_c(i, n2) > 0 || dot_c(i, n3) > 0;
+    if (unknown && dot_c(i, s) != 0) f[i] = f[opposite(i)];
+  }
+  /* eq_corner: weight |c.(n1+n2+n3)| / |c|^2 -- 1 for the six axis vectors
+   * and the six non-buried diagonals (18/36 in all), 0 for the buried six. */
+  double sum = 0.0;
+  for (int i = 1; i <= 18; ++i) {
+    const double c2 = (double)(CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i]);
+    const double weight_i = fabs((double)dot_c(i, s) / c2);
+    if (weight_i != 0.0) sum += f[i] * weight_i; /* buried (unknown) terms drop out */
+  }
+  const double fb = sum / 18.0;
+  for (int i = 1; i <= 18; ++i)
+    if (dot_c(i, s) == 0) f[i] = fb;
+  f[19] = 12.0 * fb;
+  /* No momentum correction on corners (Sec. V). */
+}
+
+/* ------------------------------------------------------------------------ */
+/* Public node-rule entry points (k-ordered arrays).                         */
+/* ------------------------------------------------------------------------ */
+void oracle_face_rule(int face, const double v[3], double fk[19]) {
+  double f[20];
+  f[0] = 0.0;
+  memcpy(f + 1, fk, 19 * sizeof(double));
+  face_rule_paper(face, v, f);
+  memcpy(fk, f + 1, 19 * sizeof(double));
+}
+
+void oracle_edge_rule(int face_a, int face_b, double fk[19]) {
+  double f[20];
+  f[0] = 0.0;
+  memcpy(f + 1, fk, 19 * sizeof(double));
+  edge_rule_paper(NORMAL[face_a], NORMAL[face_b], f);
+  memcpy(fk, f + 1, 19 * sizeof(double));
+}
+
+void oracle_corner_rule(int face_a, int face_b, int face_c, double fk[19]) {
+  double f[20];
+  f[0] = 0.0;
+  memcpy(f + 1, fk, 19 * sizeof(double));
+  corner_rule_paper(NORMAL[face_a], NORMAL[face_b], NORMAL[face_c], f);
+  memcpy(fk, f + 1, 19 * sizeof(double));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Lattice bookkeeping.                                                      */
+/* ------------------------------------------------------------------------ */
+static int lattice_valid(const oracle_lattice *L) {
+  const int n[3] = {L->nx, L->ny, L->nz};
+  if (L->nx < 1 || L->ny < 1 || L->nz < 1) return 0;
+  if (!(L->tau > 0.5)) return 0;
+  for (int a = 0; a < 3; ++a) {
+    if (L->bc_set[2 * a] != L->bc_set[2 * a + 1]) return 0;
+    if (L->bc_set[2 * a] && n[a] < 3) return 0;
+  }
+  return 1;
+}
+
+int oracle_update_node(const oracle_lattice *L, int x, int y, int z, const double pulled[19],
+                       double out[19], double u_pre[3]) {
+  if (!lattice_valid(L)) return -1;
+  double f[20];
+  f[0] = 0.0;
+  memcpy(f + 1, pulled, 19 * sizeof(double));
+
+  /* Node class: the set of boundary planes the node lies on.  Reading: a
+   * plane of a periodic axis is not a boundary; an edge or corner exists only
+   * where two or three boundary planes meet, and edges and corners always
+   * take the no-slip rules (Sec. IV end, Sec. V: the inflow must decay to
+   * zero at the edges), also next to an inflow plane. */
+  int faces[3], nf = 0;
+  const int coord[3] = {x, y, z};
+  const int size[3] = {L->nx, L->ny, L->nz};
+  for (int a = 0; a < 3; ++a) {
+    if (L->bc_set[2 * a] && coord[a] == 0) faces[nf++] = 2 * a;
+    if (L->bc_set[2 * a + 1] && coord[a] == size[a] - 1) faces[nf++] = 2 * a + 1;
+  }
+  if (nf == 1) face_rule_paper(faces[0], L->v[faces[0]], f);
+  if (nf == 2) edge_rule_paper(NORMAL[faces[0]], NORMAL[faces[1]], f);
+  if (nf == 3) corner_rule_paper(NORMAL[faces[0]], NORMAL[faces[1]], NORMAL[faces[2]], f);
+
+  /* Moments (eq_rho, eq_vel), then BGK towards f^eq (eq_bgk, eq_feq).  With a
+   * body force the velocity inside f^eq is shifted by tau F / rho
+   * (eq_gravity). */
+  double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+  for (int i = 1; i <= 19; ++i) {
+    rho += f[i];
+    j[0] += f[i] * CX[i];
+    j[1] += f[i] * CY[i];
+    j[2] += f[i] * CZ[i];
+  }
+  const double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+  if (u_pre) {
+    u_pre[0] = u[0];
+    u_pre[1] = u[1];
+    u_pre[2] = u[2];
+  }
+  const double ueq[3] = {u[0] + L->tau * L->force[0] / rho, u[1] + L->tau * L->force[1] / rho,
+                         u[2] + L->tau * L->force[2] / rho};
+  double feq[20];
+  feq_paper(rho, ueq, feq);
+  for (int i = 1; i <= 19; ++i) out[i - 1] = f[i] - (f[i] - feq[i]) / L->tau;
+  return 0;
+}
+
+void oracle_init(const oracle_lattice *L, double rho0, const double u0[3], double *f) {
+  const size_t N = (size_t)L->nx * L->ny * L->nz;
+  double feq[20];
+  feq_paper(rho0, u0, feq);
+  for (int i = 1; i <= 19; ++i)
+    for (size_t n = 0; n < N; ++n) f[(size_t)(i - 1) * N + n] = feq[i];
+}
+
+int oracle_step(const oracle_lattice *L, const double *fin, double *fout, double *u_pre, int nthreads) {
+  if (!lattice_valid(L)) return -1;
+  const int nx = L->nx, ny = L->ny, nz = L->nz;
+  const size_t N = (size_t)nx * ny * nz;
+  const int periodic[3] = {!L->bc_set[0], !L->bc_set[2], !L->bc_set[4]};
+  const int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+  /* Nodes are independent within a step, so the result does not depend on
+   * the thread count. */
+#pragma omp parallel for schedule(static) num_threads(nt)
+  for (int z = 0; z < nz; ++z) {
+    for (int y = 0; y < ny; ++y) {
+      for (int x = 0; x < nx; ++x) {
+        /* Streaming (Sec. II; Sec. III for periodic planes): the population
+         * arriving along c_i comes from x - c_i.  A source outside a boundary
+         * plane does not exist; its value is unknown (NaN here, so that any
+         * use of it would show). */
+        double pulled[19];
+        for (int i = 1; i <= 19; ++i) {
+          int s[3] = {x - CX[i], y - CY[i], z - CZ[i]};
+          const int size[3] = {nx, ny, nz};
+          int inside = 1;
+          for (int a = 0; a < 3; ++a) {
+            if (s[a] < 0 || s[a] >= size[a]) {
+              if (periodic[a])
+                s[a] = (s[a] + size[a]) % size[a];
+              else
+                inside = 0;
+            }
+          }
+          pulled[i - 1] = inside ? fin[(size_t)(i - 1) * N + (size_t)s[0] + (size_t)nx * ((size_t)s[1] + (size_t)ny * s[2])]
+                                 : NAN;
+        }
+        const size_t n = (size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z);
+        double out[19], up[3];
+        oracle_update_node(L, x, y, z, pulled, out, up);
+        for (int k = 0; k < 19; ++k) fout[(size_t)k * N + n] = out[k];
+        if (u_pre) {
+          u_pre[n] = up[0];
+          u_pre[N + n] = up[1];
+          u_pre[2 * N + n] = up[2];
+        }
+      }
+    }
+  }
+  return 0;
+}
+
+void oracle_moments(const oracle_lattice *L, const double *f, double *rho, double *u) {
+  const size_t N = (size_t)L->nx * L->ny * L->nz;
+  for (size_t n = 0; n < N; ++n) {
+    double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 1; i <= 19; ++i) {
+      const double fi = f[(size_t)(i - 1) * N + n];
+      r += fi;
+      j[0] += fi * CX[i];
+      j[1] += fi * CY[i];
+      j[2] += fi * CZ[i];
+    }
+    if (rho) rho[n] = r;
+    if (u) {
+      u[n] = j[0] / r;
+      u[N + n] = j[1] / r;
+      u[2 * N + n] = j[2] / r;
+    }
+  }
+}
+
+void oracle_totals(const oracle_lattice *L, const double *f, double *mass, double mom[3]) {
+  const size_t N = (size_t)L->nx * L->ny * L->nz;
+  double m = 0.0, j[3] = {0.0, 0.0, 0.0};
+  for (size_t n = 0; n < N; ++n) {
+    for (int i = 1; i <= 19; ++i) {
+      const double fi = f[(size_t)(i - 1) * N + n];
+      m += fi;
+      j[0] += fi * CX[i];
+      j[1] += fi * CY[i];
+      j[2] += fi * CZ[i];
+    }
+  }
+  *mass = m;
+  mom[0] = j[0];
+  mom[1] = j[1];
+  mom[2] = j[2];
+}

@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Throughput of the fused D3Q19 sweep on one MI355X.
+
+Workload: the 1024 x 512 x 512 duct (no-slip on-site walls on the y and z
+faces, on-site velocity inlet and outlet (0.04, 0.01, 0.01) on the x faces,
+tau = 0.8, FP32 storage), initial state at rest, synthetic.  A step is one
+launch of the fused sweep over all 2^28 nodes (pull streaming, boundary
+rules, BGK collision).  W untimed warm-up steps, then exactly K timed steps
+bracketed by device synchronisation.
+
+Printed: one JSON line with MLUPS (the value), the roofline object for the
+sweep kernel (algorithmic bytes per launch / average launch duration measured
+with HIP events on the launch stream), the bandwidth probes of the same
+buffers, and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+_ROOT = os.path.dirname(os.path.abspath(__file__))
+if _ROOT not in sys.path:
+    sys.path.insert(0, _ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+METRIC = "D3Q19 MLUPS & % HBM roofline; batched solves/s, p50/p99 at ≤1e-3 L2 err"
+COUNTERS_FILE = os.path.join(_ROOT, "profiles", "sweep_f32_duct_1024x512x512_counters.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("d3q19.hpp", "lbm_kernels.hip", "lbm_internal.hpp"):
+        with open(os.path.join(_ROOT, "paper_0811_4593_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(launch, storage):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
+    were taken on the current kernel source and launch shape; else None."""
+    try:
+        with open(COUNTERS_FILE) as fh:
+            c = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if c.get("kernel_source_hash") != kernel_source_hash() or c.get("launch") != list(launch) \
+            or c.get("storage") != storage:
+        return None
+    return c.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(spec_full, budget_s: float):
+    """The FP64 CPU oracle, as it stands, on a bounded sample of the workload:
+    the same duct set-up at 256 x 128 x 128 (1/64 of the nodes), stepped until
+    `budget_s` seconds have passed (at least 2 steps)."""
+    import oracle
+    from paper_0811_4593_amd import workloads
+
+    s = workloads.duct(256, 128, 128, spec_full.bc[0], spec_full.tau)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    L = oracle.Lattice(s.nx, s.ny, s.nz, s.tau, bc=s.bc)
+    f = L.init()
+    f = L.step(f, nthreads=threads)  # first touch of the buffers, untimed
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        f = L.step(f, nthreads=threads)
+        steps += 1
+        el = time.perf_counter() - t0
+        if (el >= budget_s and steps >= 2) or steps >= 50:
+            break
+    mlups = s.nodes * steps / el / 1e6
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"duct {s.nx}x{s.ny}x{s.nz} (same boundary set-up, 1/64 of the nodes), FP64, "
+                      f"{steps} steps in {el:.1f} s; effective {mlups * 304 / 1e3:.2f} GB/s at 304 B/node"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16dev"])
+    ap.add_argument("--launch", default=None, help="block_x,nodes_per_thread,xcd_remap (default: library's)")
+    ap.add_argument("--nx", type=int, default=1024)
+    ap.add_argument("--ny", type=int, default=512)
+    ap.add_argument("--nz", type=int, default=512)
+    ap.add_argument("--probe-reps", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the single-lattice path "
+              "does not shard across GPUs in this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_0811_4593_amd import lbm, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    storage = {"f32": lbm.LBM_STORE_F32, "f64": lbm.LBM_STORE_F64, "f16dev": lbm.LBM_STORE_F16_DEV}[args.storage]
+    ebytes = lbm.lbm_element_bytes(storage)
+    spec = workloads.duct(args.nx, args.ny, args.nz, (0.04, 0.01, 0.01), 0.8)
+    N = spec.nodes
+    stream = torch.cuda.current_stream()
+    h = lbm.lbm_create(spec.nx, spec.ny, spec.nz, spec.tau, spec.rho0, None, storage, stream)
+    try:
+        for face, v in spec.bc.items():
+            lbm.lbm_set_velocity_bc(h, face, v)
+        if args.launch:
+            lbm.lbm_set_launch(h, *[int(t) for t in args.launch.split(",")])
+        launch = lbm.lbm_get_launch(h)
+
+        lbm.lbm_step(h, args.warmup)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        lbm.lbm_step(h, args.steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ev_ms = ev0.elapsed_time(ev1)
+        mass, _ = lbm.lbm_totals(h)  # also checks the state is finite
+
+        # Bandwidth probes on the same buffers: the pull-pattern copy (no
+        # arithmetic, no boundary rule) and a plain contiguous copy.
+        probes = {}
+        for kind, name in ((1, "pull_pattern_copy"), (0, "contiguous_copy")):
+            lbm.lbm_probe(h, kind, 2)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            lbm.lbm_probe(h, kind, args.probe_reps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.probe_reps
+            probes[name] = round(2 * 19 * N * ebytes / (ms * 1e-3) / 1e9, 1)
+    finally:
+        lbm.lbm_destroy(h)
+
+    ms_per_step = wall * 1e3 / args.steps
+    value = N * args.steps / wall / 1e6
+    kernel_ms = ev_ms / args.steps
+    alg_bytes = 2 * 19 * ebytes * N  # 19 loads + 19 stores per node update
+    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    traffic = measured_traffic(launch, args.storage)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic",
+        "config": {
+            "workload": f"duct {spec.nx}x{spec.ny}x{spec.nz}, on-site Zou-He velocity inlet/outlet "
+                        f"(0.04,0.01,0.01), on-site no-slip y/z walls, tau 0.8, {args.storage} storage",
+            "nodes": N,
+            "bytes_per_node_update": 2 * 19 * ebytes,
+            "launch": {"block_x": launch[0], "nodes_per_thread": launch[1], "xcd_remap": launch[2]},
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": traffic,
+            "kernel": "sweep_kernel",
+            "kernel_ms_avg": round(kernel_ms, 4),
+        },
+        "probes_GBs": probes,
+        "mass_after": mass,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

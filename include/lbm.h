@@ -1,0 +1,170 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) D3Q19 lattice Boltzmann library with
+ * the on-site velocity boundary condition of M. Hecht and J. Harting,
+ * "Implementation of on-site velocity boundary conditions for D3Q19 lattice
+ * Boltzmann" (arXiv:0811.4593).
+ *
+ * What one time step computes (lbm_step):
+ *   1. streaming: every population moves one link along its lattice vector
+ *      c_i (Sec. II, the alternating stream/collide scheme); on a periodic
+ *      axis populations leaving one end enter at the other (Sec. III);
+ *   2. boundary rules at nodes on a non-periodic plane, using only the
+ *      node's own populations (Sec. IV, Sec. V, Appendix):
+ *        - face nodes: the prescribed velocity v is imposed exactly; the
+ *          density follows from the known populations (eq_uin and its
+ *          Appendix forms); the unknown populations are rebuilt by
+ *          non-equilibrium bounce-back plus the transverse momentum
+ *          corrections N (eq_f5, eq_f9-eq_f17, eq_Nx, eq_Ny, eq_bbshort);
+ *          v = 0 is the on-site no-slip wall (Sec. V);
+ *        - edge nodes (two planes meet): no-slip bounce-back, the momentum
+ *          correction along the edge (eq_Nxzy, eq_edge) and the buried links
+ *          (eq_buried);
+ *        - corner nodes (three planes meet): no-slip bounce-back and the six
+ *          buried links (eq_corner);
+ *      Edge and corner nodes are always no-slip, also where they border a
+ *      velocity plane: the paper requires the inflow to decay to zero at the
+ *      edges (end of Sec. IV; Sec. V);
+ *   3. BGK collision f <- f - (f - f^eq(rho, u))/tau with the second-order
+ *      equilibrium (eq_bgk, eq_feq, eq_weights).
+ * The stored state is the post-collision population set.
+ *
+ * Conventions
+ *   node index   n = x + nx*(y + ny*z)
+ *   population   k = i - 1, where i = 1..19 numbers the lattice vectors as the
+ *                columns of the matrix M (Sec. II, eq_deffs); k = 18 is the
+ *                rest population.  Population arrays are structure-of-arrays,
+ *                f[k*N + n] with N = nx*ny*nz.
+ *   axes         every axis is periodic until a face of it gets a velocity
+ *                BC; lbm_step then requires both faces of that axis to be set.
+ *                A non-periodic axis needs at least 3 nodes.
+ *
+ * Storage forms (lbm_storage)
+ *   LBM_STORE_F64      populations in double, arithmetic in double
+ *   LBM_STORE_F32      populations in float,  arithmetic in float
+ *   LBM_STORE_F16_DEV  populations stored as half-precision scaled deviations
+ *                      h_k = RNE((f_k - w_k) * 2^8), decoded f_k = w_k + h_k*2^-8,
+ *                      arithmetic in float (w_k: lattice weight, eq_weights)
+ *
+ * Errors: every call returns an lbm_status and never aborts.  On failure
+ * lbm_last_error() returns a message for the calling thread.  Calls on one
+ * handle are not thread-safe.
+ *
+ * Ownership: lbm_create allocates the two population buffers on the current
+ * HIP device; lbm_create_on_buffers adopts caller-owned device buffers that
+ * must outlive the handle.  The caller owns every other pointer it passes.
+ * All device work of a handle runs on the stream given at creation (NULL: the
+ * null stream).  lbm_step only enqueues; the calls that return data
+ * synchronize that stream.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_lattice lbm_lattice;
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_ERR_ARG = -1,       /* invalid argument (sizes, tau, velocity, pointer) */
+  LBM_ERR_OOM = -2,       /* device allocation failed */
+  LBM_ERR_HIP = -3,       /* a HIP runtime call failed */
+  LBM_ERR_STATE = -4,     /* handle not in a state that allows the call */
+  LBM_ERR_NONFINITE = -5  /* a reduction found NaN or Inf in the state */
+} lbm_status;
+
+typedef enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16_DEV = 2 } lbm_storage;
+
+/* Faces: x = 0 (paper: left), x = nx-1 (right), y = 0 (front),
+ * y = ny-1 (back), z = 0 (bottom), z = nz-1 (top). */
+typedef enum { LBM_X0 = 0, LBM_X1 = 1, LBM_Y0 = 2, LBM_Y1 = 3, LBM_Z0 = 4, LBM_Z1 = 5 } lbm_face;
+
+/* Create a lattice of nx*ny*nz nodes (each >= 1, N < 2^31) with relaxation
+ * time tau > 1/2, all axes periodic, every node at f^eq(rho0, u0)
+ * (eq_feq).  rho0 > 0; u0 may be NULL (rest).  hip_stream is a hipStream_t
+ * or NULL.  On success *out receives the handle.
+ * Errors: LBM_ERR_ARG (sizes, tau, rho0, storage, out == NULL),
+ * LBM_ERR_OOM, LBM_ERR_HIP. */
+lbm_status lbm_create(int nx, int ny, int nz, double tau, double rho0, const double u0[3],
+                      lbm_storage storage, void *hip_stream, lbm_lattice **out);
+
+/* As lbm_create, on two caller-owned device buffers of buf_bytes bytes each
+ * (at least 19*N*element size, 256-byte aligned).  The library never frees
+ * them.  Errors as lbm_create; LBM_ERR_ARG if a buffer is NULL, too small or
+ * misaligned. */
+lbm_status lbm_create_on_buffers(int nx, int ny, int nz, double tau, double rho0, const double u0[3],
+                                 lbm_storage storage, void *hip_stream, void *buf_a, void *buf_b,
+                                 size_t buf_bytes, lbm_lattice **out);
+
+/* Prescribe the velocity u[3] (lattice units) on a face (Sec. IV, eq_uin;
+ * u = 0: on-site no-slip, Sec. V).  The face's axis becomes non-periodic.
+ * May be called between steps (moving walls).
+ * Errors: LBM_ERR_ARG if L or u is NULL, the face is invalid, the axis has
+ * fewer than 3 nodes, |u . n| >= 1 (the density of eq_uin diverges) or
+ * |u| >= 1/sqrt(3) (the lattice speed of sound). */
+lbm_status lbm_set_velocity_bc(lbm_lattice *L, lbm_face face, const double u[3]);
+
+/* Remove the velocity BC of a face.  When both faces of an axis are cleared
+ * the axis is periodic again.  Errors: LBM_ERR_ARG. */
+lbm_status lbm_clear_bc(lbm_lattice *L, lbm_face face);
+
+/* Enqueue nsteps >= 0 time steps on the handle's stream; returns without
+ * waiting.  Errors: LBM_ERR_ARG (L NULL, nsteps < 0), LBM_ERR_STATE (an axis
+ * with a BC on one face only), LBM_ERR_HIP (launch failure). */
+lbm_status lbm_step(lbm_lattice *L, int nsteps);
+
+/* Density rho[n] and velocity u[a*N + n] of the stored state (eq_rho,
+ * eq_vel), in double.  Either pointer may be NULL.  dst_on_device != 0: the
+ * pointers are device pointers; otherwise host pointers.  Synchronizes the
+ * handle's stream.  Errors: LBM_ERR_ARG, LBM_ERR_OOM, LBM_ERR_HIP. */
+lbm_status lbm_moments(lbm_lattice *L, double *rho, double *u, int dst_on_device);
+
+/* Total mass sum_n rho and momentum sum_n rho u of the stored state, reduced
+ * in double in a fixed order (results do not depend on scheduling).
+ * Synchronizes.  Errors: LBM_ERR_ARG, LBM_ERR_HIP, LBM_ERR_NONFINITE (NaN or
+ * Inf in the totals; the values are still written). */
+lbm_status lbm_totals(lbm_lattice *L, double *mass, double momentum[3]);
+
+/* Copy the stored state to / from a host array f[19*N] of doubles (same
+ * layout as the device state).  For LBM_STORE_F32 and LBM_STORE_F16_DEV the
+ * values are converted (set: rounded to nearest even).  Synchronizes.
+ * Errors: LBM_ERR_ARG, LBM_ERR_OOM, LBM_ERR_HIP. */
+lbm_status lbm_get_populations(lbm_lattice *L, double *f);
+lbm_status lbm_set_populations(lbm_lattice *L, const double *f);
+
+/* Device pointer of the buffer that holds the stored state (it alternates
+ * between the two buffers every step).  Errors: LBM_ERR_ARG. */
+lbm_status lbm_state_buffer(const lbm_lattice *L, void **dev_ptr);
+
+/* Bytes of one population element for a storage form (8, 4 or 2); 0 if the
+ * storage value is invalid. */
+size_t lbm_element_bytes(lbm_storage storage);
+
+/* Launch shape of the sweep kernel: block_x threads along x (64, 128, 256 or
+ * 512), nodes_per_thread along x (1, 2 or 4), xcd_remap != 0 places
+ * consecutive x-rows on the same XCD (L2) of the MI355X.  Any shape gives the
+ * same results.  Errors: LBM_ERR_ARG for an unsupported shape. */
+lbm_status lbm_set_launch(lbm_lattice *L, int block_x, int nodes_per_thread, int xcd_remap);
+lbm_status lbm_get_launch(const lbm_lattice *L, int *block_x, int *nodes_per_thread, int *xcd_remap);
+
+/* Bandwidth probes on the handle's buffers (measurement only; they overwrite
+ * the non-current buffer and leave the stored state intact):
+ *   kind 0: plain contiguous copy of the 19*N elements;
+ *   kind 1: the sweep's streaming access pattern (19 pulled loads, 19
+ *           stores per node) with no boundary rule and no arithmetic.
+ * Enqueues nrep launches.  Errors: LBM_ERR_ARG, LBM_ERR_HIP. */
+lbm_status lbm_probe(lbm_lattice *L, int kind, int nrep);
+
+/* Release the handle and the buffers it allocated.  NULL is a no-op. */
+void lbm_destroy(lbm_lattice *L);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

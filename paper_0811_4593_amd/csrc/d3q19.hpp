@@ -1,0 +1,188 @@
+// d3q19.hpp -- D3Q19 lattice constants and the per-node rules of the sweep,
+// as device functions for gfx950.
+//
+// Population k = i - 1 where i numbers the lattice vectors as the columns of
+// the matrix M (Sec. II, eq_deffs); weights from eq_weights.  Every rule is a
+// template over the boundary normals, so after unrolling all population
+// indices and lattice-vector components are compile-time constants: the 19
+// populations of a node live in registers and are never indexed at run time.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace lbm {
+
+__host__ __device__ constexpr int cx(int k) {
+  constexpr int t[19] = {1, -1, 0, 0, 0, 0, 1, 1, 1, 1, -1, -1, -1, -1, 0, 0, 0, 0, 0};
+  return t[k];
+}
+__host__ __device__ constexpr int cy(int k) {
+  constexpr int t[19] = {0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0};
+  return t[k];
+}
+__host__ __device__ constexpr int cz(int k) {
+  constexpr int t[19] = {0, 0, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, 1, -1, 0};
+  return t[k];
+}
+// Weight numerators over 36 (eq_weights).
+__host__ __device__ constexpr int w36(int k) { return k < 6 ? 2 : (k < 18 ? 1 : 12); }
+
+__host__ __device__ constexpr int index_of(int x, int y, int z) {
+  for (int k = 0; k < 19; ++k)
+    if (cx(k) == x && cy(k) == y && cz(k) == z) return k;
+  return -1;
+}
+__host__ __device__ constexpr int opp(int k) { return index_of(-cx(k), -cy(k), -cz(k)); }
+
+template <class T>
+__device__ __forceinline__ T weight(int k) {
+  return T(w36(k)) / T(36);
+}
+
+// c_k . n for an integer vector n = (nx, ny, nz).
+__host__ __device__ constexpr int dotn(int k, int nx, int ny, int nz) {
+  return cx(k) * nx + cy(k) * ny + cz(k) * nz;
+}
+
+// Bit mask (bit k) of the populations whose streaming source lies outside the
+// domain at a node on boundary face f: c_k . n_f > 0, n_f the inward normal
+// of face f (x=0, x=nx-1, y=0, y=ny-1, z=0, z=nz-1).
+__host__ __device__ constexpr int face_normal(int f, int axis) {
+  return (f / 2 == axis) ? ((f % 2 == 0) ? 1 : -1) : 0;
+}
+__host__ __device__ constexpr unsigned unknown_mask(int f) {
+  unsigned m = 0;
+  for (int k = 0; k < 19; ++k)
+    if (dotn(k, face_normal(f, 0), face_normal(f, 1), face_normal(f, 2)) > 0) m |= 1u << k;
+  return m;
+}
+
+// Face velocities in the compute type, indexed by face id (x0,x1,y0,y1,z0,z1).
+template <class T>
+struct FaceVel {
+  T v[6][3];
+};
+
+// ---------------------------------------------------------------------------
+// Boundary rules of one node.  m has bit f set when the node lies on boundary
+// face f (at most one bit per axis).  The rule is written once for every
+// face, edge and corner: the set of unknown populations U, the normals and
+// the edge direction are per-lane values, every population index is a
+// compile-time constant, and each update is a select -- the 19 populations
+// stay in registers and are never indexed at run time.
+//
+// Face (one bit; Sec. IV, Appendix; general form of eq_bbshort):
+//   rho = (sum_{c.n=0} f + 2 sum_{c.n<0} f) / (1 - v.n)                 (eq_uin)
+//   for every unknown j (c_j.n > 0), i = -j:
+//   f_j = f_i - 6 w_i rho (c_i.v) - (rho/3) (t_i.v) + 1/2 t_i.M           (eq_bbshort)
+//   with t_i = c_i - (c_i.n) n = c_i + n and M = sum_{c.n=0} f c (the
+//   in-plane momentum; t_i.M = c_i.M as M is normal to n).  The factor 6 w_i
+//   is rho/3 on the normal link (eq_f5) and rho/6 on the diagonals
+//   (eq_f9-eq_f17); the last two terms are the corrections N (eq_Nx, eq_Ny).
+// Edge (two bits; Sec. V, eq_Nxzy, eq_edge, eq_buried) and corner (three
+// bits; eq_corner), both no-slip:
+//   buried links: unknown populations whose opposite is unknown as well
+//   (the pair +-(n1 - n2) on an edge, the six c.(n1+n2+n3) = 0 on a corner);
+//   every other unknown is bounced back, f_k = f_{-k}; on an edge the four
+//   bounced links with c.e != 0 (e the edge direction) also get
+//   -(c.e)(f_{+e} - f_{-e})/4, which removes the momentum along the edge;
+//   buried links = (sum of the other moving populations) / D with D = 22
+//   (edge) or 18 (corner); rest population = 12 times that.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ void boundary_rule(T (&f)[19], unsigned m, const FaceVel<T> &fv) {
+  unsigned U = 0;
+#pragma unroll
+  for (int b = 0; b < 6; ++b)
+    if (m & (1u << b)) U |= unknown_mask(b);
+  // Sum of inward normals, one component per axis.
+  const int sx = int(m & 1u) - int((m >> 1) & 1u);
+  const int sy = int((m >> 2) & 1u) - int((m >> 3) & 1u);
+  const int sz = int((m >> 4) & 1u) - int((m >> 5) & 1u);
+  const int nb = __popc(m);
+  if (nb == 1) {
+    // Face: n = (sx, sy, sz); velocity of that face.
+    T vx = T(0), vy = T(0), vz = T(0);
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+      if (m == (1u << b)) {
+        vx = fv.v[b][0];
+        vy = fv.v[b][1];
+        vz = fv.v[b][2];
+      }
+    const T vn = T(sx) * vx + T(sy) * vy + T(sz) * vz;
+    T s_known = T(0), s_out = T(0), Mx = T(0), My = T(0), Mz = T(0);
+#pragma unroll
+    for (int k = 0; k < 19; ++k) {
+      const bool unk = (U >> k) & 1u;
+      const bool out = (U >> opp(k)) & 1u;  // c_k.n < 0
+      const bool in_plane = !unk && !out;
+      s_known += unk ? T(0) : f[k];
+      s_out += out ? f[k] : T(0);
+      if (cx(k)) Mx += in_plane ? T(cx(k)) * f[k] : T(0);
+      if (cy(k)) My += in_plane ? T(cy(k)) * f[k] : T(0);
+      if (cz(k)) Mz += in_plane ? T(cz(k)) * f[k] : T(0);
+    }
+    const T rho = (s_known + s_out) / (T(1) - vn);
+    const T rho3 = rho / T(3);
+#pragma unroll
+    for (int j = 0; j < 18; ++j) {
+      const int i = opp(j);
+      const T civ = T(cx(i)) * vx + T(cy(i)) * vy + T(cz(i)) * vz;
+      const T ciM = T(cx(i)) * Mx + T(cy(i)) * My + T(cz(i)) * Mz;
+      const T fj = f[i] - T(6 * w36(i)) / T(36) * rho * civ - rho3 * (civ + vn) + T(0.5) * ciM;
+      f[j] = ((U >> j) & 1u) ? fj : f[j];
+    }
+  } else {
+    // Edge or corner, no-slip.
+    const int ex = (nb == 2 && sx == 0) ? 1 : 0;
+    const int ey = (nb == 2 && sy == 0) ? 1 : 0;
+    const int ez = (nb == 2 && sz == 0) ? 1 : 0;
+    const T Pq = T(0.25) * (T(ex) * (f[0] - f[1]) + T(ey) * (f[2] - f[3]) + T(ez) * (f[4] - f[5]));
+    unsigned bur = 0;
+#pragma unroll
+    for (int k = 0; k < 18; ++k) bur |= ((U >> k) & (U >> opp(k)) & 1u) << k;
+#pragma unroll
+    for (int k = 0; k < 18; ++k) {
+      const bool bounced = ((U & ~bur) >> k) & 1u;
+      const int ce = cx(k) * ex + cy(k) * ey + cz(k) * ez;
+      const T fk = f[opp(k)] - T(ce) * Pq;
+      f[k] = bounced ? fk : f[k];
+    }
+    T s = T(0);
+#pragma unroll
+    for (int k = 0; k < 18; ++k) s += ((bur >> k) & 1u) ? T(0) : f[k];
+    const T fb = s / (nb == 2 ? T(22) : T(18));
+#pragma unroll
+    for (int k = 0; k < 18; ++k) f[k] = ((bur >> k) & 1u) ? fb : f[k];
+    f[18] = T(12) * fb;
+  }
+}
+
+// BGK collision towards the second-order equilibrium (eq_bgk, eq_feq):
+// f_k <- f_k + omega (f_k^eq(rho, u) - f_k), omega = 1/tau, c_s^2 = 1/3.
+template <class T>
+__device__ __forceinline__ void bgk_collide(T (&f)[19], T omega) {
+  T rho = T(0), jx = T(0), jy = T(0), jz = T(0);
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    rho += f[k];
+    if (cx(k)) jx += T(cx(k)) * f[k];
+    if (cy(k)) jy += T(cy(k)) * f[k];
+    if (cz(k)) jz += T(cz(k)) * f[k];
+  }
+  const T ir = T(1) / rho;
+  const T ux = jx * ir, uy = jy * ir, uz = jz * ir;
+  const T usq15 = T(1.5) * (ux * ux + uy * uy + uz * uz);
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    T cu = T(0);
+    if (cx(k)) cu += T(cx(k)) * ux;
+    if (cy(k)) cu += T(cy(k)) * uy;
+    if (cz(k)) cu += T(cz(k)) * uz;
+    const T feq = weight<T>(k) * rho * (T(1) + T(3) * cu + T(4.5) * cu * cu - usq15);
+    f[k] = f[k] + omega * (feq - f[k]);
+  }
+}
+
+}  // namespace lbm

@@ -1,0 +1,373 @@
+// lbm_capi.hip -- the C ABI declared in include/lbm.h: handle management,
+// argument and state validation, and the launches on the handle's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "../../include/lbm.h"
+#include "lbm_internal.hpp"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+lbm_status fail(lbm_status st, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+lbm_status hip_fail(hipError_t e, const char *what) {
+  return fail(LBM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define LBM_HIP(call, what)                      \
+  do {                                           \
+    hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+constexpr int kPartialBlocks = 1024;  // fixed grid of the reduction: deterministic order
+constexpr size_t kChunkNodes = size_t(1) << 22;  // host transfers are staged in chunks
+
+}  // namespace
+
+struct lbm_lattice {
+  int nx, ny, nz;
+  size_t N;
+  double tau;
+  int storage;
+  size_t esize;
+  hipStream_t stream;
+  void *buf[2];
+  int cur;
+  bool owns;
+  unsigned bc_mask;
+  double v[6][3];
+  int block_x, npt, xcd;
+  double *d_partials;  // [kPartialBlocks * 4]
+  double *d_totals;    // [4]
+  double *d_stage;     // [19 * kChunkNodes] doubles, allocated on first use
+};
+
+extern "C" {
+
+const char *lbm_last_error(void) { return g_err; }
+
+size_t lbm_element_bytes(lbm_storage storage) {
+  switch (storage) {
+    case LBM_STORE_F64: return 8;
+    case LBM_STORE_F32: return 4;
+    case LBM_STORE_F16_DEV: return 2;
+  }
+  return 0;
+}
+
+static lbm_status validate_create(int nx, int ny, int nz, double tau, double rho0, lbm_storage storage,
+                                  lbm_lattice **out) {
+  if (!out) return fail(LBM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (nx < 1 || ny < 1 || nz < 1) return fail(LBM_ERR_ARG, "lattice sizes must be >= 1 (got %d x %d x %d)", nx, ny, nz);
+  const double n = double(nx) * double(ny) * double(nz);
+  if (n >= 2147483648.0) return fail(LBM_ERR_ARG, "lattice has %.0f nodes; at most 2^31 - 1 are supported", n);
+  if (!(tau > 0.5) || !std::isfinite(tau)) return fail(LBM_ERR_ARG, "tau must be > 1/2 (got %g)", tau);
+  if (!(rho0 > 0.0) || !std::isfinite(rho0)) return fail(LBM_ERR_ARG, "rho0 must be > 0 (got %g)", rho0);
+  if (lbm_element_bytes(storage) == 0) return fail(LBM_ERR_ARG, "invalid storage form %d", int(storage));
+  return LBM_OK;
+}
+
+static void default_launch(lbm_lattice *L) {
+  // One block covers a whole x-row when it fits: 256 threads, up to 4 nodes
+  // each.
+  L->block_x = 256;
+  L->npt = L->nx > 512 ? 4 : (L->nx > 256 ? 2 : 1);
+  L->xcd = 1;
+}
+
+static lbm_status finish_create(lbm_lattice *L, double rho0, const double u0[3], lbm_lattice **out) {
+  const double zero[3] = {0.0, 0.0, 0.0};
+  if (!u0) u0 = zero;
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(u0[d])) return fail(LBM_ERR_ARG, "u0 is not finite");
+  hipError_t e = hipMalloc(&L->d_partials, sizeof(double) * (kPartialBlocks * 4 + 4));
+  if (e != hipSuccess) return fail(LBM_ERR_OOM, "hipMalloc of reduction scratch failed: %s", hipGetErrorString(e));
+  L->d_totals = L->d_partials + kPartialBlocks * 4;
+  e = lbm::launch_init(L->storage, L->buf[0], L->N, rho0, u0, L->stream);
+  if (e != hipSuccess) return hip_fail(e, "init launch");
+  e = hipStreamSynchronize(L->stream);
+  if (e != hipSuccess) return hip_fail(e, "init");
+  *out = L;
+  g_err[0] = '\0';
+  return LBM_OK;
+}
+
+lbm_status lbm_create(int nx, int ny, int nz, double tau, double rho0, const double u0[3], lbm_storage storage,
+                      void *hip_stream, lbm_lattice **out) {
+  lbm_status st = validate_create(nx, ny, nz, tau, rho0, storage, out);
+  if (st != LBM_OK) return st;
+  lbm_lattice *L = new (std::nothrow) lbm_lattice();
+  if (!L) return fail(LBM_ERR_OOM, "host allocation failed");
+  L->nx = nx;
+  L->ny = ny;
+  L->nz = nz;
+  L->N = size_t(nx) * ny * nz;
+  L->tau = tau;
+  L->storage = int(storage);
+  L->esize = lbm_element_bytes(storage);
+  L->stream = static_cast<hipStream_t>(hip_stream);
+  L->owns = true;
+  default_launch(L);
+  const size_t bytes = 19 * L->N * L->esize;
+  for (int i = 0; i < 2; ++i) {
+    hipError_t e = hipMalloc(&L->buf[i], bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      lbm_destroy(L);
+      return fail(LBM_ERR_OOM, "hipMalloc of %zu bytes for populations failed: %s", bytes, hipGetErrorString(e));
+    }
+  }
+  st = finish_create(L, rho0, u0, out);
+  if (st != LBM_OK) lbm_destroy(L);
+  return st;
+}
+
+lbm_status lbm_create_on_buffers(int nx, int ny, int nz, double tau, double rho0, const double u0[3],
+                                 lbm_storage storage, void *hip_stream, void *buf_a, void *buf_b, size_t buf_bytes,
+                                 lbm_lattice **out) {
+  lbm_status st = validate_create(nx, ny, nz, tau, rho0, storage, out);
+  if (st != LBM_OK) return st;
+  const size_t need = 19 * size_t(nx) * ny * nz * lbm_element_bytes(storage);
+  if (!buf_a || !buf_b || buf_a == buf_b) return fail(LBM_ERR_ARG, "two distinct device buffers are required");
+  if (buf_bytes < need) return fail(LBM_ERR_ARG, "buffers hold %zu bytes, %zu needed", buf_bytes, need);
+  if ((reinterpret_cast<uintptr_t>(buf_a) | reinterpret_cast<uintptr_t>(buf_b)) & 255u)
+    return fail(LBM_ERR_ARG, "buffers must be 256-byte aligned");
+  lbm_lattice *L = new (std::nothrow) lbm_lattice();
+  if (!L) return fail(LBM_ERR_OOM, "host allocation failed");
+  L->nx = nx;
+  L->ny = ny;
+  L->nz = nz;
+  L->N = size_t(nx) * ny * nz;
+  L->tau = tau;
+  L->storage = int(storage);
+  L->esize = lbm_element_bytes(storage);
+  L->stream = static_cast<hipStream_t>(hip_stream);
+  L->owns = false;
+  L->buf[0] = buf_a;
+  L->buf[1] = buf_b;
+  default_launch(L);
+  st = finish_create(L, rho0, u0, out);
+  if (st != LBM_OK) lbm_destroy(L);
+  return st;
+}
+
+void lbm_destroy(lbm_lattice *L) {
+  if (!L) return;
+  if (L->stream) (void)hipStreamSynchronize(L->stream);
+  else (void)hipDeviceSynchronize();
+  if (L->owns) {
+    for (int i = 0; i < 2; ++i)
+      if (L->buf[i]) (void)hipFree(L->buf[i]);
+  }
+  if (L->d_partials) (void)hipFree(L->d_partials);
+  if (L->d_stage) (void)hipFree(L->d_stage);
+  delete L;
+}
+
+static const int kNormal[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+
+lbm_status lbm_set_velocity_bc(lbm_lattice *L, lbm_face face, const double u[3]) {
+  if (!L || !u) return fail(LBM_ERR_ARG, "NULL argument");
+  const int f = int(face);
+  if (f < 0 || f > 5) return fail(LBM_ERR_ARG, "invalid face %d", f);
+  const int size[3] = {L->nx, L->ny, L->nz};
+  if (size[f / 2] < 3) return fail(LBM_ERR_ARG, "a bounded axis needs at least 3 nodes (axis %d has %d)", f / 2, size[f / 2]);
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(u[d])) return fail(LBM_ERR_ARG, "velocity is not finite");
+  const double un = u[0] * kNormal[f][0] + u[1] * kNormal[f][1] + u[2] * kNormal[f][2];
+  if (std::fabs(un) >= 1.0) return fail(LBM_ERR_ARG, "|u.n| = %g >= 1: the boundary density diverges", std::fabs(un));
+  const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  if (uu >= 1.0 / 3.0) return fail(LBM_ERR_ARG, "|u| = %g is not below the speed of sound 1/sqrt(3)", std::sqrt(uu));
+  L->bc_mask |= 1u << f;
+  for (int d = 0; d < 3; ++d) L->v[f][d] = u[d];
+  return LBM_OK;
+}
+
+lbm_status lbm_clear_bc(lbm_lattice *L, lbm_face face) {
+  if (!L) return fail(LBM_ERR_ARG, "NULL handle");
+  const int f = int(face);
+  if (f < 0 || f > 5) return fail(LBM_ERR_ARG, "invalid face %d", f);
+  L->bc_mask &= ~(1u << f);
+  for (int d = 0; d < 3; ++d) L->v[f][d] = 0.0;
+  return LBM_OK;
+}
+
+static lbm::SweepConfig sweep_config(const lbm_lattice *L) {
+  lbm::SweepConfig c;
+  c.storage = L->storage;
+  c.nx = L->nx;
+  c.ny = L->ny;
+  c.nz = L->nz;
+  c.tau = L->tau;
+  c.bc_mask = L->bc_mask;
+  std::memcpy(c.v, L->v, sizeof(c.v));
+  c.block_x = L->block_x;
+  c.nodes_per_thread = L->npt;
+  c.xcd_remap = L->xcd;
+  return c;
+}
+
+lbm_status lbm_step(lbm_lattice *L, int nsteps) {
+  if (!L) return fail(LBM_ERR_ARG, "NULL handle");
+  if (nsteps < 0) return fail(LBM_ERR_ARG, "nsteps must be >= 0");
+  for (int a = 0; a < 3; ++a) {
+    const unsigned bits = (L->bc_mask >> (2 * a)) & 3u;
+    if (bits == 1u || bits == 2u)
+      return fail(LBM_ERR_STATE, "axis %d has a velocity BC on one face only; set both faces or none", a);
+  }
+  const lbm::SweepConfig c = sweep_config(L);
+  for (int s = 0; s < nsteps; ++s) {
+    hipError_t e = lbm::launch_sweep(c, L->buf[L->cur], L->buf[L->cur ^ 1], false, L->stream);
+    if (e != hipSuccess) return hip_fail(e, "sweep launch");
+    L->cur ^= 1;
+  }
+  return LBM_OK;
+}
+
+static lbm_status ensure_stage(lbm_lattice *L) {
+  if (L->d_stage) return LBM_OK;
+  hipError_t e = hipMalloc(&L->d_stage, sizeof(double) * 19 * kChunkNodes);
+  if (e != hipSuccess) {
+    L->d_stage = nullptr;
+    return fail(LBM_ERR_OOM, "hipMalloc of the staging buffer failed: %s", hipGetErrorString(e));
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_lattice *L, double *rho, double *u, int dst_on_device) {
+  if (!L) return fail(LBM_ERR_ARG, "NULL handle");
+  if (!rho && !u) return LBM_OK;
+  const void *f = L->buf[L->cur];
+  if (dst_on_device) {
+    LBM_HIP(lbm::launch_moments(L->storage, f, L->N, 0, L->N, rho, u, nullptr, kPartialBlocks, L->stream),
+            "moments launch");
+    LBM_HIP(hipStreamSynchronize(L->stream), "moments");
+    return LBM_OK;
+  }
+  lbm_status st = ensure_stage(L);
+  if (st != LBM_OK) return st;
+  for (size_t n0 = 0; n0 < L->N; n0 += kChunkNodes) {
+    const size_t cnt = (L->N - n0) < kChunkNodes ? (L->N - n0) : kChunkNodes;
+    double *drho = L->d_stage, *du = L->d_stage + cnt;
+    LBM_HIP(lbm::launch_moments(L->storage, f, L->N, n0, cnt, rho ? drho : nullptr, u ? du : nullptr, nullptr,
+                                kPartialBlocks, L->stream),
+            "moments launch");
+    if (rho) LBM_HIP(hipMemcpyAsync(rho + n0, drho, cnt * sizeof(double), hipMemcpyDeviceToHost, L->stream), "copy rho");
+    if (u)
+      for (int a = 0; a < 3; ++a)
+        LBM_HIP(hipMemcpyAsync(u + a * L->N + n0, du + a * cnt, cnt * sizeof(double), hipMemcpyDeviceToHost,
+                               L->stream),
+                "copy u");
+    LBM_HIP(hipStreamSynchronize(L->stream), "moments");
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_totals(lbm_lattice *L, double *mass, double momentum[3]) {
+  if (!L || !mass || !momentum) return fail(LBM_ERR_ARG, "NULL argument");
+  LBM_HIP(lbm::launch_moments(L->storage, L->buf[L->cur], L->N, 0, L->N, nullptr, nullptr, L->d_partials,
+                              kPartialBlocks, L->stream),
+          "totals launch");
+  LBM_HIP(lbm::launch_reduce(L->d_partials, kPartialBlocks, L->d_totals, L->stream), "reduce launch");
+  double h[4];
+  LBM_HIP(hipMemcpyAsync(h, L->d_totals, sizeof(h), hipMemcpyDeviceToHost, L->stream), "copy totals");
+  LBM_HIP(hipStreamSynchronize(L->stream), "totals");
+  *mass = h[0];
+  momentum[0] = h[1];
+  momentum[1] = h[2];
+  momentum[2] = h[3];
+  for (int c = 0; c < 4; ++c)
+    if (!std::isfinite(h[c])) return fail(LBM_ERR_NONFINITE, "the state holds NaN or Inf (totals not finite)");
+  return LBM_OK;
+}
+
+lbm_status lbm_get_populations(lbm_lattice *L, double *f) {
+  if (!L || !f) return fail(LBM_ERR_ARG, "NULL argument");
+  lbm_status st = ensure_stage(L);
+  if (st != LBM_OK) return st;
+  for (size_t n0 = 0; n0 < L->N; n0 += kChunkNodes) {
+    const size_t cnt = (L->N - n0) < kChunkNodes ? (L->N - n0) : kChunkNodes;
+    LBM_HIP(lbm::launch_to_double(L->storage, L->buf[L->cur], L->N, n0, cnt, L->d_stage, L->stream), "convert launch");
+    for (int k = 0; k < 19; ++k)
+      LBM_HIP(hipMemcpyAsync(f + size_t(k) * L->N + n0, L->d_stage + size_t(k) * cnt, cnt * sizeof(double),
+                             hipMemcpyDeviceToHost, L->stream),
+              "copy populations");
+    LBM_HIP(hipStreamSynchronize(L->stream), "get populations");
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_set_populations(lbm_lattice *L, const double *f) {
+  if (!L || !f) return fail(LBM_ERR_ARG, "NULL argument");
+  lbm_status st = ensure_stage(L);
+  if (st != LBM_OK) return st;
+  for (size_t n0 = 0; n0 < L->N; n0 += kChunkNodes) {
+    const size_t cnt = (L->N - n0) < kChunkNodes ? (L->N - n0) : kChunkNodes;
+    for (int k = 0; k < 19; ++k)
+      LBM_HIP(hipMemcpyAsync(L->d_stage + size_t(k) * cnt, f + size_t(k) * L->N + n0, cnt * sizeof(double),
+                             hipMemcpyHostToDevice, L->stream),
+              "copy populations");
+    LBM_HIP(lbm::launch_from_double(L->storage, L->buf[L->cur], L->N, n0, cnt, L->d_stage, L->stream),
+            "convert launch");
+    LBM_HIP(hipStreamSynchronize(L->stream), "set populations");
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_state_buffer(const lbm_lattice *L, void **dev_ptr) {
+  if (!L || !dev_ptr) return fail(LBM_ERR_ARG, "NULL argument");
+  *dev_ptr = L->buf[L->cur];
+  return LBM_OK;
+}
+
+lbm_status lbm_set_launch(lbm_lattice *L, int block_x, int nodes_per_thread, int xcd_remap) {
+  if (!L) return fail(LBM_ERR_ARG, "NULL handle");
+  if (block_x != 64 && block_x != 128 && block_x != 256 && block_x != 512)
+    return fail(LBM_ERR_ARG, "block_x must be 64, 128, 256 or 512 (got %d)", block_x);
+  if (nodes_per_thread != 1 && nodes_per_thread != 2 && nodes_per_thread != 4)
+    return fail(LBM_ERR_ARG, "nodes_per_thread must be 1, 2 or 4 (got %d)", nodes_per_thread);
+  L->block_x = block_x;
+  L->npt = nodes_per_thread;
+  L->xcd = xcd_remap ? 1 : 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_launch(const lbm_lattice *L, int *block_x, int *nodes_per_thread, int *xcd_remap) {
+  if (!L || !block_x || !nodes_per_thread || !xcd_remap) return fail(LBM_ERR_ARG, "NULL argument");
+  *block_x = L->block_x;
+  *nodes_per_thread = L->npt;
+  *xcd_remap = L->xcd;
+  return LBM_OK;
+}
+
+lbm_status lbm_probe(lbm_lattice *L, int kind, int nrep) {
+  if (!L) return fail(LBM_ERR_ARG, "NULL handle");
+  if (kind != 0 && kind != 1) return fail(LBM_ERR_ARG, "probe kind must be 0 or 1");
+  if (nrep < 0) return fail(LBM_ERR_ARG, "nrep must be >= 0");
+  const void *src = L->buf[L->cur];
+  void *dst = L->buf[L->cur ^ 1];
+  const lbm::SweepConfig c = sweep_config(L);
+  for (int r = 0; r < nrep; ++r) {
+    hipError_t e = kind == 0 ? lbm::launch_copy_probe(src, dst, 19 * L->N * L->esize & ~size_t(15), L->stream)
+                             : lbm::launch_sweep(c, src, dst, true, L->stream);
+    if (e != hipSuccess) return hip_fail(e, "probe launch");
+  }
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,51 @@
+// lbm_internal.hpp -- declarations shared by the C-ABI layer and the kernel
+// launchers inside the library (not installed, not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "d3q19.hpp"
+
+namespace lbm {
+
+enum { kStoreF64 = 0, kStoreF32 = 1, kStoreF16 = 2 };
+
+// Everything one sweep launch needs, in host form.
+struct SweepConfig {
+  int storage;
+  int nx, ny, nz;
+  double tau;
+  unsigned bc_mask;  // bit f: face f carries a velocity BC
+  double v[6][3];    // face velocities
+  int block_x;
+  int nodes_per_thread;
+  int xcd_remap;
+};
+
+// Kernel-argument form, arithmetic type T.
+template <class T>
+struct SweepArgs {
+  int nx, ny, nz;
+  size_t N;
+  int nxc;           // blocks per x-row
+  unsigned nblocks;  // grid size
+  int xcd_remap;
+  unsigned bc_mask;
+  T omega;  // 1 / tau
+  FaceVel<T> fv;
+};
+
+hipError_t launch_sweep(const SweepConfig &c, const void *src, void *dst, bool copy_only, hipStream_t s);
+hipError_t launch_init(int storage, void *f, size_t N, double rho0, const double u0[3], hipStream_t s);
+hipError_t launch_moments(int storage, const void *f, size_t N, size_t n0, size_t count, double *rho, double *u,
+                          double *partials, int nblk, hipStream_t s);
+hipError_t launch_reduce(const double *partials, int nblk, double *out, hipStream_t s);
+hipError_t launch_to_double(int storage, const void *f, size_t N, size_t n0, size_t count, double *out,
+                            hipStream_t s);
+hipError_t launch_from_double(int storage, void *f, size_t N, size_t n0, size_t count, const double *in,
+                              hipStream_t s);
+hipError_t launch_copy_probe(const void *src, void *dst, size_t nbytes, hipStream_t s);
+
+}  // namespace lbm

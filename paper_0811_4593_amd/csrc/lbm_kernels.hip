@@ -1,0 +1,386 @@
+// lbm_kernels.hip -- HIP kernels for gfx950: the fused D3Q19 sweep (pull
+// streaming + on-site boundary rules + BGK), initialisation, moments and
+// FP64 reductions, storage conversion and bandwidth probes.
+//
+// Layout in HBM: structure of arrays, population k of node n at k*N + n,
+// n = x + nx*(y + ny*z).  One sweep reads 19 and writes 19 elements per node;
+// every element of the source buffer is read exactly once per step (the pull
+// scheme has no reuse between nodes), so the kernel is a pure 38-stream HBM
+// copy with ~200 flops per node on top.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "d3q19.hpp"
+#include "lbm_internal.hpp"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// Storage codecs: population element type S, arithmetic type T.
+// ---------------------------------------------------------------------------
+template <class S>
+struct Codec;
+
+template <>
+struct Codec<double> {
+  using T = double;
+  static __device__ __forceinline__ T decode(double s, int) { return s; }
+  static __device__ __forceinline__ double encode(T v, int) { return v; }
+};
+
+template <>
+struct Codec<float> {
+  using T = float;
+  static __device__ __forceinline__ T decode(float s, int) { return s; }
+  static __device__ __forceinline__ float encode(T v, int) { return v; }
+};
+
+// Half-precision scaled deviation from the lattice weight:
+// h = RNE((f - w_k) * 2^8), f = w_k + h * 2^-8 (exact scaling, float math).
+template <>
+struct Codec<_Float16> {
+  using T = float;
+  static __device__ __forceinline__ T decode(_Float16 s, int k) {
+    return weight<float>(k) + static_cast<float>(s) * 0.00390625f;
+  }
+  static __device__ __forceinline__ _Float16 encode(T v, int k) {
+    return static_cast<_Float16>((v - weight<float>(k)) * 256.0f);
+  }
+};
+
+template <class S, bool NT>
+__device__ __forceinline__ void store_elem(S *p, S v) {
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
+// Logical block index.  The dispatcher hands workgroups to the 8 XCDs
+// round-robin (workgroup b runs on XCD b % 8); with the remap, logical blocks
+// [q*i, q*(i+1)) all run on XCD i, so neighbouring x-rows share one L2.
+__device__ __forceinline__ unsigned logical_block(unsigned b, unsigned nblocks, int remap) {
+  if (!remap) return b;
+  const unsigned q = nblocks >> 3;
+  if (b >= (q << 3)) return b;
+  return (b & 7u) * q + (b >> 3);
+}
+
+// ---------------------------------------------------------------------------
+// The fused sweep.  One block handles BX*NPT consecutive nodes of one x-row;
+// thread t handles x = x0 + j*BX + t, j < NPT (coalesced 64-lane accesses).
+// y and z are uniform over the block, so the row offsets of the 9 source rows
+// live in scalar registers and each load is "scalar base + lane offset".
+// COPY: streaming only (no boundary rule, no collision, raw elements) -- the
+// bandwidth ceiling of this access pattern.
+// ---------------------------------------------------------------------------
+template <class S, int BX, int NPT, bool NT, bool COPY>
+__global__ __launch_bounds__(BX) void sweep_kernel(const S *__restrict__ src, S *__restrict__ dst,
+                                                   SweepArgs<typename Codec<S>::T> a) {
+  using T = typename Codec<S>::T;
+  const unsigned b = logical_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  const unsigned row = a.nxc == 1 ? b : b / unsigned(a.nxc);
+  const int xc = int(b - row * unsigned(a.nxc));
+  const int ny = a.ny, nz = a.nz, nx = a.nx;
+  const int y = int(row % unsigned(ny));
+  const int z = int(row / unsigned(ny));
+  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+  // Row base offsets R[cy+1][cz+1] of the source row (y - cy, z - cz).
+  const unsigned unx = unsigned(nx), uny = unsigned(ny);
+  const unsigned yy[3] = {unsigned(yp), unsigned(y), unsigned(ym)};  // index cy+1 -> y - cy
+  const unsigned zz[3] = {unsigned(zp), unsigned(z), unsigned(zm)};
+  const size_t N = a.N;
+
+  // Boundary bits that depend on y and z only (uniform over the block).
+  unsigned m_yz = 0;
+  if (y == 0) m_yz |= a.bc_mask & 4u;
+  if (y == ny - 1) m_yz |= a.bc_mask & 8u;
+  if (z == 0) m_yz |= a.bc_mask & 16u;
+  if (z == nz - 1) m_yz |= a.bc_mask & 32u;
+
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int x = (xc * NPT + j) * BX + int(threadIdx.x);
+    if (x < nx) {
+      const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+      const unsigned xs[3] = {unsigned(xp), unsigned(x), unsigned(xm)};  // index cx+1 -> x - cx
+      T f[19];
+      S raw[19];
+#pragma unroll
+      for (int k = 0; k < 19; ++k) {
+        const unsigned off = (yy[cy(k) + 1] + uny * zz[cz(k) + 1]) * unx + xs[cx(k) + 1];
+        raw[k] = src[size_t(k) * N + off];
+      }
+      if constexpr (!COPY) {
+#pragma unroll
+        for (int k = 0; k < 19; ++k) f[k] = Codec<S>::decode(raw[k], k);
+        unsigned m = m_yz;
+        if (x == 0) m |= a.bc_mask & 1u;
+        if (x == nx - 1) m |= a.bc_mask & 2u;
+        if (m) boundary_rule<T>(f, m, a.fv);
+        bgk_collide<T>(f, a.omega);
+#pragma unroll
+        for (int k = 0; k < 19; ++k) raw[k] = Codec<S>::encode(f[k], k);
+      }
+      const size_t n = size_t(row) * unx + unsigned(x);
+#pragma unroll
+      for (int k = 0; k < 19; ++k) store_elem<S, NT>(dst + size_t(k) * N + n, raw[k]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation: f_k = f_k^eq(rho0, u0) at every node (eq_feq), in double,
+// then encoded.
+// ---------------------------------------------------------------------------
+template <class S>
+__global__ void init_kernel(S *__restrict__ f, size_t N, double rho0, double ux, double uy, double uz) {
+  const size_t n = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const double usq15 = 1.5 * (ux * ux + uy * uy + uz * uz);
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    const double cu = double(cx(k)) * ux + double(cy(k)) * uy + double(cz(k)) * uz;
+    const double feq = weight<double>(k) * rho0 * (1.0 + 3.0 * cu + 4.5 * cu * cu - usq15);
+    f[size_t(k) * N + n] = Codec<S>::encode(typename Codec<S>::T(feq), k);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Moments of the stored state (eq_rho, eq_vel) for nodes [n0, n0 + count):
+// rho[i], u[a*count + i] in double; optional per-block FP64 partial sums of
+// mass and momentum (wavefront shuffles, then LDS across the block's waves,
+// in a fixed order).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void moments_kernel(const S *__restrict__ f, size_t N, size_t n0,
+                                                      size_t count, double *__restrict__ rho,
+                                                      double *__restrict__ u,
+                                                      double *__restrict__ partials) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride) {
+    const size_t n = n0 + i;
+    double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int k = 0; k < 19; ++k) {
+      const double v = double(Codec<S>::decode(f[size_t(k) * N + n], k));
+      r += v;
+      if (cx(k)) jx += double(cx(k)) * v;
+      if (cy(k)) jy += double(cy(k)) * v;
+      if (cz(k)) jz += double(cz(k)) * v;
+    }
+    if (rho) rho[i] = r;
+    if (u) {
+      u[i] = jx / r;
+      u[count + i] = jy / r;
+      u[2 * count + i] = jz / r;
+    }
+    acc[0] += r;
+    acc[1] += jx;
+    acc[2] += jy;
+    acc[3] += jz;
+  }
+  if (!partials) return;
+  __shared__ double lds[4][4];  // [wave][quantity], blockDim = 256 = 4 waves
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double s = wave_sum(acc[c]);
+    if (lane == 0) lds[wave][c] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int c = threadIdx.x;
+    partials[size_t(blockIdx.x) * 4 + c] = ((lds[0][c] + lds[1][c]) + lds[2][c]) + lds[3][c];
+  }
+}
+
+// Final fixed-order reduction of nblk partial quadruples into out[4].
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const double *__restrict__ partials, int nblk,
+                                                              double *__restrict__ out) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += 256)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] += partials[size_t(b) * 4 + c];
+  __shared__ double lds[4][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double s = wave_sum(acc[c]);
+    if (lane == 0) lds[wave][c] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int c = threadIdx.x;
+    out[c] = ((lds[0][c] + lds[1][c]) + lds[2][c]) + lds[3][c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Conversion between the stored form and double, nodes [n0, n0 + count):
+// host-side layout of the chunk is buf[k*count + i].
+// ---------------------------------------------------------------------------
+template <class S>
+__global__ void to_double_kernel(const S *__restrict__ f, size_t N, size_t n0, size_t count,
+                                 double *__restrict__ out) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+#pragma unroll
+  for (int k = 0; k < 19; ++k) out[size_t(k) * count + i] = double(Codec<S>::decode(f[size_t(k) * N + n0 + i], k));
+}
+
+template <class S>
+__global__ void from_double_kernel(S *__restrict__ f, size_t N, size_t n0, size_t count,
+                                   const double *__restrict__ in) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    using T = typename Codec<S>::T;
+    f[size_t(k) * N + n0 + i] = Codec<S>::encode(T(in[size_t(k) * count + i]), k);
+  }
+}
+
+// Plain contiguous copy of nbytes (multiple of 16) with 16-byte accesses.
+__global__ __launch_bounds__(256) void copy_probe_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                         size_t n16) {
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+// ---------------------------------------------------------------------------
+template <class S, int BX, int NPT, bool NT, bool COPY>
+static hipError_t launch_sweep_t(const void *src, void *dst, const SweepArgs<typename Codec<S>::T> &a,
+                                 hipStream_t s) {
+  sweep_kernel<S, BX, NPT, NT, COPY><<<dim3(a.nblocks), dim3(BX), 0, s>>>(static_cast<const S *>(src),
+                                                                         static_cast<S *>(dst), a);
+  return hipGetLastError();
+}
+
+template <class S, bool COPY>
+static hipError_t launch_sweep_shape(const void *src, void *dst, const SweepArgs<typename Codec<S>::T> &a,
+                                     int bx, int npt, hipStream_t s) {
+  // Non-temporal stores: the destination is not read again before the next
+  // step, which streams through far more data than the caches hold.
+#define LBM_CASE(B, P)                                                       \
+  if (bx == B && npt == P) return launch_sweep_t<S, B, P, true, COPY>(src, dst, a, s);
+  LBM_CASE(64, 1) LBM_CASE(64, 2) LBM_CASE(64, 4)
+  LBM_CASE(128, 1) LBM_CASE(128, 2) LBM_CASE(128, 4)
+  LBM_CASE(256, 1) LBM_CASE(256, 2) LBM_CASE(256, 4)
+  LBM_CASE(512, 1) LBM_CASE(512, 2) LBM_CASE(512, 4)
+#undef LBM_CASE
+  return hipErrorInvalidValue;
+}
+
+template <class T>
+static SweepArgs<T> make_args(const SweepConfig &c) {
+  SweepArgs<T> a;
+  a.nx = c.nx;
+  a.ny = c.ny;
+  a.nz = c.nz;
+  a.N = size_t(c.nx) * c.ny * c.nz;
+  const int span = c.block_x * c.nodes_per_thread;
+  a.nxc = (c.nx + span - 1) / span;
+  a.nblocks = unsigned(a.nxc) * unsigned(c.ny) * unsigned(c.nz);
+  a.xcd_remap = c.xcd_remap;
+  a.bc_mask = c.bc_mask;
+  a.omega = T(1.0 / c.tau);
+  for (int f = 0; f < 6; ++f)
+    for (int d = 0; d < 3; ++d) a.fv.v[f][d] = T(c.v[f][d]);
+  return a;
+}
+
+hipError_t launch_sweep(const SweepConfig &c, const void *src, void *dst, bool copy_only, hipStream_t s) {
+  switch (c.storage) {
+    case kStoreF64: {
+      const auto a = make_args<double>(c);
+      return copy_only ? launch_sweep_shape<double, true>(src, dst, a, c.block_x, c.nodes_per_thread, s)
+                       : launch_sweep_shape<double, false>(src, dst, a, c.block_x, c.nodes_per_thread, s);
+    }
+    case kStoreF32: {
+      const auto a = make_args<float>(c);
+      return copy_only ? launch_sweep_shape<float, true>(src, dst, a, c.block_x, c.nodes_per_thread, s)
+                       : launch_sweep_shape<float, false>(src, dst, a, c.block_x, c.nodes_per_thread, s);
+    }
+    case kStoreF16: {
+      const auto a = make_args<float>(c);
+      return copy_only ? launch_sweep_shape<_Float16, true>(src, dst, a, c.block_x, c.nodes_per_thread, s)
+                       : launch_sweep_shape<_Float16, false>(src, dst, a, c.block_x, c.nodes_per_thread, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+static unsigned blocks_for(size_t n, unsigned bs) { return unsigned((n + bs - 1) / bs); }
+
+hipError_t launch_init(int storage, void *f, size_t N, double rho0, const double u0[3], hipStream_t s) {
+  const dim3 g(blocks_for(N, 256)), b(256);
+  switch (storage) {
+    case kStoreF64: init_kernel<double><<<g, b, 0, s>>>(static_cast<double *>(f), N, rho0, u0[0], u0[1], u0[2]); break;
+    case kStoreF32: init_kernel<float><<<g, b, 0, s>>>(static_cast<float *>(f), N, rho0, u0[0], u0[1], u0[2]); break;
+    case kStoreF16: init_kernel<_Float16><<<g, b, 0, s>>>(static_cast<_Float16 *>(f), N, rho0, u0[0], u0[1], u0[2]); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(int storage, const void *f, size_t N, size_t n0, size_t count, double *rho, double *u,
+                          double *partials, int nblk, hipStream_t s) {
+  const dim3 g(nblk), b(256);
+  switch (storage) {
+    case kStoreF64: moments_kernel<double><<<g, b, 0, s>>>(static_cast<const double *>(f), N, n0, count, rho, u, partials); break;
+    case kStoreF32: moments_kernel<float><<<g, b, 0, s>>>(static_cast<const float *>(f), N, n0, count, rho, u, partials); break;
+    case kStoreF16: moments_kernel<_Float16><<<g, b, 0, s>>>(static_cast<const _Float16 *>(f), N, n0, count, rho, u, partials); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double *partials, int nblk, double *out, hipStream_t s) {
+  reduce_partials_kernel<<<dim3(1), dim3(256), 0, s>>>(partials, nblk, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_double(int storage, const void *f, size_t N, size_t n0, size_t count, double *out,
+                            hipStream_t s) {
+  const dim3 g(blocks_for(count, 256)), b(256);
+  switch (storage) {
+    case kStoreF64: to_double_kernel<double><<<g, b, 0, s>>>(static_cast<const double *>(f), N, n0, count, out); break;
+    case kStoreF32: to_double_kernel<float><<<g, b, 0, s>>>(static_cast<const float *>(f), N, n0, count, out); break;
+    case kStoreF16: to_double_kernel<_Float16><<<g, b, 0, s>>>(static_cast<const _Float16 *>(f), N, n0, count, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_from_double(int storage, void *f, size_t N, size_t n0, size_t count, const double *in,
+                              hipStream_t s) {
+  const dim3 g(blocks_for(count, 256)), b(256);
+  switch (storage) {
+    case kStoreF64: from_double_kernel<double><<<g, b, 0, s>>>(static_cast<double *>(f), N, n0, count, in); break;
+    case kStoreF32: from_double_kernel<float><<<g, b, 0, s>>>(static_cast<float *>(f), N, n0, count, in); break;
+    case kStoreF16: from_double_kernel<_Float16><<<g, b, 0, s>>>(static_cast<_Float16 *>(f), N, n0, count, in); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_probe(const void *src, void *dst, size_t nbytes, hipStream_t s) {
+  const size_t n16 = nbytes / 16;
+  const unsigned nblk = 256u * 32u;  // 32 blocks per CU, grid-stride
+  copy_probe_kernel<<<dim3(nblk), dim3(256), 0, s>>>(static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), n16);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

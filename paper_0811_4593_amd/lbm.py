@@ -1,0 +1,261 @@
+"""ctypes binding of the C ABI in include/lbm.h (liblbm.so, HIP for gfx950).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  Functions keep the C names; a failed call raises LBMError carrying
+the status code and lbm_last_error().  Device pointers may be given as ints or
+as torch tensors (their data_ptr()); streams as ints, torch streams or None.
+
+Importing this module does not need a GPU; loading the library does need the
+built liblbm.so, and the module refuses to run without it (there is no
+fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm.so")
+
+LBM_OK, LBM_ERR_ARG, LBM_ERR_OOM, LBM_ERR_HIP, LBM_ERR_STATE, LBM_ERR_NONFINITE = 0, -1, -2, -3, -4, -5
+LBM_STORE_F64, LBM_STORE_F32, LBM_STORE_F16_DEV = 0, 1, 2
+LBM_X0, LBM_X1, LBM_Y0, LBM_Y1, LBM_Z0, LBM_Z1 = range(6)
+
+STORAGE_NAMES = {LBM_STORE_F64: "f64", LBM_STORE_F32: "f32", LBM_STORE_F16_DEV: "f16dev"}
+
+# Every symbol include/lbm.h declares.
+EXPORTS = (
+    "lbm_create", "lbm_create_on_buffers", "lbm_set_velocity_bc", "lbm_clear_bc", "lbm_step",
+    "lbm_moments", "lbm_totals", "lbm_get_populations", "lbm_set_populations", "lbm_state_buffer",
+    "lbm_element_bytes", "lbm_set_launch", "lbm_get_launch", "lbm_probe", "lbm_destroy",
+    "lbm_last_error",
+)
+
+
+class LBMError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"lbm status {status}: {message}")
+        self.status = status
+
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liblbm.so (once).  Raises FileNotFoundError if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            f"{path} is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
+            "or `python paper_0811_4593_amd/build.py`")
+    lib = ctypes.CDLL(path)
+    st = ctypes.c_int
+    lib.lbm_create.argtypes = [st, st, st, ctypes.c_double, ctypes.c_double, _dp, st, _vp, ctypes.POINTER(_vp)]
+    lib.lbm_create_on_buffers.argtypes = [st, st, st, ctypes.c_double, ctypes.c_double, _dp, st, _vp, _vp, _vp,
+                                          ctypes.c_size_t, ctypes.POINTER(_vp)]
+    lib.lbm_set_velocity_bc.argtypes = [_vp, st, _dp]
+    lib.lbm_clear_bc.argtypes = [_vp, st]
+    lib.lbm_step.argtypes = [_vp, st]
+    lib.lbm_moments.argtypes = [_vp, _vp, _vp, st]
+    lib.lbm_totals.argtypes = [_vp, _dp, _dp]
+    lib.lbm_get_populations.argtypes = [_vp, _dp]
+    lib.lbm_set_populations.argtypes = [_vp, _dp]
+    lib.lbm_state_buffer.argtypes = [_vp, ctypes.POINTER(_vp)]
+    lib.lbm_element_bytes.argtypes = [st]
+    lib.lbm_element_bytes.restype = ctypes.c_size_t
+    lib.lbm_set_launch.argtypes = [_vp, st, st, st]
+    lib.lbm_get_launch.argtypes = [_vp, ctypes.POINTER(st), ctypes.POINTER(st), ctypes.POINTER(st)]
+    lib.lbm_probe.argtypes = [_vp, st, st]
+    lib.lbm_destroy.argtypes = [_vp]
+    lib.lbm_destroy.restype = None
+    lib.lbm_last_error.argtypes = []
+    lib.lbm_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("lbm_element_bytes", "lbm_destroy", "lbm_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != LBM_OK:
+        raise LBMError(status, lbm_last_error())
+
+
+def _dev(p) -> int | None:
+    if p is None:
+        return None
+    if hasattr(p, "data_ptr"):
+        return int(p.data_ptr())
+    return int(p)
+
+
+def _stream(s) -> int | None:
+    if s is None:
+        return None
+    if hasattr(s, "cuda_stream"):
+        return int(s.cuda_stream)
+    return int(s)
+
+
+def _vec3(u) -> ctypes.Array:
+    a = (ctypes.c_double * 3)()
+    for i, x in enumerate(u):
+        a[i] = float(x)
+    return a
+
+
+def lbm_last_error() -> str:
+    return load_library().lbm_last_error().decode()
+
+
+def lbm_element_bytes(storage: int) -> int:
+    return int(load_library().lbm_element_bytes(int(storage)))
+
+
+def lbm_create(nx, ny, nz, tau, rho0=1.0, u0=(0.0, 0.0, 0.0), storage=LBM_STORE_F32, stream=None) -> int:
+    h = _vp()
+    _check(load_library().lbm_create(int(nx), int(ny), int(nz), float(tau), float(rho0),
+                                     None if u0 is None else _vec3(u0), int(storage), _stream(stream),
+                                     ctypes.byref(h)))
+    return h.value
+
+
+def lbm_create_on_buffers(nx, ny, nz, tau, rho0, u0, storage, stream, buf_a, buf_b, buf_bytes) -> int:
+    h = _vp()
+    _check(load_library().lbm_create_on_buffers(int(nx), int(ny), int(nz), float(tau), float(rho0),
+                                                None if u0 is None else _vec3(u0), int(storage),
+                                                _stream(stream), _dev(buf_a), _dev(buf_b), int(buf_bytes),
+                                                ctypes.byref(h)))
+    return h.value
+
+
+def lbm_set_velocity_bc(h, face, u):
+    _check(load_library().lbm_set_velocity_bc(h, int(face), _vec3(u)))
+
+
+def lbm_clear_bc(h, face):
+    _check(load_library().lbm_clear_bc(h, int(face)))
+
+
+def lbm_step(h, nsteps: int = 1):
+    _check(load_library().lbm_step(h, int(nsteps)))
+
+
+def lbm_moments(h, rho=None, u=None, dst_on_device: bool = False):
+    """Host mode: rho (N,) and u (3*N,) float64 numpy arrays (C-contiguous)
+    are filled.  Device mode: rho/u are device pointers or torch tensors."""
+    if dst_on_device:
+        _check(load_library().lbm_moments(h, _dev(rho), _dev(u), 1))
+        return
+    for a in (rho, u):
+        if a is not None:
+            assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    _check(load_library().lbm_moments(h, None if rho is None else rho.ctypes.data,
+                                      None if u is None else u.ctypes.data, 0))
+
+
+def lbm_totals(h):
+    m = ctypes.c_double()
+    j = (ctypes.c_double * 3)()
+    _check(load_library().lbm_totals(h, ctypes.byref(m), j))
+    return m.value, np.array(list(j))
+
+
+def lbm_get_populations(h, out: np.ndarray):
+    assert out.dtype == np.float64 and out.flags["C_CONTIGUOUS"]
+    _check(load_library().lbm_get_populations(h, out.ctypes.data_as(_dp)))
+    return out
+
+
+def lbm_set_populations(h, f: np.ndarray):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    _check(load_library().lbm_set_populations(h, f.ctypes.data_as(_dp)))
+
+
+def lbm_state_buffer(h) -> int:
+    p = _vp()
+    _check(load_library().lbm_state_buffer(h, ctypes.byref(p)))
+    return p.value
+
+
+def lbm_set_launch(h, block_x: int, nodes_per_thread: int, xcd_remap: int):
+    _check(load_library().lbm_set_launch(h, int(block_x), int(nodes_per_thread), int(xcd_remap)))
+
+
+def lbm_get_launch(h):
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load_library().lbm_get_launch(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def lbm_probe(h, kind: int, nrep: int = 1):
+    _check(load_library().lbm_probe(h, int(kind), int(nrep)))
+
+
+def lbm_destroy(h):
+    if h:
+        load_library().lbm_destroy(h)
+
+
+class Lattice:
+    """Owning wrapper of one lbm_lattice handle (convenience only)."""
+
+    def __init__(self, nx, ny, nz, tau, rho0=1.0, u0=(0.0, 0.0, 0.0), storage=LBM_STORE_F32, stream=None):
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.storage = int(storage)
+        self.h = lbm_create(nx, ny, nz, tau, rho0, u0, storage, stream)
+
+    @property
+    def nodes(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def shape(self):
+        return (19, self.nz, self.ny, self.nx)
+
+    def set_velocity_bc(self, face, u):
+        lbm_set_velocity_bc(self.h, face, u)
+
+    def step(self, n=1):
+        lbm_step(self.h, n)
+
+    def moments(self):
+        n = self.nodes
+        rho = np.empty(n)
+        u = np.empty(3 * n)
+        lbm_moments(self.h, rho, u)
+        return rho.reshape(self.nz, self.ny, self.nx), u.reshape(3, self.nz, self.ny, self.nx)
+
+    def totals(self):
+        return lbm_totals(self.h)
+
+    def get(self) -> np.ndarray:
+        out = np.empty(self.shape)
+        return lbm_get_populations(self.h, out)
+
+    def set(self, f):
+        lbm_set_populations(self.h, np.asarray(f).reshape(self.shape))
+
+    def close(self):
+        lbm_destroy(self.h)
+        self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                self.close()
+        except Exception:
+            pass

@@ -1,0 +1,133 @@
+"""Seeded synthetic workloads: lattice sizes, boundary velocities, relaxation
+times and random perturbation fields.
+
+This module holds no arithmetic of the method (no equilibria, no boundary
+rules): it only describes inputs, so that the HIP path and the CPU oracle can
+be driven with identical set-ups.  The paper uses no dataset; its workloads
+are geometric set-ups (Sec. VI), reproduced here with their sizes and
+velocity ranges.
+
+Faces are numbered x0, x1, y0, y1, z0, z1 = 0..5.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class LatticeSpec:
+    nx: int
+    ny: int
+    nz: int
+    tau: float
+    bc: dict = field(default_factory=dict)  # face -> (ux, uy, uz)
+    rho0: float = 1.0
+    name: str = ""
+
+    @property
+    def nodes(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+def couette(nx=16, ny=16, nz=32, u_top=0.05, tau=1.0) -> LatticeSpec:
+    """Shear flow between on-site walls: x, y periodic, z0 at rest, z1 moving
+    along x (the paper's shear test, Sec. VI)."""
+    return LatticeSpec(nx, ny, nz, tau, {4: (0.0, 0.0, 0.0), 5: (u_top, 0.0, 0.0)},
+                       name=f"couette_{nx}x{ny}x{nz}")
+
+
+def duct(nx, ny, nz, u_in=(0.04, 0.01, 0.01), tau=0.8) -> LatticeSpec:
+    """Duct: no-slip on-site walls on the y and z faces; the same oblique
+    velocity prescribed on the inlet x0 and the outlet x1."""
+    z = (0.0, 0.0, 0.0)
+    u = tuple(float(a) for a in u_in)
+    return LatticeSpec(nx, ny, nz, tau, {0: u, 1: u, 2: z, 3: z, 4: z, 5: z}, name=f"duct_{nx}x{ny}x{nz}")
+
+
+def roofline_duct() -> LatticeSpec:
+    """The 1024 x 512 x 512 duct, inlet/outlet (0.04, 0.01, 0.01), tau 0.8."""
+    return duct(1024, 512, 512, (0.04, 0.01, 0.01), 0.8)
+
+
+def precision_duct() -> LatticeSpec:
+    """The same duct at 512 x 256 x 256 (storage-precision comparison)."""
+    return duct(512, 256, 256, (0.04, 0.01, 0.01), 0.8)
+
+
+def oblique_direction(rng: np.random.Generator):
+    """Unit vector (1, a, b)/|(1, a, b)|, a, b ~ U[-0.5, 0.5] (inflow along +x)."""
+    a, b = rng.uniform(-0.5, 0.5, 2)
+    d = np.array([1.0, a, b])
+    return d / np.linalg.norm(d)
+
+
+def batch_ducts(count=64, seed=0):
+    """Uneven ducts: Nx ~ U{32..256}, Ny, Nz ~ U{16..128}, |u| ~ U[0.01, 0.05]
+    along an oblique direction, tau ~ U[0.6, 1.5]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        nx = int(rng.integers(32, 257))
+        ny = int(rng.integers(16, 129))
+        nz = int(rng.integers(16, 129))
+        speed = float(rng.uniform(0.01, 0.05))
+        d = oblique_direction(rng)
+        tau = float(rng.uniform(0.6, 1.5))
+        s = duct(nx, ny, nz, tuple(speed * d), tau)
+        s.name = f"batch{i}_{nx}x{ny}x{nz}"
+        out.append(s)
+    return out
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float  # seconds after the start of the trace
+    spec: LatticeSpec
+    storage: str    # "f32" or "f16dev"
+
+
+def serving_trace(count=2000, rate=1.0, seed=1, n_min=16, n_max=256):
+    """Poisson arrivals at `rate` per second of cubic ducts with N log-uniform
+    in [n_min, n_max], |u| ~ U[0.01, 0.05] along an oblique direction,
+    tau ~ U[0.6, 1.5], storage f32 or f16dev with probability 1/2 each."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        n = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
+        speed = float(rng.uniform(0.01, 0.05))
+        d = oblique_direction(rng)
+        tau = float(rng.uniform(0.6, 1.5))
+        storage = "f16dev" if rng.uniform() < 0.5 else "f32"
+        s = duct(n, n, n, tuple(speed * d), tau)
+        s.name = f"req{i}_{n}^3"
+        out.append(Request(i, t, s, storage))
+    return out
+
+
+def perturbation(shape, seed: int, amp: float) -> np.ndarray:
+    """Multiplicative noise 1 + amp * U(-1, 1) of the given shape."""
+    rng = np.random.default_rng(seed)
+    return 1.0 + amp * rng.uniform(-1.0, 1.0, shape)
+
+
+def all_classes_lattices():
+    """Small lattices that contain every node class (bulk, 6 faces, 12 edges,
+    8 corners), mixed periodic and bounded axes, and moving walls on every
+    face, for node-by-node parity."""
+    out = [
+        duct(5, 5, 5, (0.04, 0.01, 0.01), 0.8),
+        duct(8, 7, 6, (0.03, -0.02, 0.015), 0.7),
+        LatticeSpec(9, 6, 7, 1.3, {0: (0.02, 0.01, -0.01), 1: (-0.01, 0.02, 0.01), 2: (0.01, 0.03, -0.02),
+                                   3: (0.02, -0.01, 0.01), 4: (-0.02, 0.01, 0.03), 5: (0.01, -0.02, -0.01)},
+                    name="moving_walls_9x6x7"),
+        LatticeSpec(7, 6, 5, 0.9, {2: (0.0, 0.0, 0.0), 3: (0.0, 0.0, 0.0), 4: (0.02, 0.01, 0.0),
+                                   5: (-0.01, 0.0, 0.02)}, name="x_periodic_7x6x5"),
+        LatticeSpec(6, 5, 8, 0.75, {0: (0.03, 0.0, 0.01), 1: (0.02, 0.01, 0.0)}, name="yz_periodic_6x5x8"),
+    ]
+    return out

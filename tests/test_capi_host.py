@@ -1,0 +1,100 @@
+"""Host-only checks of the C-ABI library: it loads, exports every function
+include/lbm.h declares, and rejects invalid arguments before touching a GPU.
+No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    from paper_0811_4593_amd import lbm as m
+    m.load_library()
+    return m
+
+
+def test_header_declares_the_binding_exports(lbm):
+    assert _declared_functions() == sorted(lbm.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lbm):
+    lib = ctypes.CDLL(lbm.LIB_PATH)
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_element_bytes(lbm):
+    assert lbm.lbm_element_bytes(lbm.LBM_STORE_F64) == 8
+    assert lbm.lbm_element_bytes(lbm.LBM_STORE_F32) == 4
+    assert lbm.lbm_element_bytes(lbm.LBM_STORE_F16_DEV) == 2
+    assert lbm.lbm_element_bytes(7) == 0
+
+
+@pytest.mark.parametrize("args,frag", [
+    ((0, 4, 4, 0.8), "sizes"),
+    ((4, 4, 4, 0.5), "tau"),
+    ((4, 4, 4, 0.4), "tau"),
+    ((2048, 2048, 1024, 0.8), "2^31"),
+])
+def test_create_rejects_bad_arguments(lbm, args, frag):
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_create(*args)
+    assert e.value.status == lbm.LBM_ERR_ARG
+    assert frag in str(e.value)
+
+
+def test_create_rejects_bad_storage_and_density(lbm):
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_create(4, 4, 4, 0.8, 1.0, None, 9)
+    assert e.value.status == lbm.LBM_ERR_ARG
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_create(4, 4, 4, 0.8, -1.0)
+    assert e.value.status == lbm.LBM_ERR_ARG
+
+
+def test_create_on_buffers_validates(lbm):
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_create_on_buffers(4, 4, 4, 0.8, 1.0, None, lbm.LBM_STORE_F32, None, 0, 0, 0)
+    assert e.value.status == lbm.LBM_ERR_ARG
+    with pytest.raises(lbm.LBMError) as e:  # too small
+        lbm.lbm_create_on_buffers(4, 4, 4, 0.8, 1.0, None, lbm.LBM_STORE_F32, None, 256, 512, 100)
+    assert "needed" in str(e.value)
+    with pytest.raises(lbm.LBMError) as e:  # misaligned
+        lbm.lbm_create_on_buffers(4, 4, 4, 0.8, 1.0, None, lbm.LBM_STORE_F32, None, 4096 + 8, 8192, 1 << 20)
+    assert "aligned" in str(e.value)
+
+
+def test_null_handle_calls_fail_cleanly(lbm):
+    lib = lbm.load_library()
+    v = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    assert lib.lbm_set_velocity_bc(None, 0, v) == lbm.LBM_ERR_ARG
+    assert lib.lbm_step(None, 1) == lbm.LBM_ERR_ARG
+    assert lib.lbm_clear_bc(None, 0) == lbm.LBM_ERR_ARG
+    assert lib.lbm_set_launch(None, 256, 1, 1) == lbm.LBM_ERR_ARG
+    assert lib.lbm_probe(None, 0, 1) == lbm.LBM_ERR_ARG
+    assert lib.lbm_totals(None, None, None) == lbm.LBM_ERR_ARG
+    assert lib.lbm_moments(None, None, None, 0) == lbm.LBM_ERR_ARG
+    assert "NULL" in lbm.lbm_last_error()
+    lib.lbm_destroy(None)  # no-op
+
+
+def test_binding_refuses_to_run_without_library(tmp_path):
+    from paper_0811_4593_amd import lbm as m
+    saved = m._lib
+    m._lib = None
+    try:
+        with pytest.raises(FileNotFoundError):
+            m.load_library(str(tmp_path / "missing.so"))
+    finally:
+        m._lib = saved

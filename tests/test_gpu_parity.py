@@ -1,0 +1,373 @@
+"""GPU parity: the HIP sweep (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances:
+  * FP64 storage, one step from an identical state: max |df|/|f| <= 1e-12
+    per element (the two sides differ only in summation order and fused
+    multiply-adds, ~1e-16 per operation).
+  * FP32 storage, one step from an identical state: |df| <= 1e-5 |f|
+    (FP32 unit roundoff 6e-8 times a few hundred operations per node, with
+    the cancellation in f^eq - f).
+  * FP32 steady velocity fields: relative L2 <= 1e-5.
+"""
+import numpy as np
+import pytest
+
+from lattice_symmetry import C as PAPER_C
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+from paper_0811_4593_amd import lbm, workloads  # noqa: E402
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def make_gpu(spec, storage, stream=None):
+    h = lbm.lbm_create(spec.nx, spec.ny, spec.nz, spec.tau, spec.rho0, None, storage,
+                       stream if stream is not None else torch.cuda.current_stream())
+    for face, v in spec.bc.items():
+        lbm.lbm_set_velocity_bc(h, face, v)
+    return h
+
+
+def make_oracle(spec):
+    return oracle.Lattice(spec.nx, spec.ny, spec.nz, spec.tau, bc=spec.bc)
+
+
+def rel_err(got, expect):
+    return float(np.max(np.abs(got - expect) / np.abs(expect)))
+
+
+def per_step_parity(spec, steps, storage=lbm.LBM_STORE_F64, launch=None, seed=0, amp=0.05, tol=1e-12):
+    L = make_oracle(spec)
+    h = make_gpu(spec, storage)
+    try:
+        if launch:
+            lbm.lbm_set_launch(h, *launch)
+        f0 = L.init(spec.rho0) * workloads.perturbation(L.shape, seed, amp)
+        lbm.lbm_set_populations(h, f0)
+        cur = np.empty(L.shape)
+        nxt = np.empty(L.shape)
+        worst = 0.0
+        for _ in range(steps):
+            lbm.lbm_get_populations(h, cur)
+            expect = L.step(cur)
+            lbm.lbm_step(h, 1)
+            lbm.lbm_get_populations(h, nxt)
+            worst = max(worst, rel_err(nxt, expect))
+            assert worst <= tol, (spec.name, worst)
+        return worst
+    finally:
+        lbm.lbm_destroy(h)
+
+
+@pytest.mark.parametrize("spec", workloads.all_classes_lattices(), ids=lambda s: s.name)
+def test_fp64_every_node_class_per_step(spec):
+    say(f"fp64 per-step parity {spec.name}")
+    w = per_step_parity(spec, 25)
+    say(f"  worst rel diff {w:.2e}")
+
+
+@pytest.mark.parametrize("launch", [(64, 1, 0), (64, 1, 1), (64, 2, 1), (128, 1, 0), (256, 4, 1), (512, 1, 1)])
+def test_fp64_ragged_multi_block_rows(launch):
+    # 67 nodes along x: with 64-wide blocks a row spans two blocks and a
+    # ragged tail of 3; 300 nodes spans several 128/256 blocks.
+    for spec in (workloads.duct(67, 9, 11, (0.04, 0.01, 0.01), 0.8),
+                 workloads.duct(300, 5, 4, (0.03, -0.01, 0.02), 1.1)):
+        say(f"fp64 ragged {spec.name} launch {launch}")
+        per_step_parity(spec, 4, launch=launch)
+
+
+def test_launch_shapes_bitwise_identical():
+    spec = workloads.duct(300, 7, 6, (0.04, 0.01, 0.01), 0.8)
+    ref = None
+    for launch in [(64, 1, 0), (64, 4, 1), (128, 2, 0), (256, 1, 1), (256, 4, 1), (512, 2, 0)]:
+        say(f"launch shape {launch}")
+        h = make_gpu(spec, lbm.LBM_STORE_F32)
+        try:
+            lbm.lbm_set_launch(h, *launch)
+            assert lbm.lbm_get_launch(h) == launch
+            lbm.lbm_step(h, 30)
+            out = np.empty((19, spec.nz, spec.ny, spec.nx))
+            lbm.lbm_get_populations(h, out)
+        finally:
+            lbm.lbm_destroy(h)
+        if ref is None:
+            ref = out
+        else:
+            np.testing.assert_array_equal(out, ref)
+
+
+def test_couette_fp64_every_step_2000():
+    spec = workloads.couette()
+    say("couette 16x16x32 fp64, 2000 steps, per-step parity")
+    L = make_oracle(spec)
+    h = make_gpu(spec, lbm.LBM_STORE_F64)
+    try:
+        cur = np.empty(L.shape)
+        nxt = np.empty(L.shape)
+        worst = 0.0
+        for step in range(2000):
+            lbm.lbm_get_populations(h, cur)
+            expect = L.step(cur)
+            lbm.lbm_step(h, 1)
+            lbm.lbm_get_populations(h, nxt)
+            worst = max(worst, rel_err(nxt, expect))
+            assert worst <= 1e-12, (step, worst)
+        rho = np.empty(spec.nodes)
+        u = np.empty(3 * spec.nodes)
+        lbm.lbm_moments(h, rho, u)
+        u = u.reshape(3, spec.nz, spec.ny, spec.nx)
+        # exact wall velocities
+        assert np.abs(u[:, 0]).max() < 1e-15
+        assert np.abs(u[0, -1] - 0.05).max() < 1e-15
+        say(f"  worst rel diff {worst:.2e}")
+    finally:
+        lbm.lbm_destroy(h)
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def test_couette_fp32_steady_velocity():
+    spec = workloads.couette()
+    say("couette fp32 20000 steps vs oracle fp64")
+    L = make_oracle(spec)
+    _, u_ref = L.moments(L.run(L.init(), 20000))
+    h = make_gpu(spec, lbm.LBM_STORE_F32)
+    try:
+        lbm.lbm_step(h, 20000)
+        rho = np.empty(spec.nodes)
+        u = np.empty(3 * spec.nodes)
+        lbm.lbm_moments(h, rho, u)
+    finally:
+        lbm.lbm_destroy(h)
+    err = _rel_l2(u.reshape(u_ref.shape), u_ref)
+    say(f"  rel L2 {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_duct_fp32_steady_velocity():
+    spec = workloads.duct(24, 12, 12, (0.04, 0.01, 0.01), 0.8)
+    say("duct 24x12x12 fp32 3000 steps vs oracle fp64 (velocity steady to 1e-15)")
+    L = make_oracle(spec)
+    _, u_ref = L.moments(L.run(L.init(), 3000))
+    h = make_gpu(spec, lbm.LBM_STORE_F32)
+    try:
+        lbm.lbm_step(h, 3000)
+        rho = np.empty(spec.nodes)
+        u = np.empty(3 * spec.nodes)
+        lbm.lbm_moments(h, rho, u)
+    finally:
+        lbm.lbm_destroy(h)
+    err = _rel_l2(u.reshape(u_ref.shape), u_ref)
+    say(f"  rel L2 {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_moments_and_totals_match_oracle():
+    spec = workloads.all_classes_lattices()[2]
+    L = make_oracle(spec)
+    f0 = L.init() * workloads.perturbation(L.shape, 3, 0.1)
+    h = make_gpu(spec, lbm.LBM_STORE_F64)
+    try:
+        lbm.lbm_set_populations(h, f0)
+        rho = np.empty(spec.nodes)
+        u = np.empty(3 * spec.nodes)
+        lbm.lbm_moments(h, rho, u)
+        r_ref, u_ref = L.moments(f0)
+        np.testing.assert_allclose(rho, r_ref.ravel(), rtol=1e-14)
+        np.testing.assert_allclose(u, u_ref.ravel(), rtol=0, atol=1e-15)
+        m, j = lbm.lbm_totals(h)
+        m_ref, j_ref = L.totals(f0)
+        assert abs(m - m_ref) / m_ref < 1e-13
+        np.testing.assert_allclose(j, j_ref, rtol=0, atol=1e-13 * m_ref)
+        # device-destination moments equal host-destination ones
+        drho = torch.empty(spec.nodes, dtype=torch.float64, device="cuda")
+        du = torch.empty(3 * spec.nodes, dtype=torch.float64, device="cuda")
+        lbm.lbm_moments(h, drho, du, dst_on_device=True)
+        np.testing.assert_array_equal(drho.cpu().numpy(), rho)
+        np.testing.assert_array_equal(du.cpu().numpy(), u)
+    finally:
+        lbm.lbm_destroy(h)
+
+
+def test_set_get_roundtrip_and_storage_rounding():
+    spec = workloads.duct(10, 6, 5)
+    L = make_oracle(spec)
+    f0 = L.init() * workloads.perturbation(L.shape, 4, 0.1)
+    for storage in (lbm.LBM_STORE_F64, lbm.LBM_STORE_F32, lbm.LBM_STORE_F16_DEV):
+        h = make_gpu(spec, storage)
+        try:
+            lbm.lbm_set_populations(h, f0)
+            back = np.empty(L.shape)
+            lbm.lbm_get_populations(h, back)
+        finally:
+            lbm.lbm_destroy(h)
+        if storage == lbm.LBM_STORE_F64:
+            np.testing.assert_array_equal(back, f0)
+        elif storage == lbm.LBM_STORE_F32:
+            np.testing.assert_array_equal(back, f0.astype(np.float32).astype(np.float64))
+        else:
+            # (f - w) * 2^8 rounded to half precision: error <= 2^-11 * |f - w| (+ float rounding of w)
+            w = np.array([2] * 6 + [1] * 12 + [12]) / 36.0
+            dev = np.abs(f0 - w[:, None, None, None])
+            assert np.all(np.abs(back - f0) <= dev * 2.0 ** -11 + 1e-8)
+
+
+def test_init_is_equilibrium_and_probe_keeps_state():
+    spec = workloads.duct(20, 8, 6)
+    L = make_oracle(spec)
+    u0 = (0.02, -0.01, 0.005)
+    h = lbm.lbm_create(spec.nx, spec.ny, spec.nz, spec.tau, 1.05, u0, lbm.LBM_STORE_F64,
+                       torch.cuda.current_stream())
+    try:
+        got = np.empty(L.shape)
+        lbm.lbm_get_populations(h, got)
+        np.testing.assert_allclose(got, L.init(1.05, u0), rtol=1e-15)
+        lbm.lbm_probe(h, 0, 2)
+        lbm.lbm_probe(h, 1, 2)
+        again = np.empty(L.shape)
+        lbm.lbm_get_populations(h, again)
+        np.testing.assert_array_equal(again, got)
+    finally:
+        lbm.lbm_destroy(h)
+
+
+def test_state_and_argument_errors():
+    h = lbm.lbm_create(8, 8, 8, 0.8, 1.0, None, lbm.LBM_STORE_F32, torch.cuda.current_stream())
+    try:
+        lbm.lbm_set_velocity_bc(h, lbm.LBM_Z0, (0, 0, 0))
+        with pytest.raises(lbm.LBMError) as e:
+            lbm.lbm_step(h, 1)
+        assert e.value.status == lbm.LBM_ERR_STATE
+        lbm.lbm_clear_bc(h, lbm.LBM_Z0)
+        lbm.lbm_step(h, 1)  # fully periodic again
+        for bad in [(0.0, 0.0, 1.0), (0.0, 0.0, -1.2), (0.4, 0.4, 0.0)]:
+            with pytest.raises(lbm.LBMError) as e:
+                lbm.lbm_set_velocity_bc(h, lbm.LBM_Z1, bad)
+            assert e.value.status == lbm.LBM_ERR_ARG
+        with pytest.raises(lbm.LBMError):
+            lbm.lbm_set_launch(h, 96, 1, 0)
+        with pytest.raises(lbm.LBMError):
+            lbm.lbm_step(h, -1)
+        # a state holding NaN is reported by the FP64 reductions
+        bad_state = np.full((19, 8, 8, 8), np.nan)
+        lbm.lbm_set_populations(h, bad_state)
+        with pytest.raises(lbm.LBMError) as e:
+            lbm.lbm_totals(h)
+        assert e.value.status == lbm.LBM_ERR_NONFINITE
+    finally:
+        lbm.lbm_destroy(h)
+    h = lbm.lbm_create(8, 8, 2, 0.8, 1.0, None, lbm.LBM_STORE_F32, torch.cuda.current_stream())
+    try:
+        with pytest.raises(lbm.LBMError) as e:  # bounded axis of 2 nodes
+            lbm.lbm_set_velocity_bc(h, lbm.LBM_Z0, (0, 0, 0))
+        assert e.value.status == lbm.LBM_ERR_ARG
+    finally:
+        lbm.lbm_destroy(h)
+
+
+def _sample_nodes(spec, rng, n_bulk=1500, n_face=40, n_edge=6):
+    nx, ny, nz = spec.nx, spec.ny, spec.nz
+    pts = set()
+    for _ in range(n_bulk):
+        pts.add((int(rng.integers(nx)), int(rng.integers(ny)), int(rng.integers(nz))))
+    ext = [nx - 1, ny - 1, nz - 1]
+    for a in range(3):  # faces
+        for end in (0, ext[a]):
+            for _ in range(n_face):
+                p = [int(rng.integers(1, ext[0])), int(rng.integers(1, ext[1])), int(rng.integers(1, ext[2]))]
+                p[a] = end
+                pts.add(tuple(p))
+    for a in range(3):  # edges along axis a
+        b, c = [d for d in range(3) if d != a]
+        for eb in (0, ext[b]):
+            for ec in (0, ext[c]):
+                for _ in range(n_edge):
+                    p = [0, 0, 0]
+                    p[a] = int(rng.integers(1, ext[a]))
+                    p[b], p[c] = eb, ec
+                    pts.add(tuple(p))
+    for x in (0, nx - 1):
+        for y in (0, ny - 1):
+            for z in (0, nz - 1):
+                pts.add((x, y, z))
+    return np.array(sorted(pts))
+
+
+@pytest.mark.slow
+def test_full_size_roofline_duct_sampled_parity():
+    """The 1024x512x512 FP32 duct in the default launch shape that bench.py
+    times: one step from a perturbed state, ~1900 sampled nodes (every node
+    class) recomputed one by one by the oracle; then the exact boundary
+    velocities on every boundary node of the full lattice."""
+    spec = workloads.roofline_duct()
+    nx, ny, nz, N = spec.nx, spec.ny, spec.nz, spec.nodes
+    say(f"full-size duct {nx}x{ny}x{nz} fp32: allocating 2 x {19 * N * 4 / 1e9:.1f} GB")
+    bufs = [torch.empty(19 * N, dtype=torch.float32, device="cuda") for _ in range(2)]
+    stream = torch.cuda.current_stream()
+    h = lbm.lbm_create_on_buffers(nx, ny, nz, spec.tau, 1.0, None, lbm.LBM_STORE_F32, stream,
+                                  bufs[0], bufs[1], bufs[0].numel() * 4)
+    try:
+        for face, v in spec.bc.items():
+            lbm.lbm_set_velocity_bc(h, face, v)
+        lbm.lbm_step(h, 2)  # a few steps so boundary nodes carry non-trivial state
+        cur = 0 if lbm.lbm_state_buffer(h) == bufs[0].data_ptr() else 1
+        gen = torch.Generator(device="cuda").manual_seed(5)
+        for k in range(19):  # perturb the stored state in place, one population at a time
+            seg = bufs[cur][k * N:(k + 1) * N]
+            seg.mul_(1.0 + 0.04 * (torch.rand(N, device="cuda", generator=gen) - 0.5))
+        torch.cuda.synchronize()
+        pre = bufs[cur].view(19, nz, ny, nx)
+        pts = _sample_nodes(spec, np.random.default_rng(11))
+        say(f"  sampling {len(pts)} nodes")
+        x, y, z = (torch.as_tensor(pts[:, i], device="cuda") for i in range(3))
+        pulled = torch.empty(len(pts), 19, dtype=torch.float64)
+        outside = np.zeros((len(pts), 19), bool)
+        for k in range(19):
+            cxk, cyk, czk = (int(v) for v in PAPER_C[k])
+            pulled[:, k] = pre[k, (z - czk) % nz, (y - cyk) % ny, (x - cxk) % nx].double().cpu()
+            outside[:, k] = ((pts[:, 0] - cxk < 0) | (pts[:, 0] - cxk >= nx) | (pts[:, 1] - cyk < 0)
+                             | (pts[:, 1] - cyk >= ny) | (pts[:, 2] - czk < 0) | (pts[:, 2] - czk >= nz))
+        pulled = pulled.numpy()
+        pulled[outside] = np.nan  # sources beyond a bounded face are unknown
+        lbm.lbm_step(h, 1)
+        torch.cuda.synchronize()
+        post = bufs[cur ^ 1].view(19, nz, ny, nx)
+        assert lbm.lbm_state_buffer(h) == bufs[cur ^ 1].data_ptr()
+        got = torch.stack([post[k, z, y, x] for k in range(19)], 1).double().cpu().numpy()
+        L = make_oracle(spec)
+        expect = np.stack([L.update_node(int(a), int(b), int(c), p) for (a, b, c), p in zip(pts, pulled)])
+        assert np.isfinite(expect).all()
+        err = np.max(np.abs(got - expect) / np.abs(expect))
+        say(f"  sampled max rel diff {err:.2e}")
+        assert err <= 1e-5
+
+        # Properties at full size: prescribed velocity on every face node,
+        # zero on every edge and corner node.
+        rho = torch.empty(N, dtype=torch.float64, device="cuda")
+        u = torch.empty(3 * N, dtype=torch.float64, device="cuda")
+        lbm.lbm_moments(h, rho, u, dst_on_device=True)
+        u = u.view(3, nz, ny, nx)
+        v_in = torch.tensor(spec.bc[0], dtype=torch.float64, device="cuda").view(3, 1, 1)
+        for xs in (0, nx - 1):
+            face = u[:, 1:-1, 1:-1, xs]
+            assert float((face - v_in).abs().max()) < 1e-6
+        for sl in [u[:, 0, :, 1:-1], u[:, -1, :, 1:-1], u[:, :, 0, 1:-1], u[:, :, -1, 1:-1],
+                   u[:, 0, :, 0], u[:, 0, :, -1], u[:, -1, :, 0], u[:, -1, :, -1],
+                   u[:, :, 0, 0], u[:, :, 0, -1], u[:, :, -1, 0], u[:, :, -1, -1]]:
+            assert float(sl.abs().max()) < 1e-6
+        m, _ = lbm.lbm_totals(h)
+        assert np.isfinite(m)
+    finally:
+        lbm.lbm_destroy(h)
+        del bufs
+        torch.cuda.empty_cache()

@@ -53,6 +53,64 @@ def measured_traffic(launch, storage):
     return c.get("hbm_bytes_per_launch")
 
 
+def _counter_means(path, counter):
+    import csv
+    acc = {}
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] != counter:
+                continue
+            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def ingest_counters(args):
+    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the sweep kernel, each
+    scaled by the ratio of the known byte count of the contiguous-copy probe
+    (19 N elements read and written) to what the same counter reads for it."""
+    from paper_0811_4593_amd import lbm
+
+    fetch = _counter_means(args.ingest_counters[0], "FETCH_SIZE")
+    write = _counter_means(args.ingest_counters[1], "WRITE_SIZE")
+    storage = {"f32": lbm.LBM_STORE_F32, "f64": lbm.LBM_STORE_F64, "f16dev": lbm.LBM_STORE_F16_DEV}[args.storage]
+    N = args.nx * args.ny * args.nz
+    copy_kib = 19 * N * lbm.lbm_element_bytes(storage) / 1024.0
+
+    def pick(d, frag):
+        ks = [k for k in d if frag in k]
+        assert len(ks) == 1, (frag, list(d))
+        return ks[0], d[ks[0]]
+
+    sweep_name, f_sweep = pick(fetch, ", false>(")  # the full sweep (COPY = false)
+    _, w_sweep = pick(write, ", false>(")
+    _, f_copy = pick(fetch, "copy_probe_kernel")
+    _, w_copy = pick(write, "copy_probe_kernel")
+    fs, ws = copy_kib / f_copy, copy_kib / w_copy
+    launch = [int(t) for t in args.launch.split(",")] if args.launch else None
+    rec = {
+        "kernel": sweep_name,
+        "kernel_source_hash": kernel_source_hash(),
+        "storage": args.storage,
+        "launch": launch,
+        "lattice": [args.nx, args.ny, args.nz],
+        "fetch_kib_per_dispatch": f_sweep,
+        "write_kib_per_dispatch": w_sweep,
+        "copy_probe_fetch_kib": f_copy,
+        "copy_probe_write_kib": w_copy,
+        "copy_probe_known_kib": copy_kib,
+        "fetch_scale": fs,
+        "write_scale": ws,
+        "hbm_bytes_per_launch": (f_sweep * fs + w_sweep * ws) * 1024.0,
+        "algorithmic_bytes_per_launch": 2 * 19 * N * lbm.lbm_element_bytes(storage),
+        "command": args.counters_command,
+    }
+    os.makedirs(os.path.dirname(COUNTERS_FILE), exist_ok=True)
+    with open(COUNTERS_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(rec))
+
+
 def cpu_baseline(spec_full, budget_s: float):
     """The FP64 CPU oracle, as it stands, on a bounded sample of the workload:
     the same duct set-up at 256 x 128 x 128 (1/64 of the nodes), stepped until
@@ -71,7 +129,7 @@ def cpu_baseline(spec_full, budget_s: float):
         f = L.step(f, nthreads=threads)
         steps += 1
         el = time.perf_counter() - t0
-        if (el >= budget_s and steps >= 2) or steps >= 50:
+        if (el >= budget_s and steps >= 2) or steps >= 2000:
             break
     mlups = s.nodes * steps / el / 1e6
     return {"value": round(mlups, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
@@ -92,7 +150,15 @@ def main():
     ap.add_argument("--probe-reps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE) "
+                         "into the committed counters file and exit")
+    ap.add_argument("--counters-command", default="", help="the rocprofv3 command lines, for the record")
     args = ap.parse_args()
+
+    if args.ingest_counters:
+        ingest_counters(args)
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the single-lattice path "

@@ -38,12 +38,15 @@
  *                BC; lbm_step then requires both faces of that axis to be set.
  *                A non-periodic axis needs at least 3 nodes.
  *
- * Storage forms (lbm_storage)
- *   LBM_STORE_F64      populations in double, arithmetic in double
- *   LBM_STORE_F32      populations in float,  arithmetic in float
- *   LBM_STORE_F16_DEV  populations stored as half-precision scaled deviations
- *                      h_k = RNE((f_k - w_k) * 2^8), decoded f_k = w_k + h_k*2^-8,
- *                      arithmetic in float (w_k: lattice weight, eq_weights)
+ * Storage forms (lbm_storage).  The device buffers hold the deviation of
+ * each population from its rest value, d_k = f_k - w_k (w_k: lattice weight,
+ * eq_weights); every rule is evaluated in these variables, which keeps the
+ * narrow forms accurate.  The populations themselves are f_k = w_k + d_k.
+ *   LBM_STORE_F64      d_k in double, arithmetic in double
+ *   LBM_STORE_F32      d_k in float,  arithmetic in double
+ *   LBM_STORE_F16_DEV  d_k as half-precision scaled deviations
+ *                      h_k = RNE(d_k * 2^8), decoded d_k = h_k * 2^-8,
+ *                      arithmetic in float
  *
  * Errors: every call returns an lbm_status and never aborts.  On failure
  * lbm_last_error() returns a message for the calling thread.  Calls on one
@@ -128,15 +131,17 @@ lbm_status lbm_moments(lbm_lattice *L, double *rho, double *u, int dst_on_device
  * Inf in the totals; the values are still written). */
 lbm_status lbm_totals(lbm_lattice *L, double *mass, double momentum[3]);
 
-/* Copy the stored state to / from a host array f[19*N] of doubles (same
- * layout as the device state).  For LBM_STORE_F32 and LBM_STORE_F16_DEV the
- * values are converted (set: rounded to nearest even).  Synchronizes.
+/* Copy the stored state to / from a host array f[19*N] of populations f_k
+ * in double (same layout as the device state).  get returns w_k + d_k; set
+ * stores d_k = f_k - w_k evaluated in double, rounded to nearest even for
+ * LBM_STORE_F32 and LBM_STORE_F16_DEV.  Synchronizes.
  * Errors: LBM_ERR_ARG, LBM_ERR_OOM, LBM_ERR_HIP. */
 lbm_status lbm_get_populations(lbm_lattice *L, double *f);
 lbm_status lbm_set_populations(lbm_lattice *L, const double *f);
 
-/* Device pointer of the buffer that holds the stored state (it alternates
- * between the two buffers every step).  Errors: LBM_ERR_ARG. */
+/* Device pointer of the buffer that holds the stored state, in the storage
+ * form's encoding of d_k = f_k - w_k (it alternates between the two buffers
+ * every step).  Errors: LBM_ERR_ARG. */
 lbm_status lbm_state_buffer(const lbm_lattice *L, void **dev_ptr);
 
 /* Bytes of one population element for a storage form (8, 4 or 2); 0 if the

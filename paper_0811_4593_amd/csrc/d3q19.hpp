@@ -64,6 +64,16 @@ struct FaceVel {
 };
 
 // ---------------------------------------------------------------------------
+// All rules below act on deviations d_k = f_k - w_k from the rest state.
+// Opposite populations have equal weights and the weights of any set of
+// links closed under c -> -c or lying in a lattice plane have zero first
+// moment, so every rule of the paper keeps its form in d (bounce-back,
+// the corrections N, the buried-link averages); only the density picks up
+// the weight sum, rho = 1 + sum_k d_k.  Working in d keeps the FP32 and FP16
+// forms accurate: the stored numbers are the small deviations, not f ~ w.
+// ---------------------------------------------------------------------------
+
+// ---------------------------------------------------------------------------
 // Boundary rules of one node.  m has bit f set when the node lies on boundary
 // face f (at most one bit per axis).  The rule is written once for every
 // face, edge and corner: the set of unknown populations U, the normals and
@@ -72,7 +82,8 @@ struct FaceVel {
 // stay in registers and are never indexed at run time.
 //
 // Face (one bit; Sec. IV, Appendix; general form of eq_bbshort):
-//   rho = (sum_{c.n=0} f + 2 sum_{c.n<0} f) / (1 - v.n)                 (eq_uin)
+//   rho (1 - v.n) = sum_{c.n=0} f + 2 sum_{c.n<0} f                       (eq_uin)
+//                 = 1 + sum_{c.n<=0} d + sum_{c.n<0} d
 //   for every unknown j (c_j.n > 0), i = -j:
 //   f_j = f_i - 6 w_i rho (c_i.v) - (rho/3) (t_i.v) + 1/2 t_i.M           (eq_bbshort)
 //   with t_i = c_i - (c_i.n) n = c_i + n and M = sum_{c.n=0} f c (the
@@ -87,10 +98,12 @@ struct FaceVel {
 //   bounced links with c.e != 0 (e the edge direction) also get
 //   -(c.e)(f_{+e} - f_{-e})/4, which removes the momentum along the edge;
 //   buried links = (sum of the other moving populations) / D with D = 22
-//   (edge) or 18 (corner); rest population = 12 times that.
+//   (edge) or 18 (corner) -- in deviations, the weights' share 22/36 or
+//   18/36 cancels against the buried links' own weight 1/36; rest
+//   population = 12 times that.
 // ---------------------------------------------------------------------------
 template <class T>
-__device__ __forceinline__ void boundary_rule(T (&f)[19], unsigned m, const FaceVel<T> &fv) {
+__device__ __forceinline__ void boundary_rule(T (&d)[19], unsigned m, const FaceVel<T> &fv) {
   unsigned U = 0;
 #pragma unroll
   for (int b = 0; b < 6; ++b)
@@ -117,28 +130,28 @@ __device__ __forceinline__ void boundary_rule(T (&f)[19], unsigned m, const Face
       const bool unk = (U >> k) & 1u;
       const bool out = (U >> opp(k)) & 1u;  // c_k.n < 0
       const bool in_plane = !unk && !out;
-      s_known += unk ? T(0) : f[k];
-      s_out += out ? f[k] : T(0);
-      if (cx(k)) Mx += in_plane ? T(cx(k)) * f[k] : T(0);
-      if (cy(k)) My += in_plane ? T(cy(k)) * f[k] : T(0);
-      if (cz(k)) Mz += in_plane ? T(cz(k)) * f[k] : T(0);
+      s_known += unk ? T(0) : d[k];
+      s_out += out ? d[k] : T(0);
+      if (cx(k)) Mx += in_plane ? T(cx(k)) * d[k] : T(0);
+      if (cy(k)) My += in_plane ? T(cy(k)) * d[k] : T(0);
+      if (cz(k)) Mz += in_plane ? T(cz(k)) * d[k] : T(0);
     }
-    const T rho = (s_known + s_out) / (T(1) - vn);
+    const T rho = (T(1) + s_known + s_out) / (T(1) - vn);
     const T rho3 = rho / T(3);
 #pragma unroll
     for (int j = 0; j < 18; ++j) {
       const int i = opp(j);
       const T civ = T(cx(i)) * vx + T(cy(i)) * vy + T(cz(i)) * vz;
       const T ciM = T(cx(i)) * Mx + T(cy(i)) * My + T(cz(i)) * Mz;
-      const T fj = f[i] - T(6 * w36(i)) / T(36) * rho * civ - rho3 * (civ + vn) + T(0.5) * ciM;
-      f[j] = ((U >> j) & 1u) ? fj : f[j];
+      const T dj = d[i] - T(6 * w36(i)) / T(36) * rho * civ - rho3 * (civ + vn) + T(0.5) * ciM;
+      d[j] = ((U >> j) & 1u) ? dj : d[j];
     }
   } else {
     // Edge or corner, no-slip.
     const int ex = (nb == 2 && sx == 0) ? 1 : 0;
     const int ey = (nb == 2 && sy == 0) ? 1 : 0;
     const int ez = (nb == 2 && sz == 0) ? 1 : 0;
-    const T Pq = T(0.25) * (T(ex) * (f[0] - f[1]) + T(ey) * (f[2] - f[3]) + T(ez) * (f[4] - f[5]));
+    const T Pq = T(0.25) * (T(ex) * (d[0] - d[1]) + T(ey) * (d[2] - d[3]) + T(ez) * (d[4] - d[5]));
     unsigned bur = 0;
 #pragma unroll
     for (int k = 0; k < 18; ++k) bur |= ((U >> k) & (U >> opp(k)) & 1u) << k;
@@ -146,31 +159,34 @@ __device__ __forceinline__ void boundary_rule(T (&f)[19], unsigned m, const Face
     for (int k = 0; k < 18; ++k) {
       const bool bounced = ((U & ~bur) >> k) & 1u;
       const int ce = cx(k) * ex + cy(k) * ey + cz(k) * ez;
-      const T fk = f[opp(k)] - T(ce) * Pq;
-      f[k] = bounced ? fk : f[k];
+      const T dk = d[opp(k)] - T(ce) * Pq;
+      d[k] = bounced ? dk : d[k];
     }
     T s = T(0);
 #pragma unroll
-    for (int k = 0; k < 18; ++k) s += ((bur >> k) & 1u) ? T(0) : f[k];
-    const T fb = s / (nb == 2 ? T(22) : T(18));
+    for (int k = 0; k < 18; ++k) s += ((bur >> k) & 1u) ? T(0) : d[k];
+    const T db = s / (nb == 2 ? T(22) : T(18));
 #pragma unroll
-    for (int k = 0; k < 18; ++k) f[k] = ((bur >> k) & 1u) ? fb : f[k];
-    f[18] = T(12) * fb;
+    for (int k = 0; k < 18; ++k) d[k] = ((bur >> k) & 1u) ? db : d[k];
+    d[18] = T(12) * db;
   }
 }
 
-// BGK collision towards the second-order equilibrium (eq_bgk, eq_feq):
-// f_k <- f_k + omega (f_k^eq(rho, u) - f_k), omega = 1/tau, c_s^2 = 1/3.
+// BGK collision towards the second-order equilibrium (eq_bgk, eq_feq), in
+// deviations: rho = 1 + sum d, rho u = sum d c,
+//   d_k^eq = f_k^eq - w_k = w_k (rho - 1) + w_k rho (3 c.u + 4.5 (c.u)^2 - 1.5 u^2),
+//   d_k <- d_k + omega (d_k^eq - d_k), omega = 1/tau, c_s^2 = 1/3.
 template <class T>
-__device__ __forceinline__ void bgk_collide(T (&f)[19], T omega) {
-  T rho = T(0), jx = T(0), jy = T(0), jz = T(0);
+__device__ __forceinline__ void bgk_collide(T (&d)[19], T omega) {
+  T drho = T(0), jx = T(0), jy = T(0), jz = T(0);
 #pragma unroll
   for (int k = 0; k < 19; ++k) {
-    rho += f[k];
-    if (cx(k)) jx += T(cx(k)) * f[k];
-    if (cy(k)) jy += T(cy(k)) * f[k];
-    if (cz(k)) jz += T(cz(k)) * f[k];
+    drho += d[k];
+    if (cx(k)) jx += T(cx(k)) * d[k];
+    if (cy(k)) jy += T(cy(k)) * d[k];
+    if (cz(k)) jz += T(cz(k)) * d[k];
   }
+  const T rho = T(1) + drho;
   const T ir = T(1) / rho;
   const T ux = jx * ir, uy = jy * ir, uz = jz * ir;
   const T usq15 = T(1.5) * (ux * ux + uy * uy + uz * uz);
@@ -180,8 +196,8 @@ __device__ __forceinline__ void bgk_collide(T (&f)[19], T omega) {
     if (cx(k)) cu += T(cx(k)) * ux;
     if (cy(k)) cu += T(cy(k)) * uy;
     if (cz(k)) cu += T(cz(k)) * uz;
-    const T feq = weight<T>(k) * rho * (T(1) + T(3) * cu + T(4.5) * cu * cu - usq15);
-    f[k] = f[k] + omega * (feq - f[k]);
+    const T deq = weight<T>(k) * (drho + rho * (T(3) * cu + T(4.5) * cu * cu - usq15));
+    d[k] = d[k] + omega * (deq - d[k]);
   }
 }
 

@@ -83,10 +83,11 @@ static lbm_status validate_create(int nx, int ny, int nz, double tau, double rho
 }
 
 static void default_launch(lbm_lattice *L) {
-  // One block covers a whole x-row when it fits: 256 threads, up to 4 nodes
-  // each.
+  // 256 threads, one node each, consecutive row segments on one XCD: the
+  // fastest shape measured on the 1024 x 512 x 512 duct (lbm_set_launch
+  // overrides it; the batch autotuner searches the others).
   L->block_x = 256;
-  L->npt = L->nx > 512 ? 4 : (L->nx > 256 ? 2 : 1);
+  L->npt = 1;
   L->xcd = 1;
 }
 

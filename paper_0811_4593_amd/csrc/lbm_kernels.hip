@@ -17,7 +17,10 @@
 namespace lbm {
 
 // ---------------------------------------------------------------------------
-// Storage codecs: population element type S, arithmetic type T.
+// Storage codecs: population element type S, arithmetic type T.  The stored
+// quantity is the deviation d_k = f_k - w_k from the rest state (w_k: lattice
+// weight); the FP16 form stores it scaled, h = RNE(d * 2^8), d = h * 2^-8
+// (exact scaling).
 // ---------------------------------------------------------------------------
 template <class S>
 struct Codec;
@@ -25,28 +28,26 @@ struct Codec;
 template <>
 struct Codec<double> {
   using T = double;
-  static __device__ __forceinline__ T decode(double s, int) { return s; }
-  static __device__ __forceinline__ double encode(T v, int) { return v; }
+  static __device__ __forceinline__ T decode(double s) { return s; }
+  static __device__ __forceinline__ double encode(T v) { return v; }
 };
 
+// FP32 storage is updated in double: the per-step rounding of the arithmetic
+// then stays below the rounding of the stored deviations, so the steady state
+// of the FP32 form is set by its storage alone.  On gfx950 a double FMA costs
+// the same issue slot as an unpacked float FMA and the sweep is HBM-bound.
 template <>
 struct Codec<float> {
-  using T = float;
-  static __device__ __forceinline__ T decode(float s, int) { return s; }
-  static __device__ __forceinline__ float encode(T v, int) { return v; }
+  using T = double;
+  static __device__ __forceinline__ T decode(float s) { return double(s); }
+  static __device__ __forceinline__ float encode(T v) { return float(v); }
 };
 
-// Half-precision scaled deviation from the lattice weight:
-// h = RNE((f - w_k) * 2^8), f = w_k + h * 2^-8 (exact scaling, float math).
 template <>
 struct Codec<_Float16> {
   using T = float;
-  static __device__ __forceinline__ T decode(_Float16 s, int k) {
-    return weight<float>(k) + static_cast<float>(s) * 0.00390625f;
-  }
-  static __device__ __forceinline__ _Float16 encode(T v, int k) {
-    return static_cast<_Float16>((v - weight<float>(k)) * 256.0f);
-  }
+  static __device__ __forceinline__ T decode(_Float16 s) { return static_cast<float>(s) * 0.00390625f; }
+  static __device__ __forceinline__ _Float16 encode(T v) { return static_cast<_Float16>(v * 256.0f); }
 };
 
 template <class S, bool NT>
@@ -115,14 +116,14 @@ __global__ __launch_bounds__(BX) void sweep_kernel(const S *__restrict__ src, S 
       }
       if constexpr (!COPY) {
 #pragma unroll
-        for (int k = 0; k < 19; ++k) f[k] = Codec<S>::decode(raw[k], k);
+        for (int k = 0; k < 19; ++k) f[k] = Codec<S>::decode(raw[k]);
         unsigned m = m_yz;
         if (x == 0) m |= a.bc_mask & 1u;
         if (x == nx - 1) m |= a.bc_mask & 2u;
         if (m) boundary_rule<T>(f, m, a.fv);
         bgk_collide<T>(f, a.omega);
 #pragma unroll
-        for (int k = 0; k < 19; ++k) raw[k] = Codec<S>::encode(f[k], k);
+        for (int k = 0; k < 19; ++k) raw[k] = Codec<S>::encode(f[k]);
       }
       const size_t n = size_t(row) * unx + unsigned(x);
 #pragma unroll
@@ -132,8 +133,9 @@ __global__ __launch_bounds__(BX) void sweep_kernel(const S *__restrict__ src, S 
 }
 
 // ---------------------------------------------------------------------------
-// Initialisation: f_k = f_k^eq(rho0, u0) at every node (eq_feq), in double,
-// then encoded.
+// Initialisation: f_k = f_k^eq(rho0, u0) at every node (eq_feq), stored as
+// d_k = f_k - w_k = w_k (rho0 - 1) + w_k rho0 (3 c.u + 4.5 (c.u)^2 - 1.5 u^2),
+// evaluated in double.
 // ---------------------------------------------------------------------------
 template <class S>
 __global__ void init_kernel(S *__restrict__ f, size_t N, double rho0, double ux, double uy, double uz) {
@@ -143,14 +145,15 @@ __global__ void init_kernel(S *__restrict__ f, size_t N, double rho0, double ux,
 #pragma unroll
   for (int k = 0; k < 19; ++k) {
     const double cu = double(cx(k)) * ux + double(cy(k)) * uy + double(cz(k)) * uz;
-    const double feq = weight<double>(k) * rho0 * (1.0 + 3.0 * cu + 4.5 * cu * cu - usq15);
-    f[size_t(k) * N + n] = Codec<S>::encode(typename Codec<S>::T(feq), k);
+    const double dk = weight<double>(k) * ((rho0 - 1.0) + rho0 * (3.0 * cu + 4.5 * cu * cu - usq15));
+    f[size_t(k) * N + n] = Codec<S>::encode(typename Codec<S>::T(dk));
   }
 }
 
 // ---------------------------------------------------------------------------
 // Moments of the stored state (eq_rho, eq_vel) for nodes [n0, n0 + count):
-// rho[i], u[a*count + i] in double; optional per-block FP64 partial sums of
+// rho = 1 + sum_k d_k and rho u = sum_k d_k c_k (the weights sum to 1 and have
+// zero first moment); rho[i], u[a*count + i] in double; optional per-block FP64 partial sums of
 // mass and momentum (wavefront shuffles, then LDS across the block's waves,
 // in a fixed order).
 // ---------------------------------------------------------------------------
@@ -169,15 +172,16 @@ __global__ __launch_bounds__(256) void moments_kernel(const S *__restrict__ f, s
   const size_t stride = size_t(gridDim.x) * blockDim.x;
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride) {
     const size_t n = n0 + i;
-    double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    double dr = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
     for (int k = 0; k < 19; ++k) {
-      const double v = double(Codec<S>::decode(f[size_t(k) * N + n], k));
-      r += v;
+      const double v = double(Codec<S>::decode(f[size_t(k) * N + n]));
+      dr += v;
       if (cx(k)) jx += double(cx(k)) * v;
       if (cy(k)) jy += double(cy(k)) * v;
       if (cz(k)) jz += double(cz(k)) * v;
     }
+    const double r = 1.0 + dr;
     if (rho) rho[i] = r;
     if (u) {
       u[i] = jx / r;
@@ -226,8 +230,8 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double *__re
 }
 
 // ---------------------------------------------------------------------------
-// Conversion between the stored form and double, nodes [n0, n0 + count):
-// host-side layout of the chunk is buf[k*count + i].
+// Conversion between the stored form and populations f_k = w_k + d_k in
+// double, nodes [n0, n0 + count); the chunk's layout is buf[k*count + i].
 // ---------------------------------------------------------------------------
 template <class S>
 __global__ void to_double_kernel(const S *__restrict__ f, size_t N, size_t n0, size_t count,
@@ -235,7 +239,8 @@ __global__ void to_double_kernel(const S *__restrict__ f, size_t N, size_t n0, s
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= count) return;
 #pragma unroll
-  for (int k = 0; k < 19; ++k) out[size_t(k) * count + i] = double(Codec<S>::decode(f[size_t(k) * N + n0 + i], k));
+  for (int k = 0; k < 19; ++k)
+    out[size_t(k) * count + i] = weight<double>(k) + double(Codec<S>::decode(f[size_t(k) * N + n0 + i]));
 }
 
 template <class S>
@@ -246,7 +251,7 @@ __global__ void from_double_kernel(S *__restrict__ f, size_t N, size_t n0, size_
 #pragma unroll
   for (int k = 0; k < 19; ++k) {
     using T = typename Codec<S>::T;
-    f[size_t(k) * N + n0 + i] = Codec<S>::encode(T(in[size_t(k) * count + i]), k);
+    f[size_t(k) * N + n0 + i] = Codec<S>::encode(T(in[size_t(k) * count + i] - weight<double>(k)));
   }
 }
 
@@ -309,7 +314,7 @@ hipError_t launch_sweep(const SweepConfig &c, const void *src, void *dst, bool c
                        : launch_sweep_shape<double, false>(src, dst, a, c.block_x, c.nodes_per_thread, s);
     }
     case kStoreF32: {
-      const auto a = make_args<float>(c);
+      const auto a = make_args<double>(c);
       return copy_only ? launch_sweep_shape<float, true>(src, dst, a, c.block_x, c.nodes_per_thread, s)
                        : launch_sweep_shape<float, false>(src, dst, a, c.block_x, c.nodes_per_thread, s);
     }

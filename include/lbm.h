@@ -169,6 +169,93 @@ void lbm_destroy(lbm_lattice *L);
 /* Message of the last failed call on this thread ("" if none). */
 const char *lbm_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Batch runtime: many independent lattices resident on one GPU, advanced
+ * together by a persistent multi-lattice sweep (the same per-node update as
+ * lbm_step, so a lattice's result does not depend on what else runs).
+ * Lattices ("jobs") are admitted from a queue when a slot and memory in the
+ * HBM budget are free; steps run in chunks captured as HIP graphs; after each
+ * chunk the convergence measure
+ *     delta = max_nodes,components |u(t) - u(t - chunk)| / u_ref
+ * decides retirement (delta < tol, or steps >= max_steps).  Retired jobs'
+ * moments are copied to host memory and their device memory is returned to
+ * the pool at once.  The paper runs a fixed number of steps (Sec. VI); the
+ * convergence measure and its use for stopping are this library's.
+ * ------------------------------------------------------------------------ */
+typedef struct lbm_batch lbm_batch;
+
+typedef struct {
+  int nx, ny, nz;            /* lattice size; N = nx*ny*nz < 2^31 */
+  double tau;                /* > 1/2 */
+  double rho0;               /* initial density (> 0); initial velocity 0 */
+  lbm_storage storage;
+  unsigned bc_mask;          /* bit f: face f carries bc_velocity[f]; both faces of an axis or none */
+  double bc_velocity[6][3];  /* as lbm_set_velocity_bc, same limits */
+  double u_ref;              /* velocity scale of delta (> 0), e.g. |inflow velocity| */
+  double tol;                /* stop when delta < tol (tol <= 0: never) */
+  int max_steps;             /* stop once steps >= max_steps */
+} lbm_job;
+
+typedef enum { LBM_JOB_QUEUED = 0, LBM_JOB_RUNNING = 1, LBM_JOB_DONE = 2 } lbm_job_state;
+
+typedef struct {
+  int state;      /* lbm_job_state */
+  int steps;      /* steps taken (a multiple of 2; chunks and autotune trials) */
+  double delta;   /* convergence measure at the last check (inf before the first) */
+  int converged;  /* 1 if it stopped on delta < tol */
+} lbm_job_status;
+
+/* Device bytes a job occupies while resident: two population buffers and a
+ * float velocity snapshot, each rounded up to 256 bytes.  Errors: LBM_ERR_ARG. */
+lbm_status lbm_job_bytes(const lbm_job *job, size_t *bytes);
+
+/* Create a batch with a device pool of hbm_budget_bytes (one allocation, made
+ * here), chunks of chunk_steps (even, >= 2) steps and at most max_jobs
+ * resident jobs.  hip_stream NULL: the batch creates its own stream (graph
+ * capture needs a stream other than the null stream).
+ * Errors: LBM_ERR_ARG, LBM_ERR_OOM (pool), LBM_ERR_HIP. */
+lbm_status lbm_batch_create(size_t hbm_budget_bytes, int chunk_steps, int max_jobs, void *hip_stream,
+                            lbm_batch **out);
+
+/* Queue a job; *job_id receives its id.  Errors: LBM_ERR_ARG (invalid job),
+ * LBM_ERR_OOM (the job alone exceeds the budget). */
+lbm_status lbm_batch_submit(lbm_batch *B, const lbm_job *job, int *job_id);
+
+/* Admit queued jobs that fit, run one chunk of steps on every resident job,
+ * evaluate delta and retire finished jobs.  Blocks until the chunk is done.
+ * n_active / n_queued (may be NULL) receive the counts after the chunk.
+ * Errors: LBM_ERR_ARG, LBM_ERR_HIP, LBM_ERR_OOM (staging buffer). */
+lbm_status lbm_batch_run_chunk(lbm_batch *B, int *n_active, int *n_queued);
+
+/* Status of a job.  Errors: LBM_ERR_ARG (unknown id). */
+lbm_status lbm_batch_poll(lbm_batch *B, int job_id, lbm_job_status *st);
+
+/* Moments of a finished job, rho[N] and u[3*N] (host arrays; either may be
+ * NULL), then forget the job.  Errors: LBM_ERR_ARG (unknown id),
+ * LBM_ERR_STATE (not finished). */
+lbm_status lbm_batch_result(lbm_batch *B, int job_id, double *rho, double *u);
+
+/* Launch shape of the multi-lattice sweep: block_x threads (128 or 256),
+ * tile_nodes nodes per tile (>= 256), grid_blocks persistent blocks (0: 8 per
+ * compute unit).  Any shape gives the same results. */
+lbm_status lbm_batch_set_shape(lbm_batch *B, int block_x, int tile_nodes, int grid_blocks);
+lbm_status lbm_batch_get_shape(const lbm_batch *B, int *block_x, int *tile_nodes, int *grid_blocks);
+
+/* Admit what fits, then time trial_steps (even) steps of the resident jobs
+ * for each candidate shape (block 128/256, tiles of 1024/4096/16384 nodes,
+ * 4/8/16 blocks per compute unit) and keep the fastest.  The trial steps are
+ * real steps of every resident job (their step counts advance).  Results are
+ * cached per process by storage mix and node-count class; a cached class is
+ * not re-timed.  Outputs may be NULL.  Errors: LBM_ERR_ARG, LBM_ERR_STATE (no
+ * resident job), LBM_ERR_HIP. */
+lbm_status lbm_batch_autotune(lbm_batch *B, int trial_steps, int *block_x, int *tile_nodes, int *grid_blocks);
+
+/* Bytes of the pool in use and in total.  Errors: LBM_ERR_ARG. */
+lbm_status lbm_batch_memory(const lbm_batch *B, size_t *used, size_t *capacity);
+
+/* Release the batch, its pool and every job.  NULL is a no-op. */
+void lbm_batch_destroy(lbm_batch *B);
+
 #ifdef __cplusplus
 }
 #endif

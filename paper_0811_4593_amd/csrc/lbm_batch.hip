@@ -1,0 +1,753 @@
+// lbm_batch.hip -- many independent lattices on one GPU: a persistent
+// multi-lattice sweep over a tile list, a device memory pool with admission by
+// an HBM budget, step chunks captured in HIP graphs, a per-lattice
+// convergence measure, and an autotuner for the launch shape.
+//
+// Every lattice is advanced by the same per-node update as the single-lattice
+// sweep (node_update.hpp), so a lattice gives bit-identical results alone or
+// in any mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_internal.hpp"
+#include "node_update.hpp"
+
+namespace lbm {
+
+// Device-side description of one resident lattice.
+struct BatchLat {
+  void *buf[2];    // population buffers (state in buf[0] at chunk boundaries)
+  float *snap;     // [3][N] velocity at the previous convergence check
+  unsigned nx, ny, nz, N;
+  unsigned bc_mask;
+  int pad;
+  double omega;    // 1 / tau
+  double v[6][3];  // face velocities
+  double inv_uref; // 1 / velocity scale of the convergence measure
+};
+
+// A contiguous node range [n0, n1) of one lattice.
+struct BatchTile {
+  int lat;
+  unsigned n0, n1;
+};
+
+// One step of every lattice of storage type S listed in `tiles`.  Blocks take
+// tiles round-robin; each lane updates nodes n0 + t, n0 + t + BX, ... of its
+// block's tile.  `parity` selects source and destination buffer.
+template <class S, int BX>
+__global__ __launch_bounds__(BX) void batch_sweep_kernel(const BatchLat *__restrict__ lats,
+                                                         const BatchTile *__restrict__ tiles,
+                                                         const int *__restrict__ ntiles, int parity) {
+  using T = typename Codec<S>::T;
+  const int nt = *ntiles;
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    const BatchTile tile = tiles[t];
+    const BatchLat &L = lats[tile.lat];
+    const NodeGeom g{L.nx, L.ny, L.nz, L.N};
+    const S *src = static_cast<const S *>(L.buf[parity]);
+    S *dst = static_cast<S *>(L.buf[parity ^ 1]);
+    FaceVel<T> fv;
+#pragma unroll
+    for (int f = 0; f < 6; ++f)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) fv.v[f][d] = T(L.v[f][d]);
+    const T omega = T(L.omega);
+    for (unsigned n = tile.n0 + threadIdx.x; n < tile.n1; n += BX) {
+      const unsigned r = n / g.nx;
+      const unsigned x = n - r * g.nx;
+      const unsigned z = r / g.ny;
+      const unsigned y = r - z * g.ny;
+      update_node<S, true, false>(src, dst, g, int(x), int(y), int(z), L.bc_mask, omega, fv);
+    }
+  }
+}
+
+// Convergence measure, per lattice: max over nodes and components of
+// |u(t) - u(t_prev)| / u_ref (u from the stored state, eq_vel), then the
+// snapshot is replaced by u(t).  Maxima are combined with an atomic max on
+// the bit pattern of non-negative floats: order-independent, so the stop step
+// of every lattice is deterministic.  NaN counts as +inf.
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void batch_delta_kernel(const BatchLat *__restrict__ lats,
+                                                          const BatchTile *__restrict__ tiles,
+                                                          const int *__restrict__ ntiles,
+                                                          unsigned *__restrict__ delta_bits) {
+  __shared__ float lds[4];
+  const int nt = *ntiles;
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    const BatchTile tile = tiles[t];
+    const BatchLat &L = lats[tile.lat];
+    const S *f = static_cast<const S *>(L.buf[0]);
+    float dmax = 0.0f;
+    for (unsigned n = tile.n0 + threadIdx.x; n < tile.n1; n += 256) {
+      double dr = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < 19; ++k) {
+        const double v = double(Codec<S>::decode(f[size_t(k) * L.N + n]));
+        dr += v;
+        if (cx(k)) j[0] += double(cx(k)) * v;
+        if (cy(k)) j[1] += double(cy(k)) * v;
+        if (cz(k)) j[2] += double(cz(k)) * v;
+      }
+      const double ir = 1.0 / (1.0 + dr);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double u = j[a] * ir;
+        float *sp = L.snap + size_t(a) * L.N + n;
+        const float du = float(fabs(u - double(*sp)) * L.inv_uref);
+        dmax = (du != du) ? INFINITY : fmaxf(dmax, du);
+        *sp = float(u);
+      }
+    }
+    dmax = wave_max(dmax);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = dmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const float m = fmaxf(fmaxf(lds[0], lds[1]), fmaxf(lds[2], lds[3]));
+      atomicMax(delta_bits + tile.lat, __float_as_uint(m));
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void fill_float_kernel(float *__restrict__ p, size_t n, float v) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <class S, int BX>
+static void launch_batch_sweep_t(const BatchLat *lats, const BatchTile *tiles, const int *nt, int parity, int grid,
+                                 hipStream_t s) {
+  batch_sweep_kernel<S, BX><<<dim3(grid), dim3(BX), 0, s>>>(lats, tiles, nt, parity);
+}
+
+static hipError_t launch_batch_sweep(int storage, int bx, const BatchLat *lats, const BatchTile *tiles, const int *nt,
+                                     int parity, int grid, hipStream_t s) {
+  switch (storage * 1000 + bx) {
+    case kStoreF64 * 1000 + 128: launch_batch_sweep_t<double, 128>(lats, tiles, nt, parity, grid, s); break;
+    case kStoreF64 * 1000 + 256: launch_batch_sweep_t<double, 256>(lats, tiles, nt, parity, grid, s); break;
+    case kStoreF32 * 1000 + 128: launch_batch_sweep_t<float, 128>(lats, tiles, nt, parity, grid, s); break;
+    case kStoreF32 * 1000 + 256: launch_batch_sweep_t<float, 256>(lats, tiles, nt, parity, grid, s); break;
+    case kStoreF16 * 1000 + 128: launch_batch_sweep_t<_Float16, 128>(lats, tiles, nt, parity, grid, s); break;
+    case kStoreF16 * 1000 + 256: launch_batch_sweep_t<_Float16, 256>(lats, tiles, nt, parity, grid, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+static hipError_t launch_batch_delta(int storage, const BatchLat *lats, const BatchTile *tiles, const int *nt,
+                                     unsigned *delta, int grid, hipStream_t s) {
+  switch (storage) {
+    case kStoreF64: batch_delta_kernel<double><<<dim3(grid), dim3(256), 0, s>>>(lats, tiles, nt, delta); break;
+    case kStoreF32: batch_delta_kernel<float><<<dim3(grid), dim3(256), 0, s>>>(lats, tiles, nt, delta); break;
+    case kStoreF16: batch_delta_kernel<_Float16><<<dim3(grid), dim3(256), 0, s>>>(lats, tiles, nt, delta); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace lbm
+
+// ---------------------------------------------------------------------------
+// Host runtime.
+// ---------------------------------------------------------------------------
+namespace {
+
+#define bfail lbm::set_error
+
+#define LBM_BHIP(call, what)                                                                 \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess) return bfail(LBM_ERR_HIP, "%s: %s", what, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kNumStorage = 3;
+constexpr int kMinTileNodes = 256;
+constexpr size_t kStageNodes = size_t(1) << 22;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// First-fit allocator over one device allocation; free blocks are kept
+// sorted by offset and coalesced.
+class Pool {
+ public:
+  void reset(size_t cap) {
+    cap_ = cap;
+    free_.clear();
+    free_[0] = cap;
+    used_ = 0;
+  }
+  bool alloc(size_t bytes, size_t *off) {
+    bytes = align_up(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes, start = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[start] = rest;
+        used_ += bytes;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = align_up(bytes);
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t used() const { return used_; }
+  size_t capacity() const { return cap_; }
+
+ private:
+  size_t cap_ = 0, used_ = 0;
+  std::map<size_t, size_t> free_;
+};
+
+size_t job_bytes(const lbm_job &j) {
+  const size_t N = size_t(j.nx) * j.ny * j.nz;
+  return 2 * align_up(19 * N * lbm_element_bytes(j.storage)) + align_up(3 * N * sizeof(float));
+}
+
+struct Job {
+  lbm_job spec;
+  int state = LBM_JOB_QUEUED;
+  int slot = -1;
+  size_t off = 0, bytes = 0;
+  int steps = 0;
+  double delta = INFINITY;
+  int converged = 0;
+  int waited = 0;  // chunks spent at the head of the queue without fitting
+  std::vector<double> rho, u;  // moments at retirement
+};
+
+struct Shape {
+  int block_x = 256, tile_nodes = 4096, grid = 0;
+};
+
+// Autotune results shared by every batch in the process, keyed by a coarse
+// description of the resident work (storage mix, log2 of the node count).
+std::map<long long, Shape> g_tuned;
+
+}  // namespace
+
+struct lbm_batch {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int num_cu = 256;
+  char *pool_base = nullptr;
+  Pool pool;
+  int chunk_steps = 100;
+  int max_jobs = 0;
+  Shape shape;
+  bool tiles_dirty = true;
+  std::map<int, Job> jobs;
+  std::deque<int> queue;
+  std::vector<int> slot_job;  // slot -> job id (-1 free)
+  int next_id = 1;
+  // device tables
+  lbm::BatchLat *d_lats = nullptr;
+  lbm::BatchTile *d_tiles[kNumStorage] = {nullptr, nullptr, nullptr};
+  int *d_ntiles = nullptr;
+  unsigned *d_delta = nullptr;
+  size_t tile_cap = 0;
+  std::vector<lbm::BatchLat> h_lats;
+  std::vector<lbm::BatchTile> h_tiles[kNumStorage];
+  int h_ntiles[kNumStorage] = {0, 0, 0};
+  std::vector<unsigned> h_delta;
+  double *d_stage = nullptr;
+  std::map<long long, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+unsigned present_mask(const lbm_batch *B) {
+  unsigned m = 0;
+  for (int s = 0; s < kNumStorage; ++s)
+    if (B->h_ntiles[s] > 0) m |= 1u << s;
+  return m;
+}
+
+void drop_graphs(lbm_batch *B) {
+  for (auto &kv : B->graphs) (void)hipGraphExecDestroy(kv.second);
+  B->graphs.clear();
+}
+
+lbm_status rebuild_tiles(lbm_batch *B) {
+  for (int s = 0; s < kNumStorage; ++s) B->h_tiles[s].clear();
+  const unsigned tn = unsigned(B->shape.tile_nodes);
+  for (int slot = 0; slot < B->max_jobs; ++slot) {
+    const int id = B->slot_job[slot];
+    if (id < 0) continue;
+    const Job &J = B->jobs[id];
+    const unsigned N = unsigned(size_t(J.spec.nx) * J.spec.ny * J.spec.nz);
+    for (unsigned n0 = 0; n0 < N; n0 += tn) B->h_tiles[J.spec.storage].push_back({slot, n0, std::min(N, n0 + tn)});
+  }
+  for (int s = 0; s < kNumStorage; ++s) {
+    if (B->h_tiles[s].size() > B->tile_cap) return bfail(LBM_ERR_STATE, "tile list exceeds its capacity");
+    B->h_ntiles[s] = int(B->h_tiles[s].size());
+    if (!B->h_tiles[s].empty())
+      LBM_BHIP(hipMemcpyAsync(B->d_tiles[s], B->h_tiles[s].data(), B->h_tiles[s].size() * sizeof(lbm::BatchTile),
+                              hipMemcpyHostToDevice, B->stream),
+               "upload tiles");
+  }
+  LBM_BHIP(hipMemcpyAsync(B->d_ntiles, B->h_ntiles, sizeof(B->h_ntiles), hipMemcpyHostToDevice, B->stream),
+           "upload tile counts");
+  LBM_BHIP(hipMemcpyAsync(B->d_lats, B->h_lats.data(), B->h_lats.size() * sizeof(lbm::BatchLat),
+                          hipMemcpyHostToDevice, B->stream),
+           "upload lattices");
+  // The host vectors must stay untouched until the copies have run.
+  LBM_BHIP(hipStreamSynchronize(B->stream), "upload");
+  B->tiles_dirty = false;
+  return LBM_OK;
+}
+
+int grid_of(const lbm_batch *B) { return B->shape.grid > 0 ? B->shape.grid : 8 * B->num_cu; }
+
+lbm_status launch_steps(lbm_batch *B, int nsteps, int parity0) {
+  const int grid = grid_of(B);
+  for (int st = 0; st < nsteps; ++st)
+    for (int s = 0; s < kNumStorage; ++s)
+      if (B->h_ntiles[s] > 0)
+        LBM_BHIP(lbm::launch_batch_sweep(s, B->shape.block_x, B->d_lats, B->d_tiles[s], B->d_ntiles + s,
+                                         (parity0 + st) & 1, grid, B->stream),
+                 "batch sweep launch");
+  return LBM_OK;
+}
+
+lbm_status run_graph_chunk(lbm_batch *B) {
+  const unsigned mask = present_mask(B);
+  if (!mask) return LBM_OK;
+  const long long key = (long long)mask | ((long long)B->chunk_steps << 8) | ((long long)B->shape.block_x << 24) |
+                        ((long long)grid_of(B) << 36);
+  auto it = B->graphs.find(key);
+  if (it == B->graphs.end()) {
+    hipGraph_t graph;
+    LBM_BHIP(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    lbm_status st = launch_steps(B, B->chunk_steps, 0);
+    hipError_t e = hipStreamEndCapture(B->stream, &graph);
+    if (st != LBM_OK) return st;
+    if (e != hipSuccess) return bfail(LBM_ERR_HIP, "end capture: %s", hipGetErrorString(e));
+    hipGraphExec_t exec;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return bfail(LBM_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
+    it = B->graphs.emplace(key, exec).first;
+  }
+  LBM_BHIP(hipGraphLaunch(it->second, B->stream), "graph launch");
+  return LBM_OK;
+}
+
+lbm_status ensure_stage(lbm_batch *B) {
+  if (B->d_stage) return LBM_OK;
+  hipError_t e = hipMalloc(&B->d_stage, sizeof(double) * 4 * kStageNodes);
+  if (e != hipSuccess) {
+    B->d_stage = nullptr;
+    return bfail(LBM_ERR_OOM, "staging buffer: %s", hipGetErrorString(e));
+  }
+  return LBM_OK;
+}
+
+// Moments of a finished job into host memory, then release its device memory.
+lbm_status retire(lbm_batch *B, int id) {
+  Job &J = B->jobs[id];
+  lbm_status st = ensure_stage(B);
+  if (st != LBM_OK) return st;
+  const size_t N = size_t(J.spec.nx) * J.spec.ny * J.spec.nz;
+  J.rho.resize(N);
+  J.u.resize(3 * N);
+  const void *f = B->h_lats[J.slot].buf[0];
+  for (size_t n0 = 0; n0 < N; n0 += kStageNodes) {
+    const size_t cnt = std::min(kStageNodes, N - n0);
+    double *dr = B->d_stage, *du = B->d_stage + cnt;
+    LBM_BHIP(lbm::launch_moments(J.spec.storage, f, N, n0, cnt, dr, du, nullptr, 1024, B->stream), "moments");
+    LBM_BHIP(hipMemcpyAsync(J.rho.data() + n0, dr, cnt * sizeof(double), hipMemcpyDeviceToHost, B->stream), "copy");
+    for (int a = 0; a < 3; ++a)
+      LBM_BHIP(hipMemcpyAsync(J.u.data() + a * N + n0, du + a * cnt, cnt * sizeof(double), hipMemcpyDeviceToHost,
+                              B->stream),
+               "copy");
+    LBM_BHIP(hipStreamSynchronize(B->stream), "moments");
+  }
+  B->pool.release(J.off, J.bytes);
+  B->slot_job[J.slot] = -1;
+  std::memset(&B->h_lats[J.slot], 0, sizeof(lbm::BatchLat));
+  J.slot = -1;
+  J.state = LBM_JOB_DONE;
+  B->tiles_dirty = true;
+  return LBM_OK;
+}
+
+// Admit queued jobs in arrival order while memory and slots allow.  A job may
+// pass the head of the queue only while the head has waited fewer than four
+// chunks, so large jobs are not starved by a stream of small ones.
+lbm_status admit(lbm_batch *B) {
+  bool head_blocked = false;
+  for (auto it = B->queue.begin(); it != B->queue.end();) {
+    Job &J = B->jobs[*it];
+    int slot = -1;
+    for (int s = 0; s < B->max_jobs; ++s)
+      if (B->slot_job[s] < 0) {
+        slot = s;
+        break;
+      }
+    size_t off = 0;
+    if (slot < 0 || !B->pool.alloc(J.bytes, &off)) {
+      if (it == B->queue.begin()) {
+        ++J.waited;
+        head_blocked = J.waited >= 4;
+      }
+      if (head_blocked || slot < 0) break;
+      ++it;
+      continue;
+    }
+    const size_t N = size_t(J.spec.nx) * J.spec.ny * J.spec.nz;
+    const size_t pop_bytes = align_up(19 * N * lbm_element_bytes(J.spec.storage));
+    lbm::BatchLat L;
+    std::memset(&L, 0, sizeof(L));
+    L.buf[0] = B->pool_base + off;
+    L.buf[1] = B->pool_base + off + pop_bytes;
+    L.snap = reinterpret_cast<float *>(B->pool_base + off + 2 * pop_bytes);
+    L.nx = unsigned(J.spec.nx);
+    L.ny = unsigned(J.spec.ny);
+    L.nz = unsigned(J.spec.nz);
+    L.N = unsigned(N);
+    L.bc_mask = J.spec.bc_mask;
+    L.omega = 1.0 / J.spec.tau;
+    std::memcpy(L.v, J.spec.bc_velocity, sizeof(L.v));
+    L.inv_uref = 1.0 / J.spec.u_ref;
+    B->h_lats[slot] = L;
+    B->slot_job[slot] = *it;
+    const double zero[3] = {0.0, 0.0, 0.0};
+    LBM_BHIP(lbm::launch_init(J.spec.storage, L.buf[0], N, J.spec.rho0, zero, B->stream), "init launch");
+    const size_t n3 = 3 * N;
+    lbm::fill_float_kernel<<<dim3(unsigned((n3 + 255) / 256)), dim3(256), 0, B->stream>>>(L.snap, n3, 0.0f);
+    LBM_BHIP(hipGetLastError(), "snapshot fill");
+    J.off = off;
+    J.slot = slot;
+    J.state = LBM_JOB_RUNNING;
+    B->tiles_dirty = true;
+    it = B->queue.erase(it);
+  }
+  return LBM_OK;
+}
+
+int count_active(const lbm_batch *B) {
+  int n = 0;
+  for (int id : B->slot_job) n += id >= 0;
+  return n;
+}
+
+long long tune_key(const lbm_batch *B) {
+  size_t nodes = 0;
+  for (int id : B->slot_job)
+    if (id >= 0) {
+      const Job &J = B->jobs.at(id);
+      nodes += size_t(J.spec.nx) * J.spec.ny * J.spec.nz;
+    }
+  int lg = 0;
+  while ((size_t(1) << lg) < nodes) ++lg;
+  return (long long)present_mask(B) | ((long long)lg << 4);
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_job_bytes(const lbm_job *job, size_t *bytes) {
+  if (!job || !bytes) return bfail(LBM_ERR_ARG, "NULL argument");
+  if (lbm_element_bytes(job->storage) == 0) return bfail(LBM_ERR_ARG, "invalid storage");
+  *bytes = job_bytes(*job);
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_create(size_t hbm_budget_bytes, int chunk_steps, int max_jobs, void *hip_stream,
+                            lbm_batch **out) {
+  if (!out) return bfail(LBM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (chunk_steps < 2 || chunk_steps % 2) return bfail(LBM_ERR_ARG, "chunk_steps must be even and >= 2");
+  if (max_jobs < 1 || max_jobs > 65536) return bfail(LBM_ERR_ARG, "max_jobs must be in [1, 65536]");
+  if (hbm_budget_bytes < (size_t(1) << 20)) return bfail(LBM_ERR_ARG, "HBM budget below 1 MiB");
+  lbm_batch *B = new (std::nothrow) lbm_batch();
+  if (!B) return bfail(LBM_ERR_OOM, "host allocation failed");
+  B->chunk_steps = chunk_steps;
+  B->max_jobs = max_jobs;
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    B->num_cu = prop.multiProcessorCount;
+  if (hip_stream) {
+    B->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    // Graph capture needs a stream other than the null stream.
+    if (hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete B;
+      return bfail(LBM_ERR_HIP, "stream creation failed");
+    }
+    B->own_stream = true;
+  }
+  const size_t cap = hbm_budget_bytes / kAlign * kAlign;
+  hipError_t e = hipMalloc(&B->pool_base, cap);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    lbm_batch_destroy(B);
+    return bfail(LBM_ERR_OOM, "hipMalloc of the %zu-byte pool failed: %s", cap, hipGetErrorString(e));
+  }
+  B->pool.reset(cap);
+  // Tile capacity: the most nodes the pool can hold (88 B per FP16 node),
+  // cut into the smallest tiles, plus one partial tile per job.
+  B->tile_cap = cap / 88 / kMinTileNodes + size_t(max_jobs) + 1;
+  B->slot_job.assign(max_jobs, -1);
+  B->h_lats.assign(max_jobs, lbm::BatchLat());
+  std::memset(B->h_lats.data(), 0, B->h_lats.size() * sizeof(lbm::BatchLat));
+  B->h_delta.assign(max_jobs, 0u);
+  bool ok = hipMalloc(&B->d_lats, sizeof(lbm::BatchLat) * max_jobs) == hipSuccess &&
+            hipMalloc(&B->d_ntiles, sizeof(int) * kNumStorage) == hipSuccess &&
+            hipMalloc(&B->d_delta, sizeof(unsigned) * max_jobs) == hipSuccess;
+  for (int s = 0; s < kNumStorage && ok; ++s)
+    ok = hipMalloc(&B->d_tiles[s], sizeof(lbm::BatchTile) * B->tile_cap) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    lbm_batch_destroy(B);
+    return bfail(LBM_ERR_OOM, "device tables could not be allocated");
+  }
+  *out = B;
+  return LBM_OK;
+}
+
+void lbm_batch_destroy(lbm_batch *B) {
+  if (!B) return;
+  if (B->stream) (void)hipStreamSynchronize(B->stream);
+  drop_graphs(B);
+  if (B->pool_base) (void)hipFree(B->pool_base);
+  if (B->d_lats) (void)hipFree(B->d_lats);
+  for (int s = 0; s < kNumStorage; ++s)
+    if (B->d_tiles[s]) (void)hipFree(B->d_tiles[s]);
+  if (B->d_ntiles) (void)hipFree(B->d_ntiles);
+  if (B->d_delta) (void)hipFree(B->d_delta);
+  if (B->d_stage) (void)hipFree(B->d_stage);
+  if (B->own_stream) (void)hipStreamDestroy(B->stream);
+  delete B;
+}
+
+lbm_status lbm_batch_submit(lbm_batch *B, const lbm_job *job, int *job_id) {
+  if (!B || !job || !job_id) return bfail(LBM_ERR_ARG, "NULL argument");
+  const lbm_job &j = *job;
+  if (j.nx < 1 || j.ny < 1 || j.nz < 1) return bfail(LBM_ERR_ARG, "lattice sizes must be >= 1");
+  if (double(j.nx) * j.ny * j.nz >= 2147483648.0) return bfail(LBM_ERR_ARG, "at most 2^31 - 1 nodes");
+  if (!(j.tau > 0.5)) return bfail(LBM_ERR_ARG, "tau must be > 1/2");
+  if (!(j.rho0 > 0.0)) return bfail(LBM_ERR_ARG, "rho0 must be > 0");
+  if (lbm_element_bytes(j.storage) == 0) return bfail(LBM_ERR_ARG, "invalid storage");
+  if (!(j.u_ref > 0.0)) return bfail(LBM_ERR_ARG, "u_ref must be > 0");
+  if (j.max_steps < 0) return bfail(LBM_ERR_ARG, "max_steps must be >= 0");
+  if (j.bc_mask & ~63u) return bfail(LBM_ERR_ARG, "bc_mask has bits beyond the six faces");
+  const int size[3] = {j.nx, j.ny, j.nz};
+  static const int nrm[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+  for (int a = 0; a < 3; ++a) {
+    const unsigned bits = (j.bc_mask >> (2 * a)) & 3u;
+    if (bits == 1u || bits == 2u) return bfail(LBM_ERR_ARG, "axis %d has a velocity BC on one face only", a);
+    if (bits && size[a] < 3) return bfail(LBM_ERR_ARG, "a bounded axis needs at least 3 nodes");
+  }
+  for (int f = 0; f < 6; ++f) {
+    if (!((j.bc_mask >> f) & 1u)) continue;
+    const double *u = j.bc_velocity[f];
+    const double un = u[0] * nrm[f][0] + u[1] * nrm[f][1] + u[2] * nrm[f][2];
+    if (!(std::fabs(un) < 1.0) || !(u[0] * u[0] + u[1] * u[1] + u[2] * u[2] < 1.0 / 3.0))
+      return bfail(LBM_ERR_ARG, "face %d velocity out of range (|u.n| < 1 and |u| < 1/sqrt(3) required)", f);
+  }
+  Job J;
+  J.spec = j;
+  J.bytes = job_bytes(j);
+  if (J.bytes > B->pool.capacity())
+    return bfail(LBM_ERR_OOM, "job needs %zu bytes, more than the whole budget (%zu)", J.bytes, B->pool.capacity());
+  const int id = B->next_id++;
+  B->jobs.emplace(id, std::move(J));
+  B->queue.push_back(id);
+  *job_id = id;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_run_chunk(lbm_batch *B, int *n_active, int *n_queued) {
+  if (!B) return bfail(LBM_ERR_ARG, "NULL handle");
+  lbm_status st = admit(B);
+  if (st != LBM_OK) return st;
+  const int active = count_active(B);
+  if (active > 0) {
+    if (B->tiles_dirty) {
+      st = rebuild_tiles(B);
+      if (st != LBM_OK) return st;
+    }
+    st = run_graph_chunk(B);
+    if (st != LBM_OK) return st;
+    LBM_BHIP(hipMemsetAsync(B->d_delta, 0, sizeof(unsigned) * B->max_jobs, B->stream), "reset deltas");
+    for (int s = 0; s < kNumStorage; ++s)
+      if (B->h_ntiles[s] > 0)
+        LBM_BHIP(lbm::launch_batch_delta(s, B->d_lats, B->d_tiles[s], B->d_ntiles + s, B->d_delta, 4 * B->num_cu,
+                                         B->stream),
+                 "delta launch");
+    LBM_BHIP(hipMemcpyAsync(B->h_delta.data(), B->d_delta, sizeof(unsigned) * B->max_jobs, hipMemcpyDeviceToHost,
+                            B->stream),
+             "copy deltas");
+    LBM_BHIP(hipStreamSynchronize(B->stream), "chunk");
+    for (int slot = 0; slot < B->max_jobs; ++slot) {
+      const int id = B->slot_job[slot];
+      if (id < 0) continue;
+      Job &J = B->jobs[id];
+      J.steps += B->chunk_steps;
+      float d;
+      std::memcpy(&d, &B->h_delta[slot], sizeof(d));
+      J.delta = d;
+      const bool conv = J.spec.tol > 0.0 && J.delta < J.spec.tol;
+      if (conv || J.steps >= J.spec.max_steps) {
+        J.converged = conv ? 1 : 0;
+        st = retire(B, id);
+        if (st != LBM_OK) return st;
+      }
+    }
+  }
+  if (n_active) *n_active = count_active(B);
+  if (n_queued) *n_queued = int(B->queue.size());
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_poll(lbm_batch *B, int job_id, lbm_job_status *st) {
+  if (!B || !st) return bfail(LBM_ERR_ARG, "NULL argument");
+  auto it = B->jobs.find(job_id);
+  if (it == B->jobs.end()) return bfail(LBM_ERR_ARG, "unknown job %d", job_id);
+  st->state = it->second.state;
+  st->steps = it->second.steps;
+  st->delta = it->second.delta;
+  st->converged = it->second.converged;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_result(lbm_batch *B, int job_id, double *rho, double *u) {
+  if (!B) return bfail(LBM_ERR_ARG, "NULL handle");
+  auto it = B->jobs.find(job_id);
+  if (it == B->jobs.end()) return bfail(LBM_ERR_ARG, "unknown job %d", job_id);
+  if (it->second.state != LBM_JOB_DONE) return bfail(LBM_ERR_STATE, "job %d is not finished", job_id);
+  if (rho) std::memcpy(rho, it->second.rho.data(), it->second.rho.size() * sizeof(double));
+  if (u) std::memcpy(u, it->second.u.data(), it->second.u.size() * sizeof(double));
+  B->jobs.erase(it);
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_set_shape(lbm_batch *B, int block_x, int tile_nodes, int grid_blocks) {
+  if (!B) return bfail(LBM_ERR_ARG, "NULL handle");
+  if (block_x != 128 && block_x != 256) return bfail(LBM_ERR_ARG, "block_x must be 128 or 256");
+  if (tile_nodes < kMinTileNodes) return bfail(LBM_ERR_ARG, "tile_nodes must be >= %d", kMinTileNodes);
+  if (grid_blocks < 0 || grid_blocks > (1 << 20)) return bfail(LBM_ERR_ARG, "grid_blocks out of range");
+  if (B->shape.tile_nodes != tile_nodes) B->tiles_dirty = true;
+  if (B->shape.block_x != block_x || B->shape.grid != grid_blocks) drop_graphs(B);
+  B->shape.block_x = block_x;
+  B->shape.tile_nodes = tile_nodes;
+  B->shape.grid = grid_blocks;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_get_shape(const lbm_batch *B, int *block_x, int *tile_nodes, int *grid_blocks) {
+  if (!B || !block_x || !tile_nodes || !grid_blocks) return bfail(LBM_ERR_ARG, "NULL argument");
+  *block_x = B->shape.block_x;
+  *tile_nodes = B->shape.tile_nodes;
+  *grid_blocks = grid_of(B);
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_autotune(lbm_batch *B, int trial_steps, int *block_x, int *tile_nodes, int *grid_blocks) {
+  if (!B) return bfail(LBM_ERR_ARG, "NULL handle");
+  if (trial_steps < 2 || trial_steps % 2) return bfail(LBM_ERR_ARG, "trial_steps must be even and >= 2");
+  lbm_status st = admit(B);
+  if (st != LBM_OK) return st;
+  if (count_active(B) == 0) return bfail(LBM_ERR_STATE, "no resident job to tune on");
+  const long long key = tune_key(B);
+  auto cached = g_tuned.find(key);
+  if (cached != g_tuned.end()) {
+    st = lbm_batch_set_shape(B, cached->second.block_x, cached->second.tile_nodes, cached->second.grid);
+  } else {
+    // Every trial step is a real step of every resident lattice (results do
+    // not depend on the launch shape); the step counters advance with them.
+    hipEvent_t e0, e1;
+    LBM_BHIP(hipEventCreate(&e0), "event");
+    LBM_BHIP(hipEventCreate(&e1), "event");
+    Shape best;
+    float best_ms = INFINITY;
+    int steps_taken = 0;
+    for (int bx : {128, 256})
+      for (int tn : {1024, 4096, 16384})
+        for (int gm : {4, 8, 16}) {
+          st = lbm_batch_set_shape(B, bx, tn, gm * B->num_cu);
+          if (st == LBM_OK && B->tiles_dirty) st = rebuild_tiles(B);
+          if (st == LBM_OK) st = launch_steps(B, 2, 0);  // warm-up, even step count
+          hipError_t e = hipEventRecord(e0, B->stream);
+          if (st == LBM_OK && e == hipSuccess) st = launch_steps(B, trial_steps, 0);
+          e = e == hipSuccess ? hipEventRecord(e1, B->stream) : e;
+          e = e == hipSuccess ? hipEventSynchronize(e1) : e;
+          float ms = 0.f;
+          e = e == hipSuccess ? hipEventElapsedTime(&ms, e0, e1) : e;
+          if (st != LBM_OK || e != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return st != LBM_OK ? st : bfail(LBM_ERR_HIP, "autotune timing: %s", hipGetErrorString(e));
+          }
+          steps_taken += 2 + trial_steps;
+          if (ms < best_ms) {
+            best_ms = ms;
+            best = B->shape;
+          }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (int id : B->slot_job)
+      if (id >= 0) B->jobs[id].steps += steps_taken;
+    g_tuned[key] = best;
+    st = lbm_batch_set_shape(B, best.block_x, best.tile_nodes, best.grid);
+  }
+  if (st != LBM_OK) return st;
+  if (B->tiles_dirty) {
+    st = rebuild_tiles(B);
+    if (st != LBM_OK) return st;
+  }
+  if (block_x) *block_x = B->shape.block_x;
+  if (tile_nodes) *tile_nodes = B->shape.tile_nodes;
+  if (grid_blocks) *grid_blocks = grid_of(B);
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_memory(const lbm_batch *B, size_t *used, size_t *capacity) {
+  if (!B || !used || !capacity) return bfail(LBM_ERR_ARG, "NULL argument");
+  *used = B->pool.used();
+  *capacity = B->pool.capacity();
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -15,13 +15,19 @@ namespace {
 
 thread_local char g_err[512] = "";
 
-lbm_status fail(lbm_status st, const char *fmt, ...) {
+}  // namespace
+
+lbm_status lbm::set_error(lbm_status st, const char *fmt, ...) {
   va_list ap;
   va_start(ap, fmt);
   std::vsnprintf(g_err, sizeof(g_err), fmt, ap);
   va_end(ap);
   return st;
 }
+
+namespace {
+
+#define fail lbm::set_error
 
 lbm_status hip_fail(hipError_t e, const char *what) {
   return fail(LBM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));

@@ -6,9 +6,14 @@
 
 #include <cstddef>
 
+#include "../../include/lbm.h"
 #include "d3q19.hpp"
 
 namespace lbm {
+
+// Record a printf-style message for lbm_last_error() on this thread and
+// return st.
+lbm_status set_error(lbm_status st, const char *fmt, ...);
 
 enum { kStoreF64 = 0, kStoreF32 = 1, kStoreF16 = 2 };
 

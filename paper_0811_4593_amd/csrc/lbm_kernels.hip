@@ -13,122 +13,31 @@
 
 #include "d3q19.hpp"
 #include "lbm_internal.hpp"
+#include "node_update.hpp"
 
 namespace lbm {
 
 // ---------------------------------------------------------------------------
-// Storage codecs: population element type S, arithmetic type T.  The stored
-// quantity is the deviation d_k = f_k - w_k from the rest state (w_k: lattice
-// weight); the FP16 form stores it scaled, h = RNE(d * 2^8), d = h * 2^-8
-// (exact scaling).
-// ---------------------------------------------------------------------------
-template <class S>
-struct Codec;
-
-template <>
-struct Codec<double> {
-  using T = double;
-  static __device__ __forceinline__ T decode(double s) { return s; }
-  static __device__ __forceinline__ double encode(T v) { return v; }
-};
-
-// FP32 storage is updated in double: the per-step rounding of the arithmetic
-// then stays below the rounding of the stored deviations, so the steady state
-// of the FP32 form is set by its storage alone.  On gfx950 a double FMA costs
-// the same issue slot as an unpacked float FMA and the sweep is HBM-bound.
-template <>
-struct Codec<float> {
-  using T = double;
-  static __device__ __forceinline__ T decode(float s) { return double(s); }
-  static __device__ __forceinline__ float encode(T v) { return float(v); }
-};
-
-template <>
-struct Codec<_Float16> {
-  using T = float;
-  static __device__ __forceinline__ T decode(_Float16 s) { return static_cast<float>(s) * 0.00390625f; }
-  static __device__ __forceinline__ _Float16 encode(T v) { return static_cast<_Float16>(v * 256.0f); }
-};
-
-template <class S, bool NT>
-__device__ __forceinline__ void store_elem(S *p, S v) {
-  if constexpr (NT)
-    __builtin_nontemporal_store(v, p);
-  else
-    *p = v;
-}
-
-// Logical block index.  The dispatcher hands workgroups to the 8 XCDs
-// round-robin (workgroup b runs on XCD b % 8); with the remap, logical blocks
-// [q*i, q*(i+1)) all run on XCD i, so neighbouring x-rows share one L2.
-__device__ __forceinline__ unsigned logical_block(unsigned b, unsigned nblocks, int remap) {
-  if (!remap) return b;
-  const unsigned q = nblocks >> 3;
-  if (b >= (q << 3)) return b;
-  return (b & 7u) * q + (b >> 3);
-}
-
-// ---------------------------------------------------------------------------
-// The fused sweep.  One block handles BX*NPT consecutive nodes of one x-row;
-// thread t handles x = x0 + j*BX + t, j < NPT (coalesced 64-lane accesses).
-// y and z are uniform over the block, so the row offsets of the 9 source rows
-// live in scalar registers and each load is "scalar base + lane offset".
-// COPY: streaming only (no boundary rule, no collision, raw elements) -- the
-// bandwidth ceiling of this access pattern.
+// The fused sweep over one lattice.  One block handles BX*NPT consecutive
+// nodes of one x-row; thread t handles x = x0 + j*BX + t, j < NPT (coalesced
+// 64-lane accesses).  y and z are uniform over the block, so the row offsets
+// of the nine source rows are scalar and each load is "scalar base + lane
+// offset".  COPY: streaming only (no boundary rule, no collision, raw
+// elements) -- the bandwidth ceiling of this access pattern.
 // ---------------------------------------------------------------------------
 template <class S, int BX, int NPT, bool NT, bool COPY>
 __global__ __launch_bounds__(BX) void sweep_kernel(const S *__restrict__ src, S *__restrict__ dst,
                                                    SweepArgs<typename Codec<S>::T> a) {
-  using T = typename Codec<S>::T;
   const unsigned b = logical_block(blockIdx.x, gridDim.x, a.xcd_remap);
   const unsigned row = a.nxc == 1 ? b : b / unsigned(a.nxc);
   const int xc = int(b - row * unsigned(a.nxc));
-  const int ny = a.ny, nz = a.nz, nx = a.nx;
-  const int y = int(row % unsigned(ny));
-  const int z = int(row / unsigned(ny));
-  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
-  const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
-  // Row base offsets R[cy+1][cz+1] of the source row (y - cy, z - cz).
-  const unsigned unx = unsigned(nx), uny = unsigned(ny);
-  const unsigned yy[3] = {unsigned(yp), unsigned(y), unsigned(ym)};  // index cy+1 -> y - cy
-  const unsigned zz[3] = {unsigned(zp), unsigned(z), unsigned(zm)};
-  const size_t N = a.N;
-
-  // Boundary bits that depend on y and z only (uniform over the block).
-  unsigned m_yz = 0;
-  if (y == 0) m_yz |= a.bc_mask & 4u;
-  if (y == ny - 1) m_yz |= a.bc_mask & 8u;
-  if (z == 0) m_yz |= a.bc_mask & 16u;
-  if (z == nz - 1) m_yz |= a.bc_mask & 32u;
-
+  const NodeGeom g{unsigned(a.nx), unsigned(a.ny), unsigned(a.nz), a.N};
+  const int y = int(row % g.ny);
+  const int z = int(row / g.ny);
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
     const int x = (xc * NPT + j) * BX + int(threadIdx.x);
-    if (x < nx) {
-      const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-      const unsigned xs[3] = {unsigned(xp), unsigned(x), unsigned(xm)};  // index cx+1 -> x - cx
-      T f[19];
-      S raw[19];
-#pragma unroll
-      for (int k = 0; k < 19; ++k) {
-        const unsigned off = (yy[cy(k) + 1] + uny * zz[cz(k) + 1]) * unx + xs[cx(k) + 1];
-        raw[k] = src[size_t(k) * N + off];
-      }
-      if constexpr (!COPY) {
-#pragma unroll
-        for (int k = 0; k < 19; ++k) f[k] = Codec<S>::decode(raw[k]);
-        unsigned m = m_yz;
-        if (x == 0) m |= a.bc_mask & 1u;
-        if (x == nx - 1) m |= a.bc_mask & 2u;
-        if (m) boundary_rule<T>(f, m, a.fv);
-        bgk_collide<T>(f, a.omega);
-#pragma unroll
-        for (int k = 0; k < 19; ++k) raw[k] = Codec<S>::encode(f[k]);
-      }
-      const size_t n = size_t(row) * unx + unsigned(x);
-#pragma unroll
-      for (int k = 0; k < 19; ++k) store_elem<S, NT>(dst + size_t(k) * N + n, raw[k]);
-    }
+    if (x < a.nx) update_node<S, NT, COPY>(src, dst, g, x, y, z, a.bc_mask, a.omega, a.fv);
   }
 }
 

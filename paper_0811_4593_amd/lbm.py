@@ -31,7 +31,27 @@ EXPORTS = (
     "lbm_moments", "lbm_totals", "lbm_get_populations", "lbm_set_populations", "lbm_state_buffer",
     "lbm_element_bytes", "lbm_set_launch", "lbm_get_launch", "lbm_probe", "lbm_destroy",
     "lbm_last_error",
+    "lbm_job_bytes", "lbm_batch_create", "lbm_batch_submit", "lbm_batch_run_chunk", "lbm_batch_poll",
+    "lbm_batch_result", "lbm_batch_set_shape", "lbm_batch_get_shape", "lbm_batch_autotune",
+    "lbm_batch_memory", "lbm_batch_destroy",
 )
+
+LBM_JOB_QUEUED, LBM_JOB_RUNNING, LBM_JOB_DONE = 0, 1, 2
+
+
+class LbmJob(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("tau", ctypes.c_double), ("rho0", ctypes.c_double),
+        ("storage", ctypes.c_int), ("bc_mask", ctypes.c_uint),
+        ("bc_velocity", (ctypes.c_double * 3) * 6),
+        ("u_ref", ctypes.c_double), ("tol", ctypes.c_double), ("max_steps", ctypes.c_int),
+    ]
+
+
+class LbmJobStatus(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int), ("steps", ctypes.c_int), ("delta", ctypes.c_double),
+                ("converged", ctypes.c_int)]
 
 
 class LBMError(RuntimeError):
@@ -76,8 +96,22 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_destroy.restype = None
     lib.lbm_last_error.argtypes = []
     lib.lbm_last_error.restype = ctypes.c_char_p
+    ip = ctypes.POINTER(ctypes.c_int)
+    szp = ctypes.POINTER(ctypes.c_size_t)
+    lib.lbm_job_bytes.argtypes = [ctypes.POINTER(LbmJob), szp]
+    lib.lbm_batch_create.argtypes = [ctypes.c_size_t, st, st, _vp, ctypes.POINTER(_vp)]
+    lib.lbm_batch_submit.argtypes = [_vp, ctypes.POINTER(LbmJob), ip]
+    lib.lbm_batch_run_chunk.argtypes = [_vp, ip, ip]
+    lib.lbm_batch_poll.argtypes = [_vp, st, ctypes.POINTER(LbmJobStatus)]
+    lib.lbm_batch_result.argtypes = [_vp, st, _vp, _vp]
+    lib.lbm_batch_set_shape.argtypes = [_vp, st, st, st]
+    lib.lbm_batch_get_shape.argtypes = [_vp, ip, ip, ip]
+    lib.lbm_batch_autotune.argtypes = [_vp, st, ip, ip, ip]
+    lib.lbm_batch_memory.argtypes = [_vp, szp, szp]
+    lib.lbm_batch_destroy.argtypes = [_vp]
+    lib.lbm_batch_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("lbm_element_bytes", "lbm_destroy", "lbm_last_error"):
+        if name not in ("lbm_element_bytes", "lbm_destroy", "lbm_last_error", "lbm_batch_destroy"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -202,6 +236,91 @@ def lbm_probe(h, kind: int, nrep: int = 1):
 def lbm_destroy(h):
     if h:
         load_library().lbm_destroy(h)
+
+
+def make_job(nx, ny, nz, tau, bc, storage=LBM_STORE_F32, rho0=1.0, u_ref=None, tol=0.0, max_steps=0) -> LbmJob:
+    """An lbm_job from a face -> velocity mapping; u_ref defaults to the
+    largest prescribed speed (or 1 when every face is at rest)."""
+    j = LbmJob()
+    j.nx, j.ny, j.nz = int(nx), int(ny), int(nz)
+    j.tau, j.rho0, j.storage = float(tau), float(rho0), int(storage)
+    mask = 0
+    vmax = 0.0
+    for face, v in bc.items():
+        mask |= 1 << int(face)
+        for a in range(3):
+            j.bc_velocity[int(face)][a] = float(v[a])
+        vmax = max(vmax, float(np.linalg.norm(np.asarray(v, dtype=float))))
+    j.bc_mask = mask
+    j.u_ref = float(u_ref) if u_ref is not None else (vmax if vmax > 0 else 1.0)
+    j.tol, j.max_steps = float(tol), int(max_steps)
+    return j
+
+
+def lbm_job_bytes(job: LbmJob) -> int:
+    b = ctypes.c_size_t()
+    _check(load_library().lbm_job_bytes(ctypes.byref(job), ctypes.byref(b)))
+    return b.value
+
+
+def lbm_batch_create(hbm_budget_bytes: int, chunk_steps: int = 100, max_jobs: int = 1024, stream=None) -> int:
+    h = _vp()
+    _check(load_library().lbm_batch_create(int(hbm_budget_bytes), int(chunk_steps), int(max_jobs),
+                                           _stream(stream), ctypes.byref(h)))
+    return h.value
+
+
+def lbm_batch_submit(b, job: LbmJob) -> int:
+    i = ctypes.c_int()
+    _check(load_library().lbm_batch_submit(b, ctypes.byref(job), ctypes.byref(i)))
+    return i.value
+
+
+def lbm_batch_run_chunk(b):
+    a, q = ctypes.c_int(), ctypes.c_int()
+    _check(load_library().lbm_batch_run_chunk(b, ctypes.byref(a), ctypes.byref(q)))
+    return a.value, q.value
+
+
+def lbm_batch_poll(b, job_id: int) -> LbmJobStatus:
+    st = LbmJobStatus()
+    _check(load_library().lbm_batch_poll(b, int(job_id), ctypes.byref(st)))
+    return st
+
+
+def lbm_batch_result(b, job_id: int, nodes: int):
+    rho = np.empty(nodes)
+    u = np.empty(3 * nodes)
+    _check(load_library().lbm_batch_result(b, int(job_id), rho.ctypes.data, u.ctypes.data))
+    return rho, u
+
+
+def lbm_batch_set_shape(b, block_x: int, tile_nodes: int, grid_blocks: int = 0):
+    _check(load_library().lbm_batch_set_shape(b, int(block_x), int(tile_nodes), int(grid_blocks)))
+
+
+def lbm_batch_get_shape(b):
+    x, t, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load_library().lbm_batch_get_shape(b, ctypes.byref(x), ctypes.byref(t), ctypes.byref(g)))
+    return x.value, t.value, g.value
+
+
+def lbm_batch_autotune(b, trial_steps: int = 4):
+    x, t, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load_library().lbm_batch_autotune(b, int(trial_steps), ctypes.byref(x), ctypes.byref(t),
+                                             ctypes.byref(g)))
+    return x.value, t.value, g.value
+
+
+def lbm_batch_memory(b):
+    u, c = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(load_library().lbm_batch_memory(b, ctypes.byref(u), ctypes.byref(c)))
+    return u.value, c.value
+
+
+def lbm_batch_destroy(b):
+    if b:
+        load_library().lbm_batch_destroy(b)
 
 
 class Lattice:

@@ -1,0 +1,200 @@
+"""GPU tests of the batch runtime (multi-lattice sweep, admission by HBM
+budget, graph-captured chunks, convergence stop, autotuner) and of the FP16
+storage form.
+
+Bar: a lattice advanced in a batch is bit-identical to the same lattice
+advanced alone with lbm_step (same per-node update), whatever else is in the
+batch; the FP16 and batched forms stay within 1e-3 relative L2 of the FP64
+velocity field.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+from paper_0811_4593_amd import lbm, serving, workloads  # noqa: E402
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+MIX = [
+    (workloads.duct(37, 12, 9, (0.04, 0.01, 0.01), 0.8), "f32"),
+    (workloads.duct(16, 16, 16, (0.03, -0.02, 0.01), 1.3), "f16dev"),
+    (workloads.couette(8, 4, 20, 0.05, 1.0), "f32"),
+    (workloads.duct(70, 9, 5, (0.02, 0.01, -0.015), 0.65), "f16dev"),
+    (workloads.all_classes_lattices()[2], "f32"),
+    (workloads.duct(21, 11, 13, (0.01, 0.0, 0.02), 1.0), "f64"),
+]
+
+
+def _submit_all(b, items, steps):
+    return [lbm.lbm_batch_submit(b, serving.job_for(s, st, 0.0, steps)) for s, st in items]
+
+
+def test_batch_equals_alone_bitwise():
+    steps = 40
+    b = lbm.lbm_batch_create(4 << 30, 10, 16)
+    try:
+        ids = _submit_all(b, MIX, steps)
+        rounds = 0
+        while True:
+            active, queued = lbm.lbm_batch_run_chunk(b)
+            rounds += 1
+            if active == 0 and queued == 0:
+                break
+        assert rounds == steps // 10
+        for jid, (spec, st) in zip(ids, MIX):
+            s = lbm.lbm_batch_poll(b, jid)
+            assert s.state == lbm.LBM_JOB_DONE and s.steps == steps
+            rho_b, u_b = lbm.lbm_batch_result(b, jid, spec.nodes)
+            _, rho_p, u_p = serving.run_plain(spec, st, steps)
+            say(f"{spec.name} {st}: max |du| {np.abs(u_b - u_p).max():.1e}")
+            np.testing.assert_array_equal(rho_b, rho_p)
+            np.testing.assert_array_equal(u_b, u_p)
+    finally:
+        lbm.lbm_batch_destroy(b)
+
+
+def test_batch_fp64_job_matches_oracle():
+    spec = workloads.duct(14, 9, 7, (0.04, 0.01, 0.01), 0.8)
+    steps = 30
+    b = lbm.lbm_batch_create(1 << 30, 6, 4)
+    try:
+        jid = lbm.lbm_batch_submit(b, serving.job_for(spec, "f64", 0.0, steps))
+        while lbm.lbm_batch_run_chunk(b) != (0, 0):
+            pass
+        rho, u = lbm.lbm_batch_result(b, jid, spec.nodes)
+    finally:
+        lbm.lbm_batch_destroy(b)
+    L = oracle.Lattice(spec.nx, spec.ny, spec.nz, spec.tau, bc=spec.bc)
+    r_ref, u_ref = L.moments(L.run(L.init(), steps))
+    np.testing.assert_allclose(rho, r_ref.ravel(), rtol=1e-12)
+    np.testing.assert_allclose(u, u_ref.ravel(), rtol=0, atol=1e-13)
+
+
+def test_admission_respects_budget_and_results_unchanged():
+    items = [(workloads.duct(40, 20, 20, (0.03, 0.01, 0.0), 0.9), "f32") for _ in range(5)]
+    job_bytes = lbm.lbm_job_bytes(serving.job_for(items[0][0], "f32", 0.0, 20))
+    budget = 2 * job_bytes + job_bytes // 2  # room for two jobs at a time
+    b = lbm.lbm_batch_create(budget, 10, 8)
+    try:
+        ids = _submit_all(b, items, 20)
+        peak = 0
+        while True:
+            active, queued = lbm.lbm_batch_run_chunk(b)
+            used, cap = lbm.lbm_batch_memory(b)
+            assert used <= cap
+            peak = max(peak, active)
+            if active == 0 and queued == 0:
+                break
+        assert peak <= 2
+        _, _, u_p = serving.run_plain(items[0][0], "f32", 20)
+        for jid in ids:
+            _, u = lbm.lbm_batch_result(b, jid, items[0][0].nodes)
+            np.testing.assert_array_equal(u, u_p)
+    finally:
+        lbm.lbm_batch_destroy(b)
+
+
+def test_job_too_large_and_invalid_jobs_rejected():
+    b = lbm.lbm_batch_create(8 << 20, 10, 4)
+    try:
+        big = serving.job_for(workloads.duct(128, 64, 64), "f32", 0.0, 10)
+        with pytest.raises(lbm.LBMError) as e:
+            lbm.lbm_batch_submit(b, big)
+        assert e.value.status == lbm.LBM_ERR_OOM
+        bad = serving.job_for(workloads.duct(10, 8, 8), "f32", 0.0, 10)
+        bad.tau = 0.5
+        with pytest.raises(lbm.LBMError):
+            lbm.lbm_batch_submit(b, bad)
+        one_face = lbm.make_job(10, 8, 8, 0.8, {4: (0, 0, 0)})
+        with pytest.raises(lbm.LBMError):
+            lbm.lbm_batch_submit(b, one_face)
+        with pytest.raises(lbm.LBMError) as e:
+            lbm.lbm_batch_result(b, 12345, 10)
+        assert e.value.status == lbm.LBM_ERR_ARG
+    finally:
+        lbm.lbm_batch_destroy(b)
+
+
+def test_convergence_stop_is_deterministic_and_matches_alone():
+    spec = workloads.duct(20, 10, 10, (0.04, 0.01, 0.01), 0.8)
+    out = []
+    for companions in (0, 3):
+        b = lbm.lbm_batch_create(2 << 30, 50, 8)
+        try:
+            jid = lbm.lbm_batch_submit(b, serving.job_for(spec, "f32", 1e-6, 20000))
+            for i in range(companions):
+                lbm.lbm_batch_submit(b, serving.job_for(workloads.duct(30 + i, 12, 10), "f16dev", 0.0, 400))
+            while lbm.lbm_batch_run_chunk(b)[0] > 0:
+                pass
+            st = lbm.lbm_batch_poll(b, jid)
+            rho, u = lbm.lbm_batch_result(b, jid, spec.nodes)
+            out.append((st.steps, st.converged, st.delta, u))
+        finally:
+            lbm.lbm_batch_destroy(b)
+    (s0, c0, d0, u0), (s1, c1, d1, u1) = out
+    say(f"stopped at step {s0} (delta {d0:.2e}) alone, {s1} in the mix")
+    assert c0 == 1 and c1 == 1 and s0 == s1 and s0 < 20000 and d0 < 1e-6
+    np.testing.assert_array_equal(u0, u1)
+    # and it is the FP32 steady state: compare with the FP64 oracle
+    L = oracle.Lattice(spec.nx, spec.ny, spec.nz, spec.tau, bc=spec.bc)
+    _, u_ref = L.moments(L.run(L.init(), s0))
+    assert rel_l2(u0, u_ref.ravel()) < 1e-5
+
+
+def test_autotune_picks_a_shape_and_results_do_not_change():
+    items = MIX[:4]
+    b = lbm.lbm_batch_create(4 << 30, 10, 8)
+    try:
+        ids = _submit_all(b, items, 60)
+        shape = lbm.lbm_batch_autotune(b, 2)
+        say(f"autotuned shape {shape}")
+        assert shape[0] in (128, 256) and shape[1] in (1024, 4096, 16384)
+        while lbm.lbm_batch_run_chunk(b) != (0, 0):
+            pass
+        for jid, (spec, st) in zip(ids, items):
+            s = lbm.lbm_batch_poll(b, jid)
+            _, u_b = lbm.lbm_batch_result(b, jid, spec.nodes)
+            _, _, u_p = serving.run_plain(spec, st, s.steps)
+            np.testing.assert_array_equal(u_b, u_p)
+    finally:
+        lbm.lbm_batch_destroy(b)
+
+
+def test_fp16_and_fp32_forms_against_fp64_velocity():
+    # FP16 scaled-deviation storage with FP32 arithmetic, and FP32 storage,
+    # against the FP64 form (parity-pinned to the oracle) on a duct run until
+    # the velocity is steady: relative L2 <= 1e-3 (FP16), <= 1e-5 (FP32).
+    spec = workloads.duct(48, 24, 24, (0.04, 0.01, 0.01), 0.8)
+    steps = 4000
+    _, _, u64 = serving.run_plain(spec, "f64", steps)
+    _, _, u32 = serving.run_plain(spec, "f32", steps)
+    _, _, u16 = serving.run_plain(spec, "f16dev", steps)
+    e32, e16 = rel_l2(u32, u64), rel_l2(u16, u64)
+    say(f"rel L2 vs f64: f32 {e32:.2e}, f16dev {e16:.2e}")
+    assert e32 <= 1e-5
+    assert e16 <= 1e-3
+
+
+def test_serving_loop_small_trace_same_alone_and_in_mix():
+    trace = workloads.serving_trace(count=12, rate=40.0, seed=3, n_min=12, n_max=28)
+    rep = serving.serve_trace(trace, budget_bytes=64 << 20, chunk=50, tol=1e-6, max_steps=1500,
+                              max_jobs=4, keep_results=set(range(12)))
+    say(f"serve summary {rep.summary()}")
+    assert all(x >= 0 for x in rep.latencies)
+    assert rep.peak_resident <= 4 and rep.peak_bytes <= 64 << 20
+    for i, r in enumerate(trace):
+        _, _, u_alone = serving.run_plain(r.spec, r.storage, rep.steps[i])
+        np.testing.assert_array_equal(rep.results[i][1], u_alone)

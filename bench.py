@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 _ROOT = os.path.dirname(os.path.abspath(__file__))
 if _ROOT not in sys.path:
     sys.path.insert(0, _ROOT)
@@ -72,7 +74,8 @@ def ingest_counters(args):
 
     fetch = _counter_means(args.ingest_counters[0], "FETCH_SIZE")
     write = _counter_means(args.ingest_counters[1], "WRITE_SIZE")
-    storage = {"f32": lbm.LBM_STORE_F32, "f64": lbm.LBM_STORE_F64, "f16dev": lbm.LBM_STORE_F16_DEV}[args.storage]
+    storage = {"f32": lbm.LBM_STORE_F32, "f64": lbm.LBM_STORE_F64, "f16dev": lbm.LBM_STORE_F16_DEV,
+               "f16sr": lbm.LBM_STORE_F16_DEV_SR}[args.storage]
     N = args.nx * args.ny * args.nz
     copy_kib = 19 * N * lbm.lbm_element_bytes(storage) / 1024.0
 
@@ -137,12 +140,121 @@ def cpu_baseline(spec_full, budget_s: float):
                       f"{steps} steps in {el:.1f} s; effective {mlups * 304 / 1e3:.2f} GB/s at 304 B/node"}
 
 
+def _device_rel_l2(u, ref):
+    import torch
+    return float(torch.linalg.vector_norm(u - ref) / torch.linalg.vector_norm(ref))
+
+
+def form_precision(args):
+    """Storage precision on the 512x256x256 duct: FP16 scaled deviations (FP32
+    arithmetic) and FP32 storage against the FP64 form (the GPU FP64 path is
+    parity-pinned to the CPU oracle at 1e-12 per step) after the same number of
+    steps; MLUPS of each form on the same lattice; FP64 mass/momentum totals."""
+    import torch
+
+    from paper_0811_4593_amd import lbm, workloads
+
+    spec = workloads.precision_duct()
+    steps = args.steps if args.steps != 500 else 20000
+    N = spec.nodes
+    res, fields = {}, {}
+    for name, st in (("f64", lbm.LBM_STORE_F64), ("f32", lbm.LBM_STORE_F32), ("f16dev", lbm.LBM_STORE_F16_DEV),
+                     ("f16sr", lbm.LBM_STORE_F16_DEV_SR)):
+        stream = torch.cuda.current_stream()
+        h = lbm.lbm_create(spec.nx, spec.ny, spec.nz, spec.tau, spec.rho0, None, st, stream)
+        try:
+            for face, v in spec.bc.items():
+                lbm.lbm_set_velocity_bc(h, face, v)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lbm.lbm_step(h, steps)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            u = torch.empty(3 * N, dtype=torch.float64, device="cuda")
+            lbm.lbm_moments(h, None, u, dst_on_device=True)
+            mass, mom = lbm.lbm_totals(h)
+        finally:
+            lbm.lbm_destroy(h)
+        fields[name] = u
+        res[name] = {"MLUPS": round(N * steps / sec / 1e6, 1),
+                     "GBs": round(N * steps / sec * 2 * 19 * lbm.lbm_element_bytes(st) / 1e9, 1),
+                     "mass": mass, "momentum": [float(x) for x in mom]}
+        print(f"precision form: {name} done in {sec:.1f} s", file=sys.stderr, flush=True)
+    for name in ("f32", "f16dev", "f16sr"):
+        res[name]["rel_L2_u_vs_f64"] = _device_rel_l2(fields[name], fields["f64"])
+    return {"form": "precision", "workload": f"duct {spec.nx}x{spec.ny}x{spec.nz}, inlet/outlet (0.04,0.01,0.01), "
+            f"no-slip y/z walls, tau {spec.tau}", "steps": steps, "results": res,
+            "f16_over_f32_MLUPS": round(res["f16dev"]["MLUPS"] / res["f32"]["MLUPS"], 3)}
+
+
+def form_batch(args):
+    """64 seeded uneven ducts (Nx ~ U{32..256}, Ny, Nz ~ U{16..128}, oblique
+    inflow |u| ~ U[0.01, 0.05], tau ~ U[0.6, 1.5], FP32) in one batch:
+    autotuned shape, 100-step graph chunks, 2000 steps each; against the same
+    64 lattices run one after another with plain launches."""
+    from paper_0811_4593_amd import serving, workloads
+
+    specs = workloads.batch_ducts(64, seed=0)
+    steps = args.steps if args.steps != 500 else 2000
+    run = serving.run_batch(specs, "f32", steps=steps, chunk=100, autotune=True, keep_results=True)
+    print(f"batch form: batched run {run.seconds:.2f} s", file=sys.stderr, flush=True)
+    seq_s, worst = 0.0, 0.0
+    seq_updates = 0.0
+    for i, s in enumerate(specs):
+        sec, _, u = serving.run_plain(s, "f32", run.steps[i])
+        seq_s += sec
+        seq_updates += run.steps[i] * s.nodes
+        ub = run.results[i][1]
+        worst = max(worst, float(np.linalg.norm(ub - u) / np.linalg.norm(u)))
+    nodes = sum(s.nodes for s in specs)
+    return {"form": "batch", "lattices": len(specs), "nodes": nodes, "steps_each": sorted(set(run.steps.values())),
+            "shape": {"block_x": run.shape[0], "tile_nodes": run.shape[1], "grid": run.shape[2]},
+            "batched": {"seconds": round(run.seconds, 3), "MLUPS": round(run.node_updates / run.seconds / 1e6, 1),
+                        "solves_per_s": round(len(specs) / run.seconds, 2)},
+            "sequential_plain": {"seconds": round(seq_s, 3), "MLUPS": round(seq_updates / seq_s / 1e6, 1),
+                                 "solves_per_s": round(len(specs) / seq_s, 2)},
+            "speedup": round(seq_s / run.seconds, 2),
+            "max_rel_L2_u_batched_vs_plain": worst}
+
+
+def form_serve(args):
+    """Serving: seeded Poisson arrivals of cubic ducts, N log-uniform in
+    [16, 256], oblique inflow |u| ~ U[0.01, 0.05], tau ~ U[0.6, 1.5], FP16 or
+    FP32 per request, each run until the relative velocity change over 100
+    steps is below 1e-6 or 20000 steps.  A calibration pass submits the first
+    requests at once to measure saturated solves/s; the timed trace arrives at
+    0.7 times that rate.  Baseline: the same trace served one request at a time
+    with plain launches."""
+    import torch
+
+    from paper_0811_4593_amd import serving, workloads
+
+    free, total = torch.cuda.mem_get_info()
+    budget = int(min(free * 0.8, 200e9))
+    calib = workloads.serving_trace(count=12, rate=1e9, seed=1)
+    rep_c = serving.serve_trace(calib, budget, chunk=100, tol=1e-6, max_steps=20000, max_jobs=512)
+    sat = rep_c.solves_per_s
+    print(f"serve form: calibration {rep_c.summary()}", file=sys.stderr, flush=True)
+    rate = 0.7 * sat
+    trace = workloads.serving_trace(count=args.requests, rate=rate, seed=1)
+    rep = serving.serve_trace(trace, budget, chunk=100, tol=1e-6, max_steps=20000, max_jobs=512)
+    print(f"serve form: served {rep.summary()}", file=sys.stderr, flush=True)
+    base = serving.replay_one_at_a_time(trace, rep.steps)
+    print(f"serve form: one-at-a-time {base.summary()}", file=sys.stderr, flush=True)
+    nodes = [r.spec.nodes for r in trace]
+    return {"form": "serve", "requests": len(trace), "rate_per_s": round(rate, 4),
+            "calibration_solves_per_s": round(sat, 4), "budget_bytes": budget,
+            "mean_nodes": float(np.mean(nodes)), "storage_f16_share": float(np.mean([r.storage == "f16dev" for r in trace])),
+            "served": rep.summary(), "one_at_a_time": base.summary(),
+            "steps_mean": float(np.mean(rep.steps)), "converged": int(sum(rep.converged))}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16dev"])
+    ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16dev", "f16sr"])
     ap.add_argument("--launch", default=None, help="block_x,nodes_per_thread,xcd_remap (default: library's)")
     ap.add_argument("--nx", type=int, default=1024)
     ap.add_argument("--ny", type=int, default=512)
@@ -154,10 +266,20 @@ def main():
                     help="summarise two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE) "
                          "into the committed counters file and exit")
     ap.add_argument("--counters-command", default="", help="the rocprofv3 command lines, for the record")
+    ap.add_argument("--form", choices=["precision", "batch", "serve"], default=None,
+                    help="measure one of the systems forms instead of the roofline run (see form_* below)")
+    ap.add_argument("--requests", type=int, default=40, help="serve form: requests in the timed trace")
     args = ap.parse_args()
 
     if args.ingest_counters:
         ingest_counters(args)
+        return
+    if args.form:
+        if args.gpus != 1:
+            print("bench.py runs on one GPU only", file=sys.stderr)
+            sys.exit(2)
+        out = {"precision": form_precision, "batch": form_batch, "serve": form_serve}[args.form](args)
+        print(json.dumps(out), flush=True)
         return
 
     if args.gpus != 1:
@@ -171,7 +293,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    storage = {"f32": lbm.LBM_STORE_F32, "f64": lbm.LBM_STORE_F64, "f16dev": lbm.LBM_STORE_F16_DEV}[args.storage]
+    storage = {"f32": lbm.LBM_STORE_F32, "f64": lbm.LBM_STORE_F64, "f16dev": lbm.LBM_STORE_F16_DEV,
+               "f16sr": lbm.LBM_STORE_F16_DEV_SR}[args.storage]
     ebytes = lbm.lbm_element_bytes(storage)
     spec = workloads.duct(args.nx, args.ny, args.nz, (0.04, 0.01, 0.01), 0.8)
     N = spec.nodes

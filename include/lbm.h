@@ -32,8 +32,9 @@
  *   node index   n = x + nx*(y + ny*z)
  *   population   k = i - 1, where i = 1..19 numbers the lattice vectors as the
  *                columns of the matrix M (Sec. II, eq_deffs); k = 18 is the
- *                rest population.  Population arrays are structure-of-arrays,
- *                f[k*N + n] with N = nx*ny*nz.
+ *                rest population.  Host population arrays are structure-of-
+ *                arrays, f[k*N + n] with N = nx*ny*nz; device buffers use the
+ *                padded stride P = lbm_population_pitch(N): element k*P + n.
  *   axes         every axis is periodic until a face of it gets a velocity
  *                BC; lbm_step then requires both faces of that axis to be set.
  *                A non-periodic axis needs at least 3 nodes.
@@ -47,6 +48,11 @@
  *   LBM_STORE_F16_DEV  d_k as half-precision scaled deviations
  *                      h_k = RNE(d_k * 2^8), decoded d_k = h_k * 2^-8,
  *                      arithmetic in float
+ *   LBM_STORE_F16_DEV_SR  as LBM_STORE_F16_DEV, but each step rounds
+ *                      d_k * 2^8 stochastically to one of its two neighbouring
+ *                      half values, unbiased; the random bits are a hash of
+ *                      (step index, node, population), so results are
+ *                      reproducible and the same alone or in a batch
  *
  * Errors: every call returns an lbm_status and never aborts.  On failure
  * lbm_last_error() returns a message for the calling thread.  Calls on one
@@ -79,7 +85,7 @@ typedef enum {
   LBM_ERR_NONFINITE = -5  /* a reduction found NaN or Inf in the state */
 } lbm_status;
 
-typedef enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16_DEV = 2 } lbm_storage;
+typedef enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16_DEV = 2, LBM_STORE_F16_DEV_SR = 3 } lbm_storage;
 
 /* Faces: x = 0 (paper: left), x = nx-1 (right), y = 0 (front),
  * y = ny-1 (back), z = 0 (bottom), z = nz-1 (top). */
@@ -95,7 +101,8 @@ lbm_status lbm_create(int nx, int ny, int nz, double tau, double rho0, const dou
                       lbm_storage storage, void *hip_stream, lbm_lattice **out);
 
 /* As lbm_create, on two caller-owned device buffers of buf_bytes bytes each
- * (at least 19*N*element size, 256-byte aligned).  The library never frees
+ * (at least 19*P*element size with P = lbm_population_pitch(N), 256-byte
+ * aligned).  The library never frees
  * them.  Errors as lbm_create; LBM_ERR_ARG if a buffer is NULL, too small or
  * misaligned. */
 lbm_status lbm_create_on_buffers(int nx, int ny, int nz, double tau, double rho0, const double u0[3],
@@ -147,6 +154,12 @@ lbm_status lbm_state_buffer(const lbm_lattice *L, void **dev_ptr);
 /* Bytes of one population element for a storage form (8, 4 or 2); 0 if the
  * storage value is invalid. */
 size_t lbm_element_bytes(lbm_storage storage);
+
+/* Population stride P of the device buffers, in elements, for a lattice of
+ * `nodes` nodes: nodes rounded up to a multiple of 64, so that every
+ * population starts on a cache-line boundary.  Population k of node n is
+ * element k*P + n of a buffer; a buffer holds 19*P elements. */
+size_t lbm_population_pitch(size_t nodes);
 
 /* Launch shape of the sweep kernel: block_x threads along x (64, 128, 256 or
  * 512), nodes_per_thread along x (1, 2 or 4), xcd_remap != 0 places

@@ -30,8 +30,9 @@ struct BatchLat {
   void *buf[2];    // population buffers (state in buf[0] at chunk boundaries)
   float *snap;     // [3][N] velocity at the previous convergence check
   unsigned nx, ny, nz, N;
+  unsigned pitch;      // population stride in elements
   unsigned bc_mask;
-  int pad;
+  unsigned step_base;  // steps taken before the current launch sequence
   double omega;    // 1 / tau
   double v[6][3];  // face velocities
   double inv_uref; // 1 / velocity scale of the convergence measure
@@ -43,33 +44,53 @@ struct BatchTile {
   unsigned n0, n1;
 };
 
-// One step of every lattice of storage type S listed in `tiles`.  Blocks take
+// One step of every lattice of storage form F listed in `tiles`.  Blocks take
 // tiles round-robin; each lane updates nodes n0 + t, n0 + t + BX, ... of its
-// block's tile.  `parity` selects source and destination buffer.
-template <class S, int BX>
+// block's tile.  `s` is the index of the step within the launch sequence: it
+// selects source and destination buffer (parity) and, with the lattice's
+// step_base, the step key.
+template <class F, int BX>
 __global__ __launch_bounds__(BX) void batch_sweep_kernel(const BatchLat *__restrict__ lats,
                                                          const BatchTile *__restrict__ tiles,
-                                                         const int *__restrict__ ntiles, int parity) {
+                                                         const int *__restrict__ ntiles, int s) {
+  using S = typename F::S;
   using T = typename Codec<S>::T;
+  const int parity = s & 1;
   const int nt = *ntiles;
   for (int t = blockIdx.x; t < nt; t += gridDim.x) {
     const BatchTile tile = tiles[t];
     const BatchLat &L = lats[tile.lat];
-    const NodeGeom g{L.nx, L.ny, L.nz, L.N};
-    const S *src = static_cast<const S *>(L.buf[parity]);
-    S *dst = static_cast<S *>(L.buf[parity ^ 1]);
+    const NodeGeom g{L.nx, L.ny, L.nz};
+    const unsigned pop_bytes = L.pitch * unsigned(sizeof(S));
+    const BufAccess<S> mem{raw_buffer(L.buf[parity], 19u * pop_bytes), raw_buffer(L.buf[parity ^ 1], 19u * pop_bytes),
+                           pop_bytes};
     FaceVel<T> fv;
 #pragma unroll
     for (int f = 0; f < 6; ++f)
 #pragma unroll
       for (int d = 0; d < 3; ++d) fv.v[f][d] = T(L.v[f][d]);
     const T omega = T(L.omega);
-    for (unsigned n = tile.n0 + threadIdx.x; n < tile.n1; n += BX) {
-      const unsigned r = n / g.nx;
-      const unsigned x = n - r * g.nx;
-      const unsigned z = r / g.ny;
-      const unsigned y = r - z * g.ny;
-      update_node<S, true, false>(src, dst, g, int(x), int(y), int(z), L.bc_mask, omega, fv);
+    const unsigned key = step_key(L.step_base + unsigned(s));
+    // Coordinates of the lane's first node, then advanced by BX nodes per
+    // iteration with carries (one division per tile instead of two per node).
+    unsigned n = tile.n0 + threadIdx.x;
+    unsigned r = n / g.nx;
+    unsigned x = n - r * g.nx;
+    unsigned z = r / g.ny;
+    unsigned y = r - z * g.ny;
+    const unsigned rows = unsigned(BX) / g.nx;  // uniform
+    const unsigned dx = unsigned(BX) - rows * g.nx;
+    const unsigned dz = rows / g.ny;
+    const unsigned dy = rows - dz * g.ny;
+    for (; n < tile.n1; n += BX) {
+      update_node<F, false>(mem, g, int(x), int(y), int(z), L.bc_mask, omega, fv, key);
+      x += dx;
+      const unsigned cxr = x >= g.nx;
+      x -= cxr ? g.nx : 0u;
+      y += dy + cxr;
+      const unsigned cyr = y >= g.ny;
+      y -= cyr ? g.ny : 0u;
+      z += dz + cyr;
     }
   }
 }
@@ -95,13 +116,14 @@ __global__ __launch_bounds__(256) void batch_delta_kernel(const BatchLat *__rest
   for (int t = blockIdx.x; t < nt; t += gridDim.x) {
     const BatchTile tile = tiles[t];
     const BatchLat &L = lats[tile.lat];
-    const S *f = static_cast<const S *>(L.buf[0]);
+    const global_ptr<const S> f = (global_ptr<const S>)(L.buf[0]);
+    const global_ptr<float> snap = (global_ptr<float>)(L.snap);
     float dmax = 0.0f;
     for (unsigned n = tile.n0 + threadIdx.x; n < tile.n1; n += 256) {
       double dr = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int k = 0; k < 19; ++k) {
-        const double v = double(Codec<S>::decode(f[size_t(k) * L.N + n]));
+        const double v = double(Codec<S>::decode(f[size_t(k) * L.pitch + n]));
         dr += v;
         if (cx(k)) j[0] += double(cx(k)) * v;
         if (cy(k)) j[1] += double(cy(k)) * v;
@@ -111,7 +133,7 @@ __global__ __launch_bounds__(256) void batch_delta_kernel(const BatchLat *__rest
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const double u = j[a] * ir;
-        float *sp = L.snap + size_t(a) * L.N + n;
+        const global_ptr<float> sp = snap + size_t(a) * L.N + n;
         const float du = float(fabs(u - double(*sp)) * L.inv_uref);
         dmax = (du != du) ? INFINITY : fmaxf(dmax, du);
         *sp = float(u);
@@ -133,21 +155,23 @@ __global__ void fill_float_kernel(float *__restrict__ p, size_t n, float v) {
   if (i < n) p[i] = v;
 }
 
-template <class S, int BX>
-static void launch_batch_sweep_t(const BatchLat *lats, const BatchTile *tiles, const int *nt, int parity, int grid,
-                                 hipStream_t s) {
-  batch_sweep_kernel<S, BX><<<dim3(grid), dim3(BX), 0, s>>>(lats, tiles, nt, parity);
+template <class F, int BX>
+static void launch_batch_sweep_t(const BatchLat *lats, const BatchTile *tiles, const int *nt, int s, int grid,
+                                 hipStream_t st) {
+  batch_sweep_kernel<F, BX><<<dim3(grid), dim3(BX), 0, st>>>(lats, tiles, nt, s);
 }
 
 static hipError_t launch_batch_sweep(int storage, int bx, const BatchLat *lats, const BatchTile *tiles, const int *nt,
-                                     int parity, int grid, hipStream_t s) {
+                                     int s, int grid, hipStream_t st) {
   switch (storage * 1000 + bx) {
-    case kStoreF64 * 1000 + 128: launch_batch_sweep_t<double, 128>(lats, tiles, nt, parity, grid, s); break;
-    case kStoreF64 * 1000 + 256: launch_batch_sweep_t<double, 256>(lats, tiles, nt, parity, grid, s); break;
-    case kStoreF32 * 1000 + 128: launch_batch_sweep_t<float, 128>(lats, tiles, nt, parity, grid, s); break;
-    case kStoreF32 * 1000 + 256: launch_batch_sweep_t<float, 256>(lats, tiles, nt, parity, grid, s); break;
-    case kStoreF16 * 1000 + 128: launch_batch_sweep_t<_Float16, 128>(lats, tiles, nt, parity, grid, s); break;
-    case kStoreF16 * 1000 + 256: launch_batch_sweep_t<_Float16, 256>(lats, tiles, nt, parity, grid, s); break;
+    case kStoreF64 * 1000 + 128: launch_batch_sweep_t<FormF64, 128>(lats, tiles, nt, s, grid, st); break;
+    case kStoreF64 * 1000 + 256: launch_batch_sweep_t<FormF64, 256>(lats, tiles, nt, s, grid, st); break;
+    case kStoreF32 * 1000 + 128: launch_batch_sweep_t<FormF32, 128>(lats, tiles, nt, s, grid, st); break;
+    case kStoreF32 * 1000 + 256: launch_batch_sweep_t<FormF32, 256>(lats, tiles, nt, s, grid, st); break;
+    case kStoreF16 * 1000 + 128: launch_batch_sweep_t<FormF16, 128>(lats, tiles, nt, s, grid, st); break;
+    case kStoreF16 * 1000 + 256: launch_batch_sweep_t<FormF16, 256>(lats, tiles, nt, s, grid, st); break;
+    case kStoreF16SR * 1000 + 128: launch_batch_sweep_t<FormF16SR, 128>(lats, tiles, nt, s, grid, st); break;
+    case kStoreF16SR * 1000 + 256: launch_batch_sweep_t<FormF16SR, 256>(lats, tiles, nt, s, grid, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -158,7 +182,8 @@ static hipError_t launch_batch_delta(int storage, const BatchLat *lats, const Ba
   switch (storage) {
     case kStoreF64: batch_delta_kernel<double><<<dim3(grid), dim3(256), 0, s>>>(lats, tiles, nt, delta); break;
     case kStoreF32: batch_delta_kernel<float><<<dim3(grid), dim3(256), 0, s>>>(lats, tiles, nt, delta); break;
-    case kStoreF16: batch_delta_kernel<_Float16><<<dim3(grid), dim3(256), 0, s>>>(lats, tiles, nt, delta); break;
+    case kStoreF16:
+    case kStoreF16SR: batch_delta_kernel<_Float16><<<dim3(grid), dim3(256), 0, s>>>(lats, tiles, nt, delta); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -180,7 +205,7 @@ namespace {
   } while (0)
 
 constexpr size_t kAlign = 256;
-constexpr int kNumStorage = 3;
+constexpr int kNumStorage = 4;
 constexpr int kMinTileNodes = 256;
 constexpr size_t kStageNodes = size_t(1) << 22;
 
@@ -237,7 +262,7 @@ class Pool {
 
 size_t job_bytes(const lbm_job &j) {
   const size_t N = size_t(j.nx) * j.ny * j.nz;
-  return 2 * align_up(19 * N * lbm_element_bytes(j.storage)) + align_up(3 * N * sizeof(float));
+  return 2 * align_up(19 * lbm::population_pitch(N) * lbm_element_bytes(j.storage)) + align_up(3 * N * sizeof(float));
 }
 
 struct Job {
@@ -278,13 +303,13 @@ struct lbm_batch {
   int next_id = 1;
   // device tables
   lbm::BatchLat *d_lats = nullptr;
-  lbm::BatchTile *d_tiles[kNumStorage] = {nullptr, nullptr, nullptr};
+  lbm::BatchTile *d_tiles[kNumStorage] = {nullptr, nullptr, nullptr, nullptr};
   int *d_ntiles = nullptr;
   unsigned *d_delta = nullptr;
   size_t tile_cap = 0;
   std::vector<lbm::BatchLat> h_lats;
   std::vector<lbm::BatchTile> h_tiles[kNumStorage];
-  int h_ntiles[kNumStorage] = {0, 0, 0};
+  int h_ntiles[kNumStorage] = {0, 0, 0, 0};
   std::vector<unsigned> h_delta;
   double *d_stage = nullptr;
   std::map<long long, hipGraphExec_t> graphs;
@@ -302,6 +327,20 @@ unsigned present_mask(const lbm_batch *B) {
 void drop_graphs(lbm_batch *B) {
   for (auto &kv : B->graphs) (void)hipGraphExecDestroy(kv.second);
   B->graphs.clear();
+}
+
+// Refresh every resident lattice's step_base and upload the descriptors.
+lbm_status upload_lats(lbm_batch *B) {
+  for (int slot = 0; slot < B->max_jobs; ++slot) {
+    const int id = B->slot_job[slot];
+    if (id >= 0) B->h_lats[slot].step_base = unsigned(B->jobs[id].steps);
+  }
+  LBM_BHIP(hipMemcpyAsync(B->d_lats, B->h_lats.data(), B->h_lats.size() * sizeof(lbm::BatchLat),
+                          hipMemcpyHostToDevice, B->stream),
+           "upload lattices");
+  // The host vector must stay untouched until the copy has run.
+  LBM_BHIP(hipStreamSynchronize(B->stream), "upload");
+  return LBM_OK;
 }
 
 lbm_status rebuild_tiles(lbm_batch *B) {
@@ -324,24 +363,24 @@ lbm_status rebuild_tiles(lbm_batch *B) {
   }
   LBM_BHIP(hipMemcpyAsync(B->d_ntiles, B->h_ntiles, sizeof(B->h_ntiles), hipMemcpyHostToDevice, B->stream),
            "upload tile counts");
-  LBM_BHIP(hipMemcpyAsync(B->d_lats, B->h_lats.data(), B->h_lats.size() * sizeof(lbm::BatchLat),
-                          hipMemcpyHostToDevice, B->stream),
-           "upload lattices");
-  // The host vectors must stay untouched until the copies have run.
-  LBM_BHIP(hipStreamSynchronize(B->stream), "upload");
+  lbm_status st = upload_lats(B);
+  if (st != LBM_OK) return st;
   B->tiles_dirty = false;
   return LBM_OK;
 }
 
 int grid_of(const lbm_batch *B) { return B->shape.grid > 0 ? B->shape.grid : 8 * B->num_cu; }
 
-lbm_status launch_steps(lbm_batch *B, int nsteps, int parity0) {
+// Enqueue nsteps steps with indices first..first+nsteps-1 of a sequence that
+// starts at each lattice's step_base (first and nsteps even keep the state in
+// buf[0] at the end).
+lbm_status launch_steps(lbm_batch *B, int nsteps, int first) {
   const int grid = grid_of(B);
-  for (int st = 0; st < nsteps; ++st)
+  for (int st = first; st < first + nsteps; ++st)
     for (int s = 0; s < kNumStorage; ++s)
       if (B->h_ntiles[s] > 0)
-        LBM_BHIP(lbm::launch_batch_sweep(s, B->shape.block_x, B->d_lats, B->d_tiles[s], B->d_ntiles + s,
-                                         (parity0 + st) & 1, grid, B->stream),
+        LBM_BHIP(lbm::launch_batch_sweep(s, B->shape.block_x, B->d_lats, B->d_tiles[s], B->d_ntiles + s, st, grid,
+                                         B->stream),
                  "batch sweep launch");
   return LBM_OK;
 }
@@ -391,7 +430,8 @@ lbm_status retire(lbm_batch *B, int id) {
   for (size_t n0 = 0; n0 < N; n0 += kStageNodes) {
     const size_t cnt = std::min(kStageNodes, N - n0);
     double *dr = B->d_stage, *du = B->d_stage + cnt;
-    LBM_BHIP(lbm::launch_moments(J.spec.storage, f, N, n0, cnt, dr, du, nullptr, 1024, B->stream), "moments");
+    LBM_BHIP(lbm::launch_moments(J.spec.storage, f, lbm::population_pitch(N), n0, cnt, dr, du, nullptr, 1024, B->stream),
+             "moments");
     LBM_BHIP(hipMemcpyAsync(J.rho.data() + n0, dr, cnt * sizeof(double), hipMemcpyDeviceToHost, B->stream), "copy");
     for (int a = 0; a < 3; ++a)
       LBM_BHIP(hipMemcpyAsync(J.u.data() + a * N + n0, du + a * cnt, cnt * sizeof(double), hipMemcpyDeviceToHost,
@@ -432,7 +472,8 @@ lbm_status admit(lbm_batch *B) {
       continue;
     }
     const size_t N = size_t(J.spec.nx) * J.spec.ny * J.spec.nz;
-    const size_t pop_bytes = align_up(19 * N * lbm_element_bytes(J.spec.storage));
+    const size_t pitch = lbm::population_pitch(N);
+    const size_t pop_bytes = align_up(19 * pitch * lbm_element_bytes(J.spec.storage));
     lbm::BatchLat L;
     std::memset(&L, 0, sizeof(L));
     L.buf[0] = B->pool_base + off;
@@ -442,6 +483,7 @@ lbm_status admit(lbm_batch *B) {
     L.ny = unsigned(J.spec.ny);
     L.nz = unsigned(J.spec.nz);
     L.N = unsigned(N);
+    L.pitch = unsigned(pitch);
     L.bc_mask = J.spec.bc_mask;
     L.omega = 1.0 / J.spec.tau;
     std::memcpy(L.v, J.spec.bc_velocity, sizeof(L.v));
@@ -449,7 +491,7 @@ lbm_status admit(lbm_batch *B) {
     B->h_lats[slot] = L;
     B->slot_job[slot] = *it;
     const double zero[3] = {0.0, 0.0, 0.0};
-    LBM_BHIP(lbm::launch_init(J.spec.storage, L.buf[0], N, J.spec.rho0, zero, B->stream), "init launch");
+    LBM_BHIP(lbm::launch_init(J.spec.storage, L.buf[0], N, pitch, J.spec.rho0, zero, B->stream), "init launch");
     const size_t n3 = 3 * N;
     lbm::fill_float_kernel<<<dim3(unsigned((n3 + 255) / 256)), dim3(256), 0, B->stream>>>(L.snap, n3, 0.0f);
     LBM_BHIP(hipGetLastError(), "snapshot fill");
@@ -569,6 +611,9 @@ lbm_status lbm_batch_submit(lbm_batch *B, const lbm_job *job, int *job_id) {
   if (!(j.rho0 > 0.0)) return bfail(LBM_ERR_ARG, "rho0 must be > 0");
   if (lbm_element_bytes(j.storage) == 0) return bfail(LBM_ERR_ARG, "invalid storage");
   if (!(j.u_ref > 0.0)) return bfail(LBM_ERR_ARG, "u_ref must be > 0");
+  if (19.0 * double(lbm::population_pitch(size_t(j.nx) * j.ny * j.nz)) * double(lbm_element_bytes(j.storage)) >=
+      4294967296.0)
+    return bfail(LBM_ERR_ARG, "a batch job's population buffer must stay below 4 GiB (19 N element bytes)");
   if (j.max_steps < 0) return bfail(LBM_ERR_ARG, "max_steps must be >= 0");
   if (j.bc_mask & ~63u) return bfail(LBM_ERR_ARG, "bc_mask has bits beyond the six faces");
   const int size[3] = {j.nx, j.ny, j.nz};
@@ -603,10 +648,8 @@ lbm_status lbm_batch_run_chunk(lbm_batch *B, int *n_active, int *n_queued) {
   if (st != LBM_OK) return st;
   const int active = count_active(B);
   if (active > 0) {
-    if (B->tiles_dirty) {
-      st = rebuild_tiles(B);
-      if (st != LBM_OK) return st;
-    }
+    st = B->tiles_dirty ? rebuild_tiles(B) : upload_lats(B);
+    if (st != LBM_OK) return st;
     st = run_graph_chunk(B);
     if (st != LBM_OK) return st;
     LBM_BHIP(hipMemsetAsync(B->d_delta, 0, sizeof(unsigned) * B->max_jobs, B->stream), "reset deltas");
@@ -701,25 +744,25 @@ lbm_status lbm_batch_autotune(lbm_batch *B, int trial_steps, int *block_x, int *
     LBM_BHIP(hipEventCreate(&e1), "event");
     Shape best;
     float best_ms = INFINITY;
-    int steps_taken = 0;
     for (int bx : {128, 256})
       for (int tn : {1024, 4096, 16384})
         for (int gm : {4, 8, 16}) {
           st = lbm_batch_set_shape(B, bx, tn, gm * B->num_cu);
-          if (st == LBM_OK && B->tiles_dirty) st = rebuild_tiles(B);
-          if (st == LBM_OK) st = launch_steps(B, 2, 0);  // warm-up, even step count
-          hipError_t e = hipEventRecord(e0, B->stream);
-          if (st == LBM_OK && e == hipSuccess) st = launch_steps(B, trial_steps, 0);
-          e = e == hipSuccess ? hipEventRecord(e1, B->stream) : e;
-          e = e == hipSuccess ? hipEventSynchronize(e1) : e;
+          if (st == LBM_OK) st = B->tiles_dirty ? rebuild_tiles(B) : upload_lats(B);
+          if (st == LBM_OK) st = launch_steps(B, 2, 0);  // warm-up
+          hipError_t e = st == LBM_OK ? hipEventRecord(e0, B->stream) : hipSuccess;
+          if (st == LBM_OK && e == hipSuccess) st = launch_steps(B, trial_steps, 2);
+          if (st == LBM_OK && e == hipSuccess) e = hipEventRecord(e1, B->stream);
+          if (st == LBM_OK && e == hipSuccess) e = hipEventSynchronize(e1);
           float ms = 0.f;
-          e = e == hipSuccess ? hipEventElapsedTime(&ms, e0, e1) : e;
+          if (st == LBM_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
           if (st != LBM_OK || e != hipSuccess) {
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             return st != LBM_OK ? st : bfail(LBM_ERR_HIP, "autotune timing: %s", hipGetErrorString(e));
           }
-          steps_taken += 2 + trial_steps;
+          for (int id : B->slot_job)
+            if (id >= 0) B->jobs[id].steps += 2 + trial_steps;
           if (ms < best_ms) {
             best_ms = ms;
             best = B->shape;
@@ -727,8 +770,6 @@ lbm_status lbm_batch_autotune(lbm_batch *B, int trial_steps, int *block_x, int *
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    for (int id : B->slot_job)
-      if (id >= 0) B->jobs[id].steps += steps_taken;
     g_tuned[key] = best;
     st = lbm_batch_set_shape(B, best.block_x, best.tile_nodes, best.grid);
   }

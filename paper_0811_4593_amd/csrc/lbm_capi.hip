@@ -46,7 +46,8 @@ constexpr size_t kChunkNodes = size_t(1) << 22;  // host transfers are staged in
 
 struct lbm_lattice {
   int nx, ny, nz;
-  size_t N;
+  size_t N;      // nodes
+  size_t pitch;  // population stride in elements (N rounded up to 64)
   double tau;
   int storage;
   size_t esize;
@@ -57,6 +58,7 @@ struct lbm_lattice {
   unsigned bc_mask;
   double v[6][3];
   int block_x, npt, xcd;
+  unsigned steps;      // steps taken since creation (keys the stochastic rounding)
   double *d_partials;  // [kPartialBlocks * 4]
   double *d_totals;    // [4]
   double *d_stage;     // [19 * kChunkNodes] doubles, allocated on first use
@@ -66,11 +68,14 @@ extern "C" {
 
 const char *lbm_last_error(void) { return g_err; }
 
+size_t lbm_population_pitch(size_t nodes) { return lbm::population_pitch(nodes); }
+
 size_t lbm_element_bytes(lbm_storage storage) {
   switch (storage) {
     case LBM_STORE_F64: return 8;
     case LBM_STORE_F32: return 4;
     case LBM_STORE_F16_DEV: return 2;
+    case LBM_STORE_F16_DEV_SR: return 2;
   }
   return 0;
 }
@@ -89,10 +94,11 @@ static lbm_status validate_create(int nx, int ny, int nz, double tau, double rho
 }
 
 static void default_launch(lbm_lattice *L) {
-  // 256 threads, one node each, consecutive row segments on one XCD: the
-  // fastest shape measured on the 1024 x 512 x 512 duct (lbm_set_launch
-  // overrides it; the batch autotuner searches the others).
-  L->block_x = 256;
+  // One node per thread, consecutive row segments on one XCD; 256 threads
+  // per block (the fastest shape measured on the 1024 x 512 x 512 duct), or
+  // the narrowest block that still covers a short x-row, so that few lanes
+  // idle.  lbm_set_launch overrides it.
+  L->block_x = L->nx <= 64 ? 64 : (L->nx <= 128 ? 128 : 256);
   L->npt = 1;
   L->xcd = 1;
 }
@@ -105,7 +111,7 @@ static lbm_status finish_create(lbm_lattice *L, double rho0, const double u0[3],
   hipError_t e = hipMalloc(&L->d_partials, sizeof(double) * (kPartialBlocks * 4 + 4));
   if (e != hipSuccess) return fail(LBM_ERR_OOM, "hipMalloc of reduction scratch failed: %s", hipGetErrorString(e));
   L->d_totals = L->d_partials + kPartialBlocks * 4;
-  e = lbm::launch_init(L->storage, L->buf[0], L->N, rho0, u0, L->stream);
+  e = lbm::launch_init(L->storage, L->buf[0], L->N, L->pitch, rho0, u0, L->stream);
   if (e != hipSuccess) return hip_fail(e, "init launch");
   e = hipStreamSynchronize(L->stream);
   if (e != hipSuccess) return hip_fail(e, "init");
@@ -124,13 +130,14 @@ lbm_status lbm_create(int nx, int ny, int nz, double tau, double rho0, const dou
   L->ny = ny;
   L->nz = nz;
   L->N = size_t(nx) * ny * nz;
+  L->pitch = lbm::population_pitch(L->N);
   L->tau = tau;
   L->storage = int(storage);
   L->esize = lbm_element_bytes(storage);
   L->stream = static_cast<hipStream_t>(hip_stream);
   L->owns = true;
   default_launch(L);
-  const size_t bytes = 19 * L->N * L->esize;
+  const size_t bytes = 19 * L->pitch * L->esize;
   for (int i = 0; i < 2; ++i) {
     hipError_t e = hipMalloc(&L->buf[i], bytes);
     if (e != hipSuccess) {
@@ -149,7 +156,7 @@ lbm_status lbm_create_on_buffers(int nx, int ny, int nz, double tau, double rho0
                                  lbm_lattice **out) {
   lbm_status st = validate_create(nx, ny, nz, tau, rho0, storage, out);
   if (st != LBM_OK) return st;
-  const size_t need = 19 * size_t(nx) * ny * nz * lbm_element_bytes(storage);
+  const size_t need = 19 * lbm::population_pitch(size_t(nx) * ny * nz) * lbm_element_bytes(storage);
   if (!buf_a || !buf_b || buf_a == buf_b) return fail(LBM_ERR_ARG, "two distinct device buffers are required");
   if (buf_bytes < need) return fail(LBM_ERR_ARG, "buffers hold %zu bytes, %zu needed", buf_bytes, need);
   if ((reinterpret_cast<uintptr_t>(buf_a) | reinterpret_cast<uintptr_t>(buf_b)) & 255u)
@@ -160,6 +167,7 @@ lbm_status lbm_create_on_buffers(int nx, int ny, int nz, double tau, double rho0
   L->ny = ny;
   L->nz = nz;
   L->N = size_t(nx) * ny * nz;
+  L->pitch = lbm::population_pitch(L->N);
   L->tau = tau;
   L->storage = int(storage);
   L->esize = lbm_element_bytes(storage);
@@ -226,6 +234,7 @@ static lbm::SweepConfig sweep_config(const lbm_lattice *L) {
   c.block_x = L->block_x;
   c.nodes_per_thread = L->npt;
   c.xcd_remap = L->xcd;
+  c.step = L->steps;
   return c;
 }
 
@@ -237,11 +246,13 @@ lbm_status lbm_step(lbm_lattice *L, int nsteps) {
     if (bits == 1u || bits == 2u)
       return fail(LBM_ERR_STATE, "axis %d has a velocity BC on one face only; set both faces or none", a);
   }
-  const lbm::SweepConfig c = sweep_config(L);
+  lbm::SweepConfig c = sweep_config(L);
   for (int s = 0; s < nsteps; ++s) {
+    c.step = L->steps;
     hipError_t e = lbm::launch_sweep(c, L->buf[L->cur], L->buf[L->cur ^ 1], false, L->stream);
     if (e != hipSuccess) return hip_fail(e, "sweep launch");
     L->cur ^= 1;
+    ++L->steps;
   }
   return LBM_OK;
 }
@@ -261,7 +272,7 @@ lbm_status lbm_moments(lbm_lattice *L, double *rho, double *u, int dst_on_device
   if (!rho && !u) return LBM_OK;
   const void *f = L->buf[L->cur];
   if (dst_on_device) {
-    LBM_HIP(lbm::launch_moments(L->storage, f, L->N, 0, L->N, rho, u, nullptr, kPartialBlocks, L->stream),
+    LBM_HIP(lbm::launch_moments(L->storage, f, L->pitch, 0, L->N, rho, u, nullptr, kPartialBlocks, L->stream),
             "moments launch");
     LBM_HIP(hipStreamSynchronize(L->stream), "moments");
     return LBM_OK;
@@ -271,7 +282,7 @@ lbm_status lbm_moments(lbm_lattice *L, double *rho, double *u, int dst_on_device
   for (size_t n0 = 0; n0 < L->N; n0 += kChunkNodes) {
     const size_t cnt = (L->N - n0) < kChunkNodes ? (L->N - n0) : kChunkNodes;
     double *drho = L->d_stage, *du = L->d_stage + cnt;
-    LBM_HIP(lbm::launch_moments(L->storage, f, L->N, n0, cnt, rho ? drho : nullptr, u ? du : nullptr, nullptr,
+    LBM_HIP(lbm::launch_moments(L->storage, f, L->pitch, n0, cnt, rho ? drho : nullptr, u ? du : nullptr, nullptr,
                                 kPartialBlocks, L->stream),
             "moments launch");
     if (rho) LBM_HIP(hipMemcpyAsync(rho + n0, drho, cnt * sizeof(double), hipMemcpyDeviceToHost, L->stream), "copy rho");
@@ -287,7 +298,7 @@ lbm_status lbm_moments(lbm_lattice *L, double *rho, double *u, int dst_on_device
 
 lbm_status lbm_totals(lbm_lattice *L, double *mass, double momentum[3]) {
   if (!L || !mass || !momentum) return fail(LBM_ERR_ARG, "NULL argument");
-  LBM_HIP(lbm::launch_moments(L->storage, L->buf[L->cur], L->N, 0, L->N, nullptr, nullptr, L->d_partials,
+  LBM_HIP(lbm::launch_moments(L->storage, L->buf[L->cur], L->pitch, 0, L->N, nullptr, nullptr, L->d_partials,
                               kPartialBlocks, L->stream),
           "totals launch");
   LBM_HIP(lbm::launch_reduce(L->d_partials, kPartialBlocks, L->d_totals, L->stream), "reduce launch");
@@ -309,7 +320,8 @@ lbm_status lbm_get_populations(lbm_lattice *L, double *f) {
   if (st != LBM_OK) return st;
   for (size_t n0 = 0; n0 < L->N; n0 += kChunkNodes) {
     const size_t cnt = (L->N - n0) < kChunkNodes ? (L->N - n0) : kChunkNodes;
-    LBM_HIP(lbm::launch_to_double(L->storage, L->buf[L->cur], L->N, n0, cnt, L->d_stage, L->stream), "convert launch");
+    LBM_HIP(lbm::launch_to_double(L->storage, L->buf[L->cur], L->pitch, n0, cnt, L->d_stage, L->stream),
+            "convert launch");
     for (int k = 0; k < 19; ++k)
       LBM_HIP(hipMemcpyAsync(f + size_t(k) * L->N + n0, L->d_stage + size_t(k) * cnt, cnt * sizeof(double),
                              hipMemcpyDeviceToHost, L->stream),
@@ -329,7 +341,7 @@ lbm_status lbm_set_populations(lbm_lattice *L, const double *f) {
       LBM_HIP(hipMemcpyAsync(L->d_stage + size_t(k) * cnt, f + size_t(k) * L->N + n0, cnt * sizeof(double),
                              hipMemcpyHostToDevice, L->stream),
               "copy populations");
-    LBM_HIP(lbm::launch_from_double(L->storage, L->buf[L->cur], L->N, n0, cnt, L->d_stage, L->stream),
+    LBM_HIP(lbm::launch_from_double(L->storage, L->buf[L->cur], L->pitch, n0, cnt, L->d_stage, L->stream),
             "convert launch");
     LBM_HIP(hipStreamSynchronize(L->stream), "set populations");
   }
@@ -370,7 +382,7 @@ lbm_status lbm_probe(lbm_lattice *L, int kind, int nrep) {
   void *dst = L->buf[L->cur ^ 1];
   const lbm::SweepConfig c = sweep_config(L);
   for (int r = 0; r < nrep; ++r) {
-    hipError_t e = kind == 0 ? lbm::launch_copy_probe(src, dst, 19 * L->N * L->esize & ~size_t(15), L->stream)
+    hipError_t e = kind == 0 ? lbm::launch_copy_probe(src, dst, 19 * L->pitch * L->esize & ~size_t(15), L->stream)
                              : lbm::launch_sweep(c, src, dst, true, L->stream);
     if (e != hipSuccess) return hip_fail(e, "probe launch");
   }

@@ -15,7 +15,13 @@ namespace lbm {
 // return st.
 lbm_status set_error(lbm_status st, const char *fmt, ...);
 
-enum { kStoreF64 = 0, kStoreF32 = 1, kStoreF16 = 2 };
+enum { kStoreF64 = 0, kStoreF32 = 1, kStoreF16 = 2, kStoreF16SR = 3 };
+
+// Distance in elements between consecutive populations in a buffer: the
+// node count rounded up to a multiple of 64, so that every population starts
+// on a 128-byte cache-line boundary (for 2-, 4- and 8-byte elements) and a
+// wavefront's 64 consecutive nodes touch whole lines.
+inline size_t population_pitch(size_t nodes) { return (nodes + 63) / 64 * 64; }
 
 // Everything one sweep launch needs, in host form.
 struct SweepConfig {
@@ -27,29 +33,31 @@ struct SweepConfig {
   int block_x;
   int nodes_per_thread;
   int xcd_remap;
+  unsigned step;  // index of the step this launch performs (stochastic rounding)
 };
 
 // Kernel-argument form, arithmetic type T.
 template <class T>
 struct SweepArgs {
   int nx, ny, nz;
-  size_t N;
+  size_t pitch;      // population stride in elements
   int nxc;           // blocks per x-row
   unsigned nblocks;  // grid size
   int xcd_remap;
   unsigned bc_mask;
   T omega;  // 1 / tau
+  unsigned key;  // step key of the stochastic rounding
   FaceVel<T> fv;
 };
 
 hipError_t launch_sweep(const SweepConfig &c, const void *src, void *dst, bool copy_only, hipStream_t s);
-hipError_t launch_init(int storage, void *f, size_t N, double rho0, const double u0[3], hipStream_t s);
-hipError_t launch_moments(int storage, const void *f, size_t N, size_t n0, size_t count, double *rho, double *u,
+hipError_t launch_init(int storage, void *f, size_t N, size_t pitch, double rho0, const double u0[3], hipStream_t s);
+hipError_t launch_moments(int storage, const void *f, size_t pitch, size_t n0, size_t count, double *rho, double *u,
                           double *partials, int nblk, hipStream_t s);
 hipError_t launch_reduce(const double *partials, int nblk, double *out, hipStream_t s);
-hipError_t launch_to_double(int storage, const void *f, size_t N, size_t n0, size_t count, double *out,
+hipError_t launch_to_double(int storage, const void *f, size_t pitch, size_t n0, size_t count, double *out,
                             hipStream_t s);
-hipError_t launch_from_double(int storage, void *f, size_t N, size_t n0, size_t count, const double *in,
+hipError_t launch_from_double(int storage, void *f, size_t pitch, size_t n0, size_t count, const double *in,
                               hipStream_t s);
 hipError_t launch_copy_probe(const void *src, void *dst, size_t nbytes, hipStream_t s);
 

@@ -2,8 +2,9 @@
 // streaming + on-site boundary rules + BGK), initialisation, moments and
 // FP64 reductions, storage conversion and bandwidth probes.
 //
-// Layout in HBM: structure of arrays, population k of node n at k*N + n,
-// n = x + nx*(y + ny*z).  One sweep reads 19 and writes 19 elements per node;
+// Layout in HBM: structure of arrays, population k of node n at k*P + n,
+// n = x + nx*(y + ny*z), P = N rounded up to a multiple of 64 (population
+// starts on cache-line boundaries).  One sweep reads 19 and writes 19 elements per node;
 // every element of the source buffer is read exactly once per step (the pull
 // scheme has no reuse between nodes), so the kernel is a pure 38-stream HBM
 // copy with ~200 flops per node on top.
@@ -25,19 +26,21 @@ namespace lbm {
 // offset".  COPY: streaming only (no boundary rule, no collision, raw
 // elements) -- the bandwidth ceiling of this access pattern.
 // ---------------------------------------------------------------------------
-template <class S, int BX, int NPT, bool NT, bool COPY>
-__global__ __launch_bounds__(BX) void sweep_kernel(const S *__restrict__ src, S *__restrict__ dst,
-                                                   SweepArgs<typename Codec<S>::T> a) {
+template <class F, int BX, int NPT, bool NT, bool COPY>
+__global__ __launch_bounds__(BX) void sweep_kernel(const typename F::S *__restrict__ src,
+                                                   typename F::S *__restrict__ dst,
+                                                   SweepArgs<typename Codec<typename F::S>::T> a) {
   const unsigned b = logical_block(blockIdx.x, gridDim.x, a.xcd_remap);
   const unsigned row = a.nxc == 1 ? b : b / unsigned(a.nxc);
   const int xc = int(b - row * unsigned(a.nxc));
-  const NodeGeom g{unsigned(a.nx), unsigned(a.ny), unsigned(a.nz), a.N};
+  const NodeGeom g{unsigned(a.nx), unsigned(a.ny), unsigned(a.nz)};
+  const PtrAccess<typename F::S, NT> mem{src, dst, a.pitch};
   const int y = int(row % g.ny);
   const int z = int(row / g.ny);
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
     const int x = (xc * NPT + j) * BX + int(threadIdx.x);
-    if (x < a.nx) update_node<S, NT, COPY>(src, dst, g, x, y, z, a.bc_mask, a.omega, a.fv);
+    if (x < a.nx) update_node<F, COPY>(mem, g, x, y, z, a.bc_mask, a.omega, a.fv, a.key);
   }
 }
 
@@ -47,7 +50,7 @@ __global__ __launch_bounds__(BX) void sweep_kernel(const S *__restrict__ src, S 
 // evaluated in double.
 // ---------------------------------------------------------------------------
 template <class S>
-__global__ void init_kernel(S *__restrict__ f, size_t N, double rho0, double ux, double uy, double uz) {
+__global__ void init_kernel(S *__restrict__ f, size_t N, size_t pitch, double rho0, double ux, double uy, double uz) {
   const size_t n = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (n >= N) return;
   const double usq15 = 1.5 * (ux * ux + uy * uy + uz * uz);
@@ -55,7 +58,7 @@ __global__ void init_kernel(S *__restrict__ f, size_t N, double rho0, double ux,
   for (int k = 0; k < 19; ++k) {
     const double cu = double(cx(k)) * ux + double(cy(k)) * uy + double(cz(k)) * uz;
     const double dk = weight<double>(k) * ((rho0 - 1.0) + rho0 * (3.0 * cu + 4.5 * cu * cu - usq15));
-    f[size_t(k) * N + n] = Codec<S>::encode(typename Codec<S>::T(dk));
+    f[size_t(k) * pitch + n] = Codec<S>::encode(typename Codec<S>::T(dk));
   }
 }
 
@@ -73,7 +76,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 template <class S>
-__global__ __launch_bounds__(256) void moments_kernel(const S *__restrict__ f, size_t N, size_t n0,
+__global__ __launch_bounds__(256) void moments_kernel(const S *__restrict__ f, size_t pitch, size_t n0,
                                                       size_t count, double *__restrict__ rho,
                                                       double *__restrict__ u,
                                                       double *__restrict__ partials) {
@@ -84,7 +87,7 @@ __global__ __launch_bounds__(256) void moments_kernel(const S *__restrict__ f, s
     double dr = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
     for (int k = 0; k < 19; ++k) {
-      const double v = double(Codec<S>::decode(f[size_t(k) * N + n]));
+      const double v = double(Codec<S>::decode(f[size_t(k) * pitch + n]));
       dr += v;
       if (cx(k)) jx += double(cx(k)) * v;
       if (cy(k)) jy += double(cy(k)) * v;
@@ -143,24 +146,24 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double *__re
 // double, nodes [n0, n0 + count); the chunk's layout is buf[k*count + i].
 // ---------------------------------------------------------------------------
 template <class S>
-__global__ void to_double_kernel(const S *__restrict__ f, size_t N, size_t n0, size_t count,
+__global__ void to_double_kernel(const S *__restrict__ f, size_t pitch, size_t n0, size_t count,
                                  double *__restrict__ out) {
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= count) return;
 #pragma unroll
   for (int k = 0; k < 19; ++k)
-    out[size_t(k) * count + i] = weight<double>(k) + double(Codec<S>::decode(f[size_t(k) * N + n0 + i]));
+    out[size_t(k) * count + i] = weight<double>(k) + double(Codec<S>::decode(f[size_t(k) * pitch + n0 + i]));
 }
 
 template <class S>
-__global__ void from_double_kernel(S *__restrict__ f, size_t N, size_t n0, size_t count,
+__global__ void from_double_kernel(S *__restrict__ f, size_t pitch, size_t n0, size_t count,
                                    const double *__restrict__ in) {
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= count) return;
 #pragma unroll
   for (int k = 0; k < 19; ++k) {
     using T = typename Codec<S>::T;
-    f[size_t(k) * N + n0 + i] = Codec<S>::encode(T(in[size_t(k) * count + i] - weight<double>(k)));
+    f[size_t(k) * pitch + n0 + i] = Codec<S>::encode(T(in[size_t(k) * count + i] - weight<double>(k)));
   }
 }
 
@@ -174,21 +177,23 @@ __global__ __launch_bounds__(256) void copy_probe_kernel(const uint4 *__restrict
 // ---------------------------------------------------------------------------
 // Host-side launchers.
 // ---------------------------------------------------------------------------
-template <class S, int BX, int NPT, bool NT, bool COPY>
-static hipError_t launch_sweep_t(const void *src, void *dst, const SweepArgs<typename Codec<S>::T> &a,
+template <class F, int BX, int NPT, bool NT, bool COPY>
+static hipError_t launch_sweep_t(const void *src, void *dst, const SweepArgs<typename Codec<typename F::S>::T> &a,
                                  hipStream_t s) {
-  sweep_kernel<S, BX, NPT, NT, COPY><<<dim3(a.nblocks), dim3(BX), 0, s>>>(static_cast<const S *>(src),
+  using S = typename F::S;
+  sweep_kernel<F, BX, NPT, NT, COPY><<<dim3(a.nblocks), dim3(BX), 0, s>>>(static_cast<const S *>(src),
                                                                          static_cast<S *>(dst), a);
   return hipGetLastError();
 }
 
-template <class S, bool COPY>
-static hipError_t launch_sweep_shape(const void *src, void *dst, const SweepArgs<typename Codec<S>::T> &a,
-                                     int bx, int npt, hipStream_t s) {
+template <class F, bool COPY>
+static hipError_t launch_sweep_shape(const void *src, void *dst,
+                                     const SweepArgs<typename Codec<typename F::S>::T> &a, int bx, int npt,
+                                     hipStream_t s) {
   // Non-temporal stores: the destination is not read again before the next
   // step, which streams through far more data than the caches hold.
 #define LBM_CASE(B, P)                                                       \
-  if (bx == B && npt == P) return launch_sweep_t<S, B, P, true, COPY>(src, dst, a, s);
+  if (bx == B && npt == P) return launch_sweep_t<F, B, P, true, COPY>(src, dst, a, s);
   LBM_CASE(64, 1) LBM_CASE(64, 2) LBM_CASE(64, 4)
   LBM_CASE(128, 1) LBM_CASE(128, 2) LBM_CASE(128, 4)
   LBM_CASE(256, 1) LBM_CASE(256, 2) LBM_CASE(256, 4)
@@ -203,13 +208,14 @@ static SweepArgs<T> make_args(const SweepConfig &c) {
   a.nx = c.nx;
   a.ny = c.ny;
   a.nz = c.nz;
-  a.N = size_t(c.nx) * c.ny * c.nz;
+  a.pitch = population_pitch(size_t(c.nx) * c.ny * c.nz);
   const int span = c.block_x * c.nodes_per_thread;
   a.nxc = (c.nx + span - 1) / span;
   a.nblocks = unsigned(a.nxc) * unsigned(c.ny) * unsigned(c.nz);
   a.xcd_remap = c.xcd_remap;
   a.bc_mask = c.bc_mask;
   a.omega = T(1.0 / c.tau);
+  a.key = step_key(c.step);
   for (int f = 0; f < 6; ++f)
     for (int d = 0; d < 3; ++d) a.fv.v[f][d] = T(c.v[f][d]);
   return a;
@@ -219,18 +225,21 @@ hipError_t launch_sweep(const SweepConfig &c, const void *src, void *dst, bool c
   switch (c.storage) {
     case kStoreF64: {
       const auto a = make_args<double>(c);
-      return copy_only ? launch_sweep_shape<double, true>(src, dst, a, c.block_x, c.nodes_per_thread, s)
-                       : launch_sweep_shape<double, false>(src, dst, a, c.block_x, c.nodes_per_thread, s);
+      return copy_only ? launch_sweep_shape<FormF64, true>(src, dst, a, c.block_x, c.nodes_per_thread, s)
+                       : launch_sweep_shape<FormF64, false>(src, dst, a, c.block_x, c.nodes_per_thread, s);
     }
     case kStoreF32: {
       const auto a = make_args<double>(c);
-      return copy_only ? launch_sweep_shape<float, true>(src, dst, a, c.block_x, c.nodes_per_thread, s)
-                       : launch_sweep_shape<float, false>(src, dst, a, c.block_x, c.nodes_per_thread, s);
+      return copy_only ? launch_sweep_shape<FormF32, true>(src, dst, a, c.block_x, c.nodes_per_thread, s)
+                       : launch_sweep_shape<FormF32, false>(src, dst, a, c.block_x, c.nodes_per_thread, s);
     }
-    case kStoreF16: {
+    case kStoreF16:
+    case kStoreF16SR: {
       const auto a = make_args<float>(c);
-      return copy_only ? launch_sweep_shape<_Float16, true>(src, dst, a, c.block_x, c.nodes_per_thread, s)
-                       : launch_sweep_shape<_Float16, false>(src, dst, a, c.block_x, c.nodes_per_thread, s);
+      if (copy_only) return launch_sweep_shape<FormF16, true>(src, dst, a, c.block_x, c.nodes_per_thread, s);
+      return c.storage == kStoreF16 ? launch_sweep_shape<FormF16, false>(src, dst, a, c.block_x, c.nodes_per_thread, s)
+                                    : launch_sweep_shape<FormF16SR, false>(src, dst, a, c.block_x,
+                                                                           c.nodes_per_thread, s);
     }
   }
   return hipErrorInvalidValue;
@@ -238,24 +247,26 @@ hipError_t launch_sweep(const SweepConfig &c, const void *src, void *dst, bool c
 
 static unsigned blocks_for(size_t n, unsigned bs) { return unsigned((n + bs - 1) / bs); }
 
-hipError_t launch_init(int storage, void *f, size_t N, double rho0, const double u0[3], hipStream_t s) {
+hipError_t launch_init(int storage, void *f, size_t N, size_t pitch, double rho0, const double u0[3], hipStream_t s) {
   const dim3 g(blocks_for(N, 256)), b(256);
   switch (storage) {
-    case kStoreF64: init_kernel<double><<<g, b, 0, s>>>(static_cast<double *>(f), N, rho0, u0[0], u0[1], u0[2]); break;
-    case kStoreF32: init_kernel<float><<<g, b, 0, s>>>(static_cast<float *>(f), N, rho0, u0[0], u0[1], u0[2]); break;
-    case kStoreF16: init_kernel<_Float16><<<g, b, 0, s>>>(static_cast<_Float16 *>(f), N, rho0, u0[0], u0[1], u0[2]); break;
+    case kStoreF64: init_kernel<double><<<g, b, 0, s>>>(static_cast<double *>(f), N, pitch, rho0, u0[0], u0[1], u0[2]); break;
+    case kStoreF32: init_kernel<float><<<g, b, 0, s>>>(static_cast<float *>(f), N, pitch, rho0, u0[0], u0[1], u0[2]); break;
+    case kStoreF16:
+    case kStoreF16SR: init_kernel<_Float16><<<g, b, 0, s>>>(static_cast<_Float16 *>(f), N, pitch, rho0, u0[0], u0[1], u0[2]); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_moments(int storage, const void *f, size_t N, size_t n0, size_t count, double *rho, double *u,
+hipError_t launch_moments(int storage, const void *f, size_t pitch, size_t n0, size_t count, double *rho, double *u,
                           double *partials, int nblk, hipStream_t s) {
   const dim3 g(nblk), b(256);
   switch (storage) {
-    case kStoreF64: moments_kernel<double><<<g, b, 0, s>>>(static_cast<const double *>(f), N, n0, count, rho, u, partials); break;
-    case kStoreF32: moments_kernel<float><<<g, b, 0, s>>>(static_cast<const float *>(f), N, n0, count, rho, u, partials); break;
-    case kStoreF16: moments_kernel<_Float16><<<g, b, 0, s>>>(static_cast<const _Float16 *>(f), N, n0, count, rho, u, partials); break;
+    case kStoreF64: moments_kernel<double><<<g, b, 0, s>>>(static_cast<const double *>(f), pitch, n0, count, rho, u, partials); break;
+    case kStoreF32: moments_kernel<float><<<g, b, 0, s>>>(static_cast<const float *>(f), pitch, n0, count, rho, u, partials); break;
+    case kStoreF16:
+    case kStoreF16SR: moments_kernel<_Float16><<<g, b, 0, s>>>(static_cast<const _Float16 *>(f), pitch, n0, count, rho, u, partials); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -266,25 +277,27 @@ hipError_t launch_reduce(const double *partials, int nblk, double *out, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_to_double(int storage, const void *f, size_t N, size_t n0, size_t count, double *out,
+hipError_t launch_to_double(int storage, const void *f, size_t pitch, size_t n0, size_t count, double *out,
                             hipStream_t s) {
   const dim3 g(blocks_for(count, 256)), b(256);
   switch (storage) {
-    case kStoreF64: to_double_kernel<double><<<g, b, 0, s>>>(static_cast<const double *>(f), N, n0, count, out); break;
-    case kStoreF32: to_double_kernel<float><<<g, b, 0, s>>>(static_cast<const float *>(f), N, n0, count, out); break;
-    case kStoreF16: to_double_kernel<_Float16><<<g, b, 0, s>>>(static_cast<const _Float16 *>(f), N, n0, count, out); break;
+    case kStoreF64: to_double_kernel<double><<<g, b, 0, s>>>(static_cast<const double *>(f), pitch, n0, count, out); break;
+    case kStoreF32: to_double_kernel<float><<<g, b, 0, s>>>(static_cast<const float *>(f), pitch, n0, count, out); break;
+    case kStoreF16:
+    case kStoreF16SR: to_double_kernel<_Float16><<<g, b, 0, s>>>(static_cast<const _Float16 *>(f), pitch, n0, count, out); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_from_double(int storage, void *f, size_t N, size_t n0, size_t count, const double *in,
+hipError_t launch_from_double(int storage, void *f, size_t pitch, size_t n0, size_t count, const double *in,
                               hipStream_t s) {
   const dim3 g(blocks_for(count, 256)), b(256);
   switch (storage) {
-    case kStoreF64: from_double_kernel<double><<<g, b, 0, s>>>(static_cast<double *>(f), N, n0, count, in); break;
-    case kStoreF32: from_double_kernel<float><<<g, b, 0, s>>>(static_cast<float *>(f), N, n0, count, in); break;
-    case kStoreF16: from_double_kernel<_Float16><<<g, b, 0, s>>>(static_cast<_Float16 *>(f), N, n0, count, in); break;
+    case kStoreF64: from_double_kernel<double><<<g, b, 0, s>>>(static_cast<double *>(f), pitch, n0, count, in); break;
+    case kStoreF32: from_double_kernel<float><<<g, b, 0, s>>>(static_cast<float *>(f), pitch, n0, count, in); break;
+    case kStoreF16:
+    case kStoreF16SR: from_double_kernel<_Float16><<<g, b, 0, s>>>(static_cast<_Float16 *>(f), pitch, n0, count, in); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -46,8 +46,80 @@ struct Codec<_Float16> {
   static __device__ __forceinline__ _Float16 encode(T v) { return static_cast<_Float16>(v * 256.0f); }
 };
 
-template <class S, bool NT>
-__device__ __forceinline__ void store_elem(S *p, S v) {
+// Storage forms of the sweep: element type S, arithmetic type T and how the
+// new deviations are rounded into S.
+struct FormF64 {
+  using S = double;
+  static constexpr bool kStochastic = false;
+};
+struct FormF32 {
+  using S = float;
+  static constexpr bool kStochastic = false;
+};
+struct FormF16 {
+  using S = _Float16;
+  static constexpr bool kStochastic = false;
+};
+// FP16 with stochastic rounding: h rounds up or down to its two neighbouring
+// half values with probabilities that make the rounding unbiased,
+// E[h] = d * 2^8.  With round-to-nearest, a steady state rounds the same way
+// at every step and the rounding acts as a constant forcing whose effect
+// accumulates; unbiased rounding turns it into zero-mean noise.  The random
+// numbers come from a counter-based hash of (step, node, population), so a
+// lattice's results are reproducible and do not depend on the launch.
+struct FormF16SR {
+  using S = _Float16;
+  static constexpr bool kStochastic = true;
+};
+
+// murmur3 finalizer: a bijective 32-bit mixing function.
+__host__ __device__ __forceinline__ unsigned fmix32(unsigned h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+
+// Key of time step t for the stochastic rounding.
+__host__ __device__ __forceinline__ unsigned step_key(unsigned t) { return fmix32(t * 0x9e3779b1u + 0x7f4a7c15u); }
+
+// d * 2^8 rounded stochastically to half precision; r: 32 random bits.
+__device__ __forceinline__ _Float16 encode_half_sr(float d, unsigned r) {
+  const float x = d * 256.0f;
+  const _Float16 h = static_cast<_Float16>(x);  // nearest
+  const float xf = static_cast<float>(h);
+  const float err = x - xf;  // exact (Sterbenz), |err| <= half the gap
+  const unsigned short b = __builtin_bit_cast(unsigned short, h);
+  const bool up = err > 0.0f;
+  unsigned short b1;  // neighbour of h on the side of x
+  if (b & 0x8000u)
+    b1 = up ? (b == 0x8000u ? 0x0001u : b - 1u) : b + 1u;
+  else
+    b1 = up ? b + 1u : (b == 0u ? 0x8001u : b - 1u);
+  const _Float16 h1 = __builtin_bit_cast(_Float16, b1);
+  const float gap = static_cast<float>(h1) - xf;
+  const float u = float(r >> 8) * 0x1p-24f;  // uniform in [0, 1)
+  return (err != 0.0f && u * gap * (up ? 1.0f : -1.0f) < err * (up ? 1.0f : -1.0f)) ? h1 : h;
+}
+
+template <class F>
+__device__ __forceinline__ typename F::S encode_form(typename Codec<typename F::S>::T v, unsigned r) {
+  if constexpr (F::kStochastic)
+    return encode_half_sr(v, r);
+  else
+    return Codec<typename F::S>::encode(v);
+}
+
+// Pointer into global memory.  Kernels whose buffer addresses come from
+// memory (not from kernel arguments) use it so that the compiler emits global
+// rather than flat loads and stores.
+template <class S>
+using global_ptr = __attribute__((address_space(1))) S *;
+
+template <class S, bool NT, class P>
+__device__ __forceinline__ void store_elem(P p, S v) {
   if constexpr (NT)
     __builtin_nontemporal_store(v, p);
   else
@@ -67,15 +139,77 @@ __device__ __forceinline__ unsigned logical_block(unsigned b, unsigned nblocks, 
 // Lattice extent for the gather.
 struct NodeGeom {
   unsigned nx, ny, nz;
-  size_t N;
+};
+
+// Memory access of one population buffer pair, in elements: load(k, off)
+// reads population k at in-population offset off of the source, store(k, n,
+// v) writes population k of node n of the destination.
+//
+// PtrAccess: plain pointers (kernel arguments, any size).
+template <class S, bool NT>
+struct PtrAccess {
+  const S *__restrict__ src;
+  S *__restrict__ dst;
+  size_t pitch;  // population stride in elements
+  __device__ __forceinline__ S load(int k, unsigned off) const { return src[size_t(k) * pitch + off]; }
+  __device__ __forceinline__ void store(int k, unsigned n, S v) const {
+    store_elem<S, NT>(dst + size_t(k) * pitch + n, v);
+  }
+};
+
+// BufAccess: buffer loads and stores through one resource descriptor per
+// buffer, with the population's start as a scalar offset (for buffers below
+// 4 GiB).  Used where the buffer addresses come from memory: the scalar base
+// plus one 32-bit lane offset per access keeps register pressure low, where
+// 19 + 19 64-bit population bases would not fit in scalar registers.
+template <class S>
+__device__ __forceinline__ S buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  if constexpr (sizeof(S) == 8)
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, int(voff), int(soff), 0));
+  else if constexpr (sizeof(S) == 4)
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), int(soff), 0));
+  else
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b16(r, int(voff), int(soff), 0));
+}
+
+template <class S>
+__device__ __forceinline__ void buf_store_nt(S v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  constexpr int kNonTemporal = 2;  // cache-policy bit "nt" (gfx94x/gfx950)
+  if constexpr (sizeof(S) == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
+                                          int(voff), int(soff), kNonTemporal);
+  else if constexpr (sizeof(S) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, int(voff), int(soff), kNonTemporal);
+  else
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, int(voff), int(soff),
+                                          kNonTemporal);
+}
+
+// Descriptor of a raw buffer (stride 0) of `bytes` bytes at p; the last word
+// holds the gfx9-family data-format bits for untyped dword access.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_buffer(const void *p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), short(0), int(bytes), 0x00020000);
+}
+
+template <class S>
+struct BufAccess {
+  __amdgpu_buffer_rsrc_t src, dst;
+  unsigned pop_bytes;  // population stride in bytes: pitch * sizeof(S)
+  __device__ __forceinline__ S load(int k, unsigned off) const {
+    return buf_load<S>(src, off * unsigned(sizeof(S)), unsigned(k) * pop_bytes);
+  }
+  __device__ __forceinline__ void store(int k, unsigned n, S v) const {
+    buf_store_nt<S>(v, dst, n * unsigned(sizeof(S)), unsigned(k) * pop_bytes);
+  }
 };
 
 // One node update: pull streaming (periodic wrap on every axis; sources
 // beyond a bounded face land on in-bounds values that the boundary rule then
 // overwrites), boundary rule for the face mask, BGK, store.
-template <class S, bool NT, bool COPY, class T>
-__device__ __forceinline__ void update_node(const S *__restrict__ src, S *__restrict__ dst, const NodeGeom &g,
-                                            int x, int y, int z, unsigned bc_mask, T omega, const FaceVel<T> &fv) {
+template <class F, bool COPY, class T, class Access>
+__device__ __forceinline__ void update_node(const Access &mem, const NodeGeom &g, int x, int y, int z,
+                                            unsigned bc_mask, T omega, const FaceVel<T> &fv, unsigned key) {
+  using S = typename F::S;
   const unsigned nx = g.nx, ny = g.ny, nz = g.nz;
   const unsigned ym = y == 0 ? ny - 1 : unsigned(y) - 1, yp = unsigned(y) == ny - 1 ? 0 : unsigned(y) + 1;
   const unsigned zm = z == 0 ? nz - 1 : unsigned(z) - 1, zp = unsigned(z) == nz - 1 ? 0 : unsigned(z) + 1;
@@ -88,8 +222,9 @@ __device__ __forceinline__ void update_node(const S *__restrict__ src, S *__rest
 #pragma unroll
   for (int k = 0; k < 19; ++k) {
     const unsigned off = (yy[cy(k) + 1] + ny * zz[cz(k) + 1]) * nx + xs[cx(k) + 1];
-    raw[k] = src[size_t(k) * g.N + off];
+    raw[k] = mem.load(k, off);
   }
+  const unsigned n = (unsigned(z) * ny + unsigned(y)) * nx + unsigned(x);
   if constexpr (!COPY) {
     T f[19];
 #pragma unroll
@@ -103,12 +238,15 @@ __device__ __forceinline__ void update_node(const S *__restrict__ src, S *__rest
     if (unsigned(z) == nz - 1) m |= bc_mask & 32u;
     if (m) boundary_rule<T>(f, m, fv);
     bgk_collide<T>(f, omega);
+    unsigned r = F::kStochastic ? fmix32(n * 0x9e3779b1u + key) : 0u;
 #pragma unroll
-    for (int k = 0; k < 19; ++k) raw[k] = Codec<S>::encode(f[k]);
+    for (int k = 0; k < 19; ++k) {
+      if constexpr (F::kStochastic) r = r * 1664525u + 1013904223u;  // per-population stream
+      raw[k] = encode_form<F>(f[k], r);
+    }
   }
-  const size_t n = (size_t(z) * ny + unsigned(y)) * nx + unsigned(x);
 #pragma unroll
-  for (int k = 0; k < 19; ++k) store_elem<S, NT>(dst + size_t(k) * g.N + n, raw[k]);
+  for (int k = 0; k < 19; ++k) mem.store(k, n, raw[k]);
 }
 
 }  // namespace lbm

@@ -20,17 +20,17 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_OK, LBM_ERR_ARG, LBM_ERR_OOM, LBM_ERR_HIP, LBM_ERR_STATE, LBM_ERR_NONFINITE = 0, -1, -2, -3, -4, -5
-LBM_STORE_F64, LBM_STORE_F32, LBM_STORE_F16_DEV = 0, 1, 2
+LBM_STORE_F64, LBM_STORE_F32, LBM_STORE_F16_DEV, LBM_STORE_F16_DEV_SR = 0, 1, 2, 3
 LBM_X0, LBM_X1, LBM_Y0, LBM_Y1, LBM_Z0, LBM_Z1 = range(6)
 
-STORAGE_NAMES = {LBM_STORE_F64: "f64", LBM_STORE_F32: "f32", LBM_STORE_F16_DEV: "f16dev"}
+STORAGE_NAMES = {LBM_STORE_F64: "f64", LBM_STORE_F32: "f32", LBM_STORE_F16_DEV: "f16dev", LBM_STORE_F16_DEV_SR: "f16sr"}
 
 # Every symbol include/lbm.h declares.
 EXPORTS = (
     "lbm_create", "lbm_create_on_buffers", "lbm_set_velocity_bc", "lbm_clear_bc", "lbm_step",
     "lbm_moments", "lbm_totals", "lbm_get_populations", "lbm_set_populations", "lbm_state_buffer",
-    "lbm_element_bytes", "lbm_set_launch", "lbm_get_launch", "lbm_probe", "lbm_destroy",
-    "lbm_last_error",
+    "lbm_element_bytes", "lbm_population_pitch", "lbm_set_launch", "lbm_get_launch", "lbm_probe",
+    "lbm_destroy", "lbm_last_error",
     "lbm_job_bytes", "lbm_batch_create", "lbm_batch_submit", "lbm_batch_run_chunk", "lbm_batch_poll",
     "lbm_batch_result", "lbm_batch_set_shape", "lbm_batch_get_shape", "lbm_batch_autotune",
     "lbm_batch_memory", "lbm_batch_destroy",
@@ -74,6 +74,14 @@ def load_library(path: str = LIB_PATH):
         raise FileNotFoundError(
             f"{path} is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
             "or `python paper_0811_4593_amd/build.py`")
+    # One HIP runtime per process: when PyTorch is installed it is imported
+    # first, so that liblbm.so binds to the HIP runtime torch loaded (loading
+    # the system runtime first and torch's afterwards leaves two runtimes that
+    # do not see each other's devices and memory).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     st = ctypes.c_int
     lib.lbm_create.argtypes = [st, st, st, ctypes.c_double, ctypes.c_double, _dp, st, _vp, ctypes.POINTER(_vp)]
@@ -89,6 +97,8 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_state_buffer.argtypes = [_vp, ctypes.POINTER(_vp)]
     lib.lbm_element_bytes.argtypes = [st]
     lib.lbm_element_bytes.restype = ctypes.c_size_t
+    lib.lbm_population_pitch.argtypes = [ctypes.c_size_t]
+    lib.lbm_population_pitch.restype = ctypes.c_size_t
     lib.lbm_set_launch.argtypes = [_vp, st, st, st]
     lib.lbm_get_launch.argtypes = [_vp, ctypes.POINTER(st), ctypes.POINTER(st), ctypes.POINTER(st)]
     lib.lbm_probe.argtypes = [_vp, st, st]
@@ -111,7 +121,8 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_batch_destroy.argtypes = [_vp]
     lib.lbm_batch_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("lbm_element_bytes", "lbm_destroy", "lbm_last_error", "lbm_batch_destroy"):
+        if name not in ("lbm_element_bytes", "lbm_population_pitch", "lbm_destroy", "lbm_last_error",
+                        "lbm_batch_destroy"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -151,6 +162,10 @@ def lbm_last_error() -> str:
 
 def lbm_element_bytes(storage: int) -> int:
     return int(load_library().lbm_element_bytes(int(storage)))
+
+
+def lbm_population_pitch(nodes: int) -> int:
+    return int(load_library().lbm_population_pitch(int(nodes)))
 
 
 def lbm_create(nx, ny, nz, tau, rho0=1.0, u0=(0.0, 0.0, 0.0), storage=LBM_STORE_F32, stream=None) -> int:

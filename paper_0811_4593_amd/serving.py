@@ -14,7 +14,8 @@ import numpy as np
 
 from . import lbm
 
-STORAGE = {"f64": lbm.LBM_STORE_F64, "f32": lbm.LBM_STORE_F32, "f16dev": lbm.LBM_STORE_F16_DEV}
+STORAGE = {"f64": lbm.LBM_STORE_F64, "f32": lbm.LBM_STORE_F32, "f16dev": lbm.LBM_STORE_F16_DEV,
+           "f16sr": lbm.LBM_STORE_F16_DEV_SR}
 
 
 def job_for(spec, storage: str, tol: float = 0.0, max_steps: int = 0):

@@ -98,3 +98,11 @@ def test_binding_refuses_to_run_without_library(tmp_path):
             m.load_library(str(tmp_path / "missing.so"))
     finally:
         m._lib = saved
+
+
+def test_population_pitch(lbm):
+    assert lbm.lbm_population_pitch(64) == 64
+    assert lbm.lbm_population_pitch(65) == 128
+    assert lbm.lbm_population_pitch(1) == 64
+    assert lbm.lbm_population_pitch(1024 * 512 * 512) == 1024 * 512 * 512
+    assert lbm.lbm_population_pitch(221 * 17 * 93) % 64 == 0

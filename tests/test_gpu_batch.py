@@ -35,6 +35,7 @@ MIX = [
     (workloads.duct(70, 9, 5, (0.02, 0.01, -0.015), 0.65), "f16dev"),
     (workloads.all_classes_lattices()[2], "f32"),
     (workloads.duct(21, 11, 13, (0.01, 0.0, 0.02), 1.0), "f64"),
+    (workloads.duct(25, 14, 10, (0.035, 0.01, -0.01), 0.9), "f16sr"),
 ]
 
 
@@ -182,10 +183,12 @@ def test_fp16_and_fp32_forms_against_fp64_velocity():
     _, _, u64 = serving.run_plain(spec, "f64", steps)
     _, _, u32 = serving.run_plain(spec, "f32", steps)
     _, _, u16 = serving.run_plain(spec, "f16dev", steps)
-    e32, e16 = rel_l2(u32, u64), rel_l2(u16, u64)
-    say(f"rel L2 vs f64: f32 {e32:.2e}, f16dev {e16:.2e}")
+    _, _, u16sr = serving.run_plain(spec, "f16sr", steps)
+    e32, e16, e16sr = rel_l2(u32, u64), rel_l2(u16, u64), rel_l2(u16sr, u64)
+    say(f"rel L2 vs f64: f32 {e32:.2e}, f16dev {e16:.2e}, f16sr {e16sr:.2e}")
     assert e32 <= 1e-5
     assert e16 <= 1e-3
+    assert e16sr <= 1e-3
 
 
 def test_serving_loop_small_trace_same_alone_and_in_mix():

@@ -377,3 +377,46 @@ def test_full_size_roofline_duct_sampled_parity():
         lbm.lbm_destroy(h)
         del bufs
         torch.cuda.empty_cache()
+
+
+def _half_gap(x):
+    """Spacing of IEEE half-precision values around |x| (normal range)."""
+    ax = np.maximum(np.abs(x), 2.0 ** -14)
+    return 2.0 ** (np.floor(np.log2(ax)) - 10)
+
+
+@pytest.mark.parametrize("storage,max_gaps", [(lbm.LBM_STORE_F16_DEV, 0.5), (lbm.LBM_STORE_F16_DEV_SR, 1.0)])
+def test_fp16_rounding_of_one_step(storage, max_gaps):
+    """One step from a state exactly representable in the FP16 form: the new
+    scaled deviation h = (f - w) * 2^8 is the oracle's value rounded to half
+    precision -- to the nearest value (RNE form) or to one of the two
+    neighbours, without bias (stochastic form)."""
+    spec = workloads.all_classes_lattices()[1]
+    L = make_oracle(spec)
+    h = make_gpu(spec, storage)
+    try:
+        lbm.lbm_set_populations(h, L.init() * workloads.perturbation(L.shape, 9, 0.05))
+        cur = np.empty(L.shape)
+        lbm.lbm_get_populations(h, cur)  # representable start state
+        expect = L.step(cur)
+        lbm.lbm_step(h, 1)
+        got = np.empty(L.shape)
+        lbm.lbm_get_populations(h, got)
+    finally:
+        lbm.lbm_destroy(h)
+    x = (expect - W[:, None, None, None]) * 256.0
+    hv = (got - W[:, None, None, None]) * 256.0
+    gap = _half_gap(x)
+    # The FP32 arithmetic before the rounding is off by up to ~1e-7 in f
+    # (a few float ulps of the O(0.1..1) intermediates), i.e. 2.6e-5 in units
+    # of h.  Everywhere: |h - x| <= max_gaps * gap + that.  Where the gap is
+    # large against it (|x| >= 0.5, gap >= 2^-11), the rounding itself shows.
+    assert np.all(np.abs(hv - x) <= max_gaps * gap + 256 * 1e-7)
+    big = np.abs(x) >= 0.5
+    e = ((hv - x) / gap)[big]
+    say(f"storage {storage}: {big.sum()} elements, max |err| {np.abs(e).max():.3f} gaps, mean {e.mean():+.4f}, "
+        f"beyond half a gap {np.mean(np.abs(e) > 0.55):.3f}")
+    assert np.abs(e).max() <= max_gaps + 0.06
+    if storage == lbm.LBM_STORE_F16_DEV_SR:
+        assert abs(e.mean()) < 0.02               # unbiased
+        assert np.mean(np.abs(e) > 0.55) > 0.05   # and really stochastic

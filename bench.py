@@ -35,7 +35,7 @@ COUNTERS_FILE = os.path.join(_ROOT, "profiles", "sweep_f32_duct_1024x512x512_cou
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("d3q19.hpp", "lbm_kernels.hip", "lbm_internal.hpp"):
+    for name in ("d3q19.hpp", "node_update.hpp", "lbm_kernels.hip", "lbm_internal.hpp"):
         with open(os.path.join(_ROOT, "paper_0811_4593_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

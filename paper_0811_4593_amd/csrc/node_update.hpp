@@ -86,22 +86,21 @@ __host__ __device__ __forceinline__ unsigned fmix32(unsigned h) {
 __host__ __device__ __forceinline__ unsigned step_key(unsigned t) { return fmix32(t * 0x9e3779b1u + 0x7f4a7c15u); }
 
 // d * 2^8 rounded stochastically to half precision; r: 32 random bits.
+// A float magnitude a = e<<23 | m in the half normal range becomes the half
+// (e - 112)<<10 | m>>13, i.e. (a - 0x38000000) >> 13; adding 13 uniform
+// random bits below the cut before the shift rounds up with probability
+// (m mod 2^13) / 2^13, which makes the rounding unbiased (a carry out of the
+// mantissa moves to the next binade, as it should).  Outside the half normal
+// range (|d| < 2^-22, or |d| near 256) the nearest value is taken.
 __device__ __forceinline__ _Float16 encode_half_sr(float d, unsigned r) {
   const float x = d * 256.0f;
-  const _Float16 h = static_cast<_Float16>(x);  // nearest
-  const float xf = static_cast<float>(h);
-  const float err = x - xf;  // exact (Sterbenz), |err| <= half the gap
-  const unsigned short b = __builtin_bit_cast(unsigned short, h);
-  const bool up = err > 0.0f;
-  unsigned short b1;  // neighbour of h on the side of x
-  if (b & 0x8000u)
-    b1 = up ? (b == 0x8000u ? 0x0001u : b - 1u) : b + 1u;
-  else
-    b1 = up ? b + 1u : (b == 0u ? 0x8001u : b - 1u);
-  const _Float16 h1 = __builtin_bit_cast(_Float16, b1);
-  const float gap = static_cast<float>(h1) - xf;
-  const float u = float(r >> 8) * 0x1p-24f;  // uniform in [0, 1)
-  return (err != 0.0f && u * gap * (up ? 1.0f : -1.0f) < err * (up ? 1.0f : -1.0f)) ? h1 : h;
+  const unsigned u = __builtin_bit_cast(unsigned, x);
+  const unsigned a = u & 0x7fffffffu;
+  if (a >= 0x38800000u && a < 0x477fe000u) {
+    const unsigned h = ((u >> 16) & 0x8000u) | ((a + (r >> 19) - 0x38000000u) >> 13);
+    return __builtin_bit_cast(_Float16, static_cast<unsigned short>(h));
+  }
+  return static_cast<_Float16>(x);
 }
 
 template <class F>

@@ -117,6 +117,14 @@ lbm_status lbm_create_on_buffers(int nx, int ny, int nz, double tau, double rho0
  * |u| >= 1/sqrt(3) (the lattice speed of sound). */
 lbm_status lbm_set_velocity_bc(lbm_lattice *L, lbm_face face, const double u[3]);
 
+/* Body force F (lattice units) acting on every node: the velocity inside
+ * f^eq is shifted by tau F / rho (eq_gravity).  F = 0 (the default) is the
+ * plain method.  With a force, the stored (post-collision) state carries
+ * momentum rho u + F, where u is the post-boundary, pre-collision velocity;
+ * lbm_moments reports the stored state.  Errors: LBM_ERR_ARG (NULL, not
+ * finite). */
+lbm_status lbm_set_body_force(lbm_lattice *L, const double F[3]);
+
 /* Remove the velocity BC of a face.  When both faces of an axis are cleared
  * the axis is periodic again.  Errors: LBM_ERR_ARG. */
 lbm_status lbm_clear_bc(lbm_lattice *L, lbm_face face);
@@ -204,6 +212,7 @@ typedef struct {
   lbm_storage storage;
   unsigned bc_mask;          /* bit f: face f carries bc_velocity[f]; both faces of an axis or none */
   double bc_velocity[6][3];  /* as lbm_set_velocity_bc, same limits */
+  double force[3];           /* body force, as lbm_set_body_force (0: none) */
   double u_ref;              /* velocity scale of delta (> 0), e.g. |inflow velocity| */
   double tol;                /* stop when delta < tol (tol <= 0: never) */
   int max_steps;             /* stop once steps >= max_steps */

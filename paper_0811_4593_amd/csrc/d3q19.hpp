@@ -63,6 +63,15 @@ struct FaceVel {
   T v[6][3];
 };
 
+// Per-lattice parameters of the node update.
+template <class T>
+struct NodeParams {
+  unsigned bc_mask;  // bit f: face f carries a velocity BC
+  T omega;           // 1 / tau
+  T tau_f[3];        // tau * F: velocity shift times rho inside f^eq (body force F)
+  FaceVel<T> fv;
+};
+
 // ---------------------------------------------------------------------------
 // All rules below act on deviations d_k = f_k - w_k from the rest state.
 // Opposite populations have equal weights and the weights of any set of
@@ -176,8 +185,10 @@ __device__ __forceinline__ void boundary_rule(T (&d)[19], unsigned m, const Face
 // deviations: rho = 1 + sum d, rho u = sum d c,
 //   d_k^eq = f_k^eq - w_k = w_k (rho - 1) + w_k rho (3 c.u + 4.5 (c.u)^2 - 1.5 u^2),
 //   d_k <- d_k + omega (d_k^eq - d_k), omega = 1/tau, c_s^2 = 1/3.
+// A body force F enters as the velocity shift tau F / rho inside f^eq
+// (eq_gravity): u = (sum d c + tau F) / rho.
 template <class T>
-__device__ __forceinline__ void bgk_collide(T (&d)[19], T omega) {
+__device__ __forceinline__ void bgk_collide(T (&d)[19], T omega, const T (&tau_f)[3]) {
   T drho = T(0), jx = T(0), jy = T(0), jz = T(0);
 #pragma unroll
   for (int k = 0; k < 19; ++k) {
@@ -188,7 +199,7 @@ __device__ __forceinline__ void bgk_collide(T (&d)[19], T omega) {
   }
   const T rho = T(1) + drho;
   const T ir = T(1) / rho;
-  const T ux = jx * ir, uy = jy * ir, uz = jz * ir;
+  const T ux = (jx + tau_f[0]) * ir, uy = (jy + tau_f[1]) * ir, uz = (jz + tau_f[2]) * ir;
   const T usq15 = T(1.5) * (ux * ux + uy * uy + uz * uz);
 #pragma unroll
   for (int k = 0; k < 19; ++k) {

@@ -35,6 +35,7 @@ struct BatchLat {
   unsigned step_base;  // steps taken before the current launch sequence
   double omega;    // 1 / tau
   double v[6][3];  // face velocities
+  double tau_f[3]; // tau * body force
   double inv_uref; // 1 / velocity scale of the convergence measure
 };
 
@@ -64,12 +65,15 @@ __global__ __launch_bounds__(BX) void batch_sweep_kernel(const BatchLat *__restr
     const unsigned pop_bytes = L.pitch * unsigned(sizeof(S));
     const BufAccess<S> mem{raw_buffer(L.buf[parity], 19u * pop_bytes), raw_buffer(L.buf[parity ^ 1], 19u * pop_bytes),
                            pop_bytes};
-    FaceVel<T> fv;
+    NodeParams<T> prm;
+    prm.bc_mask = L.bc_mask;
+    prm.omega = T(L.omega);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) prm.tau_f[d] = T(L.tau_f[d]);
 #pragma unroll
     for (int f = 0; f < 6; ++f)
 #pragma unroll
-      for (int d = 0; d < 3; ++d) fv.v[f][d] = T(L.v[f][d]);
-    const T omega = T(L.omega);
+      for (int d = 0; d < 3; ++d) prm.fv.v[f][d] = T(L.v[f][d]);
     const unsigned key = step_key(L.step_base + unsigned(s));
     // Coordinates of the lane's first node, then advanced by BX nodes per
     // iteration with carries (one division per tile instead of two per node).
@@ -83,7 +87,7 @@ __global__ __launch_bounds__(BX) void batch_sweep_kernel(const BatchLat *__restr
     const unsigned dz = rows / g.ny;
     const unsigned dy = rows - dz * g.ny;
     for (; n < tile.n1; n += BX) {
-      update_node<F, false>(mem, g, int(x), int(y), int(z), L.bc_mask, omega, fv, key);
+      update_node<F, false>(mem, g, int(x), int(y), int(z), prm, key);
       x += dx;
       const unsigned cxr = x >= g.nx;
       x -= cxr ? g.nx : 0u;
@@ -487,6 +491,7 @@ lbm_status admit(lbm_batch *B) {
     L.bc_mask = J.spec.bc_mask;
     L.omega = 1.0 / J.spec.tau;
     std::memcpy(L.v, J.spec.bc_velocity, sizeof(L.v));
+    for (int d = 0; d < 3; ++d) L.tau_f[d] = J.spec.tau * J.spec.force[d];
     L.inv_uref = 1.0 / J.spec.u_ref;
     B->h_lats[slot] = L;
     B->slot_job[slot] = *it;
@@ -616,6 +621,8 @@ lbm_status lbm_batch_submit(lbm_batch *B, const lbm_job *job, int *job_id) {
     return bfail(LBM_ERR_ARG, "a batch job's population buffer must stay below 4 GiB (19 N element bytes)");
   if (j.max_steps < 0) return bfail(LBM_ERR_ARG, "max_steps must be >= 0");
   if (j.bc_mask & ~63u) return bfail(LBM_ERR_ARG, "bc_mask has bits beyond the six faces");
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(j.force[d])) return bfail(LBM_ERR_ARG, "force is not finite");
   const int size[3] = {j.nx, j.ny, j.nz};
   static const int nrm[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
   for (int a = 0; a < 3; ++a) {

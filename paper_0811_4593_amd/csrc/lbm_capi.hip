@@ -57,6 +57,7 @@ struct lbm_lattice {
   bool owns;
   unsigned bc_mask;
   double v[6][3];
+  double force[3];
   int block_x, npt, xcd;
   unsigned steps;      // steps taken since creation (keys the stochastic rounding)
   double *d_partials;  // [kPartialBlocks * 4]
@@ -222,6 +223,14 @@ lbm_status lbm_clear_bc(lbm_lattice *L, lbm_face face) {
   return LBM_OK;
 }
 
+lbm_status lbm_set_body_force(lbm_lattice *L, const double F[3]) {
+  if (!L || !F) return fail(LBM_ERR_ARG, "NULL argument");
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(F[d])) return fail(LBM_ERR_ARG, "force is not finite");
+  for (int d = 0; d < 3; ++d) L->force[d] = F[d];
+  return LBM_OK;
+}
+
 static lbm::SweepConfig sweep_config(const lbm_lattice *L) {
   lbm::SweepConfig c;
   c.storage = L->storage;
@@ -231,6 +240,7 @@ static lbm::SweepConfig sweep_config(const lbm_lattice *L) {
   c.tau = L->tau;
   c.bc_mask = L->bc_mask;
   std::memcpy(c.v, L->v, sizeof(c.v));
+  std::memcpy(c.force, L->force, sizeof(c.force));
   c.block_x = L->block_x;
   c.nodes_per_thread = L->npt;
   c.xcd_remap = L->xcd;

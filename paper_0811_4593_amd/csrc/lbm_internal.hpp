@@ -30,6 +30,7 @@ struct SweepConfig {
   double tau;
   unsigned bc_mask;  // bit f: face f carries a velocity BC
   double v[6][3];    // face velocities
+  double force[3];   // body force
   int block_x;
   int nodes_per_thread;
   int xcd_remap;
@@ -44,10 +45,8 @@ struct SweepArgs {
   int nxc;           // blocks per x-row
   unsigned nblocks;  // grid size
   int xcd_remap;
-  unsigned bc_mask;
-  T omega;  // 1 / tau
   unsigned key;  // step key of the stochastic rounding
-  FaceVel<T> fv;
+  NodeParams<T> p;
 };
 
 hipError_t launch_sweep(const SweepConfig &c, const void *src, void *dst, bool copy_only, hipStream_t s);

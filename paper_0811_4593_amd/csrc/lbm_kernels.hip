@@ -40,7 +40,7 @@ __global__ __launch_bounds__(BX) void sweep_kernel(const typename F::S *__restri
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
     const int x = (xc * NPT + j) * BX + int(threadIdx.x);
-    if (x < a.nx) update_node<F, COPY>(mem, g, x, y, z, a.bc_mask, a.omega, a.fv, a.key);
+    if (x < a.nx) update_node<F, COPY>(mem, g, x, y, z, a.p, a.key);
   }
 }
 
@@ -213,11 +213,12 @@ static SweepArgs<T> make_args(const SweepConfig &c) {
   a.nxc = (c.nx + span - 1) / span;
   a.nblocks = unsigned(a.nxc) * unsigned(c.ny) * unsigned(c.nz);
   a.xcd_remap = c.xcd_remap;
-  a.bc_mask = c.bc_mask;
-  a.omega = T(1.0 / c.tau);
+  a.p.bc_mask = c.bc_mask;
+  a.p.omega = T(1.0 / c.tau);
+  for (int d = 0; d < 3; ++d) a.p.tau_f[d] = T(c.tau * c.force[d]);
   a.key = step_key(c.step);
   for (int f = 0; f < 6; ++f)
-    for (int d = 0; d < 3; ++d) a.fv.v[f][d] = T(c.v[f][d]);
+    for (int d = 0; d < 3; ++d) a.p.fv.v[f][d] = T(c.v[f][d]);
   return a;
 }
 

@@ -207,7 +207,8 @@ struct BufAccess {
 // overwrites), boundary rule for the face mask, BGK, store.
 template <class F, bool COPY, class T, class Access>
 __device__ __forceinline__ void update_node(const Access &mem, const NodeGeom &g, int x, int y, int z,
-                                            unsigned bc_mask, T omega, const FaceVel<T> &fv, unsigned key) {
+                                            const NodeParams<T> &p, unsigned key) {
+  const unsigned bc_mask = p.bc_mask;
   using S = typename F::S;
   const unsigned nx = g.nx, ny = g.ny, nz = g.nz;
   const unsigned ym = y == 0 ? ny - 1 : unsigned(y) - 1, yp = unsigned(y) == ny - 1 ? 0 : unsigned(y) + 1;
@@ -235,8 +236,8 @@ __device__ __forceinline__ void update_node(const Access &mem, const NodeGeom &g
     if (unsigned(y) == ny - 1) m |= bc_mask & 8u;
     if (z == 0) m |= bc_mask & 16u;
     if (unsigned(z) == nz - 1) m |= bc_mask & 32u;
-    if (m) boundary_rule<T>(f, m, fv);
-    bgk_collide<T>(f, omega);
+    if (m) boundary_rule<T>(f, m, p.fv);
+    bgk_collide<T>(f, p.omega, p.tau_f);
     unsigned r = F::kStochastic ? fmix32(n * 0x9e3779b1u + key) : 0u;
 #pragma unroll
     for (int k = 0; k < 19; ++k) {

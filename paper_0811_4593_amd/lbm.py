@@ -27,7 +27,7 @@ STORAGE_NAMES = {LBM_STORE_F64: "f64", LBM_STORE_F32: "f32", LBM_STORE_F16_DEV: 
 
 # Every symbol include/lbm.h declares.
 EXPORTS = (
-    "lbm_create", "lbm_create_on_buffers", "lbm_set_velocity_bc", "lbm_clear_bc", "lbm_step",
+    "lbm_create", "lbm_create_on_buffers", "lbm_set_velocity_bc", "lbm_set_body_force", "lbm_clear_bc", "lbm_step",
     "lbm_moments", "lbm_totals", "lbm_get_populations", "lbm_set_populations", "lbm_state_buffer",
     "lbm_element_bytes", "lbm_population_pitch", "lbm_set_launch", "lbm_get_launch", "lbm_probe",
     "lbm_destroy", "lbm_last_error",
@@ -45,6 +45,7 @@ class LbmJob(ctypes.Structure):
         ("tau", ctypes.c_double), ("rho0", ctypes.c_double),
         ("storage", ctypes.c_int), ("bc_mask", ctypes.c_uint),
         ("bc_velocity", (ctypes.c_double * 3) * 6),
+        ("force", ctypes.c_double * 3),
         ("u_ref", ctypes.c_double), ("tol", ctypes.c_double), ("max_steps", ctypes.c_int),
     ]
 
@@ -88,6 +89,7 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_create_on_buffers.argtypes = [st, st, st, ctypes.c_double, ctypes.c_double, _dp, st, _vp, _vp, _vp,
                                           ctypes.c_size_t, ctypes.POINTER(_vp)]
     lib.lbm_set_velocity_bc.argtypes = [_vp, st, _dp]
+    lib.lbm_set_body_force.argtypes = [_vp, _dp]
     lib.lbm_clear_bc.argtypes = [_vp, st]
     lib.lbm_step.argtypes = [_vp, st]
     lib.lbm_moments.argtypes = [_vp, _vp, _vp, st]
@@ -189,6 +191,10 @@ def lbm_set_velocity_bc(h, face, u):
     _check(load_library().lbm_set_velocity_bc(h, int(face), _vec3(u)))
 
 
+def lbm_set_body_force(h, F):
+    _check(load_library().lbm_set_body_force(h, _vec3(F)))
+
+
 def lbm_clear_bc(h, face):
     _check(load_library().lbm_clear_bc(h, int(face)))
 
@@ -253,7 +259,8 @@ def lbm_destroy(h):
         load_library().lbm_destroy(h)
 
 
-def make_job(nx, ny, nz, tau, bc, storage=LBM_STORE_F32, rho0=1.0, u_ref=None, tol=0.0, max_steps=0) -> LbmJob:
+def make_job(nx, ny, nz, tau, bc, storage=LBM_STORE_F32, rho0=1.0, u_ref=None, tol=0.0, max_steps=0,
+             force=(0.0, 0.0, 0.0)) -> LbmJob:
     """An lbm_job from a face -> velocity mapping; u_ref defaults to the
     largest prescribed speed (or 1 when every face is at rest)."""
     j = LbmJob()
@@ -267,6 +274,8 @@ def make_job(nx, ny, nz, tau, bc, storage=LBM_STORE_F32, rho0=1.0, u_ref=None, t
             j.bc_velocity[int(face)][a] = float(v[a])
         vmax = max(vmax, float(np.linalg.norm(np.asarray(v, dtype=float))))
     j.bc_mask = mask
+    for a in range(3):
+        j.force[a] = float(force[a])
     j.u_ref = float(u_ref) if u_ref is not None else (vmax if vmax > 0 else 1.0)
     j.tol, j.max_steps = float(tol), int(max_steps)
     return j

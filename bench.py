@@ -184,7 +184,8 @@ def form_precision(args):
         res[name]["rel_L2_u_vs_f64"] = _device_rel_l2(fields[name], fields["f64"])
     return {"form": "precision", "workload": f"duct {spec.nx}x{spec.ny}x{spec.nz}, inlet/outlet (0.04,0.01,0.01), "
             f"no-slip y/z walls, tau {spec.tau}", "steps": steps, "results": res,
-            "f16_over_f32_MLUPS": round(res["f16dev"]["MLUPS"] / res["f32"]["MLUPS"], 3)}
+            "f16_over_f32_MLUPS": round(res["f16dev"]["MLUPS"] / res["f32"]["MLUPS"], 3),
+            "f16sr_over_f32_MLUPS": round(res["f16sr"]["MLUPS"] / res["f32"]["MLUPS"], 3)}
 
 
 def form_batch(args):
@@ -244,7 +245,7 @@ def form_serve(args):
     nodes = [r.spec.nodes for r in trace]
     return {"form": "serve", "requests": len(trace), "rate_per_s": round(rate, 4),
             "calibration_solves_per_s": round(sat, 4), "budget_bytes": budget,
-            "mean_nodes": float(np.mean(nodes)), "storage_f16_share": float(np.mean([r.storage == "f16dev" for r in trace])),
+            "mean_nodes": float(np.mean(nodes)), "storage_f16_share": float(np.mean([r.storage == "f16sr" for r in trace])),
             "served": rep.summary(), "one_at_a_time": base.summary(),
             "steps_mean": float(np.mean(rep.steps)), "converged": int(sum(rep.converged))}
 

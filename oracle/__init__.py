@@ -31,6 +31,8 @@ class _OracleLattice(ctypes.Structure):
         ("bc_set", ctypes.c_int * 6),
         ("v", (ctypes.c_double * 3) * 6),
         ("force", ctypes.c_double * 3),
+        ("bc_pressure", ctypes.c_int * 6),
+        ("rho_bc", ctypes.c_double * 6),
     ]
 
 
@@ -49,6 +51,10 @@ def _load():
         lib.oracle_face_rule.argtypes = [ctypes.c_int, _dp, _dp]
         lib.oracle_edge_rule.argtypes = [ctypes.c_int, ctypes.c_int, _dp]
         lib.oracle_corner_rule.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp]
+        lib.oracle_face_rule_pressure.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp]
+        lib.oracle_edge_rule_pressure.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp]
+        lib.oracle_corner_rule_pressure.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                                    _dp]
         lib.oracle_update_node.argtypes = [ctypes.POINTER(_OracleLattice), ctypes.c_int, ctypes.c_int,
                                            ctypes.c_int, _dp, _dp, _dp]
         lib.oracle_update_node.restype = ctypes.c_int
@@ -114,9 +120,34 @@ def corner_rule(face_a: int, face_b: int, face_c: int, f) -> np.ndarray:
     return g
 
 
+def face_rule_pressure(face: int, rho0: float, v, f) -> np.ndarray:
+    lib = _load()
+    g = _vec(f).copy()
+    lib.oracle_face_rule_pressure(int(face), float(rho0), _ptr(_vec(v)), _ptr(g))
+    return g
+
+
+def edge_rule_pressure(face_a: int, face_b: int, rho0: float, f) -> np.ndarray:
+    lib = _load()
+    g = _vec(f).copy()
+    lib.oracle_edge_rule_pressure(int(face_a), int(face_b), float(rho0), _ptr(g))
+    return g
+
+
+def corner_rule_pressure(face_a: int, face_b: int, face_c: int, rho0: float, f) -> np.ndarray:
+    lib = _load()
+    g = _vec(f).copy()
+    lib.oracle_corner_rule_pressure(int(face_a), int(face_b), int(face_c), float(rho0), _ptr(g))
+    return g
+
+
 @dataclass
 class Lattice:
-    """A lattice description for the oracle: size, tau, face BCs, body force."""
+    """A lattice description for the oracle: size, tau, face BCs, body force.
+
+    bc: face -> prescribed velocity (velocity faces), or the tangential
+    velocity of a pressure face; pressure: face -> prescribed density (the
+    face becomes a pressure face; its tangential velocity is bc.get(face, 0))."""
 
     nx: int
     ny: int
@@ -124,6 +155,7 @@ class Lattice:
     tau: float
     bc: dict = field(default_factory=dict)  # face index -> velocity (3,)
     force: tuple = (0.0, 0.0, 0.0)
+    pressure: dict = field(default_factory=dict)  # face index -> rho0
 
     @property
     def shape(self):
@@ -140,6 +172,10 @@ class Lattice:
             s.bc_set[face] = 1
             for a in range(3):
                 s.v[face][a] = float(v[a])
+        for face, rho0 in self.pressure.items():
+            s.bc_set[face] = 1
+            s.bc_pressure[face] = 1
+            s.rho_bc[face] = float(rho0)
         for a in range(3):
             s.force[a] = float(self.force[a])
         return s

@@ -3,6 +3,9 @@
  * the on-site velocity boundary condition of Hecht & Harting
  * (arXiv:0811.4593).
  *
+ * The pressure (density) variant of the same boundary condition (eq_rhoin,
+ * eq_buried_rho) is included.
+ *
  * TEST INFRASTRUCTURE ONLY: called from tests/, __graft_entry__.smoke() and
  * bench.py's cpu_baseline leg.  Shares nothing with the HIP library.
  *
@@ -77,12 +80,27 @@ void oracle_feq(double rho, const double u[3], double feq[19]) {
 /* eq_Ny) and the Appendix (top, left, right, front, back).  In each rule the */
 /* density and the transverse momentum corrections N use known populations */
 /* only (in-plane and outgoing), so the unknowns can be assigned after.      */
+/*                                                                          */
+/* B is the bracket of eq_uin: in-plane populations plus twice the outgoing */
+/* ones.  Velocity face (rho0 == NULL): all three velocity components are   */
+/* given and rho = B / (1 - v.n) (eq_uin and the Appendix forms).  Pressure */
+/* face (rho0 != NULL): rho = rho0 and the tangential components are given; */
+/* the normal component follows from B (eq_rhoin, Sec. IV; eq_voutx,         */
+/* eq_uinx, eq_uiny, eq_uouty and the top-plane form in the Appendix).  The */
+/* unknowns are then computed by the same formulas in both cases.           */
 /* ------------------------------------------------------------------------ */
 
 /* z = 0, inward normal +z (Sec. IV). */
-static void face_bottom(double *f, double vx, double vy, double vz) {
-  const double rho = (f[1] + f[2] + f[3] + f[4] + f[7] + f[8] + f[11] + f[12] + f[19] +
-                      2.0 * (f[6] + f[10] + f[14] + f[16] + f[18])) / (1.0 - vz);  /* eq_uin */
+static void face_bottom(double *f, double vx, double vy, double vz, const double *rho0) {
+  const double B = f[1] + f[2] + f[3] + f[4] + f[7] + f[8] + f[11] + f[12] + f[19] +
+                   2.0 * (f[6] + f[10] + f[14] + f[16] + f[18]);
+  double rho;
+  if (rho0) {
+    rho = *rho0;
+    vz = 1.0 - B / rho; /* eq_rhoin */
+  } else {
+    rho = B / (1.0 - vz); /* eq_uin */
+  }
   const double Nzx = 0.5 * (f[1] + f[7] + f[8] - (f[2] + f[11] + f[12])) - rho * vx / 3.0;  /* eq_Nx */
   const double Nzy = 0.5 * (f[3] + f[7] + f[11] - (f[4] + f[8] + f[12])) - rho * vy / 3.0;  /* eq_Ny */
   f[5] = f[6] + rho * vz / 3.0;                          /* eq_f5 */
@@ -93,9 +111,16 @@ static void face_bottom(double *f, double vx, double vy, double vz) {
 }
 
 /* z = nz-1, inward normal -z (Appendix, top plane). */
-static void face_top(double *f, double vx, double vy, double vz) {
-  const double rho = (f[1] + f[2] + f[3] + f[4] + f[7] + f[11] + f[12] + f[8] + f[19] +
-                      2.0 * (f[5] + f[9] + f[13] + f[15] + f[17])) / (vz + 1.0);
+static void face_top(double *f, double vx, double vy, double vz, const double *rho0) {
+  const double B = f[1] + f[2] + f[3] + f[4] + f[7] + f[11] + f[12] + f[8] + f[19] +
+                   2.0 * (f[5] + f[9] + f[13] + f[15] + f[17]);
+  double rho;
+  if (rho0) {
+    rho = *rho0;
+    vz = -1.0 + B / rho;
+  } else {
+    rho = B / (vz + 1.0);
+  }
   const double Nzx = 0.5 * (f[1] + f[7] + f[8] - (f[2] + f[11] + f[12])) - rho * vx / 3.0;
   const double Nzy = 0.5 * (f[3] + f[7] + f[11] - (f[4] + f[8] + f[12])) - rho * vy / 3.0;
   f[6] = f[5] - rho * vz / 3.0;
@@ -106,9 +131,16 @@ static void face_top(double *f, double vx, double vy, double vz) {
 }
 
 /* x = 0, inward normal +x (Appendix, left boundary; eq_rhooutx, eq_Nxy, eq_Nxz). */
-static void face_left(double *f, double vx, double vy, double vz) {
-  const double rho = (f[3] + f[4] + f[5] + f[6] + f[15] + f[16] + f[17] + f[18] + f[19] +
-                      2.0 * (f[2] + f[11] + f[12] + f[13] + f[14])) / (1.0 - vx);
+static void face_left(double *f, double vx, double vy, double vz, const double *rho0) {
+  const double B = f[3] + f[4] + f[5] + f[6] + f[15] + f[16] + f[17] + f[18] + f[19] +
+                   2.0 * (f[2] + f[11] + f[12] + f[13] + f[14]);
+  double rho;
+  if (rho0) {
+    rho = *rho0;
+    vx = 1.0 - B / rho; /* eq_voutx */
+  } else {
+    rho = B / (1.0 - vx); /* eq_rhooutx */
+  }
   const double Nxy = 0.5 * (f[3] + f[15] + f[16] - (f[4] + f[17] + f[18])) - rho * vy / 3.0;
   const double Nxz = 0.5 * (f[5] + f[17] + f[15] - (f[6] + f[16] + f[18])) - rho * vz / 3.0;
   f[1] = f[2] + rho * vx / 3.0;
@@ -119,9 +151,16 @@ static void face_left(double *f, double vx, double vy, double vz) {
 }
 
 /* x = nx-1, inward normal -x (Appendix, right boundary; eq_rhoinx). */
-static void face_right(double *f, double vx, double vy, double vz) {
-  const double rho = (f[3] + f[4] + f[5] + f[6] + f[15] + f[16] + f[17] + f[18] + f[19] +
-                      2.0 * (f[1] + f[7] + f[8] + f[9] + f[10])) / (vx + 1.0);
+static void face_right(double *f, double vx, double vy, double vz, const double *rho0) {
+  const double B = f[3] + f[4] + f[5] + f[6] + f[15] + f[16] + f[17] + f[18] + f[19] +
+                   2.0 * (f[1] + f[7] + f[8] + f[9] + f[10]);
+  double rho;
+  if (rho0) {
+    rho = *rho0;
+    vx = -1.0 + B / rho; /* eq_uinx */
+  } else {
+    rho = B / (vx + 1.0); /* eq_rhoinx */
+  }
   const double Nxy = 0.5 * (f[3] + f[15] + f[16] - (f[4] + f[17] + f[18])) - rho * vy / 3.0;
   const double Nxz = 0.5 * (f[5] + f[17] + f[15] - (f[6] + f[16] + f[18])) - rho * vz / 3.0;
   f[2] = f[1] - rho * vx / 3.0;
@@ -132,9 +171,16 @@ static void face_right(double *f, double vx, double vy, double vz) {
 }
 
 /* y = 0, inward normal +y (Appendix, front boundary; eq_rhoiny, eq_Nyx, eq_Nyz). */
-static void face_front(double *f, double vx, double vy, double vz) {
-  const double rho = (f[1] + f[2] + f[5] + f[6] + f[9] + f[10] + f[13] + f[14] + f[19] +
-                      2.0 * (f[4] + f[8] + f[12] + f[17] + f[18])) / (1.0 - vy);
+static void face_front(double *f, double vx, double vy, double vz, const double *rho0) {
+  const double B = f[1] + f[2] + f[5] + f[6] + f[9] + f[10] + f[13] + f[14] + f[19] +
+                   2.0 * (f[4] + f[8] + f[12] + f[17] + f[18]);
+  double rho;
+  if (rho0) {
+    rho = *rho0;
+    vy = 1.0 - B / rho; /* eq_uiny */
+  } else {
+    rho = B / (1.0 - vy); /* eq_rhoiny */
+  }
   const double Nyx = 0.5 * (f[1] + f[9] + f[10] - (f[2] + f[13] + f[14])) - rho * vx / 3.0;
   const double Nyz = 0.5 * (f[5] + f[9] + f[13] - (f[6] + f[10] + f[14])) - rho * vz / 3.0;
   f[3] = f[4] + rho * vy / 3.0;
@@ -145,9 +191,18 @@ static void face_front(double *f, double vx, double vy, double vz) {
 }
 
 /* y = ny-1, inward normal -y (Appendix, back boundary; eq_rhoouty). */
-static void face_back(double *f, double vx, double vy, double vz) {
-  const double rho = (f[1] + f[2] + f[5] + f[6] + f[9] + f[10] + f[13] + f[14] + f[19] +
-                      2.0 * (f[3] + f[7] + f[11] + f[15] + f[16])) / (vy + 1.0);
+static void face_back(double *f, double vx, double vy, double vz, const double *rho0) {
+  const double B = f[1] + f[2] + f[5] + f[6] + f[9] + f[10] + f[13] + f[14] + f[19] +
+                   2.0 * (f[3] + f[7] + f[11] + f[15] + f[16]);
+  double rho;
+  if (rho0) {
+    rho = *rho0;
+    /* eq_uouty.  Reading: the paper labels this component v_x; on the back
+     * plane (normal along y) the component fixed by the density is v_y. */
+    vy = -1.0 + B / rho;
+  } else {
+    rho = B / (vy + 1.0); /* eq_rhoouty */
+  }
   const double Nyx = 0.5 * (f[1] + f[9] + f[10] - (f[2] + f[13] + f[14])) - rho * vx / 3.0;
   const double Nyz = 0.5 * (f[5] + f[9] + f[13] - (f[6] + f[10] + f[14])) - rho * vz / 3.0;
   f[4] = f[3] - rho * vy / 3.0;
@@ -157,22 +212,26 @@ static void face_back(double *f, double vx, double vy, double vz) {
   f[17] = f[16] + rho / 6.0 * (-vy + vz) - Nyz;
 }
 
-static void face_rule_paper(int face, const double v[3], double *f) {
+/* rho0 == NULL: velocity face; else pressure face with density *rho0 (the
+ * normal component of v is then not used). */
+static void face_rule_paper(int face, const double v[3], const double *rho0, double *f) {
   switch (face) {
-    case 0: face_left(f, v[0], v[1], v[2]); break;
-    case 1: face_right(f, v[0], v[1], v[2]); break;
-    case 2: face_front(f, v[0], v[1], v[2]); break;
-    case 3: face_back(f, v[0], v[1], v[2]); break;
-    case 4: face_bottom(f, v[0], v[1], v[2]); break;
-    case 5: face_top(f, v[0], v[1], v[2]); break;
+    case 0: face_left(f, v[0], v[1], v[2], rho0); break;
+    case 1: face_right(f, v[0], v[1], v[2], rho0); break;
+    case 2: face_front(f, v[0], v[1], v[2], rho0); break;
+    case 3: face_back(f, v[0], v[1], v[2], rho0); break;
+    case 4: face_bottom(f, v[0], v[1], v[2], rho0); break;
+    case 5: face_top(f, v[0], v[1], v[2], rho0); break;
   }
 }
 
 /* ------------------------------------------------------------------------ */
 /* Edge rule, no-slip (Sec. V: eq_Nxzy, eq_edge, eq_buried).                 */
-/* n1, n2: inward normals of the two planes meeting at the edge.            */
+/* n1, n2: inward normals of the two planes meeting at the edge.  rho0:      */
+/* NULL, or the prescribed density where the edge borders a pressure plane  */
+/* (eq_buried_rho).                                                          */
 /* ------------------------------------------------------------------------ */
-static void edge_rule_paper(const int n1[3], const int n2[3], double *f) {
+static void edge_rule_paper(const int n1[3], const int n2[3], const double *rho0, double *f) {
   /* Edge direction n1 x n2. */
   const int e[3] = {n1[1] * n2[2] - n1[2] * n2[1], n1[2] * n2[0] - n1[0] * n2[2],
                     n1[0] * n2[1] - n1[1] * n2[0]};
@@ -212,16 +271,23 @@ static void edge_rule_paper(const int n1[3], const int n2[3], double *f) {
     const double bracket = 1.0 - (1.0 - fabs((double)dot_c(i, e))) * (1.0 - fabs((double)dot_c(i, s) / c2));
     if (bracket != 0.0) sum += f[i] * bracket; /* a zero bracket drops the (unknown) term */
   }
-  const double fb = sum / 22.0;
+  double fb = sum / 22.0;
+  /* Edge of a pressure plane (eq_buried_rho): the buried pair and the rest
+   * population take what the prescribed density leaves, in the ratio of
+   * their weights, 1 : 1 : 12 (14/36 in all).  Reading: f^(1,2) inside
+   * eq_buried_rho is the value eq_buried gives, so 22 f^(1,2) is the sum of
+   * the other 16 moving populations and the node's density becomes rho0. */
+  if (rho0) fb = (*rho0 - 22.0 * fb) / 14.0;
   for (int i = 1; i <= 18; ++i)
     if (buried[i]) f[i] = fb;
   f[19] = 12.0 * fb; /* w_19 / w_7 = 12 */
 }
 
 /* ------------------------------------------------------------------------ */
-/* Corner rule, no-slip (Sec. V, eq_corner).                                 */
+/* Corner rule, no-slip (Sec. V, eq_corner); rho0 as for the edge rule.    */
 /* ------------------------------------------------------------------------ */
-static void corner_rule_paper(const int n1[3], const int n2[3], const int n3[3], double *f) {
+static void corner_rule_paper(const int n1[3], const int n2[3], const int n3[3], const double *rho0,
+                              double *f) {
   const int s[3] = {n1[0] + n2[0] + n3[0], n1[1] + n2[1] + n3[1], n1[2] + n2[2] + n3[2]};
   /* Bounce back the populations coming from outside whose opposite is known;
    * the six buried vectors are those with c.(n1+n2+n3) = 0. */
@@ -237,7 +303,11 @@ static void corner_rule_paper(const int n1[3], const int n2[3], const int n3[3],
     const double weight_i = fabs((double)dot_c(i, s) / c2);
     if (weight_i != 0.0) sum += f[i] * weight_i; /* buried (unknown) terms drop out */
   }
-  const double fb = sum / 18.0;
+  double fb = sum / 18.0;
+  /* Corner of a pressure plane: f~ = rho0/18 - f^(1..6).  Reading: f^(1..6)
+   * is the eq_corner value, so the six buried links and the rest population
+   * (18/36 of weight in all) take what the prescribed density leaves. */
+  if (rho0) fb = *rho0 / 18.0 - fb;
   for (int i = 1; i <= 18; ++i)
     if (dot_c(i, s) == 0) f[i] = fb;
   f[19] = 12.0 * fb;
@@ -251,7 +321,7 @@ void oracle_face_rule(int face, const double v[3], double fk[19]) {
   double f[20];
   f[0] = 0.0;
   memcpy(f + 1, fk, 19 * sizeof(double));
-  face_rule_paper(face, v, f);
+  face_rule_paper(face, v, NULL, f);
   memcpy(fk, f + 1, 19 * sizeof(double));
 }
 
@@ -259,7 +329,7 @@ void oracle_edge_rule(int face_a, int face_b, double fk[19]) {
   double f[20];
   f[0] = 0.0;
   memcpy(f + 1, fk, 19 * sizeof(double));
-  edge_rule_paper(NORMAL[face_a], NORMAL[face_b], f);
+  edge_rule_paper(NORMAL[face_a], NORMAL[face_b], NULL, f);
   memcpy(fk, f + 1, 19 * sizeof(double));
 }
 
@@ -267,7 +337,31 @@ void oracle_corner_rule(int face_a, int face_b, int face_c, double fk[19]) {
   double f[20];
   f[0] = 0.0;
   memcpy(f + 1, fk, 19 * sizeof(double));
-  corner_rule_paper(NORMAL[face_a], NORMAL[face_b], NORMAL[face_c], f);
+  corner_rule_paper(NORMAL[face_a], NORMAL[face_b], NORMAL[face_c], NULL, f);
+  memcpy(fk, f + 1, 19 * sizeof(double));
+}
+
+void oracle_face_rule_pressure(int face, double rho0, const double v[3], double fk[19]) {
+  double f[20];
+  f[0] = 0.0;
+  memcpy(f + 1, fk, 19 * sizeof(double));
+  face_rule_paper(face, v, &rho0, f);
+  memcpy(fk, f + 1, 19 * sizeof(double));
+}
+
+void oracle_edge_rule_pressure(int face_a, int face_b, double rho0, double fk[19]) {
+  double f[20];
+  f[0] = 0.0;
+  memcpy(f + 1, fk, 19 * sizeof(double));
+  edge_rule_paper(NORMAL[face_a], NORMAL[face_b], &rho0, f);
+  memcpy(fk, f + 1, 19 * sizeof(double));
+}
+
+void oracle_corner_rule_pressure(int face_a, int face_b, int face_c, double rho0, double fk[19]) {
+  double f[20];
+  f[0] = 0.0;
+  memcpy(f + 1, fk, 19 * sizeof(double));
+  corner_rule_paper(NORMAL[face_a], NORMAL[face_b], NORMAL[face_c], &rho0, f);
   memcpy(fk, f + 1, 19 * sizeof(double));
 }
 
@@ -278,9 +372,20 @@ static int lattice_valid(const oracle_lattice *L) {
   const int n[3] = {L->nx, L->ny, L->nz};
   if (L->nx < 1 || L->ny < 1 || L->nz < 1) return 0;
   if (!(L->tau > 0.5)) return 0;
+  int pressure_axis = -1;
   for (int a = 0; a < 3; ++a) {
     if (L->bc_set[2 * a] != L->bc_set[2 * a + 1]) return 0;
     if (L->bc_set[2 * a] && n[a] < 3) return 0;
+    for (int s = 0; s < 2; ++s) {
+      const int face = 2 * a + s;
+      if (!L->bc_pressure[face]) continue;
+      if (!L->bc_set[face] || !(L->rho_bc[face] > 0.0)) return 0;
+      /* Reading: the paper gives edge and corner rules for a pressure plane
+       * (in- or outlet) meeting no-slip walls; two pressure planes meeting at
+       * an edge are not covered, so pressure planes lie on one axis. */
+      if (pressure_axis >= 0 && pressure_axis != a) return 0;
+      pressure_axis = a;
+    }
   }
   return 1;
 }
@@ -296,7 +401,9 @@ int oracle_update_node(const oracle_lattice *L, int x, int y, int z, const doubl
    * plane of a periodic axis is not a boundary; an edge or corner exists only
    * where two or three boundary planes meet, and edges and corners always
    * take the no-slip rules (Sec. IV end, Sec. V: the inflow must decay to
-   * zero at the edges), also next to an inflow plane. */
+   * zero at the edges), also next to an inflow plane; next to a pressure
+   * plane their buried links and rest population take the pressure closure
+   * (eq_buried_rho, and its corner form in Sec. V). */
   int faces[3], nf = 0;
   const int coord[3] = {x, y, z};
   const int size[3] = {L->nx, L->ny, L->nz};
@@ -304,9 +411,14 @@ int oracle_update_node(const oracle_lattice *L, int x, int y, int z, const doubl
     if (L->bc_set[2 * a] && coord[a] == 0) faces[nf++] = 2 * a;
     if (L->bc_set[2 * a + 1] && coord[a] == size[a] - 1) faces[nf++] = 2 * a + 1;
   }
-  if (nf == 1) face_rule_paper(faces[0], L->v[faces[0]], f);
-  if (nf == 2) edge_rule_paper(NORMAL[faces[0]], NORMAL[faces[1]], f);
-  if (nf == 3) corner_rule_paper(NORMAL[faces[0]], NORMAL[faces[1]], NORMAL[faces[2]], f);
+  /* The density of the node's pressure plane, if it lies on one (at most
+   * one: pressure planes lie on one axis). */
+  const double *rho0 = NULL;
+  for (int q = 0; q < nf; ++q)
+    if (L->bc_pressure[faces[q]]) rho0 = &L->rho_bc[faces[q]];
+  if (nf == 1) face_rule_paper(faces[0], L->v[faces[0]], rho0, f);
+  if (nf == 2) edge_rule_paper(NORMAL[faces[0]], NORMAL[faces[1]], rho0, f);
+  if (nf == 3) corner_rule_paper(NORMAL[faces[0]], NORMAL[faces[1]], NORMAL[faces[2]], rho0, f);
 
   /* Moments (eq_rho, eq_vel), then BGK towards f^eq (eq_bgk, eq_feq).  With a
    * body force the velocity inside f^eq is shifted by tau F / rho

@@ -2,7 +2,7 @@
  * d3q19_oracle.h -- plain FP64 CPU oracle for the D3Q19 BGK lattice Boltzmann
  * step with the on-site Zou-He velocity boundary condition of Hecht & Harting,
  * "Implementation of on-site velocity boundary conditions for D3Q19 lattice
- * Boltzmann" (arXiv:0811.4593).
+ * Boltzmann" (arXiv:0811.4593), and its pressure (density) variant.
  *
  * TEST INFRASTRUCTURE ONLY.  This code exists to check the HIP path; it is
  * called from tests/, from __graft_entry__.smoke() and from bench.py's
@@ -36,6 +36,11 @@ typedef struct {
   double force[3];     /* body force F, applied as the velocity shift
                           tau*F/rho inside f^eq (eq_gravity); 0 for the plain
                           method */
+  int bc_pressure[6];  /* 1: the face (with bc_set) is a pressure face: its
+                          density rho_bc is prescribed and v gives the
+                          tangential velocity only (eq_rhoin).  Pressure
+                          faces must all lie on one axis. */
+  double rho_bc[6];    /* prescribed density of a pressure face (> 0) */
 } oracle_lattice;
 
 /* Lattice tables as the oracle holds them: c[k][3], w[k]. */
@@ -50,6 +55,13 @@ void oracle_feq(double rho, const double u[3], double feq[19]);
 void oracle_face_rule(int face, const double v[3], double f[19]);
 void oracle_edge_rule(int face_a, int face_b, double f[19]);
 void oracle_corner_rule(int face_a, int face_b, int face_c, double f[19]);
+
+/* The same rules for a pressure face (eq_rhoin and the Appendix forms: the
+ * normal velocity follows from rho0; v gives the tangential components) and
+ * for edges and corners bordering a pressure face (eq_buried_rho, Sec. V). */
+void oracle_face_rule_pressure(int face, double rho0, const double v[3], double f[19]);
+void oracle_edge_rule_pressure(int face_a, int face_b, double rho0, double f[19]);
+void oracle_corner_rule_pressure(int face_a, int face_b, int face_c, double rho0, double f[19]);
 
 /* One node: classification, boundary rule, moments, BGK.  pulled[k] is the
  * value streamed into the node along c_k; out[k] the post-collision value.

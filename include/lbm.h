@@ -117,6 +117,20 @@ lbm_status lbm_create_on_buffers(int nx, int ny, int nz, double tau, double rho0
  * |u| >= 1/sqrt(3) (the lattice speed of sound). */
 lbm_status lbm_set_velocity_bc(lbm_lattice *L, lbm_face face, const double u[3]);
 
+/* Prescribe the density rho0 on a face (pressure boundary; Sec. IV eq_rhoin,
+ * Appendix) with the tangential velocity u_t (only its components parallel
+ * to the face are used; NULL: zero).  Each step the normal velocity follows
+ * from rho0 and the known populations, and the unknowns from the same closure
+ * as a velocity face.  Edges and corners of a pressure face take the no-slip
+ * rules with the buried links and rest population set from rho0 (Sec. V,
+ * eq_buried_rho), so every edge and corner node of that face has density
+ * rho0.  Pressure faces must lie on one axis (edges between two pressure
+ * faces are not defined): lbm_step returns LBM_ERR_STATE otherwise.  A face
+ * set with lbm_set_velocity_bc afterwards is a velocity face again.
+ * Errors: LBM_ERR_ARG if L is NULL, the face is invalid, the axis has fewer
+ * than 3 nodes, rho0 is not a positive finite number, or |u_t| >= 1/sqrt(3). */
+lbm_status lbm_set_pressure_bc(lbm_lattice *L, lbm_face face, double rho0, const double u_t[3]);
+
 /* Body force F (lattice units) acting on every node: the velocity inside
  * f^eq is shifted by tau F / rho (eq_gravity).  F = 0 (the default) is the
  * plain method.  With a force, the stored (post-collision) state carries
@@ -125,13 +139,14 @@ lbm_status lbm_set_velocity_bc(lbm_lattice *L, lbm_face face, const double u[3])
  * finite). */
 lbm_status lbm_set_body_force(lbm_lattice *L, const double F[3]);
 
-/* Remove the velocity BC of a face.  When both faces of an axis are cleared
- * the axis is periodic again.  Errors: LBM_ERR_ARG. */
+/* Remove the velocity or pressure BC of a face.  When both faces of an axis
+ * are cleared the axis is periodic again.  Errors: LBM_ERR_ARG. */
 lbm_status lbm_clear_bc(lbm_lattice *L, lbm_face face);
 
 /* Enqueue nsteps >= 0 time steps on the handle's stream; returns without
  * waiting.  Errors: LBM_ERR_ARG (L NULL, nsteps < 0), LBM_ERR_STATE (an axis
- * with a BC on one face only), LBM_ERR_HIP (launch failure). */
+ * with a BC on one face only, pressure faces on more than one axis),
+ * LBM_ERR_HIP (launch failure). */
 lbm_status lbm_step(lbm_lattice *L, int nsteps);
 
 /* Density rho[n] and velocity u[a*N + n] of the stored state (eq_rho,
@@ -210,12 +225,16 @@ typedef struct {
   double tau;                /* > 1/2 */
   double rho0;               /* initial density (> 0); initial velocity 0 */
   lbm_storage storage;
-  unsigned bc_mask;          /* bit f: face f carries bc_velocity[f]; both faces of an axis or none */
-  double bc_velocity[6][3];  /* as lbm_set_velocity_bc, same limits */
+  unsigned bc_mask;          /* bit f: face f is bounded; both faces of an axis or none */
+  double bc_velocity[6][3];  /* as lbm_set_velocity_bc, same limits (pressure faces: see pressure_mask) */
   double force[3];           /* body force, as lbm_set_body_force (0: none) */
   double u_ref;              /* velocity scale of delta (> 0), e.g. |inflow velocity| */
   double tol;                /* stop when delta < tol (tol <= 0: never) */
   int max_steps;             /* stop once steps >= max_steps */
+  unsigned pressure_mask;    /* bit f: face f (also in bc_mask) is a pressure face with density
+                                bc_rho[f] and tangential velocity bc_velocity[f], as
+                                lbm_set_pressure_bc; pressure faces on one axis only */
+  double bc_rho[6];
 } lbm_job;
 
 typedef enum { LBM_JOB_QUEUED = 0, LBM_JOB_RUNNING = 1, LBM_JOB_DONE = 2 } lbm_job_state;

@@ -66,10 +66,13 @@ struct FaceVel {
 // Per-lattice parameters of the node update.
 template <class T>
 struct NodeParams {
-  unsigned bc_mask;  // bit f: face f carries a velocity BC
+  unsigned bc_mask;  // bit f: face f is bounded (velocity or pressure BC)
+  unsigned p_mask;   // bit f: face f is a pressure face (subset of bc_mask)
   T omega;           // 1 / tau
   T tau_f[3];        // tau * F: velocity shift times rho inside f^eq (body force F)
-  FaceVel<T> fv;
+  FaceVel<T> fv;     // velocity faces: the velocity; pressure faces: the
+                     // tangential velocity (normal component zero)
+  T rho_p[6];        // prescribed density of each pressure face
 };
 
 // ---------------------------------------------------------------------------
@@ -99,6 +102,10 @@ struct NodeParams {
 //   in-plane momentum; t_i.M = c_i.M as M is normal to n).  The factor 6 w_i
 //   is rho/3 on the normal link (eq_f5) and rho/6 on the diagonals
 //   (eq_f9-eq_f17); the last two terms are the corrections N (eq_Nx, eq_Ny).
+// Pressure face (Sec. IV eq_rhoin; Appendix): rho = rho0 is prescribed with
+// the tangential velocity, and the normal component follows from the same
+// bracket, v.n = 1 - (1 + sum_{c.n<=0} d + sum_{c.n<0} d) / rho0; the
+// unknowns then take the same formula as above.
 // Edge (two bits; Sec. V, eq_Nxzy, eq_edge, eq_buried) and corner (three
 // bits; eq_corner), both no-slip:
 //   buried links: unknown populations whose opposite is unknown as well
@@ -109,10 +116,15 @@ struct NodeParams {
 //   buried links = (sum of the other moving populations) / D with D = 22
 //   (edge) or 18 (corner) -- in deviations, the weights' share 22/36 or
 //   18/36 cancels against the buried links' own weight 1/36; rest
-//   population = 12 times that.
+//   population = 12 times that.  On an edge or corner of a pressure face the
+//   buried links and the rest population instead take what the prescribed
+//   density leaves, in the ratio of their weights (eq_buried_rho; Sec. V
+//   corner form): in deviations (rho0 - 1 - s) / 14 (edge) or / 18 (corner),
+//   s the sum of the other moving populations.
 // ---------------------------------------------------------------------------
 template <class T>
-__device__ __forceinline__ void boundary_rule(T (&d)[19], unsigned m, const FaceVel<T> &fv) {
+__device__ __forceinline__ void boundary_rule(T (&d)[19], unsigned m, const NodeParams<T> &p) {
+  const FaceVel<T> &fv = p.fv;
   unsigned U = 0;
 #pragma unroll
   for (int b = 0; b < 6; ++b)
@@ -123,16 +135,18 @@ __device__ __forceinline__ void boundary_rule(T (&d)[19], unsigned m, const Face
   const int sz = int((m >> 4) & 1u) - int((m >> 5) & 1u);
   const int nb = __popc(m);
   if (nb == 1) {
-    // Face: n = (sx, sy, sz); velocity of that face.
-    T vx = T(0), vy = T(0), vz = T(0);
+    // Face: n = (sx, sy, sz); velocity (or tangential velocity and density)
+    // of that face.
+    T vx = T(0), vy = T(0), vz = T(0), r0 = T(1);
 #pragma unroll
     for (int b = 0; b < 6; ++b)
       if (m == (1u << b)) {
         vx = fv.v[b][0];
         vy = fv.v[b][1];
         vz = fv.v[b][2];
+        r0 = p.rho_p[b];
       }
-    const T vn = T(sx) * vx + T(sy) * vy + T(sz) * vz;
+    const bool pressure = (m & p.p_mask) != 0u;
     T s_known = T(0), s_out = T(0), Mx = T(0), My = T(0), Mz = T(0);
 #pragma unroll
     for (int k = 0; k < 19; ++k) {
@@ -145,7 +159,13 @@ __device__ __forceinline__ void boundary_rule(T (&d)[19], unsigned m, const Face
       if (cy(k)) My += in_plane ? T(cy(k)) * d[k] : T(0);
       if (cz(k)) Mz += in_plane ? T(cz(k)) * d[k] : T(0);
     }
-    const T rho = (T(1) + s_known + s_out) / (T(1) - vn);
+    const T B = T(1) + s_known + s_out;
+    const T vn_p = T(1) - B / r0;  // pressure face: normal velocity from rho0
+    vx = pressure ? vx + T(sx) * vn_p : vx;
+    vy = pressure ? vy + T(sy) * vn_p : vy;
+    vz = pressure ? vz + T(sz) * vn_p : vz;
+    const T vn = T(sx) * vx + T(sy) * vy + T(sz) * vz;
+    const T rho = pressure ? r0 : B / (T(1) - vn);
     const T rho3 = rho / T(3);
 #pragma unroll
     for (int j = 0; j < 18; ++j) {
@@ -156,7 +176,13 @@ __device__ __forceinline__ void boundary_rule(T (&d)[19], unsigned m, const Face
       d[j] = ((U >> j) & 1u) ? dj : d[j];
     }
   } else {
-    // Edge or corner, no-slip.
+    // Edge or corner, no-slip; density of a bordering pressure face (at most
+    // one: pressure faces lie on one axis).
+    const unsigned pm = m & p.p_mask;
+    T r0 = T(1);
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+      if (pm & (1u << b)) r0 = p.rho_p[b];
     const int ex = (nb == 2 && sx == 0) ? 1 : 0;
     const int ey = (nb == 2 && sy == 0) ? 1 : 0;
     const int ez = (nb == 2 && sz == 0) ? 1 : 0;
@@ -174,7 +200,9 @@ __device__ __forceinline__ void boundary_rule(T (&d)[19], unsigned m, const Face
     T s = T(0);
 #pragma unroll
     for (int k = 0; k < 18; ++k) s += ((bur >> k) & 1u) ? T(0) : d[k];
-    const T db = s / (nb == 2 ? T(22) : T(18));
+    const T db_v = s / (nb == 2 ? T(22) : T(18));
+    const T db_p = (r0 - T(1) - s) / (nb == 2 ? T(14) : T(18));
+    const T db = pm ? db_p : db_v;
 #pragma unroll
     for (int k = 0; k < 18; ++k) d[k] = ((bur >> k) & 1u) ? db : d[k];
     d[18] = T(12) * db;

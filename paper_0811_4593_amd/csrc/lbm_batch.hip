@@ -32,12 +32,17 @@ struct BatchLat {
   unsigned nx, ny, nz, N;
   unsigned pitch;      // population stride in elements
   unsigned bc_mask;
+  unsigned p_mask;     // pressure faces
   unsigned step_base;  // steps taken before the current launch sequence
   double omega;    // 1 / tau
-  double v[6][3];  // face velocities
+  double v[6][3];  // face velocities (pressure faces: tangential velocity)
+  double rho_p[6]; // prescribed densities of the pressure faces
   double tau_f[3]; // tau * body force
   double inv_uref; // 1 / velocity scale of the convergence measure
 };
+
+// Inward unit normals of the faces x0, x1, y0, y1, z0, z1.
+static const int kFaceNormal[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
 
 // A contiguous node range [n0, n1) of one lattice.
 struct BatchTile {
@@ -67,7 +72,10 @@ __global__ __launch_bounds__(BX) void batch_sweep_kernel(const BatchLat *__restr
                            pop_bytes};
     NodeParams<T> prm;
     prm.bc_mask = L.bc_mask;
+    prm.p_mask = L.p_mask;
     prm.omega = T(L.omega);
+#pragma unroll
+    for (int f = 0; f < 6; ++f) prm.rho_p[f] = T(L.rho_p[f]);
 #pragma unroll
     for (int d = 0; d < 3; ++d) prm.tau_f[d] = T(L.tau_f[d]);
 #pragma unroll
@@ -489,8 +497,16 @@ lbm_status admit(lbm_batch *B) {
     L.N = unsigned(N);
     L.pitch = unsigned(pitch);
     L.bc_mask = J.spec.bc_mask;
+    L.p_mask = J.spec.pressure_mask;
     L.omega = 1.0 / J.spec.tau;
     std::memcpy(L.v, J.spec.bc_velocity, sizeof(L.v));
+    for (int f = 0; f < 6; ++f) {
+      if (!((L.p_mask >> f) & 1u)) continue;
+      // pressure face: keep the tangential velocity only
+      const double un = L.v[f][0] * lbm::kFaceNormal[f][0] + L.v[f][1] * lbm::kFaceNormal[f][1] + L.v[f][2] * lbm::kFaceNormal[f][2];
+      for (int d = 0; d < 3; ++d) L.v[f][d] -= un * lbm::kFaceNormal[f][d];
+      L.rho_p[f] = J.spec.bc_rho[f];
+    }
     for (int d = 0; d < 3; ++d) L.tau_f[d] = J.spec.tau * J.spec.force[d];
     L.inv_uref = 1.0 / J.spec.u_ref;
     B->h_lats[slot] = L;
@@ -624,16 +640,28 @@ lbm_status lbm_batch_submit(lbm_batch *B, const lbm_job *job, int *job_id) {
   for (int d = 0; d < 3; ++d)
     if (!std::isfinite(j.force[d])) return bfail(LBM_ERR_ARG, "force is not finite");
   const int size[3] = {j.nx, j.ny, j.nz};
-  static const int nrm[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+  if (j.pressure_mask & ~j.bc_mask) return bfail(LBM_ERR_ARG, "pressure_mask must be a subset of bc_mask");
+  int p_axes = 0;
   for (int a = 0; a < 3; ++a) {
     const unsigned bits = (j.bc_mask >> (2 * a)) & 3u;
-    if (bits == 1u || bits == 2u) return bfail(LBM_ERR_ARG, "axis %d has a velocity BC on one face only", a);
+    if (bits == 1u || bits == 2u) return bfail(LBM_ERR_ARG, "axis %d has a BC on one face only", a);
     if (bits && size[a] < 3) return bfail(LBM_ERR_ARG, "a bounded axis needs at least 3 nodes");
+    p_axes += ((j.pressure_mask >> (2 * a)) & 3u) != 0u;
   }
+  if (p_axes > 1) return bfail(LBM_ERR_ARG, "pressure faces must lie on one axis");
   for (int f = 0; f < 6; ++f) {
     if (!((j.bc_mask >> f) & 1u)) continue;
     const double *u = j.bc_velocity[f];
-    const double un = u[0] * nrm[f][0] + u[1] * nrm[f][1] + u[2] * nrm[f][2];
+    for (int d = 0; d < 3; ++d)
+      if (!std::isfinite(u[d])) return bfail(LBM_ERR_ARG, "face %d velocity is not finite", f);
+    const double un = u[0] * lbm::kFaceNormal[f][0] + u[1] * lbm::kFaceNormal[f][1] + u[2] * lbm::kFaceNormal[f][2];
+    if ((j.pressure_mask >> f) & 1u) {
+      if (!std::isfinite(j.bc_rho[f]) || !(j.bc_rho[f] > 0.0))
+        return bfail(LBM_ERR_ARG, "face %d density must be a positive finite number", f);
+      if (!(u[0] * u[0] + u[1] * u[1] + u[2] * u[2] - un * un < 1.0 / 3.0))
+        return bfail(LBM_ERR_ARG, "face %d tangential velocity out of range (|u_t| < 1/sqrt(3) required)", f);
+      continue;
+    }
     if (!(std::fabs(un) < 1.0) || !(u[0] * u[0] + u[1] * u[1] + u[2] * u[2] < 1.0 / 3.0))
       return bfail(LBM_ERR_ARG, "face %d velocity out of range (|u.n| < 1 and |u| < 1/sqrt(3) required)", f);
   }

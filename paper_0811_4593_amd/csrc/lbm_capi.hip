@@ -56,7 +56,9 @@ struct lbm_lattice {
   int cur;
   bool owns;
   unsigned bc_mask;
+  unsigned p_mask;  // pressure faces (subset of bc_mask)
   double v[6][3];
+  double rho_p[6];
   double force[3];
   int block_x, npt, xcd;
   unsigned steps;      // steps taken since creation (keys the stochastic rounding)
@@ -210,7 +212,33 @@ lbm_status lbm_set_velocity_bc(lbm_lattice *L, lbm_face face, const double u[3])
   const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   if (uu >= 1.0 / 3.0) return fail(LBM_ERR_ARG, "|u| = %g is not below the speed of sound 1/sqrt(3)", std::sqrt(uu));
   L->bc_mask |= 1u << f;
+  L->p_mask &= ~(1u << f);
+  L->rho_p[f] = 0.0;
   for (int d = 0; d < 3; ++d) L->v[f][d] = u[d];
+  return LBM_OK;
+}
+
+lbm_status lbm_set_pressure_bc(lbm_lattice *L, lbm_face face, double rho0, const double u_t[3]) {
+  if (!L) return fail(LBM_ERR_ARG, "NULL handle");
+  const int f = int(face);
+  if (f < 0 || f > 5) return fail(LBM_ERR_ARG, "invalid face %d", f);
+  const int size[3] = {L->nx, L->ny, L->nz};
+  if (size[f / 2] < 3) return fail(LBM_ERR_ARG, "a bounded axis needs at least 3 nodes (axis %d has %d)", f / 2, size[f / 2]);
+  if (!std::isfinite(rho0) || !(rho0 > 0.0)) return fail(LBM_ERR_ARG, "density %g is not a positive finite number", rho0);
+  double t[3] = {0.0, 0.0, 0.0};
+  if (u_t) {
+    for (int d = 0; d < 3; ++d)
+      if (!std::isfinite(u_t[d])) return fail(LBM_ERR_ARG, "velocity is not finite");
+    // Keep the tangential part; the normal component is computed each step.
+    const double un = u_t[0] * kNormal[f][0] + u_t[1] * kNormal[f][1] + u_t[2] * kNormal[f][2];
+    for (int d = 0; d < 3; ++d) t[d] = u_t[d] - un * kNormal[f][d];
+  }
+  const double tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+  if (tt >= 1.0 / 3.0) return fail(LBM_ERR_ARG, "|u_t| = %g is not below the speed of sound 1/sqrt(3)", std::sqrt(tt));
+  L->bc_mask |= 1u << f;
+  L->p_mask |= 1u << f;
+  L->rho_p[f] = rho0;
+  for (int d = 0; d < 3; ++d) L->v[f][d] = t[d];
   return LBM_OK;
 }
 
@@ -219,6 +247,8 @@ lbm_status lbm_clear_bc(lbm_lattice *L, lbm_face face) {
   const int f = int(face);
   if (f < 0 || f > 5) return fail(LBM_ERR_ARG, "invalid face %d", f);
   L->bc_mask &= ~(1u << f);
+  L->p_mask &= ~(1u << f);
+  L->rho_p[f] = 0.0;
   for (int d = 0; d < 3; ++d) L->v[f][d] = 0.0;
   return LBM_OK;
 }
@@ -239,7 +269,9 @@ static lbm::SweepConfig sweep_config(const lbm_lattice *L) {
   c.nz = L->nz;
   c.tau = L->tau;
   c.bc_mask = L->bc_mask;
+  c.p_mask = L->p_mask;
   std::memcpy(c.v, L->v, sizeof(c.v));
+  std::memcpy(c.rho_p, L->rho_p, sizeof(c.rho_p));
   std::memcpy(c.force, L->force, sizeof(c.force));
   c.block_x = L->block_x;
   c.nodes_per_thread = L->npt;
@@ -254,8 +286,12 @@ lbm_status lbm_step(lbm_lattice *L, int nsteps) {
   for (int a = 0; a < 3; ++a) {
     const unsigned bits = (L->bc_mask >> (2 * a)) & 3u;
     if (bits == 1u || bits == 2u)
-      return fail(LBM_ERR_STATE, "axis %d has a velocity BC on one face only; set both faces or none", a);
+      return fail(LBM_ERR_STATE, "axis %d has a BC on one face only; set both faces or none", a);
   }
+  int p_axes = 0;
+  for (int a = 0; a < 3; ++a) p_axes += ((L->p_mask >> (2 * a)) & 3u) != 0u;
+  if (p_axes > 1)
+    return fail(LBM_ERR_STATE, "pressure faces on %d axes: edges between two pressure faces are not defined", p_axes);
   lbm::SweepConfig c = sweep_config(L);
   for (int s = 0; s < nsteps; ++s) {
     c.step = L->steps;

@@ -28,8 +28,10 @@ struct SweepConfig {
   int storage;
   int nx, ny, nz;
   double tau;
-  unsigned bc_mask;  // bit f: face f carries a velocity BC
-  double v[6][3];    // face velocities
+  unsigned bc_mask;  // bit f: face f is bounded (velocity or pressure BC)
+  unsigned p_mask;   // bit f: face f is a pressure face
+  double v[6][3];    // face velocities (pressure faces: tangential velocity)
+  double rho_p[6];   // prescribed densities of the pressure faces
   double force[3];   // body force
   int block_x;
   int nodes_per_thread;

@@ -214,6 +214,8 @@ static SweepArgs<T> make_args(const SweepConfig &c) {
   a.nblocks = unsigned(a.nxc) * unsigned(c.ny) * unsigned(c.nz);
   a.xcd_remap = c.xcd_remap;
   a.p.bc_mask = c.bc_mask;
+  a.p.p_mask = c.p_mask;
+  for (int f = 0; f < 6; ++f) a.p.rho_p[f] = T(c.rho_p[f]);
   a.p.omega = T(1.0 / c.tau);
   for (int d = 0; d < 3; ++d) a.p.tau_f[d] = T(c.tau * c.force[d]);
   a.key = step_key(c.step);

@@ -236,7 +236,7 @@ __device__ __forceinline__ void update_node(const Access &mem, const NodeGeom &g
     if (unsigned(y) == ny - 1) m |= bc_mask & 8u;
     if (z == 0) m |= bc_mask & 16u;
     if (unsigned(z) == nz - 1) m |= bc_mask & 32u;
-    if (m) boundary_rule<T>(f, m, p.fv);
+    if (m) boundary_rule<T>(f, m, p);
     bgk_collide<T>(f, p.omega, p.tau_f);
     unsigned r = F::kStochastic ? fmix32(n * 0x9e3779b1u + key) : 0u;
 #pragma unroll

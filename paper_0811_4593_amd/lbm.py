@@ -27,7 +27,8 @@ STORAGE_NAMES = {LBM_STORE_F64: "f64", LBM_STORE_F32: "f32", LBM_STORE_F16_DEV: 
 
 # Every symbol include/lbm.h declares.
 EXPORTS = (
-    "lbm_create", "lbm_create_on_buffers", "lbm_set_velocity_bc", "lbm_set_body_force", "lbm_clear_bc", "lbm_step",
+    "lbm_create", "lbm_create_on_buffers", "lbm_set_velocity_bc", "lbm_set_pressure_bc", "lbm_set_body_force",
+    "lbm_clear_bc", "lbm_step",
     "lbm_moments", "lbm_totals", "lbm_get_populations", "lbm_set_populations", "lbm_state_buffer",
     "lbm_element_bytes", "lbm_population_pitch", "lbm_set_launch", "lbm_get_launch", "lbm_probe",
     "lbm_destroy", "lbm_last_error",
@@ -47,6 +48,7 @@ class LbmJob(ctypes.Structure):
         ("bc_velocity", (ctypes.c_double * 3) * 6),
         ("force", ctypes.c_double * 3),
         ("u_ref", ctypes.c_double), ("tol", ctypes.c_double), ("max_steps", ctypes.c_int),
+        ("pressure_mask", ctypes.c_uint), ("bc_rho", ctypes.c_double * 6),
     ]
 
 
@@ -89,6 +91,7 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_create_on_buffers.argtypes = [st, st, st, ctypes.c_double, ctypes.c_double, _dp, st, _vp, _vp, _vp,
                                           ctypes.c_size_t, ctypes.POINTER(_vp)]
     lib.lbm_set_velocity_bc.argtypes = [_vp, st, _dp]
+    lib.lbm_set_pressure_bc.argtypes = [_vp, st, ctypes.c_double, _dp]
     lib.lbm_set_body_force.argtypes = [_vp, _dp]
     lib.lbm_clear_bc.argtypes = [_vp, st]
     lib.lbm_step.argtypes = [_vp, st]
@@ -191,6 +194,10 @@ def lbm_set_velocity_bc(h, face, u):
     _check(load_library().lbm_set_velocity_bc(h, int(face), _vec3(u)))
 
 
+def lbm_set_pressure_bc(h, face, rho0, u_t=None):
+    _check(load_library().lbm_set_pressure_bc(h, int(face), float(rho0), None if u_t is None else _vec3(u_t)))
+
+
 def lbm_set_body_force(h, F):
     _check(load_library().lbm_set_body_force(h, _vec3(F)))
 
@@ -260,9 +267,11 @@ def lbm_destroy(h):
 
 
 def make_job(nx, ny, nz, tau, bc, storage=LBM_STORE_F32, rho0=1.0, u_ref=None, tol=0.0, max_steps=0,
-             force=(0.0, 0.0, 0.0)) -> LbmJob:
-    """An lbm_job from a face -> velocity mapping; u_ref defaults to the
-    largest prescribed speed (or 1 when every face is at rest)."""
+             force=(0.0, 0.0, 0.0), pressure=None) -> LbmJob:
+    """An lbm_job from a face -> velocity mapping and a face -> density
+    mapping of pressure faces (whose velocity in `bc`, if any, is the
+    tangential velocity); u_ref defaults to the largest prescribed speed (or
+    1 when every face is at rest)."""
     j = LbmJob()
     j.nx, j.ny, j.nz = int(nx), int(ny), int(nz)
     j.tau, j.rho0, j.storage = float(tau), float(rho0), int(storage)
@@ -273,7 +282,13 @@ def make_job(nx, ny, nz, tau, bc, storage=LBM_STORE_F32, rho0=1.0, u_ref=None, t
         for a in range(3):
             j.bc_velocity[int(face)][a] = float(v[a])
         vmax = max(vmax, float(np.linalg.norm(np.asarray(v, dtype=float))))
+    pmask = 0
+    for face, r in (pressure or {}).items():
+        mask |= 1 << int(face)
+        pmask |= 1 << int(face)
+        j.bc_rho[int(face)] = float(r)
     j.bc_mask = mask
+    j.pressure_mask = pmask
     for a in range(3):
         j.force[a] = float(force[a])
     j.u_ref = float(u_ref) if u_ref is not None else (vmax if vmax > 0 else 1.0)

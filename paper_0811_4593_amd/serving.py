@@ -20,7 +20,7 @@ STORAGE = {"f64": lbm.LBM_STORE_F64, "f32": lbm.LBM_STORE_F32, "f16dev": lbm.LBM
 
 def job_for(spec, storage: str, tol: float = 0.0, max_steps: int = 0):
     return lbm.make_job(spec.nx, spec.ny, spec.nz, spec.tau, spec.bc, STORAGE[storage], spec.rho0,
-                        tol=tol, max_steps=max_steps)
+                        tol=tol, max_steps=max_steps, pressure=getattr(spec, "pressure", None))
 
 
 def percentile(values, q):
@@ -67,12 +67,21 @@ def run_batch(specs, storage="f32", steps=2000, chunk=100, budget_bytes=None, au
         lbm.lbm_batch_destroy(b)
 
 
+def apply_bc(h, spec):
+    """Set the faces of a workload description on a lattice handle."""
+    pressure = getattr(spec, "pressure", {}) or {}
+    for face, v in spec.bc.items():
+        if face not in pressure:
+            lbm.lbm_set_velocity_bc(h, face, v)
+    for face, r in pressure.items():
+        lbm.lbm_set_pressure_bc(h, face, r, spec.bc.get(face))
+
+
 def run_plain(spec, storage="f32", steps=2000, stream=None, launch=None):
     """One lattice with plain lbm_step launches; returns (seconds, rho, u)."""
     h = lbm.lbm_create(spec.nx, spec.ny, spec.nz, spec.tau, spec.rho0, None, STORAGE[storage], stream)
     try:
-        for face, v in spec.bc.items():
-            lbm.lbm_set_velocity_bc(h, face, v)
+        apply_bc(h, spec)
         if launch:
             lbm.lbm_set_launch(h, *launch)
         rho = np.empty(spec.nodes)

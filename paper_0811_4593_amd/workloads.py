@@ -23,9 +23,10 @@ class LatticeSpec:
     ny: int
     nz: int
     tau: float
-    bc: dict = field(default_factory=dict)  # face -> (ux, uy, uz)
+    bc: dict = field(default_factory=dict)  # face -> (ux, uy, uz); pressure faces: tangential velocity
     rho0: float = 1.0
     name: str = ""
+    pressure: dict = field(default_factory=dict)  # face -> prescribed density
 
     @property
     def nodes(self) -> int:
@@ -110,6 +111,27 @@ def serving_trace(count=2000, rate=1.0, seed=1, n_min=16, n_max=256):
         s.name = f"req{i}_{n}^3"
         out.append(Request(i, t, s, storage))
     return out
+
+
+def square_channel(n: int, tau: float = 1.0, drho: float = 1e-3) -> LatticeSpec:
+    """Square channel n x n x (n + 1) (Sec. VI): no-slip walls on the x and y
+    faces, pressure inlet z0 (density 1 + drho/2) and outlet z1 (1 - drho/2)."""
+    w = (0.0, 0.0, 0.0)
+    return LatticeSpec(n, n, n + 1, tau, {0: w, 1: w, 2: w, 3: w},
+                       pressure={4: 1.0 + drho / 2, 5: 1.0 - drho / 2}, name=f"square_channel_{n}")
+
+
+def pressure_classes_lattices():
+    """Small lattices with pressure faces: every node class next to a pressure
+    face, tangential velocities, a pressure inlet with a velocity outlet."""
+    w = (0.0, 0.0, 0.0)
+    return [
+        LatticeSpec(7, 6, 8, 0.8, {0: w, 1: w, 2: w, 3: w}, pressure={4: 1.02, 5: 0.99}, name="pressure_duct_7x6x8"),
+        LatticeSpec(9, 5, 6, 1.2, {0: (0.0, 0.01, -0.02), 2: w, 3: w, 4: (0.01, 0.0, 0.0), 5: w},
+                    pressure={0: 1.01, 1: 0.995}, name="pressure_x_9x5x6"),
+        LatticeSpec(6, 8, 5, 0.7, {0: w, 1: w, 3: (0.0, 0.03, 0.0), 4: w, 5: w}, pressure={2: 1.015},
+                    name="pressure_in_velocity_out_6x8x5"),
+    ]
 
 
 def perturbation(shape, seed: int, amp: float) -> np.ndarray:

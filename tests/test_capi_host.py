@@ -79,6 +79,8 @@ def test_null_handle_calls_fail_cleanly(lbm):
     lib = lbm.load_library()
     v = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
     assert lib.lbm_set_velocity_bc(None, 0, v) == lbm.LBM_ERR_ARG
+    assert lib.lbm_set_pressure_bc(None, 4, 1.0, v) == lbm.LBM_ERR_ARG
+    assert lib.lbm_set_body_force(None, v) == lbm.LBM_ERR_ARG
     assert lib.lbm_step(None, 1) == lbm.LBM_ERR_ARG
     assert lib.lbm_clear_bc(None, 0) == lbm.LBM_ERR_ARG
     assert lib.lbm_set_launch(None, 256, 1, 1) == lbm.LBM_ERR_ARG

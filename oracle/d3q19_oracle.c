@@ -254,7 +254,7 @@ static void edge_rule_paper(const int n1[3], const int n2[3], const double *rho0
   /* Step 2: transverse momentum correction along the edge (eq_Nxzy):
    * N = (f_{+e} - f_{-e}) / 4, spread over the four bounced populations with
    * c.e != 0.  Reading: the correction is subtracted, N (c.e), so that the
-   * momentum along the edge vanishes ("to ensure no-slip"); adding it as the
+   * momentum along the edge vanishes (the no-slip the correction is for); adding it as the
    * text literally says would double that momentum instead. */
   const double N = 0.25 * (f[vector_index(e[0], e[1], e[2])] - f[vector_index(-e[0], -e[1], -e[2])]);
   for (int i = 1; i <= 18; ++i)

@@ -1,8 +1,8 @@
 """Pins of the oracle's no-slip edge and corner rules (Sec. V: eq_Nxzy,
 eq_edge, eq_buried, eq_corner) on random populations.
 
-What the paper fixes: the node velocity is zero after the rule ("to ensure
-no-slip"); the buried links take a common value chosen so that populations at
+What the paper fixes: the node velocity is zero after the rule (the purpose
+of the rule is no-slip); the buried links take a common value chosen so that populations at
 rest reproduce their lattice weights (the 22/36 and 18/36 counts); the rest
 population is 12 times the buried value; for the edge the paper names the
 corrected populations (7, 8, 15, 17 on the y-edge of the bottom and left

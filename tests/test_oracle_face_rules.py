@@ -3,7 +3,7 @@
 The oracle types the six faces' explicit formulas.  These tests check them
 against things the paper fixes in other ways:
   * the prescribed velocity is met exactly and the density obeys the mass
-    balance of eq_uin (Sec. IV: "exactly the one which is imposed");
+    balance of eq_uin (Sec. IV: the velocity the rule yields is the imposed one);
   * the solution of the paper's Ansatz -- non-equilibrium bounce-back on every
     unknown plus two unknown transverse corrections N (eq_f5, eq_f9-eq_f17),
     closed by the moment equations (eq_rho, eq_vx-eq_vz) -- solved here as a

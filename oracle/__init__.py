@@ -33,6 +33,9 @@ class _OracleLattice(ctypes.Structure):
         ("force", ctypes.c_double * 3),
         ("bc_pressure", ctypes.c_int * 6),
         ("rho_bc", ctypes.c_double * 6),
+        ("solid", ctypes.POINTER(ctypes.c_ubyte)),
+        ("face_v", _dp * 6),
+        ("no_transverse", ctypes.c_int),
     ]
 
 
@@ -51,6 +54,7 @@ def _load():
         lib.oracle_face_rule.argtypes = [ctypes.c_int, _dp, _dp]
         lib.oracle_edge_rule.argtypes = [ctypes.c_int, ctypes.c_int, _dp]
         lib.oracle_corner_rule.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp]
+        lib.oracle_face_rule_no_transverse.argtypes = [ctypes.c_int, _dp, _dp]
         lib.oracle_face_rule_pressure.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp]
         lib.oracle_edge_rule_pressure.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp]
         lib.oracle_corner_rule_pressure.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
@@ -120,6 +124,13 @@ def corner_rule(face_a: int, face_b: int, face_c: int, f) -> np.ndarray:
     return g
 
 
+def face_rule_no_transverse(face: int, v, f) -> np.ndarray:
+    lib = _load()
+    g = _vec(f).copy()
+    lib.oracle_face_rule_no_transverse(int(face), _ptr(_vec(v)), _ptr(g))
+    return g
+
+
 def face_rule_pressure(face: int, rho0: float, v, f) -> np.ndarray:
     lib = _load()
     g = _vec(f).copy()
@@ -147,7 +158,12 @@ class Lattice:
 
     bc: face -> prescribed velocity (velocity faces), or the tangential
     velocity of a pressure face; pressure: face -> prescribed density (the
-    face becomes a pressure face; its tangential velocity is bc.get(face, 0))."""
+    face becomes a pressure face; its tangential velocity is bc.get(face, 0)).
+    solid: optional (nz, ny, nx) bool/uint8 array of solid nodes (mid-grid
+    bounce-back); face_v: face -> per-node velocities of a velocity face,
+    shape (n2, n1, 3) over the face's two other axes (z faces: (ny, nx, 3),
+    y faces: (nz, nx, 3), x faces: (nz, ny, 3)); no_transverse: the face rule
+    without the transverse corrections (comparison variant)."""
 
     nx: int
     ny: int
@@ -156,6 +172,9 @@ class Lattice:
     bc: dict = field(default_factory=dict)  # face index -> velocity (3,)
     force: tuple = (0.0, 0.0, 0.0)
     pressure: dict = field(default_factory=dict)  # face index -> rho0
+    solid: np.ndarray | None = None
+    face_v: dict = field(default_factory=dict)  # face index -> per-node velocities
+    no_transverse: bool = False
 
     @property
     def shape(self):
@@ -178,6 +197,20 @@ class Lattice:
             s.rho_bc[face] = float(rho0)
         for a in range(3):
             s.force[a] = float(self.force[a])
+        keep = []
+        if self.solid is not None:
+            sol = np.ascontiguousarray(np.asarray(self.solid).astype(np.uint8).reshape(self.nz, self.ny, self.nx))
+            keep.append(sol)
+            s.solid = sol.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))
+        for face, fv in self.face_v.items():
+            a = np.ascontiguousarray(np.asarray(fv, dtype=np.float64))
+            n_face = {0: self.ny * self.nz, 1: self.nx * self.nz, 2: self.nx * self.ny}[face // 2]
+            assert a.size == 3 * n_face, "face velocity field has the wrong size"
+            keep.append(a)
+            s.bc_set[face] = 1
+            s.face_v[face] = a.ctypes.data_as(_dp)
+        s.no_transverse = int(bool(self.no_transverse))
+        self._keep = keep  # the C struct points into these arrays
         return s
 
     def init(self, rho0: float = 1.0, u0=(0.0, 0.0, 0.0)) -> np.ndarray:

@@ -91,7 +91,7 @@ void oracle_feq(double rho, const double u[3], double feq[19]) {
 /* ------------------------------------------------------------------------ */
 
 /* z = 0, inward normal +z (Sec. IV). */
-static void face_bottom(double *f, double vx, double vy, double vz, const double *rho0) {
+static void face_bottom(double *f, double vx, double vy, double vz, const double *rho0, int noN) {
   const double B = f[1] + f[2] + f[3] + f[4] + f[7] + f[8] + f[11] + f[12] + f[19] +
                    2.0 * (f[6] + f[10] + f[14] + f[16] + f[18]);
   double rho;
@@ -101,8 +101,9 @@ static void face_bottom(double *f, double vx, double vy, double vz, const double
   } else {
     rho = B / (1.0 - vz); /* eq_uin */
   }
-  const double Nzx = 0.5 * (f[1] + f[7] + f[8] - (f[2] + f[11] + f[12])) - rho * vx / 3.0;  /* eq_Nx */
-  const double Nzy = 0.5 * (f[3] + f[7] + f[11] - (f[4] + f[8] + f[12])) - rho * vy / 3.0;  /* eq_Ny */
+  double Nzx = 0.5 * (f[1] + f[7] + f[8] - (f[2] + f[11] + f[12])) - rho * vx / 3.0;  /* eq_Nx */
+  double Nzy = 0.5 * (f[3] + f[7] + f[11] - (f[4] + f[8] + f[12])) - rho * vy / 3.0;  /* eq_Ny */
+  if (noN) Nzx = Nzy = 0.0; /* eq_f9NoNs-eq_f17NoNs: no transverse correction */
   f[5] = f[6] + rho * vz / 3.0;                          /* eq_f5 */
   f[9] = f[14] + rho / 6.0 * (vz + vx) - Nzx;            /* eq_f9 */
   f[13] = f[10] + rho / 6.0 * (vz - vx) + Nzx;           /* eq_f13 */
@@ -111,7 +112,7 @@ static void face_bottom(double *f, double vx, double vy, double vz, const double
 }
 
 /* z = nz-1, inward normal -z (Appendix, top plane). */
-static void face_top(double *f, double vx, double vy, double vz, const double *rho0) {
+static void face_top(double *f, double vx, double vy, double vz, const double *rho0, int noN) {
   const double B = f[1] + f[2] + f[3] + f[4] + f[7] + f[11] + f[12] + f[8] + f[19] +
                    2.0 * (f[5] + f[9] + f[13] + f[15] + f[17]);
   double rho;
@@ -121,8 +122,9 @@ static void face_top(double *f, double vx, double vy, double vz, const double *r
   } else {
     rho = B / (vz + 1.0);
   }
-  const double Nzx = 0.5 * (f[1] + f[7] + f[8] - (f[2] + f[11] + f[12])) - rho * vx / 3.0;
-  const double Nzy = 0.5 * (f[3] + f[7] + f[11] - (f[4] + f[8] + f[12])) - rho * vy / 3.0;
+  double Nzx = 0.5 * (f[1] + f[7] + f[8] - (f[2] + f[11] + f[12])) - rho * vx / 3.0;
+  double Nzy = 0.5 * (f[3] + f[7] + f[11] - (f[4] + f[8] + f[12])) - rho * vy / 3.0;
+  if (noN) Nzx = Nzy = 0.0; /* eq_f9NoNs-eq_f17NoNs: no transverse correction */
   f[6] = f[5] - rho * vz / 3.0;
   f[10] = f[13] + rho / 6.0 * (-vz + vx) - Nzx;
   f[14] = f[9] + rho / 6.0 * (-vz - vx) + Nzx;
@@ -131,7 +133,7 @@ static void face_top(double *f, double vx, double vy, double vz, const double *r
 }
 
 /* x = 0, inward normal +x (Appendix, left boundary; eq_rhooutx, eq_Nxy, eq_Nxz). */
-static void face_left(double *f, double vx, double vy, double vz, const double *rho0) {
+static void face_left(double *f, double vx, double vy, double vz, const double *rho0, int noN) {
   const double B = f[3] + f[4] + f[5] + f[6] + f[15] + f[16] + f[17] + f[18] + f[19] +
                    2.0 * (f[2] + f[11] + f[12] + f[13] + f[14]);
   double rho;
@@ -141,8 +143,9 @@ static void face_left(double *f, double vx, double vy, double vz, const double *
   } else {
     rho = B / (1.0 - vx); /* eq_rhooutx */
   }
-  const double Nxy = 0.5 * (f[3] + f[15] + f[16] - (f[4] + f[17] + f[18])) - rho * vy / 3.0;
-  const double Nxz = 0.5 * (f[5] + f[17] + f[15] - (f[6] + f[16] + f[18])) - rho * vz / 3.0;
+  double Nxy = 0.5 * (f[3] + f[15] + f[16] - (f[4] + f[17] + f[18])) - rho * vy / 3.0;
+  double Nxz = 0.5 * (f[5] + f[17] + f[15] - (f[6] + f[16] + f[18])) - rho * vz / 3.0;
+  if (noN) Nxy = Nxz = 0.0; /* eq_f9NoNs-eq_f17NoNs: no transverse correction */
   f[1] = f[2] + rho * vx / 3.0;
   f[8] = f[11] + rho / 6.0 * (vx - vy) + Nxy;
   f[7] = f[12] + rho / 6.0 * (vx + vy) - Nxy;
@@ -151,7 +154,7 @@ static void face_left(double *f, double vx, double vy, double vz, const double *
 }
 
 /* x = nx-1, inward normal -x (Appendix, right boundary; eq_rhoinx). */
-static void face_right(double *f, double vx, double vy, double vz, const double *rho0) {
+static void face_right(double *f, double vx, double vy, double vz, const double *rho0, int noN) {
   const double B = f[3] + f[4] + f[5] + f[6] + f[15] + f[16] + f[17] + f[18] + f[19] +
                    2.0 * (f[1] + f[7] + f[8] + f[9] + f[10]);
   double rho;
@@ -161,8 +164,9 @@ static void face_right(double *f, double vx, double vy, double vz, const double 
   } else {
     rho = B / (vx + 1.0); /* eq_rhoinx */
   }
-  const double Nxy = 0.5 * (f[3] + f[15] + f[16] - (f[4] + f[17] + f[18])) - rho * vy / 3.0;
-  const double Nxz = 0.5 * (f[5] + f[17] + f[15] - (f[6] + f[16] + f[18])) - rho * vz / 3.0;
+  double Nxy = 0.5 * (f[3] + f[15] + f[16] - (f[4] + f[17] + f[18])) - rho * vy / 3.0;
+  double Nxz = 0.5 * (f[5] + f[17] + f[15] - (f[6] + f[16] + f[18])) - rho * vz / 3.0;
+  if (noN) Nxy = Nxz = 0.0; /* eq_f9NoNs-eq_f17NoNs: no transverse correction */
   f[2] = f[1] - rho * vx / 3.0;
   f[11] = f[8] + rho / 6.0 * (-vx + vy) - Nxy;
   f[12] = f[7] + rho / 6.0 * (-vx - vy) + Nxy;
@@ -171,7 +175,7 @@ static void face_right(double *f, double vx, double vy, double vz, const double 
 }
 
 /* y = 0, inward normal +y (Appendix, front boundary; eq_rhoiny, eq_Nyx, eq_Nyz). */
-static void face_front(double *f, double vx, double vy, double vz, const double *rho0) {
+static void face_front(double *f, double vx, double vy, double vz, const double *rho0, int noN) {
   const double B = f[1] + f[2] + f[5] + f[6] + f[9] + f[10] + f[13] + f[14] + f[19] +
                    2.0 * (f[4] + f[8] + f[12] + f[17] + f[18]);
   double rho;
@@ -181,8 +185,9 @@ static void face_front(double *f, double vx, double vy, double vz, const double 
   } else {
     rho = B / (1.0 - vy); /* eq_rhoiny */
   }
-  const double Nyx = 0.5 * (f[1] + f[9] + f[10] - (f[2] + f[13] + f[14])) - rho * vx / 3.0;
-  const double Nyz = 0.5 * (f[5] + f[9] + f[13] - (f[6] + f[10] + f[14])) - rho * vz / 3.0;
+  double Nyx = 0.5 * (f[1] + f[9] + f[10] - (f[2] + f[13] + f[14])) - rho * vx / 3.0;
+  double Nyz = 0.5 * (f[5] + f[9] + f[13] - (f[6] + f[10] + f[14])) - rho * vz / 3.0;
+  if (noN) Nyx = Nyz = 0.0; /* eq_f9NoNs-eq_f17NoNs: no transverse correction */
   f[3] = f[4] + rho * vy / 3.0;
   f[7] = f[12] + rho / 6.0 * (vy + vx) - Nyx;
   f[11] = f[8] + rho / 6.0 * (vy - vx) + Nyx;
@@ -191,7 +196,7 @@ static void face_front(double *f, double vx, double vy, double vz, const double 
 }
 
 /* y = ny-1, inward normal -y (Appendix, back boundary; eq_rhoouty). */
-static void face_back(double *f, double vx, double vy, double vz, const double *rho0) {
+static void face_back(double *f, double vx, double vy, double vz, const double *rho0, int noN) {
   const double B = f[1] + f[2] + f[5] + f[6] + f[9] + f[10] + f[13] + f[14] + f[19] +
                    2.0 * (f[3] + f[7] + f[11] + f[15] + f[16]);
   double rho;
@@ -203,8 +208,9 @@ static void face_back(double *f, double vx, double vy, double vz, const double *
   } else {
     rho = B / (vy + 1.0); /* eq_rhoouty */
   }
-  const double Nyx = 0.5 * (f[1] + f[9] + f[10] - (f[2] + f[13] + f[14])) - rho * vx / 3.0;
-  const double Nyz = 0.5 * (f[5] + f[9] + f[13] - (f[6] + f[10] + f[14])) - rho * vz / 3.0;
+  double Nyx = 0.5 * (f[1] + f[9] + f[10] - (f[2] + f[13] + f[14])) - rho * vx / 3.0;
+  double Nyz = 0.5 * (f[5] + f[9] + f[13] - (f[6] + f[10] + f[14])) - rho * vz / 3.0;
+  if (noN) Nyx = Nyz = 0.0; /* eq_f9NoNs-eq_f17NoNs: no transverse correction */
   f[4] = f[3] - rho * vy / 3.0;
   f[12] = f[7] + rho / 6.0 * (-vy - vx) + Nyx;
   f[8] = f[11] + rho / 6.0 * (-vy + vx) - Nyx;
@@ -213,15 +219,17 @@ static void face_back(double *f, double vx, double vy, double vz, const double *
 }
 
 /* rho0 == NULL: velocity face; else pressure face with density *rho0 (the
- * normal component of v is then not used). */
-static void face_rule_paper(int face, const double v[3], const double *rho0, double *f) {
+ * normal component of v is then not used).  noN: comparison variant without
+ * the transverse corrections (Sec. IV, eq_f9NoNs-eq_f17NoNs: non-equilibrium
+ * bounce-back of every unknown, an over-determined system). */
+static void face_rule_paper(int face, const double v[3], const double *rho0, int noN, double *f) {
   switch (face) {
-    case 0: face_left(f, v[0], v[1], v[2], rho0); break;
-    case 1: face_right(f, v[0], v[1], v[2], rho0); break;
-    case 2: face_front(f, v[0], v[1], v[2], rho0); break;
-    case 3: face_back(f, v[0], v[1], v[2], rho0); break;
-    case 4: face_bottom(f, v[0], v[1], v[2], rho0); break;
-    case 5: face_top(f, v[0], v[1], v[2], rho0); break;
+    case 0: face_left(f, v[0], v[1], v[2], rho0, noN); break;
+    case 1: face_right(f, v[0], v[1], v[2], rho0, noN); break;
+    case 2: face_front(f, v[0], v[1], v[2], rho0, noN); break;
+    case 3: face_back(f, v[0], v[1], v[2], rho0, noN); break;
+    case 4: face_bottom(f, v[0], v[1], v[2], rho0, noN); break;
+    case 5: face_top(f, v[0], v[1], v[2], rho0, noN); break;
   }
 }
 
@@ -321,7 +329,15 @@ void oracle_face_rule(int face, const double v[3], double fk[19]) {
   double f[20];
   f[0] = 0.0;
   memcpy(f + 1, fk, 19 * sizeof(double));
-  face_rule_paper(face, v, NULL, f);
+  face_rule_paper(face, v, NULL, 0, f);
+  memcpy(fk, f + 1, 19 * sizeof(double));
+}
+
+void oracle_face_rule_no_transverse(int face, const double v[3], double fk[19]) {
+  double f[20];
+  f[0] = 0.0;
+  memcpy(f + 1, fk, 19 * sizeof(double));
+  face_rule_paper(face, v, NULL, 1, f);
   memcpy(fk, f + 1, 19 * sizeof(double));
 }
 
@@ -345,7 +361,7 @@ void oracle_face_rule_pressure(int face, double rho0, const double v[3], double 
   double f[20];
   f[0] = 0.0;
   memcpy(f + 1, fk, 19 * sizeof(double));
-  face_rule_paper(face, v, &rho0, f);
+  face_rule_paper(face, v, &rho0, 0, f);
   memcpy(fk, f + 1, 19 * sizeof(double));
 }
 
@@ -380,6 +396,7 @@ static int lattice_valid(const oracle_lattice *L) {
       const int face = 2 * a + s;
       if (!L->bc_pressure[face]) continue;
       if (!L->bc_set[face] || !(L->rho_bc[face] > 0.0)) return 0;
+      if (L->face_v[face]) return 0; /* per-node velocities are for velocity faces */
       /* Reading: the paper gives edge and corner rules for a pressure plane
        * (in- or outlet) meeting no-slip walls; two pressure planes meeting at
        * an edge are not covered, so pressure planes lie on one axis. */
@@ -416,7 +433,19 @@ int oracle_update_node(const oracle_lattice *L, int x, int y, int z, const doubl
   const double *rho0 = NULL;
   for (int q = 0; q < nf; ++q)
     if (L->bc_pressure[faces[q]]) rho0 = &L->rho_bc[faces[q]];
-  if (nf == 1) face_rule_paper(faces[0], L->v[faces[0]], rho0, f);
+  if (nf == 1) {
+    /* Velocity of the face: uniform, or this node's entry of a per-node
+     * field (e.g. the parabolic inflow of eq_pois, Sec. VI). */
+    const double *v = L->v[faces[0]];
+    const double *fld = L->face_v[faces[0]];
+    if (fld) {
+      const int a = faces[0] / 2;
+      const size_t idx = a == 0 ? (size_t)y + (size_t)L->ny * z
+                                : (a == 1 ? (size_t)x + (size_t)L->nx * z : (size_t)x + (size_t)L->nx * y);
+      v = fld + 3 * idx;
+    }
+    face_rule_paper(faces[0], v, rho0, L->no_transverse, f);
+  }
   if (nf == 2) edge_rule_paper(NORMAL[faces[0]], NORMAL[faces[1]], rho0, f);
   if (nf == 3) corner_rule_paper(NORMAL[faces[0]], NORMAL[faces[1]], NORMAL[faces[2]], rho0, f);
 
@@ -481,10 +510,24 @@ int oracle_step(const oracle_lattice *L, const double *fin, double *fout, double
                 inside = 0;
             }
           }
-          pulled[i - 1] = inside ? fin[(size_t)(i - 1) * N + (size_t)s[0] + (size_t)nx * ((size_t)s[1] + (size_t)ny * s[2])]
-                                 : NAN;
+          const size_t src = (size_t)s[0] + (size_t)nx * ((size_t)s[1] + (size_t)ny * s[2]);
+          const size_t here = (size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z);
+          if (!inside)
+            pulled[i - 1] = NAN;
+          else if (L->solid && L->solid[src])
+            /* Mid-grid bounce-back (Sec. III): the population sent towards
+             * the solid neighbour returns reversed after one step. */
+            pulled[i - 1] = fin[(size_t)(opposite(i) - 1) * N + here];
+          else
+            pulled[i - 1] = fin[(size_t)(i - 1) * N + src];
         }
         const size_t n = (size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z);
+        if (L->solid && L->solid[n]) {
+          /* Solid node: not part of the fluid; its populations stay as they are. */
+          for (int k = 0; k < 19; ++k) fout[(size_t)k * N + n] = fin[(size_t)k * N + n];
+          if (u_pre) u_pre[n] = u_pre[N + n] = u_pre[2 * N + n] = 0.0;
+          continue;
+        }
         double out[19], up[3];
         oracle_update_node(L, x, y, z, pulled, out, up);
         for (int k = 0; k < 19; ++k) fout[(size_t)k * N + n] = out[k];

@@ -41,6 +41,16 @@ typedef struct {
                           tangential velocity only (eq_rhoin).  Pressure
                           faces must all lie on one axis. */
   double rho_bc[6];    /* prescribed density of a pressure face (> 0) */
+  const unsigned char *solid; /* NULL, or [N] flags: 1 = solid node.  A
+                          population whose streaming source is a solid node
+                          is bounced back at the fluid node (mid-grid
+                          bounce-back, Sec. III); solid nodes keep their
+                          populations unchanged. */
+  const double *face_v[6]; /* NULL, or the per-node velocity of a velocity
+                          face, [n_face][3]; face node order: x faces
+                          y + ny*z, y faces x + nx*z, z faces x + nx*y */
+  int no_transverse;   /* 1: face rule without the transverse corrections N
+                          (eq_f9NoNs-eq_f17NoNs; comparison variant) */
 } oracle_lattice;
 
 /* Lattice tables as the oracle holds them: c[k][3], w[k]. */
@@ -53,6 +63,9 @@ void oracle_feq(double rho, const double u[3], double feq[19]);
  * node (k-ordered).  Unknown entries may hold anything (NaN included); they
  * are overwritten and never read. */
 void oracle_face_rule(int face, const double v[3], double f[19]);
+/* Comparison variant of the face rule without the transverse corrections N
+ * (eq_f9NoNs-eq_f17NoNs). */
+void oracle_face_rule_no_transverse(int face, const double v[3], double f[19]);
 void oracle_edge_rule(int face_a, int face_b, double f[19]);
 void oracle_corner_rule(int face_a, int face_b, int face_c, double f[19]);
 

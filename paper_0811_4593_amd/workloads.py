@@ -134,6 +134,55 @@ def pressure_classes_lattices():
     ]
 
 
+@dataclass
+class ChannelSetup:
+    """A channel through the box with staircase walls of solid nodes and
+    per-node inflow/outflow velocities on the z faces."""
+    spec: LatticeSpec
+    solid: np.ndarray      # (nz, ny, nx) uint8, 1 = solid
+    face_v: dict           # face -> (ny, nx, 3) velocities of the z faces
+    centre: np.ndarray     # (nz,) channel centre line x_c(z)
+    half_width: float      # along x
+    direction: np.ndarray  # unit vector of the channel axis
+    v0: float              # centre-line speed
+
+
+def tilted_channel(scale: int = 1, straight: bool = False, v0: float = 0.02, tau: float = 1.0,
+                   normal_inflow: bool = False, ny: int | None = None) -> ChannelSetup:
+    """The tilted channel of Sec. VI: box 64 x 8 x 128 (times `scale`), y
+    periodic, channel 20 nodes wide along x (times `scale`) whose centre line
+    runs from x = 11.5 at z = 0 to x = 51.5 at z = 127 (slope 40/127 for
+    scale 1, the same angle for larger scales), solid nodes outside the
+    channel, and the parabolic Poiseuille velocity (eq_pois) along the
+    channel axis prescribed on the channel's nodes of the z = 0 and z = nz-1
+    planes.  straight: the same channel along z through the box centre.
+    normal_inflow: prescribe only the z component of that velocity.  ny
+    overrides the periodic depth (the flow does not depend on y)."""
+    nx, nz = 64 * scale, 128 * scale
+    ny = 8 * scale if ny is None else int(ny)
+    slope = 0.0 if straight else 40.0 / 127.0
+    x0, z0 = (nx - 1) / 2.0, (nz - 1) / 2.0
+    z = np.arange(nz, dtype=float)
+    centre = x0 + slope * (z - z0)
+    half = 10.0 * scale
+    x = np.arange(nx, dtype=float)
+    dist = x[None, :] - centre[:, None]               # (nz, nx)
+    fluid = np.abs(dist) < half
+    solid = np.broadcast_to((~fluid)[:, None, :], (nz, ny, nx)).astype(np.uint8)
+    direction = np.array([slope, 0.0, 1.0]) / np.hypot(slope, 1.0)
+    face_v = {}
+    for face, zi in ((4, 0), (5, nz - 1)):
+        prof = np.where(fluid[zi], v0 * (1.0 - (dist[zi] / half) ** 2), 0.0)  # eq_pois
+        v = prof[:, None] * direction[None, :]
+        if normal_inflow:
+            v[:, 0] = 0.0
+            v[:, 1] = 0.0
+        face_v[face] = np.ascontiguousarray(np.broadcast_to(v[None, :, :], (ny, nx, 3)))
+    name = ("straight" if straight else "tilted") + f"_channel_x{scale}"
+    spec = LatticeSpec(nx, ny, nz, tau, {4: (0.0, 0.0, 0.0), 5: (0.0, 0.0, 0.0)}, name=name)
+    return ChannelSetup(spec, np.ascontiguousarray(solid), face_v, centre, half, direction, v0)
+
+
 def perturbation(shape, seed: int, amp: float) -> np.ndarray:
     """Multiplicative noise 1 + amp * U(-1, 1) of the given shape."""
     rng = np.random.default_rng(seed)

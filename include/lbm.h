@@ -131,6 +131,37 @@ lbm_status lbm_set_velocity_bc(lbm_lattice *L, lbm_face face, const double u[3])
  * than 3 nodes, rho0 is not a positive finite number, or |u_t| >= 1/sqrt(3). */
 lbm_status lbm_set_pressure_bc(lbm_lattice *L, lbm_face face, double rho0, const double u_t[3]);
 
+/* Per-node velocities of a velocity face: v[3 * i + d] is component d at face
+ * node i, where i = y + ny*z on the x faces, x + nx*z on the y faces and
+ * x + nx*y on the z faces (host memory, copied before return; the caller
+ * keeps ownership).  The face becomes a velocity face; each entry obeys the
+ * limits of lbm_set_velocity_bc.  Used for inflow profiles such as the
+ * parabolic Poiseuille velocity of the tilted channel (Sec. VI, eq_pois).
+ * v = NULL removes the field (the face keeps its uniform velocity).
+ * lbm_set_velocity_bc, lbm_set_pressure_bc and lbm_clear_bc on the face also
+ * remove it.  Errors: LBM_ERR_ARG, LBM_ERR_OOM, LBM_ERR_HIP. */
+lbm_status lbm_set_velocity_field(lbm_lattice *L, lbm_face face, const double *v);
+
+/* Solid nodes: solid[n] != 0 marks node n (n = x + nx*(y + ny*z), host
+ * memory, N bytes, copied before return) as solid.  A fluid node whose
+ * streaming source is solid receives its own opposite population of the
+ * previous step (mid-grid bounce-back, Sec. III; the wall lies half-way
+ * between the two nodes); solid nodes keep their populations unchanged.  A
+ * solid node on a bounded face takes no boundary rule.  solid = NULL removes
+ * the mask.  Lattices with a mask or a face velocity field are advanced by
+ * the extended sweep (one node per thread, the mask read as 1 byte per node
+ * and its neighbours, mostly from cache).  Errors: LBM_ERR_ARG, LBM_ERR_OOM,
+ * LBM_ERR_HIP. */
+lbm_status lbm_set_solid_mask(lbm_lattice *L, const unsigned char *solid);
+
+/* Rule options (bit mask): LBM_RULE_NO_TRANSVERSE applies the face rule
+ * without the transverse corrections N (non-equilibrium bounce-back of every
+ * unknown, Sec. IV eq_f9NoNs-eq_f17NoNs): the comparison variant of the
+ * paper's tilted-channel test, not a recommended setting.  0 (default): the
+ * paper's rule.  Errors: LBM_ERR_ARG (NULL, unknown bits). */
+#define LBM_RULE_NO_TRANSVERSE 1u
+lbm_status lbm_set_rule_options(lbm_lattice *L, unsigned flags);
+
 /* Body force F (lattice units) acting on every node: the velocity inside
  * f^eq is shifted by tau F / rho (eq_gravity).  F = 0 (the default) is the
  * plain method.  With a force, the stored (post-collision) state carries

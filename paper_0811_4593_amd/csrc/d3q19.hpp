@@ -73,7 +73,30 @@ struct NodeParams {
   FaceVel<T> fv;     // velocity faces: the velocity; pressure faces: the
                      // tangential velocity (normal component zero)
   T rho_p[6];        // prescribed density of each pressure face
+  unsigned rule_flags;  // kRuleNoTransverse: face rule without the corrections N
 };
+
+// Comparison variant of the face rule: non-equilibrium bounce-back of every
+// unknown without the transverse corrections N (Sec. IV, eq_f9NoNs-eq_f17NoNs).
+constexpr unsigned kRuleNoTransverse = 1u;
+
+// Velocity (velocity face) or tangential velocity and density (pressure face)
+// of the face a node with the single-face mask m lies on.
+template <class T>
+__device__ __forceinline__ void face_values(unsigned m, const NodeParams<T> &p, T &vx, T &vy, T &vz, T &r0) {
+  vx = T(0);
+  vy = T(0);
+  vz = T(0);
+  r0 = T(1);
+#pragma unroll
+  for (int b = 0; b < 6; ++b)
+    if (m == (1u << b)) {
+      vx = p.fv.v[b][0];
+      vy = p.fv.v[b][1];
+      vz = p.fv.v[b][2];
+      r0 = p.rho_p[b];
+    }
+}
 
 // ---------------------------------------------------------------------------
 // All rules below act on deviations d_k = f_k - w_k from the rest state.
@@ -122,9 +145,11 @@ struct NodeParams {
 //   corner form): in deviations (rho0 - 1 - s) / 14 (edge) or / 18 (corner),
 //   s the sum of the other moving populations.
 // ---------------------------------------------------------------------------
+// (vx, vy, vz, r0): the face values of a face node (face_values, or a
+// per-node field); not used on edges and corners.
 template <class T>
-__device__ __forceinline__ void boundary_rule(T (&d)[19], unsigned m, const NodeParams<T> &p) {
-  const FaceVel<T> &fv = p.fv;
+__device__ __forceinline__ void boundary_rule(T (&d)[19], unsigned m, const NodeParams<T> &p, T vx, T vy, T vz,
+                                              T r0) {
   unsigned U = 0;
 #pragma unroll
   for (int b = 0; b < 6; ++b)
@@ -135,18 +160,9 @@ __device__ __forceinline__ void boundary_rule(T (&d)[19], unsigned m, const Node
   const int sz = int((m >> 4) & 1u) - int((m >> 5) & 1u);
   const int nb = __popc(m);
   if (nb == 1) {
-    // Face: n = (sx, sy, sz); velocity (or tangential velocity and density)
-    // of that face.
-    T vx = T(0), vy = T(0), vz = T(0), r0 = T(1);
-#pragma unroll
-    for (int b = 0; b < 6; ++b)
-      if (m == (1u << b)) {
-        vx = fv.v[b][0];
-        vy = fv.v[b][1];
-        vz = fv.v[b][2];
-        r0 = p.rho_p[b];
-      }
+    // Face: n = (sx, sy, sz).
     const bool pressure = (m & p.p_mask) != 0u;
+    const T keep_n = (p.rule_flags & kRuleNoTransverse) ? T(0) : T(1);
     T s_known = T(0), s_out = T(0), Mx = T(0), My = T(0), Mz = T(0);
 #pragma unroll
     for (int k = 0; k < 19; ++k) {
@@ -172,14 +188,13 @@ __device__ __forceinline__ void boundary_rule(T (&d)[19], unsigned m, const Node
       const int i = opp(j);
       const T civ = T(cx(i)) * vx + T(cy(i)) * vy + T(cz(i)) * vz;
       const T ciM = T(cx(i)) * Mx + T(cy(i)) * My + T(cz(i)) * Mz;
-      const T dj = d[i] - T(6 * w36(i)) / T(36) * rho * civ - rho3 * (civ + vn) + T(0.5) * ciM;
+      const T dj = d[i] - T(6 * w36(i)) / T(36) * rho * civ + keep_n * (T(0.5) * ciM - rho3 * (civ + vn));
       d[j] = ((U >> j) & 1u) ? dj : d[j];
     }
   } else {
     // Edge or corner, no-slip; density of a bordering pressure face (at most
     // one: pressure faces lie on one axis).
     const unsigned pm = m & p.p_mask;
-    T r0 = T(1);
 #pragma unroll
     for (int b = 0; b < 6; ++b)
       if (pm & (1u << b)) r0 = p.rho_p[b];

@@ -73,6 +73,7 @@ __global__ __launch_bounds__(BX) void batch_sweep_kernel(const BatchLat *__restr
     NodeParams<T> prm;
     prm.bc_mask = L.bc_mask;
     prm.p_mask = L.p_mask;
+    prm.rule_flags = 0u;
     prm.omega = T(L.omega);
 #pragma unroll
     for (int f = 0; f < 6; ++f) prm.rho_p[f] = T(L.rho_p[f]);
@@ -95,7 +96,7 @@ __global__ __launch_bounds__(BX) void batch_sweep_kernel(const BatchLat *__restr
     const unsigned dz = rows / g.ny;
     const unsigned dy = rows - dz * g.ny;
     for (; n < tile.n1; n += BX) {
-      update_node<F, false>(mem, g, int(x), int(y), int(z), prm, key);
+      update_node<F, false, false>(mem, g, int(x), int(y), int(z), prm, key, NodeExt{});
       x += dx;
       const unsigned cxr = x >= g.nx;
       x -= cxr ? g.nx : 0u;

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "../../include/lbm.h"
 #include "lbm_internal.hpp"
@@ -60,6 +61,9 @@ struct lbm_lattice {
   double v[6][3];
   double rho_p[6];
   double force[3];
+  unsigned rule_flags;
+  unsigned char *d_solid;  // [N] solid flags on the device, or nullptr
+  double *d_face_v[6];     // per-node face velocities on the device, or nullptr
   int block_x, npt, xcd;
   unsigned steps;      // steps taken since creation (keys the stochastic rounding)
   double *d_partials;  // [kPartialBlocks * 4]
@@ -193,11 +197,19 @@ void lbm_destroy(lbm_lattice *L) {
       if (L->buf[i]) (void)hipFree(L->buf[i]);
   }
   if (L->d_partials) (void)hipFree(L->d_partials);
+  if (L->d_solid) (void)hipFree(L->d_solid);
+  for (int f = 0; f < 6; ++f)
+    if (L->d_face_v[f]) (void)hipFree(L->d_face_v[f]);
   if (L->d_stage) (void)hipFree(L->d_stage);
   delete L;
 }
 
 static const int kNormal[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+
+static void drop_face_field(lbm_lattice *L, int f) {
+  if (L->d_face_v[f]) (void)hipFree(L->d_face_v[f]);
+  L->d_face_v[f] = nullptr;
+}
 
 lbm_status lbm_set_velocity_bc(lbm_lattice *L, lbm_face face, const double u[3]) {
   if (!L || !u) return fail(LBM_ERR_ARG, "NULL argument");
@@ -215,6 +227,7 @@ lbm_status lbm_set_velocity_bc(lbm_lattice *L, lbm_face face, const double u[3])
   L->p_mask &= ~(1u << f);
   L->rho_p[f] = 0.0;
   for (int d = 0; d < 3; ++d) L->v[f][d] = u[d];
+  drop_face_field(L, f);
   return LBM_OK;
 }
 
@@ -239,6 +252,7 @@ lbm_status lbm_set_pressure_bc(lbm_lattice *L, lbm_face face, double rho0, const
   L->p_mask |= 1u << f;
   L->rho_p[f] = rho0;
   for (int d = 0; d < 3; ++d) L->v[f][d] = t[d];
+  drop_face_field(L, f);
   return LBM_OK;
 }
 
@@ -250,6 +264,77 @@ lbm_status lbm_clear_bc(lbm_lattice *L, lbm_face face) {
   L->p_mask &= ~(1u << f);
   L->rho_p[f] = 0.0;
   for (int d = 0; d < 3; ++d) L->v[f][d] = 0.0;
+  drop_face_field(L, f);
+  return LBM_OK;
+}
+
+static size_t face_nodes(const lbm_lattice *L, int f) {
+  const int a = f / 2;
+  return a == 0 ? size_t(L->ny) * L->nz : (a == 1 ? size_t(L->nx) * L->nz : size_t(L->nx) * L->ny);
+}
+
+lbm_status lbm_set_velocity_field(lbm_lattice *L, lbm_face face, const double *v) {
+  if (!L) return fail(LBM_ERR_ARG, "NULL handle");
+  const int f = int(face);
+  if (f < 0 || f > 5) return fail(LBM_ERR_ARG, "invalid face %d", f);
+  if (!v) {
+    drop_face_field(L, f);
+    return LBM_OK;
+  }
+  const int size[3] = {L->nx, L->ny, L->nz};
+  if (size[f / 2] < 3) return fail(LBM_ERR_ARG, "a bounded axis needs at least 3 nodes (axis %d has %d)", f / 2, size[f / 2]);
+  const size_t nf = face_nodes(L, f);
+  for (size_t i = 0; i < nf; ++i) {
+    const double *u = v + 3 * i;
+    if (!std::isfinite(u[0]) || !std::isfinite(u[1]) || !std::isfinite(u[2]))
+      return fail(LBM_ERR_ARG, "velocity of face node %zu is not finite", i);
+    const double un = u[0] * kNormal[f][0] + u[1] * kNormal[f][1] + u[2] * kNormal[f][2];
+    if (std::fabs(un) >= 1.0 || u[0] * u[0] + u[1] * u[1] + u[2] * u[2] >= 1.0 / 3.0)
+      return fail(LBM_ERR_ARG, "velocity of face node %zu out of range (|u.n| < 1 and |u| < 1/sqrt(3) required)", i);
+  }
+  if (!L->d_face_v[f]) {
+    hipError_t e = hipMalloc(&L->d_face_v[f], sizeof(double) * 3 * nf);
+    if (e != hipSuccess) {
+      L->d_face_v[f] = nullptr;
+      return fail(LBM_ERR_OOM, "hipMalloc of a face velocity field failed: %s", hipGetErrorString(e));
+    }
+  }
+  hipError_t e = hipMemcpyAsync(L->d_face_v[f], v, sizeof(double) * 3 * nf, hipMemcpyHostToDevice, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (e != hipSuccess) return hip_fail(e, "face velocity upload");
+  L->bc_mask |= 1u << f;
+  L->p_mask &= ~(1u << f);
+  L->rho_p[f] = 0.0;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_solid_mask(lbm_lattice *L, const unsigned char *solid) {
+  if (!L) return fail(LBM_ERR_ARG, "NULL handle");
+  if (!solid) {
+    if (L->d_solid) (void)hipFree(L->d_solid);
+    L->d_solid = nullptr;
+    return LBM_OK;
+  }
+  if (!L->d_solid) {
+    hipError_t e = hipMalloc(&L->d_solid, L->N);
+    if (e != hipSuccess) {
+      L->d_solid = nullptr;
+      return fail(LBM_ERR_OOM, "hipMalloc of the solid mask failed: %s", hipGetErrorString(e));
+    }
+  }
+  // Flags are stored as 0 / 1 whatever non-zero value the caller used.
+  std::vector<unsigned char> flags(solid, solid + L->N);
+  for (auto &c : flags) c = c ? 1 : 0;
+  hipError_t e = hipMemcpyAsync(L->d_solid, flags.data(), L->N, hipMemcpyHostToDevice, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (e != hipSuccess) return hip_fail(e, "solid mask upload");
+  return LBM_OK;
+}
+
+lbm_status lbm_set_rule_options(lbm_lattice *L, unsigned flags) {
+  if (!L) return fail(LBM_ERR_ARG, "NULL handle");
+  if (flags & ~unsigned(LBM_RULE_NO_TRANSVERSE)) return fail(LBM_ERR_ARG, "unknown rule option bits 0x%x", flags);
+  L->rule_flags = flags;
   return LBM_OK;
 }
 
@@ -273,6 +358,9 @@ static lbm::SweepConfig sweep_config(const lbm_lattice *L) {
   std::memcpy(c.v, L->v, sizeof(c.v));
   std::memcpy(c.rho_p, L->rho_p, sizeof(c.rho_p));
   std::memcpy(c.force, L->force, sizeof(c.force));
+  c.rule_flags = L->rule_flags;
+  c.solid = L->d_solid;
+  for (int f = 0; f < 6; ++f) c.face_v[f] = L->d_face_v[f];
   c.block_x = L->block_x;
   c.nodes_per_thread = L->npt;
   c.xcd_remap = L->xcd;

@@ -8,6 +8,7 @@
 
 #include "../../include/lbm.h"
 #include "d3q19.hpp"
+#include "node_update.hpp"
 
 namespace lbm {
 
@@ -33,6 +34,9 @@ struct SweepConfig {
   double v[6][3];    // face velocities (pressure faces: tangential velocity)
   double rho_p[6];   // prescribed densities of the pressure faces
   double force[3];   // body force
+  unsigned rule_flags;               // kRuleNoTransverse
+  const unsigned char *solid;        // device [N] solid flags, or nullptr
+  const double *face_v[6];           // device per-node face velocities, or nullptr
   int block_x;
   int nodes_per_thread;
   int xcd_remap;
@@ -49,6 +53,7 @@ struct SweepArgs {
   int xcd_remap;
   unsigned key;  // step key of the stochastic rounding
   NodeParams<T> p;
+  NodeExt ext;   // used by the extended sweep only
 };
 
 hipError_t launch_sweep(const SweepConfig &c, const void *src, void *dst, bool copy_only, hipStream_t s);

@@ -24,9 +24,10 @@ namespace lbm {
 // 64-lane accesses).  y and z are uniform over the block, so the row offsets
 // of the nine source rows are scalar and each load is "scalar base + lane
 // offset".  COPY: streaming only (no boundary rule, no collision, raw
-// elements) -- the bandwidth ceiling of this access pattern.
+// elements) -- the bandwidth ceiling of this access pattern.  EXT: the
+// extended update with solid nodes and per-node face velocities (a.ext).
 // ---------------------------------------------------------------------------
-template <class F, int BX, int NPT, bool NT, bool COPY>
+template <class F, int BX, int NPT, bool NT, bool COPY, bool EXT>
 __global__ __launch_bounds__(BX) void sweep_kernel(const typename F::S *__restrict__ src,
                                                    typename F::S *__restrict__ dst,
                                                    SweepArgs<typename Codec<typename F::S>::T> a) {
@@ -40,7 +41,7 @@ __global__ __launch_bounds__(BX) void sweep_kernel(const typename F::S *__restri
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
     const int x = (xc * NPT + j) * BX + int(threadIdx.x);
-    if (x < a.nx) update_node<F, COPY>(mem, g, x, y, z, a.p, a.key);
+    if (x < a.nx) update_node<F, COPY, EXT>(mem, g, x, y, z, a.p, a.key, a.ext);
   }
 }
 
@@ -177,12 +178,12 @@ __global__ __launch_bounds__(256) void copy_probe_kernel(const uint4 *__restrict
 // ---------------------------------------------------------------------------
 // Host-side launchers.
 // ---------------------------------------------------------------------------
-template <class F, int BX, int NPT, bool NT, bool COPY>
+template <class F, int BX, int NPT, bool NT, bool COPY, bool EXT>
 static hipError_t launch_sweep_t(const void *src, void *dst, const SweepArgs<typename Codec<typename F::S>::T> &a,
                                  hipStream_t s) {
   using S = typename F::S;
-  sweep_kernel<F, BX, NPT, NT, COPY><<<dim3(a.nblocks), dim3(BX), 0, s>>>(static_cast<const S *>(src),
-                                                                         static_cast<S *>(dst), a);
+  sweep_kernel<F, BX, NPT, NT, COPY, EXT><<<dim3(a.nblocks), dim3(BX), 0, s>>>(static_cast<const S *>(src),
+                                                                              static_cast<S *>(dst), a);
   return hipGetLastError();
 }
 
@@ -193,12 +194,25 @@ static hipError_t launch_sweep_shape(const void *src, void *dst,
   // Non-temporal stores: the destination is not read again before the next
   // step, which streams through far more data than the caches hold.
 #define LBM_CASE(B, P)                                                       \
-  if (bx == B && npt == P) return launch_sweep_t<F, B, P, true, COPY>(src, dst, a, s);
+  if (bx == B && npt == P) return launch_sweep_t<F, B, P, true, COPY, false>(src, dst, a, s);
   LBM_CASE(64, 1) LBM_CASE(64, 2) LBM_CASE(64, 4)
   LBM_CASE(128, 1) LBM_CASE(128, 2) LBM_CASE(128, 4)
   LBM_CASE(256, 1) LBM_CASE(256, 2) LBM_CASE(256, 4)
   LBM_CASE(512, 1) LBM_CASE(512, 2) LBM_CASE(512, 4)
 #undef LBM_CASE
+  return hipErrorInvalidValue;
+}
+
+// The extended sweep runs one node per thread.
+template <class F>
+static hipError_t launch_sweep_ext(const void *src, void *dst, const SweepArgs<typename Codec<typename F::S>::T> &a,
+                                   int bx, hipStream_t s) {
+  switch (bx) {
+    case 64: return launch_sweep_t<F, 64, 1, true, false, true>(src, dst, a, s);
+    case 128: return launch_sweep_t<F, 128, 1, true, false, true>(src, dst, a, s);
+    case 256: return launch_sweep_t<F, 256, 1, true, false, true>(src, dst, a, s);
+    case 512: return launch_sweep_t<F, 512, 1, true, false, true>(src, dst, a, s);
+  }
   return hipErrorInvalidValue;
 }
 
@@ -215,6 +229,9 @@ static SweepArgs<T> make_args(const SweepConfig &c) {
   a.xcd_remap = c.xcd_remap;
   a.p.bc_mask = c.bc_mask;
   a.p.p_mask = c.p_mask;
+  a.p.rule_flags = c.rule_flags;
+  a.ext.solid = c.solid;
+  for (int f = 0; f < 6; ++f) a.ext.face_v[f] = c.face_v[f];
   for (int f = 0; f < 6; ++f) a.p.rho_p[f] = T(c.rho_p[f]);
   a.p.omega = T(1.0 / c.tau);
   for (int d = 0; d < 3; ++d) a.p.tau_f[d] = T(c.tau * c.force[d]);
@@ -224,7 +241,20 @@ static SweepArgs<T> make_args(const SweepConfig &c) {
   return a;
 }
 
-hipError_t launch_sweep(const SweepConfig &c, const void *src, void *dst, bool copy_only, hipStream_t s) {
+hipError_t launch_sweep(const SweepConfig &c_in, const void *src, void *dst, bool copy_only, hipStream_t s) {
+  SweepConfig c = c_in;
+  bool ext = c.solid != nullptr;
+  for (int f = 0; f < 6; ++f) ext = ext || c.face_v[f] != nullptr;
+  if (ext && !copy_only) {
+    c.nodes_per_thread = 1;
+    switch (c.storage) {
+      case kStoreF64: return launch_sweep_ext<FormF64>(src, dst, make_args<double>(c), c.block_x, s);
+      case kStoreF32: return launch_sweep_ext<FormF32>(src, dst, make_args<double>(c), c.block_x, s);
+      case kStoreF16: return launch_sweep_ext<FormF16>(src, dst, make_args<float>(c), c.block_x, s);
+      case kStoreF16SR: return launch_sweep_ext<FormF16SR>(src, dst, make_args<float>(c), c.block_x, s);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (c.storage) {
     case kStoreF64: {
       const auto a = make_args<double>(c);

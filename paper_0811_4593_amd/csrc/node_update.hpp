@@ -202,12 +202,25 @@ struct BufAccess {
   }
 };
 
+// Optional per-node data of the extended sweep: solid nodes (mid-grid
+// bounce-back, Sec. III) and per-node velocities of velocity faces.
+struct NodeExt {
+  const unsigned char *solid;  // [N] 1 = solid node, or nullptr
+  const double *face_v[6];     // [n_face][3] per face, or nullptr; face node
+                               // order: x faces y + ny z, y faces x + nx z,
+                               // z faces x + nx y
+};
+
 // One node update: pull streaming (periodic wrap on every axis; sources
 // beyond a bounded face land on in-bounds values that the boundary rule then
-// overwrites), boundary rule for the face mask, BGK, store.
-template <class F, bool COPY, class T, class Access>
+// overwrites), boundary rule for the face mask, BGK, store.  EXT: the node
+// may be solid (its populations are copied through), a population whose
+// source is a solid node is bounced back (the node's own opposite
+// population of the previous step), and a face node may take its velocity
+// from a per-node field.
+template <class F, bool COPY, bool EXT, class T, class Access>
 __device__ __forceinline__ void update_node(const Access &mem, const NodeGeom &g, int x, int y, int z,
-                                            const NodeParams<T> &p, unsigned key) {
+                                            const NodeParams<T> &p, unsigned key, const NodeExt &ext) {
   const unsigned bc_mask = p.bc_mask;
   using S = typename F::S;
   const unsigned nx = g.nx, ny = g.ny, nz = g.nz;
@@ -219,13 +232,28 @@ __device__ __forceinline__ void update_node(const Access &mem, const NodeGeom &g
   const unsigned zz[3] = {zp, unsigned(z), zm};
   const unsigned xs[3] = {xp, unsigned(x), xm};
   S raw[19];
-#pragma unroll
-  for (int k = 0; k < 19; ++k) {
-    const unsigned off = (yy[cy(k) + 1] + ny * zz[cz(k) + 1]) * nx + xs[cx(k) + 1];
-    raw[k] = mem.load(k, off);
-  }
   const unsigned n = (unsigned(z) * ny + unsigned(y)) * nx + unsigned(x);
-  if constexpr (!COPY) {
+  bool solid_node = false;
+  if constexpr (EXT) {
+    if (ext.solid) solid_node = ext.solid[n] != 0;
+  }
+  if (EXT && ext.solid) {
+#pragma unroll
+    for (int k = 0; k < 19; ++k) {
+      const unsigned off = (yy[cy(k) + 1] + ny * zz[cz(k) + 1]) * nx + xs[cx(k) + 1];
+      // solid source (or a solid node itself): the node's own population
+      const bool own = solid_node || (k != 18 && ext.solid[off] != 0);
+      const int kk = solid_node ? k : opp(k);
+      raw[k] = mem.load(own ? kk : k, own ? n : off);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 19; ++k) {
+      const unsigned off = (yy[cy(k) + 1] + ny * zz[cz(k) + 1]) * nx + xs[cx(k) + 1];
+      raw[k] = mem.load(k, off);
+    }
+  }
+  if (!COPY && !solid_node) {
     T f[19];
 #pragma unroll
     for (int k = 0; k < 19; ++k) f[k] = Codec<S>::decode(raw[k]);
@@ -236,7 +264,26 @@ __device__ __forceinline__ void update_node(const Access &mem, const NodeGeom &g
     if (unsigned(y) == ny - 1) m |= bc_mask & 8u;
     if (z == 0) m |= bc_mask & 16u;
     if (unsigned(z) == nz - 1) m |= bc_mask & 32u;
-    if (m) boundary_rule<T>(f, m, p);
+    if (m) {
+      T vx, vy, vz, r0;
+      face_values<T>(m, p, vx, vy, vz, r0);
+      if constexpr (EXT) {
+        const double *fld = nullptr;
+        unsigned idx = 0;
+#pragma unroll
+        for (int b = 0; b < 6; ++b)
+          if (m == (1u << b)) {
+            fld = ext.face_v[b];
+            idx = b < 2 ? unsigned(y) + ny * unsigned(z) : (b < 4 ? unsigned(x) + nx * unsigned(z) : unsigned(x) + nx * unsigned(y));
+          }
+        if (fld) {
+          vx = T(fld[3 * idx]);
+          vy = T(fld[3 * idx + 1]);
+          vz = T(fld[3 * idx + 2]);
+        }
+      }
+      boundary_rule<T>(f, m, p, vx, vy, vz, r0);
+    }
     bgk_collide<T>(f, p.omega, p.tau_f);
     unsigned r = F::kStochastic ? fmix32(n * 0x9e3779b1u + key) : 0u;
 #pragma unroll

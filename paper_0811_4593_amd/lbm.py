@@ -27,8 +27,8 @@ STORAGE_NAMES = {LBM_STORE_F64: "f64", LBM_STORE_F32: "f32", LBM_STORE_F16_DEV: 
 
 # Every symbol include/lbm.h declares.
 EXPORTS = (
-    "lbm_create", "lbm_create_on_buffers", "lbm_set_velocity_bc", "lbm_set_pressure_bc", "lbm_set_body_force",
-    "lbm_clear_bc", "lbm_step",
+    "lbm_create", "lbm_create_on_buffers", "lbm_set_velocity_bc", "lbm_set_pressure_bc", "lbm_set_velocity_field",
+    "lbm_set_solid_mask", "lbm_set_rule_options", "lbm_set_body_force", "lbm_clear_bc", "lbm_step",
     "lbm_moments", "lbm_totals", "lbm_get_populations", "lbm_set_populations", "lbm_state_buffer",
     "lbm_element_bytes", "lbm_population_pitch", "lbm_set_launch", "lbm_get_launch", "lbm_probe",
     "lbm_destroy", "lbm_last_error",
@@ -38,6 +38,7 @@ EXPORTS = (
 )
 
 LBM_JOB_QUEUED, LBM_JOB_RUNNING, LBM_JOB_DONE = 0, 1, 2
+LBM_RULE_NO_TRANSVERSE = 1
 
 
 class LbmJob(ctypes.Structure):
@@ -92,6 +93,9 @@ def load_library(path: str = LIB_PATH):
                                           ctypes.c_size_t, ctypes.POINTER(_vp)]
     lib.lbm_set_velocity_bc.argtypes = [_vp, st, _dp]
     lib.lbm_set_pressure_bc.argtypes = [_vp, st, ctypes.c_double, _dp]
+    lib.lbm_set_velocity_field.argtypes = [_vp, st, _dp]
+    lib.lbm_set_solid_mask.argtypes = [_vp, ctypes.POINTER(ctypes.c_ubyte)]
+    lib.lbm_set_rule_options.argtypes = [_vp, ctypes.c_uint]
     lib.lbm_set_body_force.argtypes = [_vp, _dp]
     lib.lbm_clear_bc.argtypes = [_vp, st]
     lib.lbm_step.argtypes = [_vp, st]
@@ -196,6 +200,29 @@ def lbm_set_velocity_bc(h, face, u):
 
 def lbm_set_pressure_bc(h, face, rho0, u_t=None):
     _check(load_library().lbm_set_pressure_bc(h, int(face), float(rho0), None if u_t is None else _vec3(u_t)))
+
+
+def lbm_set_velocity_field(h, face, v=None):
+    """v: per-node velocities of the face, float64 array of 3 * n_face values
+    (e.g. shape (n2, n1, 3) over the face's two other axes), or None."""
+    if v is None:
+        _check(load_library().lbm_set_velocity_field(h, int(face), None))
+        return
+    a = np.ascontiguousarray(np.asarray(v, dtype=np.float64))
+    _check(load_library().lbm_set_velocity_field(h, int(face), a.ctypes.data_as(_dp)))
+
+
+def lbm_set_solid_mask(h, solid=None):
+    """solid: (nz, ny, nx) array, non-zero = solid node; None removes it."""
+    if solid is None:
+        _check(load_library().lbm_set_solid_mask(h, None))
+        return
+    a = np.ascontiguousarray(np.asarray(solid).astype(np.uint8))
+    _check(load_library().lbm_set_solid_mask(h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))))
+
+
+def lbm_set_rule_options(h, flags: int):
+    _check(load_library().lbm_set_rule_options(h, int(flags)))
 
 
 def lbm_set_body_force(h, F):

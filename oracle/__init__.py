@@ -36,6 +36,7 @@ class _OracleLattice(ctypes.Structure):
         ("solid", ctypes.POINTER(ctypes.c_ubyte)),
         ("face_v", _dp * 6),
         ("no_transverse", ctypes.c_int),
+        ("cell", ctypes.POINTER(ctypes.c_ubyte)),
     ]
 
 
@@ -55,6 +56,11 @@ def _load():
         lib.oracle_edge_rule.argtypes = [ctypes.c_int, ctypes.c_int, _dp]
         lib.oracle_corner_rule.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp]
         lib.oracle_face_rule_no_transverse.argtypes = [ctypes.c_int, _dp, _dp]
+        lib.oracle_convex_edge_rule.argtypes = [ctypes.c_int, ctypes.c_int, _dp]
+        lib.oracle_general_rule.argtypes = [ctypes.c_uint, _dp]
+        lib.oracle_classify.argtypes = [ctypes.POINTER(_OracleLattice), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_uint)]
+        lib.oracle_classify.restype = ctypes.c_int
         lib.oracle_face_rule_pressure.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp]
         lib.oracle_edge_rule_pressure.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp]
         lib.oracle_corner_rule_pressure.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
@@ -131,6 +137,24 @@ def face_rule_no_transverse(face: int, v, f) -> np.ndarray:
     return g
 
 
+def convex_edge_rule(face_a: int, face_b: int, f) -> np.ndarray:
+    lib = _load()
+    g = _vec(f).copy()
+    lib.oracle_convex_edge_rule(int(face_a), int(face_b), _ptr(g))
+    return g
+
+
+def general_rule(unknown: int, f) -> np.ndarray:
+    lib = _load()
+    g = _vec(f).copy()
+    lib.oracle_general_rule(int(unknown), _ptr(g))
+    return g
+
+
+# Rule kinds of wall nodes (oracle_classify).
+NODE_FLUID, NODE_FACE, NODE_EDGE, NODE_CORNER, NODE_CONVEX_EDGE, NODE_GENERAL = range(6)
+
+
 def face_rule_pressure(face: int, rho0: float, v, f) -> np.ndarray:
     lib = _load()
     g = _vec(f).copy()
@@ -163,7 +187,9 @@ class Lattice:
     bounce-back); face_v: face -> per-node velocities of a velocity face,
     shape (n2, n1, 3) over the face's two other axes (z faces: (ny, nx, 3),
     y faces: (nz, nx, 3), x faces: (nz, ny, 3)); no_transverse: the face rule
-    without the transverse corrections (comparison variant)."""
+    without the transverse corrections (comparison variant).  cell: optional
+    (nz, ny, nx) node types for complex geometry: 0 fluid, 1 wall node
+    (on-site no-slip), 2 solid interior; every axis periodic then."""
 
     nx: int
     ny: int
@@ -175,6 +201,7 @@ class Lattice:
     solid: np.ndarray | None = None
     face_v: dict = field(default_factory=dict)  # face index -> per-node velocities
     no_transverse: bool = False
+    cell: np.ndarray | None = None
 
     @property
     def shape(self):
@@ -210,6 +237,10 @@ class Lattice:
             s.bc_set[face] = 1
             s.face_v[face] = a.ctypes.data_as(_dp)
         s.no_transverse = int(bool(self.no_transverse))
+        if self.cell is not None:
+            cel = np.ascontiguousarray(np.asarray(self.cell).astype(np.uint8).reshape(self.nz, self.ny, self.nx))
+            keep.append(cel)
+            s.cell = cel.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))
         self._keep = keep  # the C struct points into these arrays
         return s
 
@@ -242,6 +273,12 @@ class Lattice:
         if rc != 0:
             raise ValueError("invalid lattice description for the oracle")
         return out
+
+    def classify(self, x: int, y: int, z: int):
+        """(rule kind, unknown bit set) of a wall node, or (-1, 0)."""
+        u = ctypes.c_uint(0)
+        k = _load().oracle_classify(ctypes.byref(self._c()), int(x), int(y), int(z), ctypes.byref(u))
+        return k, u.value
 
     def moments(self, f: np.ndarray):
         f = np.ascontiguousarray(f, dtype=np.float64)

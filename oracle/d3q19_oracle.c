@@ -323,6 +323,125 @@ static void corner_rule_paper(const int n1[3], const int n2[3], const int n3[3],
 }
 
 /* ------------------------------------------------------------------------ */
+/* Convex edge (Sec. V, eq_edge2).  n1, n2: normals of the two solid faces,   */
+/* pointing into the fluid; the fluid surrounds the edge on three sides.    */
+/* ------------------------------------------------------------------------ */
+static void convex_edge_rule_paper(const int n1[3], const int n2[3], double *f) {
+  const int e[3] = {n1[1] * n2[2] - n1[2] * n2[1], n1[2] * n2[0] - n1[0] * n2[2],
+                    n1[0] * n2[1] - n1[1] * n2[0]};
+  /* Only the population arriving from the solid's interior, along n1 + n2,
+   * is unknown: bounce it back (its opposite left into the fluid). */
+  const int i_in = vector_index(n1[0] + n2[0], n1[1] + n2[1], n1[2] + n2[2]);
+  f[i_in] = f[opposite(i_in)];
+  /* eq_edge2: the momentum along the edge, sum_j f_j c_j.e, is spread as
+   * -(c_i.e) N, N = (1/4) sum_j f_j c_j.e, over the four populations with
+   * c_i.e != 0 that travel into the bulk (c_i = +-e + n1 or +-e + n2).
+   * Reading: as for the concave edge, the correction removes the momentum
+   * along the edge (slip is reduced, not doubled). */
+  double P = 0.0;
+  for (int j = 1; j <= 18; ++j) P += f[j] * dot_c(j, e);
+  const double N = 0.25 * P;
+  for (int i = 1; i <= 18; ++i)
+    if (dot_c(i, e) != 0 && dot_c(i, n1) + dot_c(i, n2) == 1) f[i] -= N * dot_c(i, e);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Any other wall node (Sec. V, points where an edge meets a plane; also     */
+/* thin features): bounce back every unknown population whose opposite is   */
+/* known; the buried ones (opposite unknown too) and the rest population    */
+/* take the mass of the others in the ratio of their lattice weights.       */
+/* Reading: the paper sets the rest population of an edge-plane point to     */
+/* (12/36) times the sum of the moving populations; that does not return a  */
+/* fluid at rest unchanged (it needs w_19 / sum of the moving weights = 1/2),*/
+/* so the weight-ratio closure that gives eq_buried's 1/22 and eq_corner's  */
+/* 1/18 is used here as well.                                               */
+/* ------------------------------------------------------------------------ */
+static void general_rule_paper(const int unknown[20], double *f) {
+  int buried[20] = {0};
+  for (int i = 1; i <= 18; ++i) buried[i] = unknown[i] && unknown[opposite(i)];
+  for (int i = 1; i <= 18; ++i)
+    if (unknown[i] && !buried[i]) f[i] = f[opposite(i)];
+  double sum = 0.0, wsum = 0.0;
+  for (int i = 1; i <= 18; ++i)
+    if (!buried[i]) {
+      sum += f[i];
+      wsum += weight(i);
+    }
+  for (int i = 1; i <= 18; ++i)
+    if (buried[i]) f[i] = weight(i) / wsum * sum;
+  f[19] = weight(19) / wsum * sum;
+}
+
+/* Unknown set and rule kind of a wall node (Sec. V; the per-node normal
+ * index of the paper is derived here from the geometry): a plane with
+ * inward normal n is a wall of the node when every population arriving
+ * along c.n > 0 is unknown. */
+static int classify_node(const oracle_lattice *L, int x, int y, int z, int unknown[20], int walls[3], int *nwalls) {
+  const int size[3] = {L->nx, L->ny, L->nz};
+  int nunk = 0;
+  for (int i = 0; i <= 19; ++i) unknown[i] = 0;
+  for (int i = 1; i <= 18; ++i) {
+    int s[3] = {x - CX[i], y - CY[i], z - CZ[i]};
+    for (int a = 0; a < 3; ++a) s[a] = (s[a] + size[a]) % size[a];
+    const size_t src = (size_t)s[0] + (size_t)L->nx * ((size_t)s[1] + (size_t)L->ny * s[2]);
+    if (L->cell[src] == 2) {
+      unknown[i] = 1;
+      ++nunk;
+    }
+  }
+  *nwalls = 0;
+  int covered[20] = {0};
+  for (int fc = 0; fc < 6; ++fc) {
+    int all = 1;
+    for (int i = 1; i <= 18; ++i)
+      if (dot_c(i, NORMAL[fc]) > 0 && !unknown[i]) all = 0;
+    if (!all) continue;
+    if (*nwalls < 3) walls[*nwalls] = fc;
+    ++*nwalls;
+    for (int i = 1; i <= 18; ++i)
+      if (dot_c(i, NORMAL[fc]) > 0) covered[i] = 1;
+  }
+  int exact = 1; /* the unknown set is exactly the union of the walls' sets */
+  for (int i = 1; i <= 18; ++i)
+    if (covered[i] != unknown[i]) exact = 0;
+  if (nunk == 0) return ORACLE_NODE_FLUID;
+  if (exact && *nwalls >= 1 && *nwalls <= 3) {
+    int orth = 1; /* walls on distinct axes */
+    for (int p = 0; p < *nwalls; ++p)
+      for (int q = p + 1; q < *nwalls; ++q)
+        if (walls[p] / 2 == walls[q] / 2) orth = 0;
+    if (orth) return *nwalls == 1 ? ORACLE_NODE_FACE : (*nwalls == 2 ? ORACLE_NODE_EDGE : ORACLE_NODE_CORNER);
+  }
+  if (*nwalls == 0 && nunk == 1) {
+    for (int i = 7; i <= 18; ++i)
+      if (unknown[i]) {
+        /* the unknown diagonal is n1 + n2 */
+        int k = 0;
+        const int comp[3] = {CX[i], CY[i], CZ[i]};
+        for (int a = 0; a < 3; ++a)
+          if (comp[a] != 0) walls[k++] = 2 * a + (comp[a] > 0 ? 0 : 1);
+        *nwalls = 2;
+        return ORACLE_NODE_CONVEX_EDGE;
+      }
+  }
+  return ORACLE_NODE_GENERAL;
+}
+
+int oracle_classify(const oracle_lattice *L, int x, int y, int z, unsigned *unknown) {
+  if (!L->cell) return -1;
+  const size_t n = (size_t)x + (size_t)L->nx * ((size_t)y + (size_t)L->ny * z);
+  if (L->cell[n] != 1) return -1;
+  int unk[20], walls[3], nw;
+  const int kind = classify_node(L, x, y, z, unk, walls, &nw);
+  if (unknown) {
+    *unknown = 0;
+    for (int i = 1; i <= 18; ++i)
+      if (unk[i]) *unknown |= 1u << (i - 1);
+  }
+  return kind;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Public node-rule entry points (k-ordered arrays).                         */
 /* ------------------------------------------------------------------------ */
 void oracle_face_rule(int face, const double v[3], double fk[19]) {
@@ -357,6 +476,24 @@ void oracle_corner_rule(int face_a, int face_b, int face_c, double fk[19]) {
   memcpy(fk, f + 1, 19 * sizeof(double));
 }
 
+void oracle_convex_edge_rule(int face_a, int face_b, double fk[19]) {
+  double f[20];
+  f[0] = 0.0;
+  memcpy(f + 1, fk, 19 * sizeof(double));
+  convex_edge_rule_paper(NORMAL[face_a], NORMAL[face_b], f);
+  memcpy(fk, f + 1, 19 * sizeof(double));
+}
+
+void oracle_general_rule(unsigned unknown, double fk[19]) {
+  double f[20];
+  int unk[20] = {0};
+  f[0] = 0.0;
+  memcpy(f + 1, fk, 19 * sizeof(double));
+  for (int i = 1; i <= 18; ++i) unk[i] = (unknown >> (i - 1)) & 1u;
+  general_rule_paper(unk, f);
+  memcpy(fk, f + 1, 19 * sizeof(double));
+}
+
 void oracle_face_rule_pressure(int face, double rho0, const double v[3], double fk[19]) {
   double f[20];
   f[0] = 0.0;
@@ -388,6 +525,11 @@ static int lattice_valid(const oracle_lattice *L) {
   const int n[3] = {L->nx, L->ny, L->nz};
   if (L->nx < 1 || L->ny < 1 || L->nz < 1) return 0;
   if (!(L->tau > 0.5)) return 0;
+  if (L->cell) {
+    if (L->solid) return 0;
+    for (int f = 0; f < 6; ++f)
+      if (L->bc_set[f]) return 0; /* the geometry carries every wall */
+  }
   int pressure_axis = -1;
   for (int a = 0; a < 3; ++a) {
     if (L->bc_set[2 * a] != L->bc_set[2 * a + 1]) return 0;
@@ -427,6 +569,23 @@ int oracle_update_node(const oracle_lattice *L, int x, int y, int z, const doubl
   for (int a = 0; a < 3; ++a) {
     if (L->bc_set[2 * a] && coord[a] == 0) faces[nf++] = 2 * a;
     if (L->bc_set[2 * a + 1] && coord[a] == size[a] - 1) faces[nf++] = 2 * a + 1;
+  }
+  if (L->cell && L->cell[(size_t)x + (size_t)L->nx * ((size_t)y + (size_t)L->ny * z)] == 1) {
+    /* Wall node of a complex geometry (Sec. V): the rule follows from the
+     * node's unknown populations; every wall is at rest. */
+    int unk[20], walls[3], nw;
+    const double zero[3] = {0.0, 0.0, 0.0};
+    switch (classify_node(L, x, y, z, unk, walls, &nw)) {
+      case ORACLE_NODE_FACE: face_rule_paper(walls[0], zero, NULL, 0, f); break;
+      case ORACLE_NODE_EDGE: edge_rule_paper(NORMAL[walls[0]], NORMAL[walls[1]], NULL, f); break;
+      case ORACLE_NODE_CORNER:
+        corner_rule_paper(NORMAL[walls[0]], NORMAL[walls[1]], NORMAL[walls[2]], NULL, f);
+        break;
+      case ORACLE_NODE_CONVEX_EDGE: convex_edge_rule_paper(NORMAL[walls[0]], NORMAL[walls[1]], f); break;
+      case ORACLE_NODE_GENERAL: general_rule_paper(unk, f); break;
+      default: break;
+    }
+    nf = 0; /* no box faces with cells */
   }
   /* The density of the node's pressure plane, if it lies on one (at most
    * one: pressure planes lie on one axis). */
@@ -512,8 +671,8 @@ int oracle_step(const oracle_lattice *L, const double *fin, double *fout, double
           }
           const size_t src = (size_t)s[0] + (size_t)nx * ((size_t)s[1] + (size_t)ny * s[2]);
           const size_t here = (size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z);
-          if (!inside)
-            pulled[i - 1] = NAN;
+          if (!inside || (L->cell && L->cell[src] == 2))
+            pulled[i - 1] = NAN; /* unknown: outside the domain or inside a solid */
           else if (L->solid && L->solid[src])
             /* Mid-grid bounce-back (Sec. III): the population sent towards
              * the solid neighbour returns reversed after one step. */
@@ -522,7 +681,7 @@ int oracle_step(const oracle_lattice *L, const double *fin, double *fout, double
             pulled[i - 1] = fin[(size_t)(i - 1) * N + src];
         }
         const size_t n = (size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z);
-        if (L->solid && L->solid[n]) {
+        if ((L->solid && L->solid[n]) || (L->cell && L->cell[n] == 2)) {
           /* Solid node: not part of the fluid; its populations stay as they are. */
           for (int k = 0; k < 19; ++k) fout[(size_t)k * N + n] = fin[(size_t)k * N + n];
           if (u_pre) u_pre[n] = u_pre[N + n] = u_pre[2 * N + n] = 0.0;

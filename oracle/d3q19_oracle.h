@@ -51,7 +51,24 @@ typedef struct {
                           y + ny*z, y faces x + nx*z, z faces x + nx*y */
   int no_transverse;   /* 1: face rule without the transverse corrections N
                           (eq_f9NoNs-eq_f17NoNs; comparison variant) */
+  const unsigned char *cell; /* NULL, or [N] node types for complex geometry
+                          (Sec. V): 0 fluid, 1 wall node (on-site no-slip),
+                          2 solid interior (no populations: a population
+                          streaming from it is unknown at the receiving wall
+                          node).  With cells, every axis must be periodic
+                          (the geometry carries all walls) and solid (the
+                          mid-grid option) must be NULL. */
 } oracle_lattice;
+
+/* Rule kinds of a wall node, from its set of unknown populations. */
+enum {
+  ORACLE_NODE_FLUID = 0,       /* no unknowns: no rule */
+  ORACLE_NODE_FACE = 1,        /* unknowns of one plane (eq_bbshort, v = 0) */
+  ORACLE_NODE_EDGE = 2,        /* concave edge (eq_edge, eq_buried) */
+  ORACLE_NODE_CORNER = 3,      /* concave corner (eq_corner) */
+  ORACLE_NODE_CONVEX_EDGE = 4, /* convex edge (eq_edge2) */
+  ORACLE_NODE_GENERAL = 5      /* any other set, e.g. an edge meeting a plane */
+};
 
 /* Lattice tables as the oracle holds them: c[k][3], w[k]. */
 void oracle_tables(int c[19][3], double w[19]);
@@ -75,6 +92,17 @@ void oracle_corner_rule(int face_a, int face_b, int face_c, double f[19]);
 void oracle_face_rule_pressure(int face, double rho0, const double v[3], double f[19]);
 void oracle_edge_rule_pressure(int face_a, int face_b, double rho0, double f[19]);
 void oracle_corner_rule_pressure(int face_a, int face_b, int face_c, double rho0, double f[19]);
+
+/* Rule kind of the wall node (x, y, z) of a lattice with cells, and its
+ * unknown set (bit k: population k).  Returns -1 if the lattice has no
+ * cells or the node is not a wall node. */
+int oracle_classify(const oracle_lattice *L, int x, int y, int z, unsigned *unknown);
+
+/* The convex-edge and general rules on one node's populations (k-ordered,
+ * in place): n1, n2 are the inward normals (face ids) of the two planes;
+ * unknown is the bit set of unknown populations. */
+void oracle_convex_edge_rule(int face_a, int face_b, double f[19]);
+void oracle_general_rule(unsigned unknown, double f[19]);
 
 /* One node: classification, boundary rule, moments, BGK.  pulled[k] is the
  * value streamed into the node along c_k; out[k] the post-collision value.

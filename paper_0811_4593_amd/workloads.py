@@ -183,6 +183,40 @@ def tilted_channel(scale: int = 1, straight: bool = False, v0: float = 0.02, tau
     return ChannelSetup(spec, np.ascontiguousarray(solid), face_v, centre, half, direction, v0)
 
 
+CELL_FLUID, CELL_WALL, CELL_SOLID = 0, 1, 2
+
+
+def cells_from_solid(solid: np.ndarray) -> np.ndarray:
+    """Node types of a complex geometry from a solid occupancy (nz, ny, nx)
+    (periodic wrap): solid nodes with a fluid node among their 26 neighbours
+    are wall nodes (the wall lies on them, Sec. V; the 26-neighbourhood makes
+    the corner of a box a wall node), the others solid interior."""
+    solid = np.asarray(solid, bool)
+    fluid_nb = np.zeros_like(solid)
+    for cz in (-1, 0, 1):
+        for cy in (-1, 0, 1):
+            for cx in (-1, 0, 1):
+                if cx or cy or cz:
+                    fluid_nb |= np.roll(~solid, shift=(cz, cy, cx), axis=(0, 1, 2))
+    cell = np.full(solid.shape, CELL_FLUID, np.uint8)
+    cell[solid & fluid_nb] = CELL_WALL
+    cell[solid & ~fluid_nb] = CELL_SOLID
+    return cell
+
+
+def rib_channel(nx: int = 24, ny: int = 10, nz: int = 14, rib=(8, 13, 6), tau: float = 0.9) -> tuple:
+    """A channel along x (periodic) with solid slabs two nodes thick on the
+    y and z sides and a rib on the bottom wall across the whole width: rib
+    nodes x in [rib[0], rib[1]], z up to rib[2].  Has plane, concave-edge,
+    corner, convex-edge and edge-meets-plane wall nodes.  Returns (spec,
+    cell)."""
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    solid = (y <= 1) | (y >= ny - 2) | (z <= 1) | (z >= nz - 2)
+    solid |= (x >= rib[0]) & (x <= rib[1]) & (z <= rib[2])
+    spec = LatticeSpec(nx, ny, nz, tau, {}, name=f"rib_channel_{nx}x{ny}x{nz}")
+    return spec, cells_from_solid(solid)
+
+
 def perturbation(shape, seed: int, amp: float) -> np.ndarray:
     """Multiplicative noise 1 + amp * U(-1, 1) of the given shape."""
     rng = np.random.default_rng(seed)

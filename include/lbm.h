@@ -154,6 +154,35 @@ lbm_status lbm_set_velocity_field(lbm_lattice *L, lbm_face face, const double *v
  * LBM_ERR_HIP. */
 lbm_status lbm_set_solid_mask(lbm_lattice *L, const unsigned char *solid);
 
+/* Complex geometry (Sec. V): cell[n] (host, N bytes, copied before return)
+ * is 0 for a fluid node, 1 for a wall node (the on-site no-slip wall lies on
+ * it) and 2 for a solid-interior node (no populations; what would stream
+ * from it is unknown at the receiving wall node).  Each wall node's rule
+ * follows from its unknown populations, classified once here (the paper's
+ * per-node normal index): the unknowns of one plane -> the plane rule with
+ * v = 0; of two planes on different axes -> the concave-edge rule; of three
+ * -> the corner rule; a single unknown diagonal n1 + n2 -> the convex-edge
+ * rule (eq_edge2: bounce back, then remove the momentum along the edge from
+ * the four populations with c.e != 0 that travel into the bulk); any other
+ * set (an edge meeting a plane, thin features) -> bounce back every unknown
+ * whose opposite is known and give the buried links and the rest population
+ * the others' mass in the ratio of the lattice weights.  All axes are
+ * periodic (the geometry carries every wall): lbm_step returns
+ * LBM_ERR_STATE if a face BC or a solid mask is also set.  cell = NULL
+ * removes the geometry.  Errors: LBM_ERR_ARG (a type other than 0, 1, 2),
+ * LBM_ERR_OOM, LBM_ERR_HIP. */
+lbm_status lbm_set_geometry(lbm_lattice *L, const unsigned char *cell);
+
+/* Host only (no GPU needed): the classification lbm_set_geometry uses.
+ * code[n] (N unsigned, caller-owned): bits 0-17 the unknown populations,
+ * bits 18-23 the wall planes as a face mask (bit f: a wall with the inward
+ * normal of face f), bits 24-26 the kind: 0 fluid, 1 solid interior,
+ * 2 plane / concave edge / corner, 3 convex edge, 4 general.  counts (NULL
+ * or 5 entries) receives the number of nodes of each kind.  Errors:
+ * LBM_ERR_ARG. */
+lbm_status lbm_classify_geometry(int nx, int ny, int nz, const unsigned char *cell, unsigned *code,
+                                 long long counts[5]);
+
 /* Rule options (bit mask): LBM_RULE_NO_TRANSVERSE applies the face rule
  * without the transverse corrections N (non-equilibrium bounce-back of every
  * unknown, Sec. IV eq_f9NoNs-eq_f17NoNs): the comparison variant of the

@@ -147,9 +147,11 @@ __device__ __forceinline__ void face_values(unsigned m, const NodeParams<T> &p, 
 // ---------------------------------------------------------------------------
 // (vx, vy, vz, r0): the face values of a face node (face_values, or a
 // per-node field); not used on edges and corners.
+// pmask: the pressure faces among m's faces (p.p_mask for box faces, 0 for the
+// walls of a complex geometry).
 template <class T>
-__device__ __forceinline__ void boundary_rule(T (&d)[19], unsigned m, const NodeParams<T> &p, T vx, T vy, T vz,
-                                              T r0) {
+__device__ __forceinline__ void boundary_rule(T (&d)[19], unsigned m, const NodeParams<T> &p, unsigned pmask, T vx,
+                                              T vy, T vz, T r0) {
   unsigned U = 0;
 #pragma unroll
   for (int b = 0; b < 6; ++b)
@@ -161,7 +163,7 @@ __device__ __forceinline__ void boundary_rule(T (&d)[19], unsigned m, const Node
   const int nb = __popc(m);
   if (nb == 1) {
     // Face: n = (sx, sy, sz).
-    const bool pressure = (m & p.p_mask) != 0u;
+    const bool pressure = (m & pmask) != 0u;
     const T keep_n = (p.rule_flags & kRuleNoTransverse) ? T(0) : T(1);
     T s_known = T(0), s_out = T(0), Mx = T(0), My = T(0), Mz = T(0);
 #pragma unroll
@@ -194,7 +196,7 @@ __device__ __forceinline__ void boundary_rule(T (&d)[19], unsigned m, const Node
   } else {
     // Edge or corner, no-slip; density of a bordering pressure face (at most
     // one: pressure faces lie on one axis).
-    const unsigned pm = m & p.p_mask;
+    const unsigned pm = m & pmask;
 #pragma unroll
     for (int b = 0; b < 6; ++b)
       if (pm & (1u << b)) r0 = p.rho_p[b];
@@ -222,6 +224,74 @@ __device__ __forceinline__ void boundary_rule(T (&d)[19], unsigned m, const Node
     for (int k = 0; k < 18; ++k) d[k] = ((bur >> k) & 1u) ? db : d[k];
     d[18] = T(12) * db;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Wall nodes of a complex geometry (Sec. V) that are not plane, concave-edge
+// or corner nodes.  U: bit set of the unknown populations.
+//
+// Convex edge (eq_edge2): U is the single diagonal n1 + n2 (n1, n2 the
+// normals of the two solid faces, pointing into the fluid).  It is bounced
+// back; then the momentum along the edge e = n1 x n2, P = sum_j d_j c_j.e,
+// is removed from the four populations travelling into the bulk with
+// c.e != 0 (c = +-e + n1, +-e + n2): d_c -= (c.e) P / 4.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ void convex_edge_rule(T (&d)[19], unsigned U) {
+  int sx = 0, sy = 0, sz = 0;  // n1 + n2
+#pragma unroll
+  for (int k = 6; k < 18; ++k)
+    if ((U >> k) & 1u) {
+      sx = cx(k);
+      sy = cy(k);
+      sz = cz(k);
+    }
+  // e is the axis with no component in n1 + n2 (its sign does not matter).
+  const int ex = sx == 0 ? 1 : 0, ey = sy == 0 ? 1 : 0, ez = sz == 0 ? 1 : 0;
+  // (+ 0: a select between two plain array elements would be turned into a
+  // load through a selected address, which forces the array into scratch.)
+#pragma unroll
+  for (int k = 6; k < 18; ++k) d[k] = ((U >> k) & 1u) ? d[opp(k)] + T(0) : d[k];
+  T P = T(0);
+#pragma unroll
+  for (int k = 0; k < 18; ++k) {
+    const int ce = cx(k) * ex + cy(k) * ey + cz(k) * ez;
+    if (ce != 0) P += T(ce) * d[k];
+  }
+  const T Pq = T(0.25) * P;
+#pragma unroll
+  for (int k = 0; k < 18; ++k) {
+    const int ce = cx(k) * ex + cy(k) * ey + cz(k) * ez;
+    const int cs = cx(k) * sx + cy(k) * sy + cz(k) * sz;
+    d[k] = (ce != 0 && cs == 1) ? d[k] - T(ce) * Pq : d[k];
+  }
+}
+
+// Any other wall node (an edge meeting a plane, thin features): bounce back
+// every unknown whose opposite is known; the buried links (opposite unknown
+// as well) and the rest population take the others' mass in the ratio of the
+// lattice weights -- in deviations d_b = w36_b * s / W36, s the sum of the
+// non-buried moving deviations, W36 their weight sum in units of 1/36 (22 on
+// a concave edge, 18 on a corner, 24 when nothing is buried).
+template <class T>
+__device__ __forceinline__ void general_wall_rule(T (&d)[19], unsigned U) {
+  unsigned bur = 0;
+#pragma unroll
+  for (int k = 0; k < 18; ++k) bur |= ((U >> k) & (U >> opp(k)) & 1u) << k;
+#pragma unroll
+  for (int k = 0; k < 18; ++k) d[k] = (((U & ~bur) >> k) & 1u) ? d[opp(k)] + T(0) : d[k];  // + 0: see above
+  T s = T(0);
+  int W = 0;
+#pragma unroll
+  for (int k = 0; k < 18; ++k) {
+    const bool b = (bur >> k) & 1u;
+    s += b ? T(0) : d[k];
+    W += b ? 0 : w36(k);
+  }
+  const T per = s / T(W);
+#pragma unroll
+  for (int k = 0; k < 18; ++k) d[k] = ((bur >> k) & 1u) ? T(w36(k)) * per : d[k];
+  d[18] = T(12) * per;
 }
 
 // BGK collision towards the second-order equilibrium (eq_bgk, eq_feq), in

@@ -64,6 +64,7 @@ struct lbm_lattice {
   unsigned rule_flags;
   unsigned char *d_solid;  // [N] solid flags on the device, or nullptr
   double *d_face_v[6];     // per-node face velocities on the device, or nullptr
+  unsigned *d_geo;         // complex-geometry node codes on the device, or nullptr
   int block_x, npt, xcd;
   unsigned steps;      // steps taken since creation (keys the stochastic rounding)
   double *d_partials;  // [kPartialBlocks * 4]
@@ -198,6 +199,7 @@ void lbm_destroy(lbm_lattice *L) {
   }
   if (L->d_partials) (void)hipFree(L->d_partials);
   if (L->d_solid) (void)hipFree(L->d_solid);
+  if (L->d_geo) (void)hipFree(L->d_geo);
   for (int f = 0; f < 6; ++f)
     if (L->d_face_v[f]) (void)hipFree(L->d_face_v[f]);
   if (L->d_stage) (void)hipFree(L->d_stage);
@@ -331,6 +333,47 @@ lbm_status lbm_set_solid_mask(lbm_lattice *L, const unsigned char *solid) {
   return LBM_OK;
 }
 
+static lbm_status check_cells(const unsigned char *cell, size_t N) {
+  for (size_t n = 0; n < N; ++n)
+    if (cell[n] > 2) return fail(LBM_ERR_ARG, "node type %d at node %zu (0 fluid, 1 wall, 2 solid)", int(cell[n]), n);
+  return LBM_OK;
+}
+
+lbm_status lbm_classify_geometry(int nx, int ny, int nz, const unsigned char *cell, unsigned *code,
+                                 long long counts[5]) {
+  if (!cell || !code) return fail(LBM_ERR_ARG, "NULL argument");
+  if (nx < 1 || ny < 1 || nz < 1) return fail(LBM_ERR_ARG, "lattice sizes must be >= 1");
+  if (double(nx) * ny * nz >= 2147483648.0) return fail(LBM_ERR_ARG, "at most 2^31 - 1 nodes");
+  const lbm_status st = check_cells(cell, size_t(nx) * ny * nz);
+  if (st != LBM_OK) return st;
+  lbm::classify_geometry(nx, ny, nz, cell, code, counts);
+  return LBM_OK;
+}
+
+lbm_status lbm_set_geometry(lbm_lattice *L, const unsigned char *cell) {
+  if (!L) return fail(LBM_ERR_ARG, "NULL handle");
+  if (!cell) {
+    if (L->d_geo) (void)hipFree(L->d_geo);
+    L->d_geo = nullptr;
+    return LBM_OK;
+  }
+  const lbm_status st = check_cells(cell, L->N);
+  if (st != LBM_OK) return st;
+  std::vector<unsigned> code(L->N);
+  lbm::classify_geometry(L->nx, L->ny, L->nz, cell, code.data(), nullptr);
+  if (!L->d_geo) {
+    hipError_t e = hipMalloc(&L->d_geo, sizeof(unsigned) * L->N);
+    if (e != hipSuccess) {
+      L->d_geo = nullptr;
+      return fail(LBM_ERR_OOM, "hipMalloc of the geometry codes failed: %s", hipGetErrorString(e));
+    }
+  }
+  hipError_t e = hipMemcpyAsync(L->d_geo, code.data(), sizeof(unsigned) * L->N, hipMemcpyHostToDevice, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (e != hipSuccess) return hip_fail(e, "geometry upload");
+  return LBM_OK;
+}
+
 lbm_status lbm_set_rule_options(lbm_lattice *L, unsigned flags) {
   if (!L) return fail(LBM_ERR_ARG, "NULL handle");
   if (flags & ~unsigned(LBM_RULE_NO_TRANSVERSE)) return fail(LBM_ERR_ARG, "unknown rule option bits 0x%x", flags);
@@ -360,6 +403,7 @@ static lbm::SweepConfig sweep_config(const lbm_lattice *L) {
   std::memcpy(c.force, L->force, sizeof(c.force));
   c.rule_flags = L->rule_flags;
   c.solid = L->d_solid;
+  c.geo_code = L->d_geo;
   for (int f = 0; f < 6; ++f) c.face_v[f] = L->d_face_v[f];
   c.block_x = L->block_x;
   c.nodes_per_thread = L->npt;
@@ -376,6 +420,9 @@ lbm_status lbm_step(lbm_lattice *L, int nsteps) {
     if (bits == 1u || bits == 2u)
       return fail(LBM_ERR_STATE, "axis %d has a BC on one face only; set both faces or none", a);
   }
+  if (L->d_geo && L->bc_mask)
+    return fail(LBM_ERR_STATE, "a lattice with a complex geometry carries its walls in the geometry; clear the face BCs");
+  if (L->d_geo && L->d_solid) return fail(LBM_ERR_STATE, "a complex geometry and a solid mask cannot be combined");
   int p_axes = 0;
   for (int a = 0; a < 3; ++a) p_axes += ((L->p_mask >> (2 * a)) & 3u) != 0u;
   if (p_axes > 1)

@@ -37,6 +37,7 @@ struct SweepConfig {
   unsigned rule_flags;               // kRuleNoTransverse
   const unsigned char *solid;        // device [N] solid flags, or nullptr
   const double *face_v[6];           // device per-node face velocities, or nullptr
+  const unsigned *geo_code;          // device complex-geometry node codes, or nullptr
   int block_x;
   int nodes_per_thread;
   int xcd_remap;
@@ -57,6 +58,12 @@ struct SweepArgs {
 };
 
 hipError_t launch_sweep(const SweepConfig &c, const void *src, void *dst, bool copy_only, hipStream_t s);
+
+// Node codes of a complex geometry from node types (0 fluid, 1 wall node,
+// 2 solid interior), all axes periodic; code[n] as geo_code().  Returns the
+// number of nodes of each kind in counts[5] (fluid, solid, plane/edge/corner,
+// convex edge, general) if counts is non-null.
+void classify_geometry(int nx, int ny, int nz, const unsigned char *cell, unsigned *code, long long *counts);
 hipError_t launch_init(int storage, void *f, size_t N, size_t pitch, double rho0, const double u0[3], hipStream_t s);
 hipError_t launch_moments(int storage, const void *f, size_t pitch, size_t n0, size_t count, double *rho, double *u,
                           double *partials, int nblk, hipStream_t s);

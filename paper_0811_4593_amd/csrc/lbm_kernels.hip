@@ -231,6 +231,7 @@ static SweepArgs<T> make_args(const SweepConfig &c) {
   a.p.p_mask = c.p_mask;
   a.p.rule_flags = c.rule_flags;
   a.ext.solid = c.solid;
+  a.ext.code = c.geo_code;
   for (int f = 0; f < 6; ++f) a.ext.face_v[f] = c.face_v[f];
   for (int f = 0; f < 6; ++f) a.p.rho_p[f] = T(c.rho_p[f]);
   a.p.omega = T(1.0 / c.tau);
@@ -243,7 +244,7 @@ static SweepArgs<T> make_args(const SweepConfig &c) {
 
 hipError_t launch_sweep(const SweepConfig &c_in, const void *src, void *dst, bool copy_only, hipStream_t s) {
   SweepConfig c = c_in;
-  bool ext = c.solid != nullptr;
+  bool ext = c.solid != nullptr || c.geo_code != nullptr;
   for (int f = 0; f < 6; ++f) ext = ext || c.face_v[f] != nullptr;
   if (ext && !copy_only) {
     c.nodes_per_thread = 1;
@@ -276,6 +277,58 @@ hipError_t launch_sweep(const SweepConfig &c_in, const void *src, void *dst, boo
     }
   }
   return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Complex geometry (Sec. V): a wall node's rule follows from which of its
+// populations stream in from solid-interior nodes (unknown).  A plane with
+// inward normal n is a wall of the node when all five populations with
+// c.n > 0 are unknown.  Unknown set = union of 1, 2 or 3 walls on distinct
+// axes: plane, concave edge, corner (the box rules, walls at rest); a single
+// unknown diagonal: convex edge; anything else: the general rule.
+// ---------------------------------------------------------------------------
+void classify_geometry(int nx, int ny, int nz, const unsigned char *cell, unsigned *code, long long *counts) {
+  if (counts)
+    for (int i = 0; i < 5; ++i) counts[i] = 0;
+  unsigned plane_set[6];
+  for (int f = 0; f < 6; ++f) plane_set[f] = unknown_mask(f) & 0x3ffffu;
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const size_t n = size_t(x) + size_t(nx) * (size_t(y) + size_t(ny) * size_t(z));
+        unsigned c = geo_code(kGeoFluid, 0u, 0u);
+        if (cell[n] == 2) {
+          c = geo_code(kGeoSolid, 0u, 0u);
+        } else if (cell[n] == 1) {
+          unsigned U = 0;
+          for (int k = 0; k < 18; ++k) {
+            const int sx = (x - cx(k) + nx) % nx, sy = (y - cy(k) + ny) % ny, sz = (z - cz(k) + nz) % nz;
+            if (cell[size_t(sx) + size_t(nx) * (size_t(sy) + size_t(ny) * size_t(sz))] == 2) U |= 1u << k;
+          }
+          unsigned m = 0, covered = 0;
+          int walls = 0, axes_used = 0;
+          bool distinct = true;
+          for (int f = 0; f < 6; ++f)
+            if ((U & plane_set[f]) == plane_set[f]) {
+              m |= 1u << f;
+              covered |= plane_set[f];
+              ++walls;
+              if (axes_used & (1 << (f / 2))) distinct = false;
+              axes_used |= 1 << (f / 2);
+            }
+          const int nunk = __builtin_popcount(U);
+          if (U == 0u)
+            c = geo_code(kGeoFluid, 0u, 0u);
+          else if (covered == U && walls >= 1 && walls <= 3 && distinct)
+            c = geo_code(kGeoPlaneEdgeCorner, m, U);
+          else if (walls == 0 && nunk == 1 && (U & 0x3ffc0u))
+            c = geo_code(kGeoConvexEdge, 0u, U);
+          else
+            c = geo_code(kGeoGeneral, 0u, U);
+        }
+        code[n] = c;
+        if (counts) ++counts[c >> 24];
+      }
 }
 
 static unsigned blocks_for(size_t n, unsigned bs) { return unsigned((n + bs - 1) / bs); }

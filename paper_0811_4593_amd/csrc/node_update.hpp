@@ -209,7 +209,17 @@ struct NodeExt {
   const double *face_v[6];     // [n_face][3] per face, or nullptr; face node
                                // order: x faces y + ny z, y faces x + nx z,
                                // z faces x + nx y
+  const unsigned *code;        // [N] complex-geometry node codes, or nullptr
 };
+
+// Complex-geometry node code (built on the host from the node types):
+// bits 0-17 the unknown populations U, bits 18-23 the wall planes as a face
+// mask m (bit f: a wall with the inward normal of face f), bits 24-26 the
+// rule kind.
+constexpr unsigned kGeoFluid = 0u, kGeoSolid = 1u, kGeoPlaneEdgeCorner = 2u, kGeoConvexEdge = 3u, kGeoGeneral = 4u;
+__host__ __device__ constexpr unsigned geo_code(unsigned kind, unsigned m, unsigned U) {
+  return (kind << 24) | (m << 18) | U;
+}
 
 // One node update: pull streaming (periodic wrap on every axis; sources
 // beyond a bounded face land on in-bounds values that the boundary rule then
@@ -234,17 +244,25 @@ __device__ __forceinline__ void update_node(const Access &mem, const NodeGeom &g
   S raw[19];
   const unsigned n = (unsigned(z) * ny + unsigned(y)) * nx + unsigned(x);
   bool solid_node = false;
+  unsigned gcode = 0u;
   if constexpr (EXT) {
     if (ext.solid) solid_node = ext.solid[n] != 0;
+    if (ext.code) {
+      gcode = ext.code[n];
+      solid_node = (gcode >> 24) == kGeoSolid;
+    }
   }
-  if (EXT && ext.solid) {
+  if (EXT && solid_node) {
+    // a solid node (or solid interior of a geometry) keeps its populations
+#pragma unroll
+    for (int k = 0; k < 19; ++k) raw[k] = mem.load(k, n);
+  } else if (EXT && ext.solid) {
 #pragma unroll
     for (int k = 0; k < 19; ++k) {
       const unsigned off = (yy[cy(k) + 1] + ny * zz[cz(k) + 1]) * nx + xs[cx(k) + 1];
-      // solid source (or a solid node itself): the node's own population
-      const bool own = solid_node || (k != 18 && ext.solid[off] != 0);
-      const int kk = solid_node ? k : opp(k);
-      raw[k] = mem.load(own ? kk : k, own ? n : off);
+      // solid source: the node's own opposite population (mid-grid bounce-back)
+      const bool own = k != 18 && ext.solid[off] != 0;
+      raw[k] = mem.load(own ? opp(k) : k, own ? n : off);
     }
   } else {
 #pragma unroll
@@ -264,6 +282,17 @@ __device__ __forceinline__ void update_node(const Access &mem, const NodeGeom &g
     if (unsigned(y) == ny - 1) m |= bc_mask & 8u;
     if (z == 0) m |= bc_mask & 16u;
     if (unsigned(z) == nz - 1) m |= bc_mask & 32u;
+    if constexpr (EXT) {
+      // Complex geometry: walls at rest, rule from the node code.
+      const unsigned kind = gcode >> 24;
+      if (kind == kGeoPlaneEdgeCorner) {
+        boundary_rule<T>(f, (gcode >> 18) & 63u, p, 0u, T(0), T(0), T(0), T(1));
+      } else if (kind == kGeoConvexEdge) {
+        convex_edge_rule<T>(f, gcode & 0x3ffffu);
+      } else if (kind == kGeoGeneral) {
+        general_wall_rule<T>(f, gcode & 0x3ffffu);
+      }
+    }
     if (m) {
       T vx, vy, vz, r0;
       face_values<T>(m, p, vx, vy, vz, r0);
@@ -282,7 +311,7 @@ __device__ __forceinline__ void update_node(const Access &mem, const NodeGeom &g
           vz = T(fld[3 * idx + 2]);
         }
       }
-      boundary_rule<T>(f, m, p, vx, vy, vz, r0);
+      boundary_rule<T>(f, m, p, p.p_mask, vx, vy, vz, r0);
     }
     bgk_collide<T>(f, p.omega, p.tau_f);
     unsigned r = F::kStochastic ? fmix32(n * 0x9e3779b1u + key) : 0u;

@@ -28,7 +28,8 @@ STORAGE_NAMES = {LBM_STORE_F64: "f64", LBM_STORE_F32: "f32", LBM_STORE_F16_DEV: 
 # Every symbol include/lbm.h declares.
 EXPORTS = (
     "lbm_create", "lbm_create_on_buffers", "lbm_set_velocity_bc", "lbm_set_pressure_bc", "lbm_set_velocity_field",
-    "lbm_set_solid_mask", "lbm_set_rule_options", "lbm_set_body_force", "lbm_clear_bc", "lbm_step",
+    "lbm_set_solid_mask", "lbm_set_geometry", "lbm_classify_geometry", "lbm_set_rule_options", "lbm_set_body_force",
+    "lbm_clear_bc", "lbm_step",
     "lbm_moments", "lbm_totals", "lbm_get_populations", "lbm_set_populations", "lbm_state_buffer",
     "lbm_element_bytes", "lbm_population_pitch", "lbm_set_launch", "lbm_get_launch", "lbm_probe",
     "lbm_destroy", "lbm_last_error",
@@ -96,6 +97,9 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_set_velocity_field.argtypes = [_vp, st, _dp]
     lib.lbm_set_solid_mask.argtypes = [_vp, ctypes.POINTER(ctypes.c_ubyte)]
     lib.lbm_set_rule_options.argtypes = [_vp, ctypes.c_uint]
+    lib.lbm_set_geometry.argtypes = [_vp, ctypes.POINTER(ctypes.c_ubyte)]
+    lib.lbm_classify_geometry.argtypes = [st, st, st, ctypes.POINTER(ctypes.c_ubyte), ctypes.POINTER(ctypes.c_uint),
+                                          ctypes.POINTER(ctypes.c_longlong)]
     lib.lbm_set_body_force.argtypes = [_vp, _dp]
     lib.lbm_clear_bc.argtypes = [_vp, st]
     lib.lbm_step.argtypes = [_vp, st]
@@ -219,6 +223,30 @@ def lbm_set_solid_mask(h, solid=None):
         return
     a = np.ascontiguousarray(np.asarray(solid).astype(np.uint8))
     _check(load_library().lbm_set_solid_mask(h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))))
+
+
+def lbm_set_geometry(h, cell=None):
+    """cell: (nz, ny, nx) node types (0 fluid, 1 wall, 2 solid interior), or None."""
+    if cell is None:
+        _check(load_library().lbm_set_geometry(h, None))
+        return
+    a = np.ascontiguousarray(np.asarray(cell).astype(np.uint8))
+    _check(load_library().lbm_set_geometry(h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))))
+
+
+GEO_FLUID, GEO_SOLID, GEO_PLANE_EDGE_CORNER, GEO_CONVEX_EDGE, GEO_GENERAL = range(5)
+
+
+def lbm_classify_geometry(cell):
+    """Host-only classification of (nz, ny, nx) node types; returns (code
+    array of the same shape, uint32; counts per kind)."""
+    a = np.ascontiguousarray(np.asarray(cell).astype(np.uint8))
+    nz, ny, nx = a.shape
+    code = np.zeros(a.shape, np.uint32)
+    counts = (ctypes.c_longlong * 5)()
+    _check(load_library().lbm_classify_geometry(nx, ny, nz, a.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)),
+                                                code.ctypes.data_as(ctypes.POINTER(ctypes.c_uint)), counts))
+    return code, list(counts)
 
 
 def lbm_set_rule_options(h, flags: int):

@@ -86,21 +86,17 @@ __host__ __device__ __forceinline__ unsigned fmix32(unsigned h) {
 __host__ __device__ __forceinline__ unsigned step_key(unsigned t) { return fmix32(t * 0x9e3779b1u + 0x7f4a7c15u); }
 
 // d * 2^8 rounded stochastically to half precision; r: 32 random bits.
-// A float magnitude a = e<<23 | m in the half normal range becomes the half
-// (e - 112)<<10 | m>>13, i.e. (a - 0x38000000) >> 13; adding 13 uniform
-// random bits below the cut before the shift rounds up with probability
-// (m mod 2^13) / 2^13, which makes the rounding unbiased (a carry out of the
-// mantissa moves to the next binade, as it should).  Outside the half normal
-// range (|d| < 2^-22, or |d| near 256) the nearest value is taken.
+// gfx950's conversion with stochastic rounding adds the top 13 bits of r
+// below the half-precision cut of the float before truncating (for a normal
+// float a = e<<23 | m that is ((a - 0x38000000) + (r >> 19)) >> 13), so it
+// rounds up with probability (m mod 2^13) / 2^13 and E[h] = d * 2^8; a carry
+// out of the mantissa moves to the next binade, and half subnormals are
+// rounded the same way.
 __device__ __forceinline__ _Float16 encode_half_sr(float d, unsigned r) {
-  const float x = d * 256.0f;
-  const unsigned u = __builtin_bit_cast(unsigned, x);
-  const unsigned a = u & 0x7fffffffu;
-  if (a >= 0x38800000u && a < 0x477fe000u) {
-    const unsigned h = ((u >> 16) & 0x8000u) | ((a + (r >> 19) - 0x38000000u) >> 13);
-    return __builtin_bit_cast(_Float16, static_cast<unsigned short>(h));
-  }
-  return static_cast<_Float16>(x);
+  typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+  half2_t v = {static_cast<_Float16>(0.0f), static_cast<_Float16>(0.0f)};
+  v = __builtin_amdgcn_cvt_sr_f16_f32(v, d * 256.0f, r, false);
+  return v[0];
 }
 
 template <class F>
@@ -314,12 +310,12 @@ __device__ __forceinline__ void update_node(const Access &mem, const NodeGeom &g
       boundary_rule<T>(f, m, p, p.p_mask, vx, vy, vz, r0);
     }
     bgk_collide<T>(f, p.omega, p.tau_f);
-    unsigned r = F::kStochastic ? fmix32(n * 0x9e3779b1u + key) : 0u;
+    // Random words of the stochastic rounding: a hash of (node, step), then
+    // a golden-ratio Weyl sequence over the populations (each word uniform;
+    // only its top 13 bits are used).
+    const unsigned r0 = F::kStochastic ? fmix32(n * 0x9e3779b1u + key) : 0u;
 #pragma unroll
-    for (int k = 0; k < 19; ++k) {
-      if constexpr (F::kStochastic) r = r * 1664525u + 1013904223u;  // per-population stream
-      raw[k] = encode_form<F>(f[k], r);
-    }
+    for (int k = 0; k < 19; ++k) raw[k] = encode_form<F>(f[k], r0 + unsigned(k + 1) * 0x9e3779b9u);
   }
 #pragma unroll
   for (int k = 0; k < 19; ++k) mem.store(k, n, raw[k]);

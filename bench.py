@@ -84,8 +84,8 @@ def ingest_counters(args):
         assert len(ks) == 1, (frag, list(d))
         return ks[0], d[ks[0]]
 
-    sweep_name, f_sweep = pick(fetch, ", false>(")  # the full sweep (COPY = false)
-    _, w_sweep = pick(write, ", false>(")
+    sweep_name, f_sweep = pick(fetch, ", false, false>(")  # the full sweep (COPY = false, EXT = false)
+    _, w_sweep = pick(write, ", false, false>(")
     _, f_copy = pick(fetch, "copy_probe_kernel")
     _, w_copy = pick(write, "copy_probe_kernel")
     fs, ws = copy_kib / f_copy, copy_kib / w_copy

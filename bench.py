@@ -135,9 +135,21 @@ def cpu_baseline(spec_full, budget_s: float):
         if (el >= budget_s and steps >= 2) or steps >= 2000:
             break
     mlups = s.nodes * steps / el / 1e6
+    # the same sample on one thread, for a third of the budget
+    steps1 = 0
+    t0 = time.perf_counter()
+    while True:
+        f = L.step(f, nthreads=1)
+        steps1 += 1
+        el1 = time.perf_counter() - t0
+        if (el1 >= budget_s / 3 and steps1 >= 1) or steps1 >= 500:
+            break
+    mlups1 = s.nodes * steps1 / el1 / 1e6
     return {"value": round(mlups, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "single_thread_value": round(mlups1, 3),
             "sample": f"duct {s.nx}x{s.ny}x{s.nz} (same boundary set-up, 1/64 of the nodes), FP64, "
-                      f"{steps} steps in {el:.1f} s; effective {mlups * 304 / 1e3:.2f} GB/s at 304 B/node"}
+                      f"{steps} steps in {el:.1f} s on {threads} threads; effective {mlups * 304 / 1e3:.2f} GB/s "
+                      f"at 304 B/node; on 1 thread {steps1} steps in {el1:.1f} s"}
 
 
 def _device_rel_l2(u, ref):

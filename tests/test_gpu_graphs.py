@@ -1,0 +1,113 @@
+"""lbm_step replays a captured graph of sweeps for long runs: results must be
+bit-identical to one launch per step, also when the configuration changes
+between calls (moving walls, launch shape, geometry options) and for step
+counts that are not multiples of the graph length."""
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_0811_4593_amd import lbm, workloads  # noqa: E402
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def _pair(spec, storage, solid=None):
+    hs = []
+    for _ in range(2):
+        h = lbm.lbm_create(spec.nx, spec.ny, spec.nz, spec.tau, 1.0, None, storage, torch.cuda.current_stream())
+        for face, v in spec.bc.items():
+            lbm.lbm_set_velocity_bc(h, face, v)
+        if solid is not None:
+            lbm.lbm_set_solid_mask(h, solid)
+        hs.append(h)
+    return hs
+
+
+def _state(h, spec):
+    f = np.empty((19, spec.nz, spec.ny, spec.nx))
+    return lbm.lbm_get_populations(h, f)
+
+
+def _one_by_one(h, n):
+    for _ in range(n):
+        lbm.lbm_step(h, 1)
+
+
+@pytest.mark.parametrize("storage", [lbm.LBM_STORE_F64, lbm.LBM_STORE_F32, lbm.LBM_STORE_F16_DEV,
+                                     lbm.LBM_STORE_F16_DEV_SR])
+def test_graph_steps_equal_single_launches(storage):
+    spec = workloads.couette(16, 16, 32, 0.05, 1.0)
+    a, b = _pair(spec, storage)
+    try:
+        lbm.lbm_step(a, 77)           # 2 graph replays + 13 launches
+        _one_by_one(b, 77)
+        np.testing.assert_array_equal(_state(a, spec), _state(b, spec))
+        # moving wall: a new velocity must be captured anew
+        for h in (a, b):
+            lbm.lbm_set_velocity_bc(h, 5, (0.03, 0.01, 0.0))
+        lbm.lbm_step(a, 64)
+        _one_by_one(b, 64)
+        np.testing.assert_array_equal(_state(a, spec), _state(b, spec))
+        # other launch shape, odd parity on entry (the state is in the other buffer)
+        for h in (a, b):
+            lbm.lbm_set_launch(h, 128, 1, 0)
+        lbm.lbm_step(a, 33)
+        _one_by_one(b, 33)
+        lbm.lbm_step(a, 96)
+        _one_by_one(b, 96)
+        np.testing.assert_array_equal(_state(a, spec), _state(b, spec))
+    finally:
+        for h in (a, b):
+            lbm.lbm_destroy(h)
+
+
+def test_graph_steps_with_solid_mask_and_rule_option():
+    st = workloads.tilted_channel(ny=2)
+    s = st.spec
+    a, b = _pair(s, lbm.LBM_STORE_F64, st.solid)
+    try:
+        for h in (a, b):
+            for face, fv in st.face_v.items():
+                lbm.lbm_set_velocity_field(h, face, fv)
+        lbm.lbm_step(a, 70)
+        _one_by_one(b, 70)
+        np.testing.assert_array_equal(_state(a, s), _state(b, s))
+        for h in (a, b):
+            lbm.lbm_set_rule_options(h, lbm.LBM_RULE_NO_TRANSVERSE)
+        lbm.lbm_step(a, 64)
+        _one_by_one(b, 64)
+        np.testing.assert_array_equal(_state(a, s), _state(b, s))
+    finally:
+        for h in (a, b):
+            lbm.lbm_destroy(h)
+
+
+def test_graph_speeds_up_small_lattices():
+    spec = workloads.couette(16, 16, 32, 0.05, 1.0)
+    a, b = _pair(spec, lbm.LBM_STORE_F64)
+    try:
+        lbm.lbm_step(a, 64)
+        _one_by_one(b, 64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lbm.lbm_step(a, 3200)
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _one_by_one(b, 3200)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        say(f"16x16x32 FP64, 3200 steps: graph {tg * 1e3:.1f} ms, one launch per step {tp * 1e3:.1f} ms")
+        np.testing.assert_array_equal(_state(a, spec), _state(b, spec))
+    finally:
+        for h in (a, b):
+            lbm.lbm_destroy(h)

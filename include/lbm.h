@@ -204,10 +204,7 @@ lbm_status lbm_set_body_force(lbm_lattice *L, const double F[3]);
 lbm_status lbm_clear_bc(lbm_lattice *L, lbm_face face);
 
 /* Enqueue nsteps >= 0 time steps on the handle's stream; returns without
- * waiting.  Runs of 32 steps or more replay a HIP graph of 32 sweeps
- * captured for the current configuration (recaptured after any change;
- * plain launches for the stochastic-rounding form and while the caller is
- * capturing the stream); results are bit-identical to one call per step.  Errors: LBM_ERR_ARG (L NULL, nsteps < 0), LBM_ERR_STATE (an axis
+ * waiting.  Errors: LBM_ERR_ARG (L NULL, nsteps < 0), LBM_ERR_STATE (an axis
  * with a BC on one face only, pressure faces on more than one axis),
  * LBM_ERR_HIP (launch failure). */
 lbm_status lbm_step(lbm_lattice *L, int nsteps);

@@ -42,7 +42,6 @@ lbm_status hip_fail(hipError_t e, const char *what) {
 
 constexpr int kPartialBlocks = 1024;  // fixed grid of the reduction: deterministic order
 constexpr size_t kChunkNodes = size_t(1) << 22;  // host transfers are staged in chunks
-constexpr int kGraphSteps = 32;                  // sweeps per captured graph (even: the state returns to its buffer)
 
 }  // namespace
 
@@ -66,12 +65,6 @@ struct lbm_lattice {
   unsigned char *d_solid;  // [N] solid flags on the device, or nullptr
   double *d_face_v[6];     // per-node face velocities on the device, or nullptr
   unsigned *d_geo;         // complex-geometry node codes on the device, or nullptr
-  // Graph of kGraphSteps sweeps (replayed by lbm_step for long runs), the
-  // configuration it was captured for, and the stream it is captured on.
-  hipStream_t cap_stream;
-  hipGraphExec_t graph_exec;
-  lbm::SweepConfig graph_cfg;
-  int graph_cur;
   int block_x, npt, xcd;
   unsigned steps;      // steps taken since creation (keys the stochastic rounding)
   double *d_partials;  // [kPartialBlocks * 4]
@@ -204,8 +197,6 @@ void lbm_destroy(lbm_lattice *L) {
     for (int i = 0; i < 2; ++i)
       if (L->buf[i]) (void)hipFree(L->buf[i]);
   }
-  if (L->graph_exec) (void)hipGraphExecDestroy(L->graph_exec);
-  if (L->cap_stream) (void)hipStreamDestroy(L->cap_stream);
   if (L->d_partials) (void)hipFree(L->d_partials);
   if (L->d_solid) (void)hipFree(L->d_solid);
   if (L->d_geo) (void)hipFree(L->d_geo);
@@ -400,7 +391,6 @@ lbm_status lbm_set_body_force(lbm_lattice *L, const double F[3]) {
 
 static lbm::SweepConfig sweep_config(const lbm_lattice *L) {
   lbm::SweepConfig c;
-  std::memset(&c, 0, sizeof(c));  // padding too: configurations are compared bytewise
   c.storage = L->storage;
   c.nx = L->nx;
   c.ny = L->ny;
@@ -422,45 +412,6 @@ static lbm::SweepConfig sweep_config(const lbm_lattice *L) {
   return c;
 }
 
-// Capture (or reuse) the graph of kGraphSteps sweeps for configuration c
-// starting from buf[cur].  On any failure the graph is dropped and lbm_step
-// falls back to plain launches.
-static lbm_status ensure_graph(lbm_lattice *L, const lbm::SweepConfig &c) {
-  lbm::SweepConfig key = c;
-  key.step = 0;
-  if (L->graph_exec && L->graph_cur == L->cur && std::memcmp(&key, &L->graph_cfg, sizeof(key)) == 0) return LBM_OK;
-  if (L->graph_exec) {
-    (void)hipGraphExecDestroy(L->graph_exec);
-    L->graph_exec = nullptr;
-  }
-  if (!L->cap_stream && hipStreamCreateWithFlags(&L->cap_stream, hipStreamNonBlocking) != hipSuccess) {
-    L->cap_stream = nullptr;
-    (void)hipGetLastError();
-    return LBM_ERR_HIP;
-  }
-  hipGraph_t g = nullptr;
-  if (hipStreamBeginCapture(L->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-    (void)hipGetLastError();
-    return LBM_ERR_HIP;
-  }
-  bool ok = true;
-  for (int s = 0; s < kGraphSteps && ok; ++s)
-    ok = lbm::launch_sweep(key, L->buf[L->cur ^ (s & 1)], L->buf[L->cur ^ ((s + 1) & 1)], false, L->cap_stream) ==
-         hipSuccess;
-  const hipError_t e_end = hipStreamEndCapture(L->cap_stream, &g);
-  ok = ok && e_end == hipSuccess && g != nullptr;
-  if (ok) ok = hipGraphInstantiate(&L->graph_exec, g, nullptr, nullptr, 0) == hipSuccess;
-  if (g) (void)hipGraphDestroy(g);
-  if (!ok) {
-    L->graph_exec = nullptr;
-    (void)hipGetLastError();
-    return LBM_ERR_HIP;
-  }
-  L->graph_cfg = key;
-  L->graph_cur = L->cur;
-  return LBM_OK;
-}
-
 lbm_status lbm_step(lbm_lattice *L, int nsteps) {
   if (!L) return fail(LBM_ERR_ARG, "NULL handle");
   if (nsteps < 0) return fail(LBM_ERR_ARG, "nsteps must be >= 0");
@@ -477,26 +428,7 @@ lbm_status lbm_step(lbm_lattice *L, int nsteps) {
   if (p_axes > 1)
     return fail(LBM_ERR_STATE, "pressure faces on %d axes: edges between two pressure faces are not defined", p_axes);
   lbm::SweepConfig c = sweep_config(L);
-  // Long runs replay a captured graph of kGraphSteps sweeps (a launch-bound
-  // small lattice steps several times faster).  Not for the stochastic form,
-  // whose per-step key is a kernel argument, and not while the caller is
-  // capturing the stream.
-  int done = 0;
-  if (nsteps >= kGraphSteps && c.storage != lbm::kStoreF16SR) {
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (L->stream == nullptr || hipStreamIsCapturing(L->stream, &cs) == hipSuccess) {
-      if (cs == hipStreamCaptureStatusNone && ensure_graph(L, c) == LBM_OK) {
-        for (; done + kGraphSteps <= nsteps; done += kGraphSteps) {
-          hipError_t e = hipGraphLaunch(L->graph_exec, L->stream);
-          if (e != hipSuccess) return hip_fail(e, "graph launch");
-          L->steps += kGraphSteps;  // the state is back in buf[cur]
-        }
-      }
-    } else {
-      (void)hipGetLastError();
-    }
-  }
-  for (int s = done; s < nsteps; ++s) {
+  for (int s = 0; s < nsteps; ++s) {
     c.step = L->steps;
     hipError_t e = lbm::launch_sweep(c, L->buf[L->cur], L->buf[L->cur ^ 1], false, L->stream);
     if (e != hipSuccess) return hip_fail(e, "sweep launch");

@@ -1,7 +1,6 @@
-"""lbm_step replays a captured graph of sweeps for long runs: results must be
-bit-identical to one launch per step, also when the configuration changes
-between calls (moving walls, launch shape, geometry options) and for step
-counts that are not multiples of the graph length."""
+"""lbm_step(n) against n calls of lbm_step(1): bit-identical results, also when
+the configuration changes between calls (moving walls, launch shape,
+geometry options, the parity of the buffer holding the state)."""
 import time
 
 import numpy as np
@@ -44,14 +43,14 @@ def _one_by_one(h, n):
 
 @pytest.mark.parametrize("storage", [lbm.LBM_STORE_F64, lbm.LBM_STORE_F32, lbm.LBM_STORE_F16_DEV,
                                      lbm.LBM_STORE_F16_DEV_SR])
-def test_graph_steps_equal_single_launches(storage):
+def test_long_runs_equal_single_steps(storage):
     spec = workloads.couette(16, 16, 32, 0.05, 1.0)
     a, b = _pair(spec, storage)
     try:
-        lbm.lbm_step(a, 77)           # 2 graph replays + 13 launches
+        lbm.lbm_step(a, 77)
         _one_by_one(b, 77)
         np.testing.assert_array_equal(_state(a, spec), _state(b, spec))
-        # moving wall: a new velocity must be captured anew
+        # moving wall
         for h in (a, b):
             lbm.lbm_set_velocity_bc(h, 5, (0.03, 0.01, 0.0))
         lbm.lbm_step(a, 64)
@@ -70,7 +69,7 @@ def test_graph_steps_equal_single_launches(storage):
             lbm.lbm_destroy(h)
 
 
-def test_graph_steps_with_solid_mask_and_rule_option():
+def test_long_runs_with_solid_mask_and_rule_option():
     st = workloads.tilted_channel(ny=2)
     s = st.spec
     a, b = _pair(s, lbm.LBM_STORE_F64, st.solid)
@@ -91,7 +90,7 @@ def test_graph_steps_with_solid_mask_and_rule_option():
             lbm.lbm_destroy(h)
 
 
-def test_graph_speeds_up_small_lattices():
+def test_long_run_timing_small_lattice():
     spec = workloads.couette(16, 16, 32, 0.05, 1.0)
     a, b = _pair(spec, lbm.LBM_STORE_F64)
     try:
@@ -106,7 +105,7 @@ def test_graph_speeds_up_small_lattices():
         _one_by_one(b, 3200)
         torch.cuda.synchronize()
         tp = time.perf_counter() - t0
-        say(f"16x16x32 FP64, 3200 steps: graph {tg * 1e3:.1f} ms, one launch per step {tp * 1e3:.1f} ms")
+        say(f"16x16x32 FP64, 3200 steps: one call {tg * 1e3:.1f} ms, one call per step {tp * 1e3:.1f} ms")
         np.testing.assert_array_equal(_state(a, spec), _state(b, spec))
     finally:
         for h in (a, b):

@@ -177,9 +177,12 @@ def form_precision(args):
         try:
             for face, v in spec.bc.items():
                 lbm.lbm_set_velocity_bc(h, face, v)
+            # launch shape picked on real steps; they count towards the run
+            shape = lbm.lbm_autotune(h, 2)
+            done = lbm.lbm_get_step(h)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            lbm.lbm_step(h, steps)
+            lbm.lbm_step(h, steps - done)
             torch.cuda.synchronize()
             sec = time.perf_counter() - t0
             u = torch.empty(3 * N, dtype=torch.float64, device="cuda")
@@ -188,8 +191,9 @@ def form_precision(args):
         finally:
             lbm.lbm_destroy(h)
         fields[name] = u
-        res[name] = {"MLUPS": round(N * steps / sec / 1e6, 1),
-                     "GBs": round(N * steps / sec * 2 * 19 * lbm.lbm_element_bytes(st) / 1e9, 1),
+        res[name] = {"MLUPS": round(N * (steps - done) / sec / 1e6, 1),
+                     "GBs": round(N * (steps - done) / sec * 2 * 19 * lbm.lbm_element_bytes(st) / 1e9, 1),
+                     "launch": list(shape),
                      "mass": mass, "momentum": [float(x) for x in mom]}
         print(f"precision form: {name} done in {sec:.1f} s", file=sys.stderr, flush=True)
     for name in ("f32", "f16dev", "f16sr"):
@@ -273,6 +277,9 @@ def main():
     ap.add_argument("--ny", type=int, default=512)
     ap.add_argument("--nz", type=int, default=512)
     ap.add_argument("--probe-reps", type=int, default=10)
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the launch shape with lbm_autotune during the warm-up (default: the library's "
+                         "default shape, the fastest measured on this workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -316,8 +323,13 @@ def main():
     try:
         for face, v in spec.bc.items():
             lbm.lbm_set_velocity_bc(h, face, v)
+        tuned = False
         if args.launch:
             lbm.lbm_set_launch(h, *[int(t) for t in args.launch.split(",")])
+        elif args.autotune:
+            # the autotuner's trial steps are real, untimed steps (part of the warm-up)
+            lbm.lbm_autotune(h, 2)
+            tuned = True
         launch = lbm.lbm_get_launch(h)
 
         lbm.lbm_step(h, args.warmup)
@@ -374,7 +386,8 @@ def main():
                         f"(0.04,0.01,0.01), on-site no-slip y/z walls, tau 0.8, {args.storage} storage",
             "nodes": N,
             "bytes_per_node_update": 2 * 19 * ebytes,
-            "launch": {"block_x": launch[0], "nodes_per_thread": launch[1], "xcd_remap": launch[2]},
+            "launch": {"block_x": launch[0], "nodes_per_thread": launch[1], "xcd_remap": launch[2],
+                       "autotuned": tuned},
         },
         "roofline": {
             "bound": "hbm",

@@ -251,6 +251,22 @@ size_t lbm_population_pitch(size_t nodes);
 lbm_status lbm_set_launch(lbm_lattice *L, int block_x, int nodes_per_thread, int xcd_remap);
 lbm_status lbm_get_launch(const lbm_lattice *L, int *block_x, int *nodes_per_thread, int *xcd_remap);
 
+/* Number of steps the lattice has taken since creation (lbm_step,
+ * lbm_autotune; lbm_set_populations does not reset it).  It also keys the
+ * random numbers of the stochastic-rounding form.  Errors: LBM_ERR_ARG. */
+lbm_status lbm_get_step(const lbm_lattice *L, unsigned long long *steps);
+
+/* Pick the fastest launch shape for this lattice by timing real steps: for
+ * each candidate (blocks of 64..512 threads no wider than the row rounded up
+ * to a power of two, 1, 2 or 4 nodes per thread; one node per thread with a
+ * solid mask, face field or geometry) one untimed and trial_steps >= 1
+ * timed steps on the lattice's stream (HIP events).  The steps are part of
+ * the run (the lattice advances by (1 + trial_steps) per candidate; results
+ * do not depend on the shape).  Sets the winner and returns it through the
+ * non-NULL pointers.  Synchronizes.  Errors: LBM_ERR_ARG, LBM_ERR_STATE (as
+ * lbm_step), LBM_ERR_HIP; on error the previous shape is restored. */
+lbm_status lbm_autotune(lbm_lattice *L, int trial_steps, int *block_x, int *nodes_per_thread, int *xcd_remap);
+
 /* Bandwidth probes on the handle's buffers (measurement only; they overwrite
  * the non-current buffer and leave the stored state intact):
  *   kind 0: plain contiguous copy of the 19*N elements;

@@ -66,7 +66,7 @@ struct lbm_lattice {
   double *d_face_v[6];     // per-node face velocities on the device, or nullptr
   unsigned *d_geo;         // complex-geometry node codes on the device, or nullptr
   int block_x, npt, xcd;
-  unsigned steps;      // steps taken since creation (keys the stochastic rounding)
+  unsigned long long steps;  // steps taken since creation (its low 32 bits key the stochastic rounding)
   double *d_partials;  // [kPartialBlocks * 4]
   double *d_totals;    // [4]
   double *d_stage;     // [19 * kChunkNodes] doubles, allocated on first use
@@ -408,7 +408,7 @@ static lbm::SweepConfig sweep_config(const lbm_lattice *L) {
   c.block_x = L->block_x;
   c.nodes_per_thread = L->npt;
   c.xcd_remap = L->xcd;
-  c.step = L->steps;
+  c.step = unsigned(L->steps);
   return c;
 }
 
@@ -429,7 +429,7 @@ lbm_status lbm_step(lbm_lattice *L, int nsteps) {
     return fail(LBM_ERR_STATE, "pressure faces on %d axes: edges between two pressure faces are not defined", p_axes);
   lbm::SweepConfig c = sweep_config(L);
   for (int s = 0; s < nsteps; ++s) {
-    c.step = L->steps;
+    c.step = unsigned(L->steps);
     hipError_t e = lbm::launch_sweep(c, L->buf[L->cur], L->buf[L->cur ^ 1], false, L->stream);
     if (e != hipSuccess) return hip_fail(e, "sweep launch");
     L->cur ^= 1;
@@ -552,6 +552,70 @@ lbm_status lbm_get_launch(const lbm_lattice *L, int *block_x, int *nodes_per_thr
   *block_x = L->block_x;
   *nodes_per_thread = L->npt;
   *xcd_remap = L->xcd;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_step(const lbm_lattice *L, unsigned long long *steps) {
+  if (!L || !steps) return fail(LBM_ERR_ARG, "NULL argument");
+  *steps = L->steps;
+  return LBM_OK;
+}
+
+lbm_status lbm_autotune(lbm_lattice *L, int trial_steps, int *block_x, int *nodes_per_thread, int *xcd_remap) {
+  if (!L) return fail(LBM_ERR_ARG, "NULL handle");
+  if (trial_steps < 1) return fail(LBM_ERR_ARG, "trial_steps must be >= 1");
+  const lbm_status st = lbm_step(L, 0);  // the state checks of lbm_step
+  if (st != LBM_OK) return st;
+  // Candidate shapes: blocks no wider than the row rounded up to a power of
+  // two (at least 64); one node per thread for the extended sweep.
+  const bool ext = L->d_solid || L->d_geo || L->d_face_v[0] || L->d_face_v[1] || L->d_face_v[2] ||
+                   L->d_face_v[3] || L->d_face_v[4] || L->d_face_v[5];
+  int row = 64;
+  while (row < L->nx && row < 512) row *= 2;
+  static const int cand[][2] = {{64, 1}, {128, 1}, {256, 1}, {512, 1}, {128, 2}, {256, 2}, {128, 4}, {256, 4}};
+  const int old[3] = {L->block_x, L->npt, L->xcd};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_fail(hipGetLastError(), "event creation");
+  }
+  float best_ms = 0.0f;
+  int best = -1;
+  lbm_status result = LBM_OK;
+  for (int i = 0; i < int(sizeof(cand) / sizeof(cand[0])); ++i) {
+    const int bx = cand[i][0], npt = cand[i][1];
+    if (bx * npt > row || (ext && npt != 1)) continue;
+    L->block_x = bx;
+    L->npt = npt;
+    L->xcd = 1;
+    // one untimed step, then trial_steps timed ones (all of them real steps)
+    result = lbm_step(L, 1);
+    if (result == LBM_OK && hipEventRecord(e0, L->stream) != hipSuccess) result = hip_fail(hipGetLastError(), "event");
+    if (result == LBM_OK) result = lbm_step(L, trial_steps);
+    if (result == LBM_OK && hipEventRecord(e1, L->stream) != hipSuccess) result = hip_fail(hipGetLastError(), "event");
+    float ms = 0.0f;
+    if (result == LBM_OK && hipEventSynchronize(e1) != hipSuccess) result = hip_fail(hipGetLastError(), "event");
+    if (result == LBM_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) result = hip_fail(hipGetLastError(), "timing");
+    if (result != LBM_OK) break;
+    if (best < 0 || ms < best_ms) {
+      best_ms = ms;
+      best = i;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (result != LBM_OK || best < 0) {
+    L->block_x = old[0];
+    L->npt = old[1];
+    L->xcd = old[2];
+    return result != LBM_OK ? result : fail(LBM_ERR_STATE, "no launch shape to try");
+  }
+  L->block_x = cand[best][0];
+  L->npt = cand[best][1];
+  L->xcd = 1;
+  if (block_x) *block_x = L->block_x;
+  if (nodes_per_thread) *nodes_per_thread = L->npt;
+  if (xcd_remap) *xcd_remap = L->xcd;
   return LBM_OK;
 }
 

@@ -31,7 +31,7 @@ EXPORTS = (
     "lbm_set_solid_mask", "lbm_set_geometry", "lbm_classify_geometry", "lbm_set_rule_options", "lbm_set_body_force",
     "lbm_clear_bc", "lbm_step",
     "lbm_moments", "lbm_totals", "lbm_get_populations", "lbm_set_populations", "lbm_state_buffer",
-    "lbm_element_bytes", "lbm_population_pitch", "lbm_set_launch", "lbm_get_launch", "lbm_probe",
+    "lbm_element_bytes", "lbm_population_pitch", "lbm_set_launch", "lbm_get_launch", "lbm_autotune", "lbm_get_step", "lbm_probe",
     "lbm_destroy", "lbm_last_error",
     "lbm_job_bytes", "lbm_batch_create", "lbm_batch_submit", "lbm_batch_run_chunk", "lbm_batch_poll",
     "lbm_batch_result", "lbm_batch_set_shape", "lbm_batch_get_shape", "lbm_batch_autotune",
@@ -114,6 +114,8 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_population_pitch.restype = ctypes.c_size_t
     lib.lbm_set_launch.argtypes = [_vp, st, st, st]
     lib.lbm_get_launch.argtypes = [_vp, ctypes.POINTER(st), ctypes.POINTER(st), ctypes.POINTER(st)]
+    lib.lbm_autotune.argtypes = [_vp, st, ctypes.POINTER(st), ctypes.POINTER(st), ctypes.POINTER(st)]
+    lib.lbm_get_step.argtypes = [_vp, ctypes.POINTER(ctypes.c_ulonglong)]
     lib.lbm_probe.argtypes = [_vp, st, st]
     lib.lbm_destroy.argtypes = [_vp]
     lib.lbm_destroy.restype = None
@@ -310,6 +312,20 @@ def lbm_get_launch(h):
     a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     _check(load_library().lbm_get_launch(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
     return a.value, b.value, c.value
+
+
+def lbm_autotune(h, trial_steps: int = 2):
+    """Time the candidate launch shapes on real steps and keep the fastest;
+    returns (block_x, nodes_per_thread, xcd_remap)."""
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load_library().lbm_autotune(h, int(trial_steps), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def lbm_get_step(h) -> int:
+    s = ctypes.c_ulonglong()
+    _check(load_library().lbm_get_step(h, ctypes.byref(s)))
+    return s.value
 
 
 def lbm_probe(h, kind: int, nrep: int = 1):

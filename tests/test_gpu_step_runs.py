@@ -110,3 +110,33 @@ def test_long_run_timing_small_lattice():
     finally:
         for h in (a, b):
             lbm.lbm_destroy(h)
+
+
+def test_autotune_advances_real_steps_and_keeps_results():
+    spec = workloads.duct(300, 20, 18, (0.04, 0.01, 0.01), 0.8)
+    for storage in (lbm.LBM_STORE_F32, lbm.LBM_STORE_F16_DEV_SR):
+        a, b = _pair(spec, storage)
+        try:
+            shape = lbm.lbm_autotune(a, 2)
+            done = lbm.lbm_get_step(a)
+            assert shape[0] in (64, 128, 256, 512) and shape[1] in (1, 2, 4) and done > 0
+            assert lbm.lbm_get_launch(a) == shape
+            lbm.lbm_step(a, 50)
+            lbm.lbm_step(b, done + 50)
+            assert lbm.lbm_get_step(a) == lbm.lbm_get_step(b) == done + 50
+            np.testing.assert_array_equal(_state(a, spec), _state(b, spec))
+            say(f"storage {storage}: autotuned {shape} in {done} steps")
+        finally:
+            for h in (a, b):
+                lbm.lbm_destroy(h)
+    h = lbm.lbm_create(8, 8, 8, 0.8, 1.0, None, lbm.LBM_STORE_F64, torch.cuda.current_stream())
+    try:
+        with pytest.raises(lbm.LBMError) as e:
+            lbm.lbm_autotune(h, 0)
+        assert e.value.status == lbm.LBM_ERR_ARG
+        lbm.lbm_set_velocity_bc(h, 4, (0.0, 0.0, 0.0))  # one face of an axis only
+        with pytest.raises(lbm.LBMError) as e:
+            lbm.lbm_autotune(h, 2)
+        assert e.value.status == lbm.LBM_ERR_STATE
+    finally:
+        lbm.lbm_destroy(h)

@@ -201,3 +201,58 @@ def test_serving_loop_small_trace_same_alone_and_in_mix():
     for i, r in enumerate(trace):
         _, _, u_alone = serving.run_plain(r.spec, r.storage, rep.steps[i])
         np.testing.assert_array_equal(rep.results[i][1], u_alone)
+
+
+def test_large_job_is_not_starved_by_small_ones():
+    # Budget: a large job fits only when no small job is resident; three
+    # small jobs fit together.  Small jobs may pass the waiting large job
+    # during its first four chunks at the head of the queue, then queue
+    # behind it.
+    small = workloads.duct(24, 12, 12)
+    large = workloads.duct(48, 24, 18)
+    sb = lbm.lbm_job_bytes(serving.job_for(small, "f32", 0.0, 10))
+    lb = lbm.lbm_job_bytes(serving.job_for(large, "f32", 0.0, 10))
+    assert lb > 3 * sb
+    b = lbm.lbm_batch_create(lb + sb // 2, 10, 16)
+    try:
+        first = lbm.lbm_batch_submit(b, serving.job_for(small, "f32", 0.0, 30))
+        big = lbm.lbm_batch_submit(b, serving.job_for(large, "f32", 0.0, 20))
+        later = [lbm.lbm_batch_submit(b, serving.job_for(small, "f32", 0.0, 20)) for _ in range(12)]
+        admitted = {}
+        chunk = 0
+        while True:
+            active, queued = lbm.lbm_batch_run_chunk(b)
+            chunk += 1
+            for jid in [first, big] + later:
+                if jid not in admitted and lbm.lbm_batch_poll(b, jid).state != lbm.LBM_JOB_QUEUED:
+                    admitted[jid] = chunk
+            if active == 0 and queued == 0:
+                break
+            assert chunk < 200
+        say(f"large job admitted at chunk {admitted[big]}; small ones at {[admitted[j] for j in later]}")
+        assert lbm.lbm_batch_poll(b, big).state == lbm.LBM_JOB_DONE
+        passed = [j for j in later if admitted[j] < admitted[big]]
+        behind = [j for j in later if admitted[j] > admitted[big]]
+        assert passed and behind                      # some passed it, the rest waited
+        assert max(admitted[j] for j in passed) <= 4  # only during its first four chunks
+        rho_l, u_l = lbm.lbm_batch_result(b, big, large.nodes)
+        with pytest.raises(lbm.LBMError) as e:        # a result can be taken once
+            lbm.lbm_batch_result(b, big, large.nodes)
+        assert e.value.status == lbm.LBM_ERR_ARG
+    finally:
+        lbm.lbm_batch_destroy(b)
+    _, _, u_alone = serving.run_plain(large, "f32", 20)
+    np.testing.assert_array_equal(u_l, u_alone)
+
+
+def test_result_of_an_unfinished_job_is_refused():
+    b = lbm.lbm_batch_create(256 << 20, 10, 4)
+    try:
+        jid = lbm.lbm_batch_submit(b, serving.job_for(workloads.duct(20, 10, 10), "f32", 0.0, 40))
+        lbm.lbm_batch_run_chunk(b)
+        assert lbm.lbm_batch_poll(b, jid).state == lbm.LBM_JOB_RUNNING
+        with pytest.raises(lbm.LBMError) as e:
+            lbm.lbm_batch_result(b, jid, 2000)
+        assert e.value.status == lbm.LBM_ERR_STATE
+    finally:
+        lbm.lbm_batch_destroy(b)  # destroying a batch with a resident job is fine

@@ -254,9 +254,16 @@ def form_serve(args):
     print(f"serve form: calibration {rep_c.summary()}", file=sys.stderr, flush=True)
     rate = 0.7 * sat
     trace = workloads.serving_trace(count=args.requests, rate=rate, seed=1)
-    rep = serving.serve_trace(trace, budget, chunk=100, tol=1e-6, max_steps=20000, max_jobs=512)
+    def progress(what):
+        def report(done, total):
+            if done % 10 == 0 or done == total:
+                print(f"serve form: {what} {done}/{total}", file=sys.stderr, flush=True)
+        return report
+
+    rep = serving.serve_trace(trace, budget, chunk=100, tol=1e-6, max_steps=20000, max_jobs=512,
+                              progress=progress("served"))
     print(f"serve form: served {rep.summary()}", file=sys.stderr, flush=True)
-    base = serving.replay_one_at_a_time(trace, rep.steps)
+    base = serving.replay_one_at_a_time(trace, rep.steps, progress=progress("one at a time"))
     print(f"serve form: one-at-a-time {base.summary()}", file=sys.stderr, flush=True)
     nodes = [r.spec.nodes for r in trace]
     return {"form": "serve", "requests": len(trace), "rate_per_s": round(rate, 4),

@@ -17,6 +17,7 @@
 #include <deque>
 #include <map>
 #include <new>
+#include <mutex>
 #include <vector>
 
 #include "../../include/lbm.h"
@@ -295,8 +296,10 @@ struct Shape {
 };
 
 // Autotune results shared by every batch in the process, keyed by a coarse
-// description of the resident work (storage mix, log2 of the node count).
+// description of the resident work (storage mix, log2 of the node count);
+// batches on different threads share it under a lock.
 std::map<long long, Shape> g_tuned;
+std::mutex g_tuned_mutex;
 
 }  // namespace
 
@@ -688,7 +691,11 @@ lbm_status lbm_batch_run_chunk(lbm_batch *B, int *n_active, int *n_queued) {
     if (st != LBM_OK) return st;
     st = run_graph_chunk(B);
     if (st != LBM_OK) return st;
-    LBM_BHIP(hipMemsetAsync(B->d_delta, 0, sizeof(unsigned) * B->max_jobs, B->stream), "reset deltas");
+    // (a fill kernel rather than a memset node: the convergence maxima are
+    // the bit patterns of non-negative floats, and 0.0f is all zero bits)
+    lbm::fill_float_kernel<<<dim3(unsigned((B->max_jobs + 255) / 256)), dim3(256), 0, B->stream>>>(
+        reinterpret_cast<float *>(B->d_delta), size_t(B->max_jobs), 0.0f);
+    LBM_BHIP(hipGetLastError(), "reset deltas");
     for (int s = 0; s < kNumStorage; ++s)
       if (B->h_ntiles[s] > 0)
         LBM_BHIP(lbm::launch_batch_delta(s, B->d_lats, B->d_tiles[s], B->d_ntiles + s, B->d_delta, 4 * B->num_cu,
@@ -769,9 +776,18 @@ lbm_status lbm_batch_autotune(lbm_batch *B, int trial_steps, int *block_x, int *
   if (st != LBM_OK) return st;
   if (count_active(B) == 0) return bfail(LBM_ERR_STATE, "no resident job to tune on");
   const long long key = tune_key(B);
-  auto cached = g_tuned.find(key);
-  if (cached != g_tuned.end()) {
-    st = lbm_batch_set_shape(B, cached->second.block_x, cached->second.tile_nodes, cached->second.grid);
+  Shape cached_shape;
+  bool have_cached = false;
+  {
+    std::lock_guard<std::mutex> lock(g_tuned_mutex);
+    auto cached = g_tuned.find(key);
+    if (cached != g_tuned.end()) {
+      cached_shape = cached->second;
+      have_cached = true;
+    }
+  }
+  if (have_cached) {
+    st = lbm_batch_set_shape(B, cached_shape.block_x, cached_shape.tile_nodes, cached_shape.grid);
   } else {
     // Every trial step is a real step of every resident lattice (results do
     // not depend on the launch shape); the step counters advance with them.
@@ -806,7 +822,10 @@ lbm_status lbm_batch_autotune(lbm_batch *B, int trial_steps, int *block_x, int *
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    g_tuned[key] = best;
+    {
+      std::lock_guard<std::mutex> lock(g_tuned_mutex);
+      g_tuned[key] = best;
+    }
     st = lbm_batch_set_shape(B, best.block_x, best.tile_nodes, best.grid);
   }
   if (st != LBM_OK) return st;

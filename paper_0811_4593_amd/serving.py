@@ -117,11 +117,12 @@ class ServeReport:
 
 
 def serve_trace(trace, budget_bytes, chunk=100, tol=1e-6, max_steps=20000, max_jobs=256, shape=None,
-                keep_results=(), stream=None):
+                keep_results=(), stream=None, progress=None):
     """Replay `trace` (workloads.Request list, sorted by arrival) in real time:
     each request is submitted at its arrival time; between submissions the
     batch runs chunks, admitting queued requests as slots and memory free up
-    (continuous batching).  Latency = completion time - arrival time."""
+    (continuous batching).  Latency = completion time - arrival time.
+    progress(done, total), if given, is called after every completion."""
     b = lbm.lbm_batch_create(budget_bytes, chunk, max_jobs, stream)
     rep = ServeReport()
     try:
@@ -161,6 +162,8 @@ def serve_trace(trace, budget_bytes, chunk=100, tol=1e-6, max_steps=20000, max_j
                     if i in keep_results:
                         rep.results[i] = (rho, u)
                     outstanding -= 1
+                    if progress:
+                        progress(sum(d is not None for d in done_at), nreq)
         rep.seconds = time.perf_counter() - t0
         rep.latencies = [done_at[i] - trace[i].arrival for i in range(nreq)]
         rep.steps = steps
@@ -170,7 +173,7 @@ def serve_trace(trace, budget_bytes, chunk=100, tol=1e-6, max_steps=20000, max_j
         lbm.lbm_batch_destroy(b)
 
 
-def replay_one_at_a_time(trace, steps, stream=None):
+def replay_one_at_a_time(trace, steps, stream=None, progress=None):
     """Baseline: the same arrival trace served first-come first-served, one
     request at a time with plain lbm_step launches, each for the step count
     the batched run needed for it.  Returns a ServeReport."""
@@ -185,6 +188,8 @@ def replay_one_at_a_time(trace, steps, stream=None):
         run_plain(r.spec, r.storage, n, stream)
         free_at = time.perf_counter() - t0
         lat.append(free_at - r.arrival)
+        if progress:
+            progress(len(lat), len(trace))
     rep.seconds = time.perf_counter() - t0
     rep.latencies = lat
     rep.steps = list(steps)

@@ -145,8 +145,16 @@ def cpu_baseline(spec_full, budget_s: float):
         if (el1 >= budget_s / 3 and steps1 >= 1) or steps1 >= 500:
             break
     mlups1 = s.nodes * steps1 / el1 / 1e6
+    # the 16 x 16 x 32 Couette flow, 2000 steps in FP64, in full
+    c = workloads.couette(16, 16, 32, 0.05, 1.0)
+    Lc = oracle.Lattice(c.nx, c.ny, c.nz, c.tau, bc=c.bc)
+    fc = Lc.init()
+    t0 = time.perf_counter()
+    for _ in range(2000):
+        fc = Lc.step(fc, nthreads=threads)
+    el_c = time.perf_counter() - t0
     return {"value": round(mlups, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "single_thread_value": round(mlups1, 3),
+            "single_thread_value": round(mlups1, 3), "couette_16x16x32_2000_steps_s": round(el_c, 3),
             "sample": f"duct {s.nx}x{s.ny}x{s.nz} (same boundary set-up, 1/64 of the nodes), FP64, "
                       f"{steps} steps in {el:.1f} s on {threads} threads; effective {mlups * 304 / 1e3:.2f} GB/s "
                       f"at 304 B/node; on 1 thread {steps1} steps in {el1:.1f} s"}

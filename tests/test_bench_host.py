@@ -1,0 +1,59 @@
+"""Host-side checks of bench.py (no GPU): the one-GPU rule and the counter
+summary written from two rocprofv3 --pmc CSV files."""
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def _csv(path, counter, rows):
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for name, value in rows:
+            w.writerow({"Kernel_Name": name, "Counter_Name": counter, "Counter_Value": value})
+
+
+def test_counter_ingest(tmp_path, monkeypatch):
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    out = tmp_path / "counters.json"
+    monkeypatch.setattr(bench, "COUNTERS_FILE", str(out))
+    nx, ny, nz = 64, 32, 16
+    N = nx * ny * nz
+    known_kib = 19 * N * 4 / 1024.0
+    sweep = "void lbm::sweep_kernel<lbm::FormF32, 256, 1, true, false, false>(float const*, float*, args)"
+    pull = "void lbm::sweep_kernel<lbm::FormF32, 256, 1, true, true, false>(float const*, float*, args)"
+    copy = "lbm::copy_probe_kernel(uint4 const*, uint4*, unsigned long)"
+    # counters read half the fetched bytes and all written bytes (the ratios the box shows)
+    _csv(tmp_path / "f.csv", "FETCH_SIZE", [(sweep, known_kib / 2 * 1.01), (sweep, known_kib / 2 * 0.99),
+                                            (pull, 1.0), (copy, known_kib / 2)])
+    _csv(tmp_path / "w.csv", "WRITE_SIZE", [(sweep, known_kib), (pull, 1.0), (copy, known_kib)])
+
+    class A:
+        ingest_counters = (str(tmp_path / "f.csv"), str(tmp_path / "w.csv"))
+        storage = "f32"
+        nx, ny, nz = 64, 32, 16
+        launch = "256,1,1"
+        counters_command = "test"
+
+    bench.ingest_counters(A)
+    rec = json.loads(out.read_text())
+    assert rec["kernel"] == sweep
+    assert rec["fetch_scale"] == pytest.approx(2.0) and rec["write_scale"] == pytest.approx(1.0)
+    assert rec["hbm_bytes_per_launch"] == pytest.approx(rec["algorithmic_bytes_per_launch"], rel=1e-12)
+    assert rec["launch"] == [256, 1, 1] and rec["kernel_source_hash"] == bench.kernel_source_hash()

@@ -69,7 +69,8 @@ def _counter_means(path, counter):
 def ingest_counters(args):
     """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the sweep kernel, each
     scaled by the ratio of the known byte count of the contiguous-copy probe
-    (19 N elements read and written) to what the same counter reads for it."""
+    (the 19 P elements of a buffer read and written) to what the same counter
+    reads for it."""
     from paper_0811_4593_amd import lbm
 
     fetch = _counter_means(args.ingest_counters[0], "FETCH_SIZE")
@@ -77,7 +78,8 @@ def ingest_counters(args):
     storage = {"f32": lbm.LBM_STORE_F32, "f64": lbm.LBM_STORE_F64, "f16dev": lbm.LBM_STORE_F16_DEV,
                "f16sr": lbm.LBM_STORE_F16_DEV_SR}[args.storage]
     N = args.nx * args.ny * args.nz
-    copy_kib = 19 * N * lbm.lbm_element_bytes(storage) / 1024.0
+    # the probe copies the whole buffer, 19 populations of pitch P, in 16-byte units
+    copy_kib = (19 * lbm.lbm_population_pitch(N) * lbm.lbm_element_bytes(storage) // 16 * 16) / 1024.0
 
     def pick(d, frag):
         ks = [k for k in d if frag in k]
@@ -373,7 +375,10 @@ def main():
             e1.record(stream)
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / args.probe_reps
-            probes[name] = round(2 * 19 * N * ebytes / (ms * 1e-3) / 1e9, 1)
+            # the pull-pattern copy moves the 19 N elements of the nodes, the
+            # contiguous copy the whole buffer (19 P elements, in 16-byte units)
+            moved = 19 * N * ebytes if kind == 1 else 19 * lbm.lbm_population_pitch(N) * ebytes // 16 * 16
+            probes[name] = round(2 * moved / (ms * 1e-3) / 1e9, 1)
     finally:
         lbm.lbm_destroy(h)
 

@@ -244,10 +244,18 @@ size_t lbm_element_bytes(lbm_storage storage);
  * element k*P + n of a buffer; a buffer holds 19*P elements. */
 size_t lbm_population_pitch(size_t nodes);
 
+/* Placement of the sweep's blocks on the 8 XCDs (each with its own L2) of
+ * the MI355X, which deals workgroups to the XCDs in turn:
+ *   LBM_XCD_NONE   dispatch order;
+ *   LBM_XCD_SLABS  each XCD sweeps one contiguous eighth of the lattice;
+ *   LBM_XCD_ROWS   the blocks of one x-row run on one XCD, rows dealt to the
+ *                  XCDs in turn (the same as NONE with one block per row). */
+enum { LBM_XCD_NONE = 0, LBM_XCD_SLABS = 1, LBM_XCD_ROWS = 2 };
+
 /* Launch shape of the sweep kernel: block_x threads along x (64, 128, 256 or
- * 512), nodes_per_thread along x (1, 2 or 4), xcd_remap != 0 places
- * consecutive x-rows on the same XCD (L2) of the MI355X.  Any shape gives the
- * same results.  Errors: LBM_ERR_ARG for an unsupported shape. */
+ * 512), nodes_per_thread along x (1, 2 or 4), xcd_remap one of LBM_XCD_*.
+ * Any shape gives the same results.  Errors: LBM_ERR_ARG for an unsupported
+ * shape. */
 lbm_status lbm_set_launch(lbm_lattice *L, int block_x, int nodes_per_thread, int xcd_remap);
 lbm_status lbm_get_launch(const lbm_lattice *L, int *block_x, int *nodes_per_thread, int *xcd_remap);
 
@@ -259,8 +267,8 @@ lbm_status lbm_get_step(const lbm_lattice *L, unsigned long long *steps);
 /* Pick the fastest launch shape for this lattice by timing real steps: for
  * each candidate (blocks of 64..512 threads no wider than the row rounded up
  * to a power of two, 1, 2 or 4 nodes per thread; one node per thread with a
- * solid mask, face field or geometry) one untimed and trial_steps >= 1
- * timed steps on the lattice's stream (HIP events).  The steps are part of
+ * solid mask, face field or geometry; each XCD placement) one untimed and
+ * trial_steps >= 1 timed steps on the lattice's stream (HIP events).  The steps are part of
  * the run (the lattice advances by (1 + trial_steps) per candidate; results
  * do not depend on the shape).  Sets the winner and returns it through the
  * non-NULL pointers.  Synchronizes.  Errors: LBM_ERR_ARG, LBM_ERR_STATE (as

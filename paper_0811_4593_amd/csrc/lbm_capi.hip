@@ -102,13 +102,28 @@ static lbm_status validate_create(int nx, int ny, int nz, double tau, double rho
 }
 
 static void default_launch(lbm_lattice *L) {
-  // One node per thread, consecutive row segments on one XCD; 256 threads
-  // per block (the fastest shape measured on the 1024 x 512 x 512 duct), or
-  // the narrowest block that still covers a short x-row, so that few lanes
-  // idle.  lbm_set_launch overrides it.
-  L->block_x = L->nx <= 64 ? 64 : (L->nx <= 128 ? 128 : 256);
+  // One node per thread, each XCD on its own eighth of the lattice; the
+  // widest block (256 threads is the fastest shape measured on the
+  // 1024 x 512 x 512 duct) whose row segments leave at most 1/16 of the
+  // lanes idle, else the one that leaves the fewest (a 300-node row takes
+  // 64-thread blocks: 20 idle lanes in 320 instead of 212 in 512).
+  // lbm_set_launch and lbm_autotune override it.
+  int best = 0;
+  long best_lanes = 0;
+  for (int bx : {256, 128, 64}) {
+    const long lanes = (long(L->nx) + bx - 1) / bx * bx;
+    if (16 * (lanes - L->nx) <= lanes) {
+      best = bx;
+      break;
+    }
+    if (best == 0 || lanes < best_lanes) {
+      best = bx;
+      best_lanes = lanes;
+    }
+  }
+  L->block_x = best;
   L->npt = 1;
-  L->xcd = 1;
+  L->xcd = LBM_XCD_SLABS;
 }
 
 static lbm_status finish_create(lbm_lattice *L, double rho0, const double u0[3], lbm_lattice **out) {
@@ -541,9 +556,11 @@ lbm_status lbm_set_launch(lbm_lattice *L, int block_x, int nodes_per_thread, int
     return fail(LBM_ERR_ARG, "block_x must be 64, 128, 256 or 512 (got %d)", block_x);
   if (nodes_per_thread != 1 && nodes_per_thread != 2 && nodes_per_thread != 4)
     return fail(LBM_ERR_ARG, "nodes_per_thread must be 1, 2 or 4 (got %d)", nodes_per_thread);
+  if (xcd_remap != LBM_XCD_NONE && xcd_remap != LBM_XCD_SLABS && xcd_remap != LBM_XCD_ROWS)
+    return fail(LBM_ERR_ARG, "xcd_remap must be 0, 1 or 2 (got %d)", xcd_remap);
   L->block_x = block_x;
   L->npt = nodes_per_thread;
-  L->xcd = xcd_remap ? 1 : 0;
+  L->xcd = xcd_remap;
   return LBM_OK;
 }
 
@@ -573,6 +590,8 @@ lbm_status lbm_autotune(lbm_lattice *L, int trial_steps, int *block_x, int *node
   int row = 64;
   while (row < L->nx && row < 512) row *= 2;
   static const int cand[][2] = {{64, 1}, {128, 1}, {256, 1}, {512, 1}, {128, 2}, {256, 2}, {128, 4}, {256, 4}};
+  static const int place[] = {LBM_XCD_SLABS, LBM_XCD_NONE, LBM_XCD_ROWS};
+  constexpr int nplace = int(sizeof(place) / sizeof(place[0]));
   const int old[3] = {L->block_x, L->npt, L->xcd};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -582,12 +601,14 @@ lbm_status lbm_autotune(lbm_lattice *L, int trial_steps, int *block_x, int *node
   float best_ms = 0.0f;
   int best = -1;
   lbm_status result = LBM_OK;
-  for (int i = 0; i < int(sizeof(cand) / sizeof(cand[0])); ++i) {
-    const int bx = cand[i][0], npt = cand[i][1];
+  for (int i = 0; i < int(sizeof(cand) / sizeof(cand[0])) * nplace; ++i) {
+    const int bx = cand[i / nplace][0], npt = cand[i / nplace][1], xcd = place[i % nplace];
     if (bx * npt > row || (ext && npt != 1)) continue;
+    // with one block per row the rows placement is the dispatch order
+    if (xcd == LBM_XCD_ROWS && bx * npt >= L->nx) continue;
     L->block_x = bx;
     L->npt = npt;
-    L->xcd = 1;
+    L->xcd = xcd;
     // one untimed step, then trial_steps timed ones (all of them real steps)
     result = lbm_step(L, 1);
     if (result == LBM_OK && hipEventRecord(e0, L->stream) != hipSuccess) result = hip_fail(hipGetLastError(), "event");
@@ -610,9 +631,9 @@ lbm_status lbm_autotune(lbm_lattice *L, int trial_steps, int *block_x, int *node
     L->xcd = old[2];
     return result != LBM_OK ? result : fail(LBM_ERR_STATE, "no launch shape to try");
   }
-  L->block_x = cand[best][0];
-  L->npt = cand[best][1];
-  L->xcd = 1;
+  L->block_x = cand[best / nplace][0];
+  L->npt = cand[best / nplace][1];
+  L->xcd = place[best % nplace];
   if (block_x) *block_x = L->block_x;
   if (nodes_per_thread) *nodes_per_thread = L->npt;
   if (xcd_remap) *xcd_remap = L->xcd;

@@ -31,7 +31,7 @@ template <class F, int BX, int NPT, bool NT, bool COPY, bool EXT>
 __global__ __launch_bounds__(BX) void sweep_kernel(const typename F::S *__restrict__ src,
                                                    typename F::S *__restrict__ dst,
                                                    SweepArgs<typename Codec<typename F::S>::T> a) {
-  const unsigned b = logical_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  const unsigned b = logical_block(blockIdx.x, gridDim.x, a.xcd_remap, unsigned(a.nxc));
   const unsigned row = a.nxc == 1 ? b : b / unsigned(a.nxc);
   const int xc = int(b - row * unsigned(a.nxc));
   const NodeGeom g{unsigned(a.nx), unsigned(a.ny), unsigned(a.nz)};

@@ -122,13 +122,26 @@ __device__ __forceinline__ void store_elem(P p, S v) {
 }
 
 // Logical block index.  The dispatcher hands workgroups to the 8 XCDs
-// round-robin (workgroup b runs on XCD b % 8); with the remap, logical blocks
-// [q*i, q*(i+1)) all run on XCD i, so neighbouring x-rows share one L2.
-__device__ __forceinline__ unsigned logical_block(unsigned b, unsigned nblocks, int remap) {
-  if (!remap) return b;
-  const unsigned q = nblocks >> 3;
-  if (b >= (q << 3)) return b;
-  return (b & 7u) * q + (b >> 3);
+// round-robin (workgroup b runs on XCD b % 8).  remap 1 (slabs): logical
+// blocks [q*i, q*(i+1)) all run on XCD i, so each XCD sweeps one contiguous
+// eighth of the lattice.  remap 2 (rows): the g segments of one x-row run one
+// after another on one XCD and rows are dealt to the XCDs in turn, so the
+// x-shift overlap of a row's segments stays in one L2 while the whole chip
+// sweeps one compact front (with g = 1 this is the dispatch order).  Blocks
+// past the last whole round keep their index.
+__host__ __device__ __forceinline__ unsigned logical_block(unsigned b, unsigned nblocks, int remap, unsigned g) {
+  if (remap == 1) {
+    const unsigned q = nblocks >> 3;
+    if (b >= (q << 3)) return b;
+    return (b & 7u) * q + (b >> 3);
+  }
+  if (remap == 2 && g > 1) {
+    const unsigned round = 8u * g;
+    if (b >= nblocks / round * round) return b;
+    const unsigned j = b >> 3;
+    return ((j / g) * 8u + (b & 7u)) * g + j % g;
+  }
+  return b;
 }
 
 // Lattice extent for the gather.

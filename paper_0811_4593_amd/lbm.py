@@ -40,6 +40,7 @@ EXPORTS = (
 
 LBM_JOB_QUEUED, LBM_JOB_RUNNING, LBM_JOB_DONE = 0, 1, 2
 LBM_RULE_NO_TRANSVERSE = 1
+LBM_XCD_NONE, LBM_XCD_SLABS, LBM_XCD_ROWS = 0, 1, 2  # sweep block placement on the XCDs
 
 
 class LbmJob(ctypes.Structure):

@@ -35,14 +35,16 @@ def test_counter_ingest(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "COUNTERS_FILE", str(out))
     nx, ny, nz = 64, 32, 16
     N = nx * ny * nz
-    known_kib = 19 * N * 4 / 1024.0
+    known_kib = 19 * N * 4 / 1024.0  # the sweep's algorithmic reads (and writes)
+    from paper_0811_4593_amd import lbm
+    copy_kib = 19 * lbm.lbm_population_pitch(N) * 4 / 1024.0  # the copy probe moves the whole buffer
     sweep = "void lbm::sweep_kernel<lbm::FormF32, 256, 1, true, false, false>(float const*, float*, args)"
     pull = "void lbm::sweep_kernel<lbm::FormF32, 256, 1, true, true, false>(float const*, float*, args)"
     copy = "lbm::copy_probe_kernel(uint4 const*, uint4*, unsigned long)"
     # counters read half the fetched bytes and all written bytes (the ratios the box shows)
     _csv(tmp_path / "f.csv", "FETCH_SIZE", [(sweep, known_kib / 2 * 1.01), (sweep, known_kib / 2 * 0.99),
-                                            (pull, 1.0), (copy, known_kib / 2)])
-    _csv(tmp_path / "w.csv", "WRITE_SIZE", [(sweep, known_kib), (pull, 1.0), (copy, known_kib)])
+                                            (pull, 1.0), (copy, copy_kib / 2)])
+    _csv(tmp_path / "w.csv", "WRITE_SIZE", [(sweep, known_kib), (pull, 1.0), (copy, copy_kib)])
 
     class A:
         ingest_counters = (str(tmp_path / "f.csv"), str(tmp_path / "w.csv"))

@@ -90,7 +90,9 @@ def test_fp64_ragged_multi_block_rows(launch):
 def test_launch_shapes_bitwise_identical():
     spec = workloads.duct(300, 7, 6, (0.04, 0.01, 0.01), 0.8)
     ref = None
-    for launch in [(64, 1, 0), (64, 4, 1), (128, 2, 0), (256, 1, 1), (256, 4, 1), (512, 2, 0)]:
+    # rows placement: 5, 3 and 2 blocks per row, 210, 126 and 84 blocks (ragged last round)
+    for launch in [(64, 1, 0), (64, 4, 1), (128, 2, 0), (256, 1, 1), (256, 4, 1), (512, 2, 0), (64, 1, 2), (64, 2, 2),
+                   (128, 2, 2)]:
         say(f"launch shape {launch}")
         h = make_gpu(spec, lbm.LBM_STORE_F32)
         try:
@@ -105,6 +107,18 @@ def test_launch_shapes_bitwise_identical():
             ref = out
         else:
             np.testing.assert_array_equal(out, ref)
+
+
+def test_default_launch_by_row_length():
+    """Default shape: the widest block of 256, 128 or 64 threads whose row
+    segments leave at most 1/16 of the lanes idle, else the fewest idle lanes;
+    one node per thread, slab placement on the XCDs."""
+    for nx, bx in [(1024, 256), (512, 256), (300, 64), (200, 256), (96, 128), (16, 64), (240, 256), (120, 128)]:
+        h = lbm.lbm_create(nx, 3, 3, 0.8, 1.0, None, lbm.LBM_STORE_F32, torch.cuda.current_stream())
+        try:
+            assert lbm.lbm_get_launch(h) == (bx, 1, lbm.LBM_XCD_SLABS), nx
+        finally:
+            lbm.lbm_destroy(h)
 
 
 def test_couette_fp64_every_step_2000():
@@ -262,6 +276,8 @@ def test_state_and_argument_errors():
         with pytest.raises(lbm.LBMError):
             lbm.lbm_set_launch(h, 96, 1, 0)
         with pytest.raises(lbm.LBMError):
+            lbm.lbm_set_launch(h, 256, 1, 3)  # no such XCD placement
+        with pytest.raises(lbm.LBMError):
             lbm.lbm_step(h, -1)
         # a state holding NaN is reported by the FP64 reductions
         bad_state = np.full((19, 8, 8, 8), np.nan)
@@ -316,8 +332,9 @@ def test_full_size_roofline_duct_sampled_parity():
     velocities on every boundary node of the full lattice."""
     spec = workloads.roofline_duct()
     nx, ny, nz, N = spec.nx, spec.ny, spec.nz, spec.nodes
-    say(f"full-size duct {nx}x{ny}x{nz} fp32: allocating 2 x {19 * N * 4 / 1e9:.1f} GB")
-    bufs = [torch.empty(19 * N, dtype=torch.float32, device="cuda") for _ in range(2)]
+    P = lbm.lbm_population_pitch(N)  # population k of node n is element k P + n
+    say(f"full-size duct {nx}x{ny}x{nz} fp32: allocating 2 x {19 * P * 4 / 1e9:.1f} GB")
+    bufs = [torch.empty(19 * P, dtype=torch.float32, device="cuda") for _ in range(2)]
     stream = torch.cuda.current_stream()
     h = lbm.lbm_create_on_buffers(nx, ny, nz, spec.tau, 1.0, None, lbm.LBM_STORE_F32, stream,
                                   bufs[0], bufs[1], bufs[0].numel() * 4)
@@ -328,10 +345,10 @@ def test_full_size_roofline_duct_sampled_parity():
         cur = 0 if lbm.lbm_state_buffer(h) == bufs[0].data_ptr() else 1
         gen = torch.Generator(device="cuda").manual_seed(5)
         for k in range(19):  # perturb the stored deviations in place, one population at a time
-            seg = bufs[cur][k * N:(k + 1) * N]
+            seg = bufs[cur][k * P:k * P + N]
             seg.add_(float(W[k]) * 0.04 * (torch.rand(N, device="cuda", generator=gen) - 0.5))
         torch.cuda.synchronize()
-        pre = bufs[cur].view(19, nz, ny, nx)
+        pre = bufs[cur].view(19, P)[:, :N].unflatten(1, (nz, ny, nx))
         pts = _sample_nodes(spec, np.random.default_rng(11))
         say(f"  sampling {len(pts)} nodes")
         x, y, z = (torch.as_tensor(pts[:, i], device="cuda") for i in range(3))
@@ -347,7 +364,7 @@ def test_full_size_roofline_duct_sampled_parity():
         pulled[outside] = np.nan  # sources beyond a bounded face are unknown
         lbm.lbm_step(h, 1)
         torch.cuda.synchronize()
-        post = bufs[cur ^ 1].view(19, nz, ny, nx)
+        post = bufs[cur ^ 1].view(19, P)[:, :N].unflatten(1, (nz, ny, nx))
         assert lbm.lbm_state_buffer(h) == bufs[cur ^ 1].data_ptr()
         got = torch.stack([post[k, z, y, x] for k in range(19)], 1).double().cpu().numpy() + W[None, :]
         L = make_oracle(spec)

@@ -187,8 +187,9 @@ def form_precision(args):
         try:
             for face, v in spec.bc.items():
                 lbm.lbm_set_velocity_bc(h, face, v)
-            # launch shape picked on real steps; they count towards the run
+            # launch shape and buffer placement picked on real steps; they count towards the run
             shape = lbm.lbm_autotune(h, 2)
+            tried, ms0, ms1 = lbm.lbm_tune_placement(h, 6, 1)
             done = lbm.lbm_get_step(h)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -204,6 +205,7 @@ def form_precision(args):
         res[name] = {"MLUPS": round(N * (steps - done) / sec / 1e6, 1),
                      "GBs": round(N * (steps - done) / sec * 2 * 19 * lbm.lbm_element_bytes(st) / 1e9, 1),
                      "launch": list(shape),
+                     "placement_ms_per_step": [round(ms0, 4), round(ms1, 4)],
                      "mass": mass, "momentum": [float(x) for x in mom]}
         print(f"precision form: {name} done in {sec:.1f} s", file=sys.stderr, flush=True)
     for name in ("f32", "f16dev", "f16sr"):
@@ -297,6 +299,9 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch shape with lbm_autotune during the warm-up (default: the library's "
                          "default shape, the fastest measured on this workload)")
+    ap.add_argument("--placement", type=int, default=6,
+                    help="buffers in the pool of lbm_tune_placement before the warm-up (the sweep's speed depends "
+                         "on where its two buffers lie; its trial steps are real, untimed steps); < 2: off")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -348,6 +353,10 @@ def main():
             lbm.lbm_autotune(h, 2)
             tuned = True
         launch = lbm.lbm_get_launch(h)
+        placement = None
+        if args.placement >= 2:
+            tried, ms0, ms1 = lbm.lbm_tune_placement(h, args.placement, 1)
+            placement = {"buffers_tried": tried, "ms_per_step_before": round(ms0, 4), "ms_per_step_after": round(ms1, 4)}
 
         lbm.lbm_step(h, args.warmup)
         torch.cuda.synchronize()
@@ -408,6 +417,7 @@ def main():
             "bytes_per_node_update": 2 * 19 * ebytes,
             "launch": {"block_x": launch[0], "nodes_per_thread": launch[1], "xcd_remap": launch[2],
                        "autotuned": tuned},
+            "placement": placement,
         },
         "roofline": {
             "bound": "hbm",

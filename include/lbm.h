@@ -275,6 +275,27 @@ lbm_status lbm_get_step(const lbm_lattice *L, unsigned long long *steps);
  * lbm_step), LBM_ERR_HIP; on error the previous shape is restored. */
 lbm_status lbm_autotune(lbm_lattice *L, int trial_steps, int *block_x, int *nodes_per_thread, int *xcd_remap);
 
+/* Pick the physical placement of the two population buffers by timing real
+ * steps.  The sweep's speed depends on where its source and destination
+ * buffers lie in device memory, as a fixed property of each pair of
+ * allocations (measured on the 1024 x 512 x 512 FP32 duct: 5.3 to 6.0 TB/s
+ * for different pairs, each steady to 0.2%).  The call keeps the lattice's
+ * two buffers, allocates up to max_buffers - 2 more (2 <= max_buffers <= 8;
+ * fewer when the device would keep less than 1/8 of its memory, and at
+ * least 1 GiB, free), and times every pair: with the state in the pair's
+ * first buffer, two untimed and 2 * trial_steps timed steps (trial_steps >=
+ * 1; HIP events on the lattice's stream).  The lattice keeps the fastest
+ * pair, with the state copied into it, and every other buffer is freed.  The
+ * steps are part of the run: the lattice advances by 2 + 2 * trial_steps
+ * steps per pair (at most 28 pairs), and results do not depend on placement.
+ * Out (each may be NULL): buffers_tried, and the milliseconds per step of
+ * the lattice's own pair (ms_before) and of the chosen one (ms_after).
+ * Synchronizes; lbm_state_buffer changes.  Errors: LBM_ERR_ARG,
+ * LBM_ERR_STATE (as lbm_step, or a lattice on caller-owned buffers),
+ * LBM_ERR_HIP; on error the lattice keeps a valid pair holding its state. */
+lbm_status lbm_tune_placement(lbm_lattice *L, int max_buffers, int trial_steps, int *buffers_tried,
+                              double *ms_before, double *ms_after);
+
 /* Bandwidth probes on the handle's buffers (measurement only; they overwrite
  * the non-current buffer and leave the stored state intact):
  *   kind 0: plain contiguous copy of the 19*N elements;

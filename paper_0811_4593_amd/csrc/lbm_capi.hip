@@ -42,6 +42,7 @@ lbm_status hip_fail(hipError_t e, const char *what) {
 
 constexpr int kPartialBlocks = 1024;  // fixed grid of the reduction: deterministic order
 constexpr size_t kChunkNodes = size_t(1) << 22;  // host transfers are staged in chunks
+constexpr int kMaxPlacementBuffers = 8;          // pool size limit of lbm_tune_placement
 
 }  // namespace
 
@@ -637,6 +638,103 @@ lbm_status lbm_autotune(lbm_lattice *L, int trial_steps, int *block_x, int *node
   if (block_x) *block_x = L->block_x;
   if (nodes_per_thread) *nodes_per_thread = L->npt;
   if (xcd_remap) *xcd_remap = L->xcd;
+  return LBM_OK;
+}
+
+lbm_status lbm_tune_placement(lbm_lattice *L, int max_buffers, int trial_steps, int *buffers_tried,
+                              double *ms_before, double *ms_after) {
+  if (!L) return fail(LBM_ERR_ARG, "NULL handle");
+  if (!L->owns) return fail(LBM_ERR_STATE, "the lattice runs on caller-owned buffers; their placement is the caller's");
+  if (max_buffers < 2 || max_buffers > kMaxPlacementBuffers)
+    return fail(LBM_ERR_ARG, "max_buffers must be 2..%d (got %d)", kMaxPlacementBuffers, max_buffers);
+  if (trial_steps < 1) return fail(LBM_ERR_ARG, "trial_steps must be >= 1");
+  lbm_status result = lbm_step(L, 0);  // the state checks of lbm_step
+  if (result != LBM_OK) return result;
+  const size_t bytes = 19 * L->pitch * L->esize;
+  // The pool: the state buffer, its partner, then new buffers while the device
+  // keeps at least 1/8 of its memory (and 1 GiB) free.  All stay allocated
+  // until the choice is made, so each new one lands on memory of its own.
+  void *pool[kMaxPlacementBuffers] = {L->buf[L->cur], L->buf[L->cur ^ 1]};
+  int n = 2;
+  while (n < max_buffers) {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+      (void)hipGetLastError();
+      break;
+    }
+    const size_t reserve = total_b / 8 > (size_t(1) << 30) ? total_b / 8 : (size_t(1) << 30);
+    if (free_b < bytes + reserve) break;
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      break;
+    }
+    pool[n++] = p;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    result = hip_fail(hipGetLastError(), "event creation");
+  }
+  // Every unordered pair (i, j), i < j, with the state in pool[i]: two
+  // untimed and 2 * trial_steps timed steps (an even count, so the state is
+  // back in pool[i]).  L->buf always holds the state buffer and its partner.
+  float first_ms = -1.0f, best_ms = 0.0f;
+  int bi = 0, bj = 1;
+  for (int i = 0; i + 1 < n && result == LBM_OK; ++i) {
+    for (int j = i + 1; j < n && result == LBM_OK; ++j) {
+      void *state = L->buf[L->cur];
+      if (state != pool[i]) {
+        hipError_t e = hipMemcpyAsync(pool[i], state, bytes, hipMemcpyDeviceToDevice, L->stream);
+        if (e != hipSuccess) {
+          result = hip_fail(e, "state copy");
+          break;
+        }
+      }
+      L->buf[0] = pool[i];
+      L->buf[1] = pool[j];
+      L->cur = 0;
+      result = lbm_step(L, 2);
+      if (result == LBM_OK && hipEventRecord(e0, L->stream) != hipSuccess) result = hip_fail(hipGetLastError(), "event");
+      if (result == LBM_OK) result = lbm_step(L, 2 * trial_steps);
+      if (result == LBM_OK && hipEventRecord(e1, L->stream) != hipSuccess) result = hip_fail(hipGetLastError(), "event");
+      float ms = 0.0f;
+      if (result == LBM_OK && hipEventSynchronize(e1) != hipSuccess) result = hip_fail(hipGetLastError(), "event");
+      if (result == LBM_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) result = hip_fail(hipGetLastError(), "timing");
+      if (result != LBM_OK) break;
+      ms /= float(2 * trial_steps);
+      if (first_ms < 0.0f) first_ms = best_ms = ms;  // the lattice's own pair, measured first
+      if (ms < best_ms) {
+        best_ms = ms;
+        bi = i;
+        bj = j;
+      }
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (result == LBM_OK) {
+    // move the state into the first buffer of the fastest pair
+    void *state = L->buf[L->cur];
+    if (state != pool[bi]) {
+      hipError_t e = hipMemcpyAsync(pool[bi], state, bytes, hipMemcpyDeviceToDevice, L->stream);
+      if (e != hipSuccess) result = hip_fail(e, "state copy");
+    }
+    if (result == LBM_OK) {
+      L->buf[0] = pool[bi];
+      L->buf[1] = pool[bj];
+      L->cur = 0;
+    }
+  }
+  // Free every pool buffer the lattice does not hold (after the stream has
+  // finished with them).
+  if (hipStreamSynchronize(L->stream) != hipSuccess && result == LBM_OK)
+    result = hip_fail(hipGetLastError(), "placement");
+  for (int k = 0; k < n; ++k)
+    if (pool[k] != L->buf[0] && pool[k] != L->buf[1]) (void)hipFree(pool[k]);
+  if (result != LBM_OK) return result;
+  if (buffers_tried) *buffers_tried = n;
+  if (ms_before) *ms_before = double(first_ms);
+  if (ms_after) *ms_after = double(best_ms);
   return LBM_OK;
 }
 

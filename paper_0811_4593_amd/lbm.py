@@ -31,7 +31,8 @@ EXPORTS = (
     "lbm_set_solid_mask", "lbm_set_geometry", "lbm_classify_geometry", "lbm_set_rule_options", "lbm_set_body_force",
     "lbm_clear_bc", "lbm_step",
     "lbm_moments", "lbm_totals", "lbm_get_populations", "lbm_set_populations", "lbm_state_buffer",
-    "lbm_element_bytes", "lbm_population_pitch", "lbm_set_launch", "lbm_get_launch", "lbm_autotune", "lbm_get_step", "lbm_probe",
+    "lbm_element_bytes", "lbm_population_pitch", "lbm_set_launch", "lbm_get_launch", "lbm_autotune", "lbm_get_step",
+    "lbm_tune_placement", "lbm_probe",
     "lbm_destroy", "lbm_last_error",
     "lbm_job_bytes", "lbm_batch_create", "lbm_batch_submit", "lbm_batch_run_chunk", "lbm_batch_poll",
     "lbm_batch_result", "lbm_batch_set_shape", "lbm_batch_get_shape", "lbm_batch_autotune",
@@ -117,6 +118,7 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_get_launch.argtypes = [_vp, ctypes.POINTER(st), ctypes.POINTER(st), ctypes.POINTER(st)]
     lib.lbm_autotune.argtypes = [_vp, st, ctypes.POINTER(st), ctypes.POINTER(st), ctypes.POINTER(st)]
     lib.lbm_get_step.argtypes = [_vp, ctypes.POINTER(ctypes.c_ulonglong)]
+    lib.lbm_tune_placement.argtypes = [_vp, st, st, ctypes.POINTER(st), _dp, _dp]
     lib.lbm_probe.argtypes = [_vp, st, st]
     lib.lbm_destroy.argtypes = [_vp]
     lib.lbm_destroy.restype = None
@@ -321,6 +323,17 @@ def lbm_autotune(h, trial_steps: int = 2):
     a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     _check(load_library().lbm_autotune(h, int(trial_steps), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
     return a.value, b.value, c.value
+
+
+def lbm_tune_placement(h, max_buffers: int = 6, trial_steps: int = 1):
+    """Time the lattice's state on every pair of a pool of up to max_buffers
+    device buffers (real steps) and keep the fastest pair; returns
+    (buffers_tried, ms_per_step_before, ms_per_step_after)."""
+    n = ctypes.c_int()
+    before, after = ctypes.c_double(), ctypes.c_double()
+    _check(load_library().lbm_tune_placement(h, int(max_buffers), int(trial_steps), ctypes.byref(n),
+                                             ctypes.byref(before), ctypes.byref(after)))
+    return n.value, before.value, after.value
 
 
 def lbm_get_step(h) -> int:

@@ -87,6 +87,7 @@ def test_null_handle_calls_fail_cleanly(lbm):
     assert lib.lbm_set_geometry(None, None) == lbm.LBM_ERR_ARG
     assert lib.lbm_autotune(None, 2, None, None, None) == lbm.LBM_ERR_ARG
     assert lib.lbm_get_step(None, None) == lbm.LBM_ERR_ARG
+    assert lib.lbm_tune_placement(None, 4, 1, None, None, None) == lbm.LBM_ERR_ARG
     assert lib.lbm_classify_geometry(4, 4, 4, None, None, None) == lbm.LBM_ERR_ARG
     assert lib.lbm_step(None, 1) == lbm.LBM_ERR_ARG
     assert lib.lbm_clear_bc(None, 0) == lbm.LBM_ERR_ARG

@@ -140,3 +140,50 @@ def test_autotune_advances_real_steps_and_keeps_results():
         assert e.value.status == lbm.LBM_ERR_STATE
     finally:
         lbm.lbm_destroy(h)
+
+
+def test_tune_placement_keeps_the_state_and_counts_its_steps():
+    """lbm_tune_placement moves the state between buffers and times real steps:
+    afterwards the lattice equals one stepped plainly by the same count (FP32,
+    and the stochastic-rounding form whose random words follow the step
+    count), its state lies in one of the pool's buffers, and a lattice on
+    caller-owned buffers is refused."""
+    spec = workloads.duct(96, 20, 18, (0.04, 0.01, 0.01), 0.8)
+    for storage, pool, trial in ((lbm.LBM_STORE_F32, 5, 1), (lbm.LBM_STORE_F16_DEV_SR, 3, 2)):
+        a, b = _pair(spec, storage)
+        try:
+            lbm.lbm_step(a, 3)  # the state starts in the second buffer
+            lbm.lbm_step(b, 3)
+            before = lbm.lbm_state_buffer(a)
+            tried, ms0, ms1 = lbm.lbm_tune_placement(a, pool, trial)
+            pairs = tried * (tried - 1) // 2
+            assert tried == pool and 0.0 < ms1 <= ms0
+            assert lbm.lbm_get_step(a) == 3 + pairs * (2 + 2 * trial)
+            lbm.lbm_step(a, 7)
+            lbm.lbm_step(b, pairs * (2 + 2 * trial) + 7)
+            np.testing.assert_array_equal(_state(a, spec), _state(b, spec))
+            say(f"storage {storage}: {tried} buffers, {ms0:.4f} -> {ms1:.4f} ms/step, state moved: "
+                f"{lbm.lbm_state_buffer(a) != before}")
+        finally:
+            for h in (a, b):
+                lbm.lbm_destroy(h)
+    h = lbm.lbm_create(8, 8, 8, 0.8, 1.0, None, lbm.LBM_STORE_F64, torch.cuda.current_stream())
+    try:
+        for bad in ((1, 1), (9, 1), (4, 0)):
+            with pytest.raises(lbm.LBMError) as e:
+                lbm.lbm_tune_placement(h, *bad)
+            assert e.value.status == lbm.LBM_ERR_ARG
+        tried, _, _ = lbm.lbm_tune_placement(h, 2, 1)  # the lattice's own pair only
+        assert tried == 2 and lbm.lbm_get_step(h) == 4
+    finally:
+        lbm.lbm_destroy(h)
+    P = lbm.lbm_population_pitch(8 * 8 * 8)
+    bufs = [torch.empty(19 * P, dtype=torch.float64, device="cuda") for _ in range(2)]
+    h = lbm.lbm_create_on_buffers(8, 8, 8, 0.8, 1.0, None, lbm.LBM_STORE_F64, torch.cuda.current_stream(),
+                                  bufs[0], bufs[1], bufs[0].numel() * 8)
+    try:
+        with pytest.raises(lbm.LBMError) as e:
+            lbm.lbm_tune_placement(h, 4, 1)
+        assert e.value.status == lbm.LBM_ERR_STATE
+    finally:
+        lbm.lbm_destroy(h)

@@ -41,7 +41,7 @@ def test_counter_ingest(tmp_path, monkeypatch):
     sweep = "void lbm::sweep_kernel<lbm::FormF32, 256, 1, true, false, false>(float const*, float*, args)"
     pull = "void lbm::sweep_kernel<lbm::FormF32, 256, 1, true, true, false>(float const*, float*, args)"
     copy = "lbm::copy_probe_kernel(uint4 const*, uint4*, unsigned long)"
-    # counters read half the fetched bytes and all written bytes (the ratios the box shows)
+    # counters read half the fetched bytes and all written bytes (the ratios measured on MI355X)
     _csv(tmp_path / "f.csv", "FETCH_SIZE", [(sweep, known_kib / 2 * 1.01), (sweep, known_kib / 2 * 0.99),
                                             (pull, 1.0), (copy, copy_kib / 2)])
     _csv(tmp_path / "w.csv", "WRITE_SIZE", [(sweep, known_kib), (pull, 1.0), (copy, copy_kib)])

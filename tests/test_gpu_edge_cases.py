@@ -78,10 +78,12 @@ def _sample(spec, rng, count=600):
 
 @pytest.mark.parametrize("storage,max_gaps", [(lbm.LBM_STORE_F16_DEV, 0.5), (lbm.LBM_STORE_F16_DEV_SR, 1.0)])
 def test_full_size_precision_duct_fp16_sampled(storage, max_gaps):
-    """512 x 256 x 256 duct, FP16 form, default launch: one step after a few
-    from rest plus a perturbation written through the ABI; sampled nodes are
-    recomputed by the oracle from the decoded FP16 state; the new scaled
-    deviations must be within max_gaps of the half grid of the oracle's."""
+    """512 x 256 x 256 duct, FP16 form, in the configuration the precision
+    form times (launch shape from lbm_autotune, buffers from
+    lbm_tune_placement): one step after those trial steps from rest; sampled
+    nodes are recomputed by the oracle from the decoded FP16 state; the new
+    scaled deviations must be within max_gaps of the half grid of the
+    oracle's."""
     spec = workloads.precision_duct()
     nx, ny, nz = spec.nx, spec.ny, spec.nz
     stream = torch.cuda.current_stream()
@@ -90,6 +92,9 @@ def test_full_size_precision_duct_fp16_sampled(storage, max_gaps):
         for face, v in spec.bc.items():
             lbm.lbm_set_velocity_bc(h, face, v)
         lbm.lbm_step(h, 4)
+        shape = lbm.lbm_autotune(h, 2)
+        tried, _, _ = lbm.lbm_tune_placement(h, 3, 1)
+        say(f"storage {storage}: autotuned {shape}, placement over {tried} buffers")
         host = np.empty((19, nz, ny, nx))
         lbm.lbm_get_populations(h, host)  # f = w + h 2^-8, exact decode
         pts = _sample(spec, np.random.default_rng(21))

@@ -329,7 +329,10 @@ def test_full_size_roofline_duct_sampled_parity():
     """The 1024x512x512 FP32 duct in the default launch shape that bench.py
     times: one step from a perturbed state, ~1900 sampled nodes (every node
     class) recomputed one by one by the oracle; then the exact boundary
-    velocities on every boundary node of the full lattice."""
+    velocities on every boundary node of the full lattice.  (bench.py also
+    tunes the buffer placement, which moves the state between allocations
+    without touching the arithmetic; that move is checked bit for bit in
+    test_gpu_step_runs.)"""
     spec = workloads.roofline_duct()
     nx, ny, nz, N = spec.nx, spec.ny, spec.nz, spec.nodes
     P = lbm.lbm_population_pitch(N)  # population k of node n is element k P + n

@@ -23,6 +23,7 @@ The oracle (FP64) must agree to rounding: 1e-14 relative after each step.
 from fractions import Fraction as Fr
 
 import numpy as np
+import pytest
 
 from lattice_symmetry import C, NORMALS
 
@@ -105,8 +106,45 @@ def face_rule(f, face):
     return g
 
 
-def wall_rule(f, faces):
-    """Edge (two faces) or corner (three), walls at rest."""
+def face_rule_pressure(f, face, rho0):
+    """Pressure face (eq_rhoin, Appendix): the density rho0 and the tangential
+    velocity V[face] minus its normal part are given; the unknowns are the
+    five populations, N_a, N_b and the normal velocity v_n, from the same
+    bounce-back Ansatz plus mass and momentum."""
+    n = NL[face]
+    vt = tuple(V[face][a] - dot(V[face], n) * n[a] for a in range(3))
+    unk = [j for j in range(19) if dot(CL[j], n) > 0]
+    tang = [a for a in range(3) if n[a] == 0]
+    nu = len(unk)
+    ncol = nu + 3  # unknown f, N_a, N_b, v_n
+    A, b = [], []
+    for r, j in enumerate(unk):
+        row = [Fr(0)] * ncol
+        row[r] = Fr(1)
+        # f_j - 6 w_j rho0 (c_j.n) v_n [+ sgn N] = f_-j + 6 w_j rho0 c_j.v_t
+        row[-1] = -6 * W[j] * rho0 * dot(CL[j], n)
+        if CL[j] != n:
+            a = next(t for t in tang if CL[j][t] != 0)
+            row[nu + tang.index(a)] = Fr(CL[j][a])
+        A.append(row)
+        b.append(f[OPP[j]] + 6 * W[j] * rho0 * dot(CL[j], vt))
+    known = [i for i in range(19) if i not in unk]
+    A.append([Fr(1)] * nu + [Fr(0)] * 3)
+    b.append(rho0 - sum(f[i] for i in known))
+    for al in range(3):
+        A.append([Fr(CL[j][al]) for j in unk] + [Fr(0), Fr(0), -rho0 * n[al]])
+        b.append(rho0 * vt[al] - sum(f[i] * CL[i][al] for i in known))
+    x = solve_exact(A, b)
+    g = f[:]
+    for r, j in enumerate(unk):
+        g[j] = x[r]
+    return g
+
+
+def wall_rule(f, faces, rho0=None):
+    """Edge (two faces) or corner (three), walls at rest; next to a pressure
+    plane (rho0 given) the buried links and the rest population share what
+    the prescribed density leaves, in the ratio of their weights."""
     ns = [NL[fc] for fc in faces]
     unknown = [any(dot(CL[i], n) > 0 for n in ns) for i in range(18)]
     buried = [unknown[i] and unknown[OPP[i]] for i in range(18)]
@@ -122,18 +160,22 @@ def wall_rule(f, faces):
         for i in along:  # equal shares of the edge momentum, cancelling it
             g[i] -= Fr(dot(CL[i], e)) * P / 4
     # buried links and rest: the value that returns a fluid at rest unchanged,
-    # w_b / (sum of the other moving weights) times their sum
+    # w_b / (sum of the other moving weights) times their sum; or, next to a
+    # pressure plane, the node's density made rho0
     s = sum(g[i] for i in range(18) if not buried[i])
     ws = sum(W[i] for i in range(18) if not buried[i])
+    share = s / ws if rho0 is None else (rho0 - s) / (1 - ws)
     for i in range(18):
         if buried[i]:
-            g[i] = W[i] / ws * s
-    g[18] = W[18] / ws * s
+            g[i] = W[i] * share
+    g[18] = W[18] * share
     return g
 
 
-def exact_step(F):
-    """F[z][y][x] -> list of 19 Fractions (post-collision)."""
+def exact_step(F, pressure=None):
+    """F[z][y][x] -> list of 19 Fractions (post-collision).  pressure: face ->
+    prescribed density of the pressure faces."""
+    pressure = pressure or {}
     out = [[[None] * SIZE for _ in range(SIZE)] for _ in range(SIZE)]
     for z in range(SIZE):
         for y in range(SIZE):
@@ -145,10 +187,11 @@ def exact_step(F):
                         f[i] = F[sz][sy][sx][i]
                 faces = [fc for fc, (a, lo) in enumerate([(0, 1), (0, 0), (1, 1), (1, 0), (2, 1), (2, 0)])
                          if (x, y, z)[a] == (0 if lo else SIZE - 1)]
+                rho0 = next((pressure[fc] for fc in faces if fc in pressure), None)
                 if len(faces) == 1:
-                    f = face_rule(f, faces[0])
+                    f = face_rule(f, faces[0]) if rho0 is None else face_rule_pressure(f, faces[0], rho0)
                 elif len(faces) >= 2:
-                    f = wall_rule(f, faces)
+                    f = wall_rule(f, faces, rho0)
                 assert all(v is not None for v in f)
                 rho = sum(f)
                 u = tuple(sum(f[i] * CL[i][a] for i in range(19)) / rho for a in range(3))
@@ -172,3 +215,31 @@ def test_two_steps_exact_against_oracle(oracle_mod):
         exact = np.array([[[[float(F[z][y][x][i]) for x in range(SIZE)] for y in range(SIZE)] for z in range(SIZE)]
                           for i in range(19)])
         assert np.max(np.abs(f_or - exact) / np.abs(exact)) < 1e-14
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_two_steps_exact_with_pressure_faces_against_oracle(oracle_mod, axis):
+    """The same lattice with the two faces of one axis as pressure faces
+    (densities 51/50 and 49/50, tangential velocities from V): the pressure
+    face rule of all six faces (the normal velocity solved for), pressure
+    edges and corners."""
+    rng = np.random.default_rng(4 + axis)
+    pressure = {2 * axis: Fr(51, 50), 2 * axis + 1: Fr(49, 50)}
+    base = feq(Fr(1), (Fr(1, 100), Fr(-1, 50), Fr(1, 40)))
+    F = [[[[base[i] * (1 + Fr(int(rng.integers(-50, 51)), 1000)) for i in range(19)]
+           for _ in range(SIZE)] for _ in range(SIZE)] for _ in range(SIZE)]
+    L = oracle_mod.Lattice(SIZE, SIZE, SIZE, float(TAU), bc={fc: tuple(float(a) for a in V[fc]) for fc in range(6)},
+                           pressure={fc: float(r) for fc, r in pressure.items()})
+    f_or = np.array([[[[float(F[z][y][x][i]) for x in range(SIZE)] for y in range(SIZE)] for z in range(SIZE)]
+                     for i in range(19)])
+    for _ in range(2):
+        F = exact_step(F, pressure)
+        f_or = L.step(f_or)
+        exact = np.array([[[[float(F[z][y][x][i]) for x in range(SIZE)] for y in range(SIZE)] for z in range(SIZE)]
+                          for i in range(19)])
+        assert np.max(np.abs(f_or - exact) / np.abs(exact)) < 1e-14
+    # every node of a pressure plane (edges and corners included) carries
+    # its density exactly: the stored post-collision state keeps its mass
+    rho = np.moveaxis(exact.sum(axis=0), 2 - axis, 0)  # (plane axis, ...)
+    assert np.allclose(rho[0], 51 / 50, rtol=0, atol=1e-15)
+    assert np.allclose(rho[-1], 49 / 50, rtol=0, atol=1e-15)

@@ -343,3 +343,73 @@ def test_one_step_exact_complex_geometry_against_oracle(oracle_mod):
     exact = np.array([[[[float(F[z][y][x][i]) for x in range(spec.nx)] for y in range(spec.ny)] for z in range(spec.nz)]
                       for i in range(19)])
     assert np.max(np.abs(f_or - exact) / np.abs(exact)) < 1e-14
+
+
+def face_rule_no_n(f, face):
+    """Face rule without the transverse corrections (eq_f9NoNs-eq_f17NoNs):
+    the density from mass and normal momentum (eq_uin), then every unknown
+    is its opposite plus 6 w rho c.v."""
+    n = NL[face]
+    v = V[face]
+    rho = (sum(f[i] for i in range(19) if dot(CL[i], n) == 0)
+           + 2 * sum(f[i] for i in range(19) if dot(CL[i], n) < 0)) / (1 - dot(v, n))
+    g = f[:]
+    for j in range(19):
+        if dot(CL[j], n) > 0:
+            g[j] = f[OPP[j]] + 6 * W[j] * rho * dot(CL[j], v)
+    return g
+
+
+def exact_step_options(F, periodic_x, solid, force, no_n):
+    """Two-face-pair lattice (x periodic, y and z bounded), mid-grid
+    bounce-back at solid nodes (a population from a solid node is the
+    node's own opposite one of the previous step; solid nodes keep theirs,
+    Sec. III), body force as the velocity shift tau F / rho in f^eq
+    (eq_gravity), optionally the face rule without N."""
+    out = [[[None] * SIZE for _ in range(SIZE)] for _ in range(SIZE)]
+    bounded = [(1, 1), (1, 0), (2, 1), (2, 0)]  # (axis, low side) of faces 2..5
+    for z in range(SIZE):
+        for y in range(SIZE):
+            for x in range(SIZE):
+                if (x, y, z) in solid:
+                    out[z][y][x] = F[z][y][x][:]
+                    continue
+                f = [None] * 19
+                for i in range(19):
+                    sx, sy, sz = (x - CL[i][0]) % SIZE, y - CL[i][1], z - CL[i][2]
+                    if 0 <= sy < SIZE and 0 <= sz < SIZE:
+                        f[i] = F[z][y][x][OPP[i]] if (sx, sy, sz) in solid else F[sz][sy][sx][i]
+                faces = [2 + k for k, (a, lo) in enumerate(bounded) if (x, y, z)[a] == (0 if lo else SIZE - 1)]
+                if len(faces) == 1:
+                    f = face_rule_no_n(f, faces[0]) if no_n else face_rule(f, faces[0])
+                elif len(faces) == 2:
+                    f = wall_rule(f, faces)
+                assert all(v is not None for v in f)
+                rho = sum(f)
+                u = tuple((sum(f[i] * CL[i][a] for i in range(19)) + TAU * force[a]) / rho for a in range(3))
+                fe = feq(rho, u)
+                out[z][y][x] = [f[i] - (f[i] - fe[i]) / TAU for i in range(19)]
+    return out
+
+
+@pytest.mark.parametrize("no_n", [False, True])
+def test_two_steps_exact_with_force_solid_nodes_and_rule_variant(oracle_mod, no_n):
+    rng = np.random.default_rng(6)
+    solid = {(1, 1, 2), (2, 2, 1), (3, 1, 1)}
+    force = (Fr(1, 1000), Fr(-1, 2000), Fr(1, 1500))
+    base = feq(Fr(1), (Fr(1, 100), Fr(-1, 50), Fr(1, 40)))
+    F = [[[[base[i] * (1 + Fr(int(rng.integers(-50, 51)), 1000)) for i in range(19)]
+           for _ in range(SIZE)] for _ in range(SIZE)] for _ in range(SIZE)]
+    mask = np.zeros((SIZE, SIZE, SIZE), np.uint8)
+    for x, y, z in solid:
+        mask[z, y, x] = 1
+    L = oracle_mod.Lattice(SIZE, SIZE, SIZE, float(TAU), bc={fc: tuple(float(a) for a in V[fc]) for fc in range(2, 6)},
+                           force=tuple(float(a) for a in force), solid=mask, no_transverse=no_n)
+    f_or = np.array([[[[float(F[z][y][x][i]) for x in range(SIZE)] for y in range(SIZE)] for z in range(SIZE)]
+                     for i in range(19)])
+    for _ in range(2):
+        F = exact_step_options(F, True, solid, force, no_n)
+        f_or = L.step(f_or)
+        exact = np.array([[[[float(F[z][y][x][i]) for x in range(SIZE)] for y in range(SIZE)] for z in range(SIZE)]
+                          for i in range(19)])
+        assert np.max(np.abs(f_or - exact) / np.abs(exact)) < 1e-14

@@ -71,9 +71,9 @@ def solve_exact(A, b):
     return [M[i][n] for i in range(n)]
 
 
-def face_rule(f, face):
+def face_rule(f, face, v=None):
     n = NL[face]
-    v = V[face]
+    v = V[face] if v is None else v
     unk = [j for j in range(19) if dot(CL[j], n) > 0]
     tang = [a for a in range(3) if n[a] == 0]
     nu = len(unk)
@@ -409,6 +409,50 @@ def test_two_steps_exact_with_force_solid_nodes_and_rule_variant(oracle_mod, no_
                      for i in range(19)])
     for _ in range(2):
         F = exact_step_options(F, True, solid, force, no_n)
+        f_or = L.step(f_or)
+        exact = np.array([[[[float(F[z][y][x][i]) for x in range(SIZE)] for y in range(SIZE)] for z in range(SIZE)]
+                          for i in range(19)])
+        assert np.max(np.abs(f_or - exact) / np.abs(exact)) < 1e-14
+
+
+def test_two_steps_exact_with_per_node_face_velocities(oracle_mod):
+    """Velocity fields on the two x faces varying over y and z (face node
+    order y + ny z, given to the oracle as (nz, ny, 3) arrays), uniform
+    moving walls on y and z: the face rule takes each node's own velocity."""
+    rng = np.random.default_rng(8)
+    fields = {fc: [[tuple(Fr(int(rng.integers(-30, 31)), 1000) for _ in range(3)) for _ in range(SIZE)]
+                   for _ in range(SIZE)] for fc in (0, 1)}  # [z][y] -> v
+    base = feq(Fr(1), (Fr(1, 100), Fr(-1, 50), Fr(1, 40)))
+    F = [[[[base[i] * (1 + Fr(int(rng.integers(-50, 51)), 1000)) for i in range(19)]
+           for _ in range(SIZE)] for _ in range(SIZE)] for _ in range(SIZE)]
+    face_v = {fc: np.array([[[float(a) for a in fields[fc][z][y]] for y in range(SIZE)] for z in range(SIZE)])
+              for fc in (0, 1)}
+    L = oracle_mod.Lattice(SIZE, SIZE, SIZE, float(TAU), bc={fc: tuple(float(a) for a in V[fc]) for fc in range(6)},
+                           face_v=face_v)
+    f_or = np.array([[[[float(F[z][y][x][i]) for x in range(SIZE)] for y in range(SIZE)] for z in range(SIZE)]
+                     for i in range(19)])
+    for _ in range(2):
+        out = [[[None] * SIZE for _ in range(SIZE)] for _ in range(SIZE)]
+        for z in range(SIZE):
+            for y in range(SIZE):
+                for x in range(SIZE):
+                    f = [None] * 19
+                    for i in range(19):
+                        sx, sy, sz = x - CL[i][0], y - CL[i][1], z - CL[i][2]
+                        if 0 <= sx < SIZE and 0 <= sy < SIZE and 0 <= sz < SIZE:
+                            f[i] = F[sz][sy][sx][i]
+                    faces = [fc for fc, (a, lo) in enumerate([(0, 1), (0, 0), (1, 1), (1, 0), (2, 1), (2, 0)])
+                             if (x, y, z)[a] == (0 if lo else SIZE - 1)]
+                    if len(faces) == 1:
+                        v = fields[faces[0]][z][y] if faces[0] in fields else None
+                        f = face_rule(f, faces[0], v)
+                    elif len(faces) >= 2:
+                        f = wall_rule(f, faces)
+                    rho = sum(f)
+                    u = tuple(sum(f[i] * CL[i][a] for i in range(19)) / rho for a in range(3))
+                    fe = feq(rho, u)
+                    out[z][y][x] = [f[i] - (f[i] - fe[i]) / TAU for i in range(19)]
+        F = out
         f_or = L.step(f_or)
         exact = np.array([[[[float(F[z][y][x][i]) for x in range(SIZE)] for y in range(SIZE)] for z in range(SIZE)]
                           for i in range(19)])

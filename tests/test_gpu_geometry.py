@@ -43,7 +43,8 @@ def _obstacle_case():
     nx, ny, nz = 12, 9, 10
     solid = (rng.uniform(size=(nz, ny, nx)) < 0.12).astype(np.uint8)
     solid[:, :, 0] = solid[:, :, -1] = 0  # keep the inflow planes fluid
-    fv = {0: rng.uniform(-0.02, 0.03, (nz, ny, 3)), 1: rng.uniform(-0.02, 0.03, (nz, ny, 3))}
+    fv = {0: rng.uniform(-0.02, 0.03, (nz, ny, 3)), 1: rng.uniform(-0.02, 0.03, (nz, ny, 3)),
+          3: rng.uniform(-0.01, 0.01, (nz, nx, 3))}  # x faces and a moving y wall: node order y + ny z, x + nx z
     spec = workloads.LatticeSpec(nx, ny, nz, 0.85, {0: WALL, 1: WALL, 2: WALL, 3: WALL}, name="obstacles_12x9x10")
     return spec, solid, fv
 

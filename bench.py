@@ -5,8 +5,11 @@ Workload: the 1024 x 512 x 512 duct (no-slip on-site walls on the y and z
 faces, on-site velocity inlet and outlet (0.04, 0.01, 0.01) on the x faces,
 tau = 0.8, FP32 storage), initial state at rest, synthetic.  A step is one
 launch of the fused sweep over all 2^28 nodes (pull streaming, boundary
-rules, BGK collision).  W untimed warm-up steps, then exactly K timed steps
-bracketed by device synchronisation.
+rules, BGK collision).  Before the timed region the lattice's two buffers
+are chosen by lbm_tune_placement from a pool of 6 allocations (its trial
+steps are real, untimed steps; --placement 0 keeps the lattice's own), then
+W untimed warm-up steps, then exactly K timed steps bracketed by device
+synchronisation.
 
 Printed: one JSON line with MLUPS (the value), the roofline object for the
 sweep kernel (algorithmic bytes per launch / average launch duration measured

@@ -155,6 +155,42 @@ def test_convergence_stop_is_deterministic_and_matches_alone():
     assert rel_l2(u0, u_ref.ravel()) < 1e-5
 
 
+def test_convergence_measure_against_host_computation():
+    """The delta reported after each chunk is max over nodes and components
+    of |u(t) - u(t - chunk)| / u_ref (the snapshot starts at zero), here
+    recomputed in double on the host from the same lattice run alone."""
+    spec = workloads.duct(20, 10, 10, (0.04, 0.01, 0.01), 0.8)
+    chunk, chunks = 20, 5
+    u_ref = float(np.linalg.norm(spec.bc[0]))
+    b = lbm.lbm_batch_create(1 << 30, chunk, 4)
+    got = []
+    try:
+        jid = lbm.lbm_batch_submit(b, serving.job_for(spec, "f32", 0.0, chunk * chunks))
+        for _ in range(chunks):
+            lbm.lbm_batch_run_chunk(b)
+            st = lbm.lbm_batch_poll(b, jid)
+            got.append((st.steps, st.delta))
+    finally:
+        lbm.lbm_batch_destroy(b)
+    h = lbm.lbm_create(spec.nx, spec.ny, spec.nz, spec.tau, 1.0, None, lbm.LBM_STORE_F32, torch.cuda.current_stream())
+    try:
+        serving.apply_bc(h, spec)
+        u_prev = np.zeros(3 * spec.nodes)
+        for k, (steps, delta) in enumerate(got):
+            lbm.lbm_step(h, chunk)
+            u = np.empty(3 * spec.nodes)
+            lbm.lbm_moments(h, None, u)
+            expect = float(np.abs(u - u_prev).max()) / u_ref
+            say(f"chunk {k + 1}: step {steps}, delta {delta:.6e}, host {expect:.6e}")
+            assert steps == chunk * (k + 1)
+            # the snapshot u(t - chunk) is kept in float: half an ulp of
+            # |u| ~ 0.04 over u_ref is 3e-8 in delta
+            assert delta == pytest.approx(expect, rel=1e-3, abs=1e-7)
+            u_prev = u
+    finally:
+        lbm.lbm_destroy(h)
+
+
 def test_autotune_picks_a_shape_and_results_do_not_change():
     items = MIX[:4]
     b = lbm.lbm_batch_create(4 << 30, 10, 8)

@@ -319,8 +319,9 @@ const char *lbm_last_error(void);
  * chunk the convergence measure
  *     delta = max_nodes,components |u(t) - u(t - chunk)| / u_ref
  * decides retirement (delta < tol, or steps >= max_steps).  Retired jobs'
- * moments are copied to host memory and their device memory is returned to
- * the pool at once.  The paper runs a fixed number of steps (Sec. VI); the
+ * moments are copied to host memory (page-locked when the runtime grants it,
+ * held until lbm_batch_result or lbm_batch_destroy) and their device memory
+ * is returned to the pool at once.  The paper runs a fixed number of steps (Sec. VI); the
  * convergence measure and its use for stopping are this library's.
  * ------------------------------------------------------------------------ */
 typedef struct lbm_batch lbm_batch;
@@ -377,8 +378,8 @@ lbm_status lbm_batch_run_chunk(lbm_batch *B, int *n_active, int *n_queued);
 lbm_status lbm_batch_poll(lbm_batch *B, int job_id, lbm_job_status *st);
 
 /* Moments of a finished job, rho[N] and u[3*N] (host arrays; either may be
- * NULL), then forget the job.  Errors: LBM_ERR_ARG (unknown id),
- * LBM_ERR_STATE (not finished). */
+ * NULL), then forget the job and free its host copy.  Errors: LBM_ERR_ARG
+ * (unknown id), LBM_ERR_STATE (not finished). */
 lbm_status lbm_batch_result(lbm_batch *B, int job_id, double *rho, double *u);
 
 /* Launch shape of the multi-lattice sweep: block_x threads (128 or 256),

@@ -279,6 +279,57 @@ size_t job_bytes(const lbm_job &j) {
   return 2 * align_up(19 * lbm::population_pitch(N) * lbm_element_bytes(j.storage)) + align_up(3 * N * sizeof(float));
 }
 
+// Host memory for a retired job's moments, rho [N] then u [3][N].  Pinned
+// (page-locked) when the runtime grants it: a device-to-host copy into fresh
+// pageable memory runs at about 4 GB/s on this host, page faults included,
+// into a fresh pinned allocation at about 40 GB/s.  Pageable otherwise.
+class HostResult {
+ public:
+  HostResult() = default;
+  HostResult(const HostResult &) = delete;
+  HostResult &operator=(const HostResult &) = delete;
+  HostResult(HostResult &&o) noexcept : p_(o.p_), n_(o.n_), pinned_(o.pinned_) { o.p_ = nullptr, o.n_ = 0; }
+  HostResult &operator=(HostResult &&o) noexcept {
+    if (this != &o) {
+      release();
+      p_ = o.p_, n_ = o.n_, pinned_ = o.pinned_;
+      o.p_ = nullptr, o.n_ = 0;
+    }
+    return *this;
+  }
+  ~HostResult() { release(); }
+  bool allocate(size_t count) {
+    release();
+    void *p = nullptr;
+    pinned_ = hipHostMalloc(&p, count * sizeof(double), hipHostMallocDefault) == hipSuccess;
+    if (!pinned_) {
+      (void)hipGetLastError();
+      p = new (std::nothrow) double[count];
+      if (!p) return false;
+    }
+    p_ = static_cast<double *>(p);
+    n_ = count;
+    return true;
+  }
+  void release() {
+    if (p_) {
+      if (pinned_)
+        (void)hipHostFree(p_);
+      else
+        delete[] p_;
+    }
+    p_ = nullptr;
+    n_ = 0;
+  }
+  double *data() const { return p_; }
+  size_t size() const { return n_; }
+
+ private:
+  double *p_ = nullptr;
+  size_t n_ = 0;
+  bool pinned_ = false;
+};
+
 struct Job {
   lbm_job spec;
   int state = LBM_JOB_QUEUED;
@@ -288,7 +339,7 @@ struct Job {
   double delta = INFINITY;
   int converged = 0;
   int waited = 0;  // chunks spent at the head of the queue without fitting
-  std::vector<double> rho, u;  // moments at retirement
+  HostResult result;  // moments at retirement: rho [N], then u [3][N]
 };
 
 struct Shape {
@@ -440,17 +491,17 @@ lbm_status retire(lbm_batch *B, int id) {
   lbm_status st = ensure_stage(B);
   if (st != LBM_OK) return st;
   const size_t N = size_t(J.spec.nx) * J.spec.ny * J.spec.nz;
-  J.rho.resize(N);
-  J.u.resize(3 * N);
+  if (!J.result.allocate(4 * N)) return bfail(LBM_ERR_OOM, "host memory for the moments of job %d", id);
+  double *rho_h = J.result.data(), *u_h = J.result.data() + N;
   const void *f = B->h_lats[J.slot].buf[0];
   for (size_t n0 = 0; n0 < N; n0 += kStageNodes) {
     const size_t cnt = std::min(kStageNodes, N - n0);
     double *dr = B->d_stage, *du = B->d_stage + cnt;
     LBM_BHIP(lbm::launch_moments(J.spec.storage, f, lbm::population_pitch(N), n0, cnt, dr, du, nullptr, 1024, B->stream),
              "moments");
-    LBM_BHIP(hipMemcpyAsync(J.rho.data() + n0, dr, cnt * sizeof(double), hipMemcpyDeviceToHost, B->stream), "copy");
+    LBM_BHIP(hipMemcpyAsync(rho_h + n0, dr, cnt * sizeof(double), hipMemcpyDeviceToHost, B->stream), "copy");
     for (int a = 0; a < 3; ++a)
-      LBM_BHIP(hipMemcpyAsync(J.u.data() + a * N + n0, du + a * cnt, cnt * sizeof(double), hipMemcpyDeviceToHost,
+      LBM_BHIP(hipMemcpyAsync(u_h + a * N + n0, du + a * cnt, cnt * sizeof(double), hipMemcpyDeviceToHost,
                               B->stream),
                "copy");
     LBM_BHIP(hipStreamSynchronize(B->stream), "moments");
@@ -742,9 +793,11 @@ lbm_status lbm_batch_result(lbm_batch *B, int job_id, double *rho, double *u) {
   auto it = B->jobs.find(job_id);
   if (it == B->jobs.end()) return bfail(LBM_ERR_ARG, "unknown job %d", job_id);
   if (it->second.state != LBM_JOB_DONE) return bfail(LBM_ERR_STATE, "job %d is not finished", job_id);
-  if (rho) std::memcpy(rho, it->second.rho.data(), it->second.rho.size() * sizeof(double));
-  if (u) std::memcpy(u, it->second.u.data(), it->second.u.size() * sizeof(double));
-  B->jobs.erase(it);
+  const HostResult &r = it->second.result;
+  const size_t N = r.size() / 4;
+  if (rho) std::memcpy(rho, r.data(), N * sizeof(double));
+  if (u) std::memcpy(u, r.data() + N, 3 * N * sizeof(double));
+  B->jobs.erase(it);  // frees the host copy
   return LBM_OK;
 }
 

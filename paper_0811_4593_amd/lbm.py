@@ -412,7 +412,12 @@ def lbm_batch_poll(b, job_id: int) -> LbmJobStatus:
     return st
 
 
-def lbm_batch_result(b, job_id: int, nodes: int):
+def lbm_batch_result(b, job_id: int, nodes):
+    """(rho, u) of a finished job, then the job is forgotten; nodes=None
+    forgets it without copying and returns (None, None)."""
+    if nodes is None:
+        _check(load_library().lbm_batch_result(b, int(job_id), None, None))
+        return None, None
     rho = np.empty(nodes)
     u = np.empty(3 * nodes)
     _check(load_library().lbm_batch_result(b, int(job_id), rho.ctypes.data, u.ctypes.data))

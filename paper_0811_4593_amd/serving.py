@@ -77,6 +77,19 @@ def apply_bc(h, spec):
         lbm.lbm_set_pressure_bc(h, face, r, spec.bc.get(face))
 
 
+def _host_array(n):
+    """A float64 host array in page-locked memory when a GPU runtime is there
+    (the batch runtime holds its results in page-locked memory too, so both
+    sides of a comparison copy at the same speed), else ordinary memory."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.empty(n, dtype=torch.float64, pin_memory=True).numpy()
+    except ImportError:
+        pass
+    return np.empty(n)
+
+
 def run_plain(spec, storage="f32", steps=2000, stream=None, launch=None):
     """One lattice with plain lbm_step launches; returns (seconds, rho, u)."""
     h = lbm.lbm_create(spec.nx, spec.ny, spec.nz, spec.tau, spec.rho0, None, STORAGE[storage], stream)
@@ -84,8 +97,8 @@ def run_plain(spec, storage="f32", steps=2000, stream=None, launch=None):
         apply_bc(h, spec)
         if launch:
             lbm.lbm_set_launch(h, *launch)
-        rho = np.empty(spec.nodes)
-        u = np.empty(3 * spec.nodes)
+        rho = _host_array(spec.nodes)
+        u = _host_array(3 * spec.nodes)
         t0 = time.perf_counter()
         lbm.lbm_step(h, steps)
         lbm.lbm_moments(h, rho, u)  # synchronizes
@@ -158,9 +171,12 @@ def serve_trace(trace, budget_bytes, chunk=100, tol=1e-6, max_steps=20000, max_j
                     done_at[i] = t_now
                     steps[i] = st.steps
                     conv[i] = st.converged
-                    rho, u = lbm.lbm_batch_result(b, jid, trace[i].spec.nodes)
+                    # the moments are on the host (page-locked) since the
+                    # chunk retired the job; copy out only the kept ones
                     if i in keep_results:
-                        rep.results[i] = (rho, u)
+                        rep.results[i] = lbm.lbm_batch_result(b, jid, trace[i].spec.nodes)
+                    else:
+                        lbm.lbm_batch_result(b, jid, None)
                     outstanding -= 1
                     if progress:
                         progress(sum(d is not None for d in done_at), nreq)

@@ -36,7 +36,8 @@
  *                arrays, f[k*N + n] with N = nx*ny*nz; device buffers use the
  *                padded stride P = lbm_population_pitch(N): element k*P + n.
  *   axes         every axis is periodic until a face of it gets a velocity
- *                BC; lbm_step then requires both faces of that axis to be set.
+ *                or pressure BC; lbm_step then requires both faces of that
+ *                axis to be set.
  *                A non-periodic axis needs at least 3 nodes.
  *
  * Storage forms (lbm_storage).  The device buffers hold the deviation of
@@ -224,7 +225,8 @@ lbm_status lbm_totals(lbm_lattice *L, double *mass, double momentum[3]);
 /* Copy the stored state to / from a host array f[19*N] of populations f_k
  * in double (same layout as the device state).  get returns w_k + d_k; set
  * stores d_k = f_k - w_k evaluated in double, rounded to nearest even for
- * LBM_STORE_F32 and LBM_STORE_F16_DEV.  Synchronizes.
+ * LBM_STORE_F32 and both FP16 forms (the stochastic rounding of
+ * LBM_STORE_F16_DEV_SR applies to steps only).  Synchronizes.
  * Errors: LBM_ERR_ARG, LBM_ERR_OOM, LBM_ERR_HIP. */
 lbm_status lbm_get_populations(lbm_lattice *L, double *f);
 lbm_status lbm_set_populations(lbm_lattice *L, const double *f);

@@ -174,7 +174,9 @@ def form_precision(args):
     """Storage precision on the 512x256x256 duct: FP16 scaled deviations (FP32
     arithmetic) and FP32 storage against the FP64 form (the GPU FP64 path is
     parity-pinned to the CPU oracle at 1e-12 per step) after the same number of
-    steps; MLUPS of each form on the same lattice; FP64 mass/momentum totals."""
+    steps; MLUPS of each form on the same lattice, including the FP64
+    mass/momentum reductions taken every 100 steps to monitor the density
+    drift (its mass at the first and last reduction is reported)."""
     import torch
 
     from paper_0811_4593_amd import lbm, workloads
@@ -191,17 +193,23 @@ def form_precision(args):
             for face, v in spec.bc.items():
                 lbm.lbm_set_velocity_bc(h, face, v)
             # launch shape and buffer placement picked on real steps; they count towards the run
-            shape = lbm.lbm_autotune(h, 2)
+            shape = lbm.lbm_autotune(h, 4)
             tried, ms0, ms1 = lbm.lbm_tune_placement(h, 6, 1)
             done = lbm.lbm_get_step(h)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            lbm.lbm_step(h, steps - done)
+            masses = []
+            left = steps - done
+            while left > 0:
+                n = min(100, left)
+                lbm.lbm_step(h, n)
+                left -= n
+                mass, mom = lbm.lbm_totals(h)  # FP64 reduction (synchronizes)
+                masses.append(mass)
             torch.cuda.synchronize()
             sec = time.perf_counter() - t0
             u = torch.empty(3 * N, dtype=torch.float64, device="cuda")
             lbm.lbm_moments(h, None, u, dst_on_device=True)
-            mass, mom = lbm.lbm_totals(h)
         finally:
             lbm.lbm_destroy(h)
         fields[name] = u
@@ -209,7 +217,8 @@ def form_precision(args):
                      "GBs": round(N * (steps - done) / sec * 2 * 19 * lbm.lbm_element_bytes(st) / 1e9, 1),
                      "launch": list(shape),
                      "placement_ms_per_step": [round(ms0, 4), round(ms1, 4)],
-                     "mass": mass, "momentum": [float(x) for x in mom]}
+                     "mass": mass, "momentum": [float(x) for x in mom],
+                     "reductions": len(masses), "mass_first_last": [masses[0], masses[-1]]}
         print(f"precision form: {name} done in {sec:.1f} s", file=sys.stderr, flush=True)
     for name in ("f32", "f16dev", "f16sr"):
         res[name]["rel_L2_u_vs_f64"] = _device_rel_l2(fields[name], fields["f64"])

@@ -440,6 +440,9 @@ def main():
             "traffic": traffic,
             "kernel": "sweep_kernel",
             "kernel_ms_avg": round(kernel_ms, 4),
+            # against the measured ceiling of the same access pattern: the pull-pattern
+            # copy (streaming only) on the same buffers
+            "frac_of_pull_copy": round(achieved / probes["pull_pattern_copy"], 4),
         },
         "probes_GBs": probes,
         "mass_after": mass,

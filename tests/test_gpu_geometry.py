@@ -68,6 +68,32 @@ def _parity(spec, solid, fv, no_transverse, steps=12):
         lbm.lbm_destroy(h)
 
 
+def test_extended_sweep_launch_shapes_bitwise_identical():
+    """The extended sweep (solid nodes, per-node face fields) gives the same
+    bits in every block width and XCD placement (150-node rows: 3, 2 or 1
+    blocks per row, ragged last blocks)."""
+    rng = np.random.default_rng(12)
+    nx, ny, nz = 150, 9, 10
+    solid = (rng.uniform(size=(nz, ny, nx)) < 0.1).astype(np.uint8)
+    solid[:, :, 0] = solid[:, :, -1] = 0
+    fv = {0: rng.uniform(-0.02, 0.03, (nz, ny, 3)), 1: rng.uniform(-0.02, 0.03, (nz, ny, 3))}
+    spec = workloads.LatticeSpec(nx, ny, nz, 0.85, {0: WALL, 1: WALL, 2: WALL, 3: WALL}, name="obstacles_150x9x10")
+    ref = None
+    for launch in [(64, 1, 0), (64, 1, 1), (64, 1, 2), (128, 1, 2), (256, 1, 1), (512, 1, 0)]:
+        h = _gpu(spec, lbm.LBM_STORE_F32, solid, fv)
+        try:
+            lbm.lbm_set_launch(h, *launch)
+            lbm.lbm_step(h, 15)
+            out = np.empty((19, nz, ny, nx))
+            lbm.lbm_get_populations(h, out)
+        finally:
+            lbm.lbm_destroy(h)
+        if ref is None:
+            ref = out
+        else:
+            np.testing.assert_array_equal(out, ref)
+
+
 @pytest.mark.parametrize("case", ["full", "no_transverse", "normal_inflow", "obstacles"])
 def test_extended_sweep_per_step_parity_fp64(case):
     if case == "obstacles":

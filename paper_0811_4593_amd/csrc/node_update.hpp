@@ -233,8 +233,28 @@ struct BufAccess {
     buf_store_nt<S>(v, dst, n * unsigned(sizeof(S)), unsigned(k) * pop_bytes);
   }
   __device__ __forceinline__ S load_at(int k, unsigned row, unsigned x) const { return load(k, row + x); }
+  // As load_at, but where the value is not needed (skip) the lane's offset is
+  // moved past the buffer's range: the load returns zero and reads no memory.
+  static constexpr bool kSkipsLoads = true;
+  __device__ __forceinline__ S load_at_if(int k, unsigned row, unsigned x, bool skip) const {
+    const unsigned voff = skip ? 19u * pop_bytes : (row + x) * unsigned(sizeof(S));
+    return buf_load<S>(src, voff, unsigned(k) * pop_bytes);
+  }
   __device__ __forceinline__ void store_at(int k, unsigned row, unsigned x, S v) const { store(k, row + x, v); }
 };
+
+// Whether an access type can skip a load whose value is not needed
+// (load_at_if); the others take the plain gather.
+template <class Access, class = void>
+struct SkipsLoads {
+  static constexpr bool value = false;
+};
+template <class Access>
+struct SkipsLoads<Access, decltype(void(Access::kSkipsLoads))> {
+  static constexpr bool value = Access::kSkipsLoads;
+};
+template <class Access>
+__host__ __device__ constexpr bool skips_loads() { return SkipsLoads<Access>::value; }
 
 // Optional per-node data of the extended sweep: solid nodes (mid-grid
 // bounce-back, Sec. III) and per-node velocities of velocity faces.
@@ -299,8 +319,25 @@ __device__ __forceinline__ void update_node(const Access &mem, const NodeGeom &g
       raw[k] = mem.load(own ? opp(k) : k, own ? n : off);
     }
   } else {
+    // A population entering from beyond a bounded face is unknown: the
+    // boundary rule replaces it without reading it, so an access that can
+    // skip a load cheaply does (the batch sweep's buffer loads; with rows of
+    // a few dozen nodes the wrapped source of a face node lies in a cache
+    // line that another wave fetches again).
+    if constexpr (skips_loads<Access>()) {
+      const bool fx0 = (bc_mask & 1u) && x == 0, fx1 = (bc_mask & 2u) && unsigned(x) == nx - 1;
+      const bool fy0 = (bc_mask & 4u) && y == 0, fy1 = (bc_mask & 8u) && unsigned(y) == ny - 1;
+      const bool fz0 = (bc_mask & 16u) && z == 0, fz1 = (bc_mask & 32u) && unsigned(z) == nz - 1;
 #pragma unroll
-    for (int k = 0; k < 19; ++k) raw[k] = mem.load_at(k, (yy[cy(k) + 1] + ny * zz[cz(k) + 1]) * nx, xs[cx(k) + 1]);
+      for (int k = 0; k < 19; ++k) {
+        const bool unk = (cx(k) > 0 && fx0) || (cx(k) < 0 && fx1) || (cy(k) > 0 && fy0) ||
+                         (cy(k) < 0 && fy1) || (cz(k) > 0 && fz0) || (cz(k) < 0 && fz1);
+        raw[k] = mem.load_at_if(k, (yy[cy(k) + 1] + ny * zz[cz(k) + 1]) * nx, xs[cx(k) + 1], unk);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 19; ++k) raw[k] = mem.load_at(k, (yy[cy(k) + 1] + ny * zz[cz(k) + 1]) * nx, xs[cx(k) + 1]);
+    }
   }
   if (!COPY && !solid_node) {
     T f[19];

@@ -314,6 +314,9 @@ def main():
     ap.add_argument("--placement", type=int, default=6,
                     help="buffers in the pool of lbm_tune_placement before the warm-up (the sweep's speed depends "
                          "on where its two buffers lie; its trial steps are real, untimed steps); < 2: off")
+    ap.add_argument("--layout", default="pop", choices=["pop", "rows"],
+                    help="population layout of the device buffers: population-major (k*P + n) or row-major "
+                         "(the 19 populations of each x-row together)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -357,6 +360,8 @@ def main():
     try:
         for face, v in spec.bc.items():
             lbm.lbm_set_velocity_bc(h, face, v)
+        layout = {"pop": lbm.LBM_LAYOUT_POPULATION_MAJOR, "rows": lbm.LBM_LAYOUT_ROW_MAJOR}[args.layout]
+        lbm.lbm_set_layout(h, layout)
         tuned = False
         if args.launch:
             lbm.lbm_set_launch(h, *[int(t) for t in args.launch.split(",")])
@@ -430,6 +435,7 @@ def main():
             "launch": {"block_x": launch[0], "nodes_per_thread": launch[1], "xcd_remap": launch[2],
                        "autotuned": tuned},
             "placement": placement,
+            "layout": {"pop": "population-major", "rows": "row-major"}[args.layout],
         },
         "roofline": {
             "bound": "hbm",

@@ -33,8 +33,11 @@
  *   population   k = i - 1, where i = 1..19 numbers the lattice vectors as the
  *                columns of the matrix M (Sec. II, eq_deffs); k = 18 is the
  *                rest population.  Host population arrays are structure-of-
- *                arrays, f[k*N + n] with N = nx*ny*nz; device buffers use the
- *                padded stride P = lbm_population_pitch(N): element k*P + n.
+ *                arrays, f[k*N + n] with N = nx*ny*nz.  Device buffers hold
+ *                19*P elements, P = lbm_population_pitch(N), in one of two
+ *                layouts (lbm_set_layout): population-major, element k*P + n
+ *                (the default), or row-major, element k*nx + 19*nx*r + x for
+ *                the x-row r = y + ny*z.
  *   axes         every axis is periodic until a face of it gets a velocity
  *                or pressure BC; lbm_step then requires both faces of that
  *                axis to be set.
@@ -232,9 +235,30 @@ lbm_status lbm_get_populations(lbm_lattice *L, double *f);
 lbm_status lbm_set_populations(lbm_lattice *L, const double *f);
 
 /* Device pointer of the buffer that holds the stored state, in the storage
- * form's encoding of d_k = f_k - w_k (it alternates between the two buffers
- * every step).  Errors: LBM_ERR_ARG. */
+ * form's encoding of d_k = f_k - w_k and the lattice's layout (it alternates
+ * between the two buffers every step).  Errors: LBM_ERR_ARG. */
 lbm_status lbm_state_buffer(const lbm_lattice *L, void **dev_ptr);
+
+/* Layout of the populations in the device buffers (the host-side arrays of
+ * lbm_get_populations / lbm_set_populations and every result are the same
+ * in both):
+ *   LBM_LAYOUT_POPULATION_MAJOR  element k*P + n, P = lbm_population_pitch(N):
+ *                                19 arrays of N nodes (the default);
+ *   LBM_LAYOUT_ROW_MAJOR         element k*nx + 19*nx*r + x, r = y + ny*z:
+ *                                the 19 populations of each x-row stored
+ *                                next to each other.  A sweep then streams
+ *                                through a few neighbouring regions of HBM
+ *                                instead of 38 regions P elements apart; on
+ *                                the MI355X this moves more bytes per second
+ *                                and depends less on where the two buffers
+ *                                lie.
+ * Every layout gives bitwise the same results.  lbm_set_layout moves the
+ * state into the other buffer in the new layout (enqueued on the stream, so
+ * lbm_state_buffer changes; caller-owned buffers are rewritten likewise).
+ * Errors: LBM_ERR_ARG (unknown layout, NULL), LBM_ERR_HIP. */
+enum { LBM_LAYOUT_POPULATION_MAJOR = 0, LBM_LAYOUT_ROW_MAJOR = 1 };
+lbm_status lbm_set_layout(lbm_lattice *L, int layout);
+lbm_status lbm_get_layout(const lbm_lattice *L, int *layout);
 
 /* Bytes of one population element for a storage form (8, 4 or 2); 0 if the
  * storage value is invalid. */
@@ -242,8 +266,9 @@ size_t lbm_element_bytes(lbm_storage storage);
 
 /* Population stride P of the device buffers, in elements, for a lattice of
  * `nodes` nodes: nodes rounded up to a multiple of 64, so that every
- * population starts on a cache-line boundary.  Population k of node n is
- * element k*P + n of a buffer; a buffer holds 19*P elements. */
+ * population starts on a cache-line boundary.  In the population-major
+ * layout population k of node n is element k*P + n of a buffer; a buffer
+ * holds 19*P elements in either layout. */
 size_t lbm_population_pitch(size_t nodes);
 
 /* Placement of the sweep's blocks on the 8 XCDs (each with its own L2) of

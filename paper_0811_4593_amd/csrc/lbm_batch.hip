@@ -67,7 +67,7 @@ __global__ __launch_bounds__(BX) void batch_sweep_kernel(const BatchLat *__restr
   for (int t = blockIdx.x; t < nt; t += gridDim.x) {
     const BatchTile tile = tiles[t];
     const BatchLat &L = lats[tile.lat];
-    const NodeGeom g{L.nx, L.ny, L.nz};
+    const NodeGeom g{L.nx, L.ny, L.nz, size_t(L.nx)};  // population-major rows
     const unsigned pop_bytes = L.pitch * unsigned(sizeof(S));
     const BufAccess<S> mem{raw_buffer(L.buf[parity], 19u * pop_bytes), raw_buffer(L.buf[parity ^ 1], 19u * pop_bytes),
                            pop_bytes};
@@ -497,7 +497,7 @@ lbm_status retire(lbm_batch *B, int id) {
   for (size_t n0 = 0; n0 < N; n0 += kStageNodes) {
     const size_t cnt = std::min(kStageNodes, N - n0);
     double *dr = B->d_stage, *du = B->d_stage + cnt;
-    LBM_BHIP(lbm::launch_moments(J.spec.storage, f, lbm::population_pitch(N), n0, cnt, dr, du, nullptr, 1024, B->stream),
+    LBM_BHIP(lbm::launch_moments(J.spec.storage, f, lbm::population_major(N, J.spec.nx), n0, cnt, dr, du, nullptr, 1024, B->stream),
              "moments");
     LBM_BHIP(hipMemcpyAsync(rho_h + n0, dr, cnt * sizeof(double), hipMemcpyDeviceToHost, B->stream), "copy");
     for (int a = 0; a < 3; ++a)
@@ -567,7 +567,7 @@ lbm_status admit(lbm_batch *B) {
     B->h_lats[slot] = L;
     B->slot_job[slot] = *it;
     const double zero[3] = {0.0, 0.0, 0.0};
-    LBM_BHIP(lbm::launch_init(J.spec.storage, L.buf[0], N, pitch, J.spec.rho0, zero, B->stream), "init launch");
+    LBM_BHIP(lbm::launch_init(J.spec.storage, L.buf[0], N, lbm::population_major(N, J.spec.nx), J.spec.rho0, zero, B->stream), "init launch");
     const size_t n3 = 3 * N;
     lbm::fill_float_kernel<<<dim3(unsigned((n3 + 255) / 256)), dim3(256), 0, B->stream>>>(L.snap, n3, 0.0f);
     LBM_BHIP(hipGetLastError(), "snapshot fill");

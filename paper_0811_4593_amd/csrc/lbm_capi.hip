@@ -49,7 +49,9 @@ constexpr int kMaxPlacementBuffers = 8;          // pool size limit of lbm_tune_
 struct lbm_lattice {
   int nx, ny, nz;
   size_t N;      // nodes
-  size_t pitch;  // population stride in elements (N rounded up to 64)
+  size_t pitch;  // population stride in elements (N rounded up to 64); buffers hold 19 * pitch
+  int layout;    // lbm_layout of the state
+  lbm::PopLayout lay;
   double tau;
   int storage;
   size_t esize;
@@ -135,7 +137,7 @@ static lbm_status finish_create(lbm_lattice *L, double rho0, const double u0[3],
   hipError_t e = hipMalloc(&L->d_partials, sizeof(double) * (kPartialBlocks * 4 + 4));
   if (e != hipSuccess) return fail(LBM_ERR_OOM, "hipMalloc of reduction scratch failed: %s", hipGetErrorString(e));
   L->d_totals = L->d_partials + kPartialBlocks * 4;
-  e = lbm::launch_init(L->storage, L->buf[0], L->N, L->pitch, rho0, u0, L->stream);
+  e = lbm::launch_init(L->storage, L->buf[0], L->N, L->lay, rho0, u0, L->stream);
   if (e != hipSuccess) return hip_fail(e, "init launch");
   e = hipStreamSynchronize(L->stream);
   if (e != hipSuccess) return hip_fail(e, "init");
@@ -155,6 +157,8 @@ lbm_status lbm_create(int nx, int ny, int nz, double tau, double rho0, const dou
   L->nz = nz;
   L->N = size_t(nx) * ny * nz;
   L->pitch = lbm::population_pitch(L->N);
+  L->layout = LBM_LAYOUT_POPULATION_MAJOR;
+  L->lay = lbm::population_major(L->N, nx);
   L->tau = tau;
   L->storage = int(storage);
   L->esize = lbm_element_bytes(storage);
@@ -192,6 +196,8 @@ lbm_status lbm_create_on_buffers(int nx, int ny, int nz, double tau, double rho0
   L->nz = nz;
   L->N = size_t(nx) * ny * nz;
   L->pitch = lbm::population_pitch(L->N);
+  L->layout = LBM_LAYOUT_POPULATION_MAJOR;
+  L->lay = lbm::population_major(L->N, nx);
   L->tau = tau;
   L->storage = int(storage);
   L->esize = lbm_element_bytes(storage);
@@ -411,6 +417,7 @@ static lbm::SweepConfig sweep_config(const lbm_lattice *L) {
   c.nx = L->nx;
   c.ny = L->ny;
   c.nz = L->nz;
+  c.layout = L->lay;
   c.tau = L->tau;
   c.bc_mask = L->bc_mask;
   c.p_mask = L->p_mask;
@@ -469,7 +476,7 @@ lbm_status lbm_moments(lbm_lattice *L, double *rho, double *u, int dst_on_device
   if (!rho && !u) return LBM_OK;
   const void *f = L->buf[L->cur];
   if (dst_on_device) {
-    LBM_HIP(lbm::launch_moments(L->storage, f, L->pitch, 0, L->N, rho, u, nullptr, kPartialBlocks, L->stream),
+    LBM_HIP(lbm::launch_moments(L->storage, f, L->lay, 0, L->N, rho, u, nullptr, kPartialBlocks, L->stream),
             "moments launch");
     LBM_HIP(hipStreamSynchronize(L->stream), "moments");
     return LBM_OK;
@@ -479,7 +486,7 @@ lbm_status lbm_moments(lbm_lattice *L, double *rho, double *u, int dst_on_device
   for (size_t n0 = 0; n0 < L->N; n0 += kChunkNodes) {
     const size_t cnt = (L->N - n0) < kChunkNodes ? (L->N - n0) : kChunkNodes;
     double *drho = L->d_stage, *du = L->d_stage + cnt;
-    LBM_HIP(lbm::launch_moments(L->storage, f, L->pitch, n0, cnt, rho ? drho : nullptr, u ? du : nullptr, nullptr,
+    LBM_HIP(lbm::launch_moments(L->storage, f, L->lay, n0, cnt, rho ? drho : nullptr, u ? du : nullptr, nullptr,
                                 kPartialBlocks, L->stream),
             "moments launch");
     if (rho) LBM_HIP(hipMemcpyAsync(rho + n0, drho, cnt * sizeof(double), hipMemcpyDeviceToHost, L->stream), "copy rho");
@@ -495,7 +502,7 @@ lbm_status lbm_moments(lbm_lattice *L, double *rho, double *u, int dst_on_device
 
 lbm_status lbm_totals(lbm_lattice *L, double *mass, double momentum[3]) {
   if (!L || !mass || !momentum) return fail(LBM_ERR_ARG, "NULL argument");
-  LBM_HIP(lbm::launch_moments(L->storage, L->buf[L->cur], L->pitch, 0, L->N, nullptr, nullptr, L->d_partials,
+  LBM_HIP(lbm::launch_moments(L->storage, L->buf[L->cur], L->lay, 0, L->N, nullptr, nullptr, L->d_partials,
                               kPartialBlocks, L->stream),
           "totals launch");
   LBM_HIP(lbm::launch_reduce(L->d_partials, kPartialBlocks, L->d_totals, L->stream), "reduce launch");
@@ -517,7 +524,7 @@ lbm_status lbm_get_populations(lbm_lattice *L, double *f) {
   if (st != LBM_OK) return st;
   for (size_t n0 = 0; n0 < L->N; n0 += kChunkNodes) {
     const size_t cnt = (L->N - n0) < kChunkNodes ? (L->N - n0) : kChunkNodes;
-    LBM_HIP(lbm::launch_to_double(L->storage, L->buf[L->cur], L->pitch, n0, cnt, L->d_stage, L->stream),
+    LBM_HIP(lbm::launch_to_double(L->storage, L->buf[L->cur], L->lay, n0, cnt, L->d_stage, L->stream),
             "convert launch");
     for (int k = 0; k < 19; ++k)
       LBM_HIP(hipMemcpyAsync(f + size_t(k) * L->N + n0, L->d_stage + size_t(k) * cnt, cnt * sizeof(double),
@@ -538,10 +545,31 @@ lbm_status lbm_set_populations(lbm_lattice *L, const double *f) {
       LBM_HIP(hipMemcpyAsync(L->d_stage + size_t(k) * cnt, f + size_t(k) * L->N + n0, cnt * sizeof(double),
                              hipMemcpyHostToDevice, L->stream),
               "copy populations");
-    LBM_HIP(lbm::launch_from_double(L->storage, L->buf[L->cur], L->pitch, n0, cnt, L->d_stage, L->stream),
+    LBM_HIP(lbm::launch_from_double(L->storage, L->buf[L->cur], L->lay, n0, cnt, L->d_stage, L->stream),
             "convert launch");
     LBM_HIP(hipStreamSynchronize(L->stream), "set populations");
   }
+  return LBM_OK;
+}
+
+lbm_status lbm_set_layout(lbm_lattice *L, int layout) {
+  if (!L) return fail(LBM_ERR_ARG, "NULL handle");
+  if (layout != LBM_LAYOUT_POPULATION_MAJOR && layout != LBM_LAYOUT_ROW_MAJOR)
+    return fail(LBM_ERR_ARG, "layout must be LBM_LAYOUT_POPULATION_MAJOR or LBM_LAYOUT_ROW_MAJOR (got %d)", layout);
+  if (layout == L->layout) return LBM_OK;
+  const lbm::PopLayout to = layout == LBM_LAYOUT_ROW_MAJOR ? lbm::row_major(L->nx) : lbm::population_major(L->N, L->nx);
+  // the state moves into the other buffer in the new layout (both hold 19 * pitch >= 19 * N elements)
+  LBM_HIP(lbm::launch_relayout(int(L->esize), L->buf[L->cur], L->lay, L->buf[L->cur ^ 1], to, L->N, L->stream),
+          "relayout launch");
+  L->cur ^= 1;
+  L->layout = layout;
+  L->lay = to;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_layout(const lbm_lattice *L, int *layout) {
+  if (!L || !layout) return fail(LBM_ERR_ARG, "NULL argument");
+  *layout = L->layout;
   return LBM_OK;
 }
 

@@ -24,10 +24,28 @@ enum { kStoreF64 = 0, kStoreF32 = 1, kStoreF16 = 2, kStoreF16SR = 3 };
 // wavefront's 64 consecutive nodes touch whole lines.
 inline size_t population_pitch(size_t nodes) { return (nodes + 63) / 64 * 64; }
 
+// Where population k of node n = x + nx*r (r = y + ny*z, the x-row) lives in
+// a buffer: element k*pop_stride + r*row_stride + x.  Population-major
+// (structure of arrays): pop_stride = P, row_stride = nx, i.e. k*P + n.
+// Row-major: pop_stride = nx, row_stride = 19*nx -- the 19 populations of
+// one x-row lie next to each other, so a sweep streams through a few nearby
+// regions instead of 19 regions P elements apart.
+struct PopLayout {
+  size_t pop_stride, row_stride;
+  unsigned nx;
+  __host__ __device__ size_t index(int k, size_t n) const {
+    const size_t r = n / nx;
+    return size_t(k) * pop_stride + r * row_stride + (n - r * nx);
+  }
+};
+inline PopLayout population_major(size_t nodes, int nx) { return {population_pitch(nodes), size_t(nx), unsigned(nx)}; }
+inline PopLayout row_major(int nx) { return {size_t(nx), 19 * size_t(nx), unsigned(nx)}; }
+
 // Everything one sweep launch needs, in host form.
 struct SweepConfig {
   int storage;
   int nx, ny, nz;
+  PopLayout layout;
   double tau;
   unsigned bc_mask;  // bit f: face f is bounded (velocity or pressure BC)
   unsigned p_mask;   // bit f: face f is a pressure face
@@ -48,8 +66,8 @@ struct SweepConfig {
 template <class T>
 struct SweepArgs {
   int nx, ny, nz;
-  size_t pitch;      // population stride in elements
-  int nxc;           // blocks per x-row
+  size_t pop_stride, row_stride;  // PopLayout
+  int nxc;                        // blocks per x-row
   unsigned nblocks;  // grid size
   int xcd_remap;
   unsigned key;  // step key of the stochastic rounding
@@ -64,14 +82,17 @@ hipError_t launch_sweep(const SweepConfig &c, const void *src, void *dst, bool c
 // number of nodes of each kind in counts[5] (fluid, solid, plane/edge/corner,
 // convex edge, general) if counts is non-null.
 void classify_geometry(int nx, int ny, int nz, const unsigned char *cell, unsigned *code, long long *counts);
-hipError_t launch_init(int storage, void *f, size_t N, size_t pitch, double rho0, const double u0[3], hipStream_t s);
-hipError_t launch_moments(int storage, const void *f, size_t pitch, size_t n0, size_t count, double *rho, double *u,
+hipError_t launch_init(int storage, void *f, size_t N, PopLayout lay, double rho0, const double u0[3],
+                       hipStream_t s);
+hipError_t launch_moments(int storage, const void *f, PopLayout lay, size_t n0, size_t count, double *rho, double *u,
                           double *partials, int nblk, hipStream_t s);
 hipError_t launch_reduce(const double *partials, int nblk, double *out, hipStream_t s);
-hipError_t launch_to_double(int storage, const void *f, size_t pitch, size_t n0, size_t count, double *out,
+hipError_t launch_to_double(int storage, const void *f, PopLayout lay, size_t n0, size_t count, double *out,
                             hipStream_t s);
-hipError_t launch_from_double(int storage, void *f, size_t pitch, size_t n0, size_t count, const double *in,
+hipError_t launch_from_double(int storage, void *f, PopLayout lay, size_t n0, size_t count, const double *in,
                               hipStream_t s);
+hipError_t launch_relayout(int esize, const void *src, PopLayout from, void *dst, PopLayout to, size_t N,
+                           hipStream_t s);
 hipError_t launch_copy_probe(const void *src, void *dst, size_t nbytes, hipStream_t s);
 
 }  // namespace lbm

@@ -2,9 +2,11 @@
 // streaming + on-site boundary rules + BGK), initialisation, moments and
 // FP64 reductions, storage conversion and bandwidth probes.
 //
-// Layout in HBM: structure of arrays, population k of node n at k*P + n,
-// n = x + nx*(y + ny*z), P = N rounded up to a multiple of 64 (population
-// starts on cache-line boundaries).  One sweep reads 19 and writes 19 elements per node;
+// Layout in HBM (PopLayout): population-major, population k of node n at
+// k*P + n, n = x + nx*(y + ny*z), P = N rounded up to a multiple of 64
+// (population starts on cache-line boundaries); or row-major, the 19
+// populations of each x-row next to each other (element k*nx + 19*nx*r + x
+// for row r = y + ny*z).  One sweep reads 19 and writes 19 elements per node;
 // every element of the source buffer is read exactly once per step (the pull
 // scheme has no reuse between nodes), so the kernel is a pure 38-stream HBM
 // copy with ~200 flops per node on top.
@@ -34,8 +36,8 @@ __global__ __launch_bounds__(BX) void sweep_kernel(const typename F::S *__restri
   const unsigned b = logical_block(blockIdx.x, gridDim.x, a.xcd_remap, unsigned(a.nxc));
   const unsigned row = a.nxc == 1 ? b : b / unsigned(a.nxc);
   const int xc = int(b - row * unsigned(a.nxc));
-  const NodeGeom g{unsigned(a.nx), unsigned(a.ny), unsigned(a.nz)};
-  const PtrAccess<typename F::S, NT> mem{src, dst, a.pitch};
+  const NodeGeom g{unsigned(a.nx), unsigned(a.ny), unsigned(a.nz), a.row_stride};
+  const PtrAccess<typename F::S, NT> mem{src, dst, a.pop_stride};
   const int y = int(row % g.ny);
   const int z = int(row / g.ny);
 #pragma unroll
@@ -51,15 +53,17 @@ __global__ __launch_bounds__(BX) void sweep_kernel(const typename F::S *__restri
 // evaluated in double.
 // ---------------------------------------------------------------------------
 template <class S>
-__global__ void init_kernel(S *__restrict__ f, size_t N, size_t pitch, double rho0, double ux, double uy, double uz) {
+__global__ void init_kernel(S *__restrict__ f, size_t N, PopLayout lay, double rho0, double ux, double uy,
+                            double uz) {
   const size_t n = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (n >= N) return;
+  const size_t at = lay.index(0, n);
   const double usq15 = 1.5 * (ux * ux + uy * uy + uz * uz);
 #pragma unroll
   for (int k = 0; k < 19; ++k) {
     const double cu = double(cx(k)) * ux + double(cy(k)) * uy + double(cz(k)) * uz;
     const double dk = weight<double>(k) * ((rho0 - 1.0) + rho0 * (3.0 * cu + 4.5 * cu * cu - usq15));
-    f[size_t(k) * pitch + n] = Codec<S>::encode(typename Codec<S>::T(dk));
+    f[at + size_t(k) * lay.pop_stride] = Codec<S>::encode(typename Codec<S>::T(dk));
   }
 }
 
@@ -77,18 +81,18 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 template <class S>
-__global__ __launch_bounds__(256) void moments_kernel(const S *__restrict__ f, size_t pitch, size_t n0,
+__global__ __launch_bounds__(256) void moments_kernel(const S *__restrict__ f, PopLayout lay, size_t n0,
                                                       size_t count, double *__restrict__ rho,
                                                       double *__restrict__ u,
                                                       double *__restrict__ partials) {
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   const size_t stride = size_t(gridDim.x) * blockDim.x;
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride) {
-    const size_t n = n0 + i;
+    const size_t at = lay.index(0, n0 + i);
     double dr = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
     for (int k = 0; k < 19; ++k) {
-      const double v = double(Codec<S>::decode(f[size_t(k) * pitch + n]));
+      const double v = double(Codec<S>::decode(f[at + size_t(k) * lay.pop_stride]));
       dr += v;
       if (cx(k)) jx += double(cx(k)) * v;
       if (cy(k)) jy += double(cy(k)) * v;
@@ -147,25 +151,40 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double *__re
 // double, nodes [n0, n0 + count); the chunk's layout is buf[k*count + i].
 // ---------------------------------------------------------------------------
 template <class S>
-__global__ void to_double_kernel(const S *__restrict__ f, size_t pitch, size_t n0, size_t count,
+__global__ void to_double_kernel(const S *__restrict__ f, PopLayout lay, size_t n0, size_t count,
                                  double *__restrict__ out) {
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= count) return;
+  const size_t at = lay.index(0, n0 + i);
 #pragma unroll
   for (int k = 0; k < 19; ++k)
-    out[size_t(k) * count + i] = weight<double>(k) + double(Codec<S>::decode(f[size_t(k) * pitch + n0 + i]));
+    out[size_t(k) * count + i] =
+        weight<double>(k) + double(Codec<S>::decode(f[at + size_t(k) * lay.pop_stride]));
 }
 
 template <class S>
-__global__ void from_double_kernel(S *__restrict__ f, size_t pitch, size_t n0, size_t count,
+__global__ void from_double_kernel(S *__restrict__ f, PopLayout lay, size_t n0, size_t count,
                                    const double *__restrict__ in) {
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= count) return;
+  const size_t at = lay.index(0, n0 + i);
 #pragma unroll
   for (int k = 0; k < 19; ++k) {
     using T = typename Codec<S>::T;
-    f[size_t(k) * pitch + n0 + i] = Codec<S>::encode(T(in[size_t(k) * count + i] - weight<double>(k)));
+    f[at + size_t(k) * lay.pop_stride] = Codec<S>::encode(T(in[size_t(k) * count + i] - weight<double>(k)));
   }
+}
+
+// Raw element copy of a state from one layout into another (no arithmetic:
+// the stored encodings move unchanged).
+template <class E>
+__global__ void relayout_kernel(const E *__restrict__ src, PopLayout from, E *__restrict__ dst, PopLayout to,
+                                size_t N) {
+  const size_t n = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const size_t a = from.index(0, n), b = to.index(0, n);
+#pragma unroll
+  for (int k = 0; k < 19; ++k) dst[b + size_t(k) * to.pop_stride] = src[a + size_t(k) * from.pop_stride];
 }
 
 // Plain contiguous copy of nbytes (multiple of 16) with 16-byte accesses.
@@ -222,7 +241,8 @@ static SweepArgs<T> make_args(const SweepConfig &c) {
   a.nx = c.nx;
   a.ny = c.ny;
   a.nz = c.nz;
-  a.pitch = population_pitch(size_t(c.nx) * c.ny * c.nz);
+  a.pop_stride = c.layout.pop_stride;
+  a.row_stride = c.layout.row_stride;
   const int span = c.block_x * c.nodes_per_thread;
   a.nxc = (c.nx + span - 1) / span;
   a.nblocks = unsigned(a.nxc) * unsigned(c.ny) * unsigned(c.nz);
@@ -333,26 +353,27 @@ void classify_geometry(int nx, int ny, int nz, const unsigned char *cell, unsign
 
 static unsigned blocks_for(size_t n, unsigned bs) { return unsigned((n + bs - 1) / bs); }
 
-hipError_t launch_init(int storage, void *f, size_t N, size_t pitch, double rho0, const double u0[3], hipStream_t s) {
+hipError_t launch_init(int storage, void *f, size_t N, PopLayout lay, double rho0, const double u0[3],
+                       hipStream_t s) {
   const dim3 g(blocks_for(N, 256)), b(256);
   switch (storage) {
-    case kStoreF64: init_kernel<double><<<g, b, 0, s>>>(static_cast<double *>(f), N, pitch, rho0, u0[0], u0[1], u0[2]); break;
-    case kStoreF32: init_kernel<float><<<g, b, 0, s>>>(static_cast<float *>(f), N, pitch, rho0, u0[0], u0[1], u0[2]); break;
+    case kStoreF64: init_kernel<double><<<g, b, 0, s>>>(static_cast<double *>(f), N, lay, rho0, u0[0], u0[1], u0[2]); break;
+    case kStoreF32: init_kernel<float><<<g, b, 0, s>>>(static_cast<float *>(f), N, lay, rho0, u0[0], u0[1], u0[2]); break;
     case kStoreF16:
-    case kStoreF16SR: init_kernel<_Float16><<<g, b, 0, s>>>(static_cast<_Float16 *>(f), N, pitch, rho0, u0[0], u0[1], u0[2]); break;
+    case kStoreF16SR: init_kernel<_Float16><<<g, b, 0, s>>>(static_cast<_Float16 *>(f), N, lay, rho0, u0[0], u0[1], u0[2]); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_moments(int storage, const void *f, size_t pitch, size_t n0, size_t count, double *rho, double *u,
+hipError_t launch_moments(int storage, const void *f, PopLayout lay, size_t n0, size_t count, double *rho, double *u,
                           double *partials, int nblk, hipStream_t s) {
   const dim3 g(nblk), b(256);
   switch (storage) {
-    case kStoreF64: moments_kernel<double><<<g, b, 0, s>>>(static_cast<const double *>(f), pitch, n0, count, rho, u, partials); break;
-    case kStoreF32: moments_kernel<float><<<g, b, 0, s>>>(static_cast<const float *>(f), pitch, n0, count, rho, u, partials); break;
+    case kStoreF64: moments_kernel<double><<<g, b, 0, s>>>(static_cast<const double *>(f), lay, n0, count, rho, u, partials); break;
+    case kStoreF32: moments_kernel<float><<<g, b, 0, s>>>(static_cast<const float *>(f), lay, n0, count, rho, u, partials); break;
     case kStoreF16:
-    case kStoreF16SR: moments_kernel<_Float16><<<g, b, 0, s>>>(static_cast<const _Float16 *>(f), pitch, n0, count, rho, u, partials); break;
+    case kStoreF16SR: moments_kernel<_Float16><<<g, b, 0, s>>>(static_cast<const _Float16 *>(f), lay, n0, count, rho, u, partials); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -363,27 +384,42 @@ hipError_t launch_reduce(const double *partials, int nblk, double *out, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_to_double(int storage, const void *f, size_t pitch, size_t n0, size_t count, double *out,
+hipError_t launch_to_double(int storage, const void *f, PopLayout lay, size_t n0, size_t count, double *out,
                             hipStream_t s) {
   const dim3 g(blocks_for(count, 256)), b(256);
   switch (storage) {
-    case kStoreF64: to_double_kernel<double><<<g, b, 0, s>>>(static_cast<const double *>(f), pitch, n0, count, out); break;
-    case kStoreF32: to_double_kernel<float><<<g, b, 0, s>>>(static_cast<const float *>(f), pitch, n0, count, out); break;
+    case kStoreF64: to_double_kernel<double><<<g, b, 0, s>>>(static_cast<const double *>(f), lay, n0, count, out); break;
+    case kStoreF32: to_double_kernel<float><<<g, b, 0, s>>>(static_cast<const float *>(f), lay, n0, count, out); break;
     case kStoreF16:
-    case kStoreF16SR: to_double_kernel<_Float16><<<g, b, 0, s>>>(static_cast<const _Float16 *>(f), pitch, n0, count, out); break;
+    case kStoreF16SR: to_double_kernel<_Float16><<<g, b, 0, s>>>(static_cast<const _Float16 *>(f), lay, n0, count, out); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_from_double(int storage, void *f, size_t pitch, size_t n0, size_t count, const double *in,
+hipError_t launch_from_double(int storage, void *f, PopLayout lay, size_t n0, size_t count, const double *in,
                               hipStream_t s) {
   const dim3 g(blocks_for(count, 256)), b(256);
   switch (storage) {
-    case kStoreF64: from_double_kernel<double><<<g, b, 0, s>>>(static_cast<double *>(f), pitch, n0, count, in); break;
-    case kStoreF32: from_double_kernel<float><<<g, b, 0, s>>>(static_cast<float *>(f), pitch, n0, count, in); break;
+    case kStoreF64: from_double_kernel<double><<<g, b, 0, s>>>(static_cast<double *>(f), lay, n0, count, in); break;
+    case kStoreF32: from_double_kernel<float><<<g, b, 0, s>>>(static_cast<float *>(f), lay, n0, count, in); break;
     case kStoreF16:
-    case kStoreF16SR: from_double_kernel<_Float16><<<g, b, 0, s>>>(static_cast<_Float16 *>(f), pitch, n0, count, in); break;
+    case kStoreF16SR: from_double_kernel<_Float16><<<g, b, 0, s>>>(static_cast<_Float16 *>(f), lay, n0, count, in); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_relayout(int esize, const void *src, PopLayout from, void *dst, PopLayout to, size_t N,
+                           hipStream_t s) {
+  const dim3 g(blocks_for(N, 256)), b(256);
+  switch (esize) {
+    case 8: relayout_kernel<unsigned long long><<<g, b, 0, s>>>(static_cast<const unsigned long long *>(src), from,
+                                                                 static_cast<unsigned long long *>(dst), to, N); break;
+    case 4: relayout_kernel<unsigned><<<g, b, 0, s>>>(static_cast<const unsigned *>(src), from,
+                                                       static_cast<unsigned *>(dst), to, N); break;
+    case 2: relayout_kernel<unsigned short><<<g, b, 0, s>>>(static_cast<const unsigned short *>(src), from,
+                                                             static_cast<unsigned short *>(dst), to, N); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

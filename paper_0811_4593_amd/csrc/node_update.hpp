@@ -144,25 +144,27 @@ __host__ __device__ __forceinline__ unsigned logical_block(unsigned b, unsigned 
   return b;
 }
 
-// Lattice extent for the gather.
+// Lattice extent for the gather, and the distance in elements between the
+// starts of consecutive x-rows (nx in the population-major layout, 19 nx in
+// the row-major one).
 struct NodeGeom {
   unsigned nx, ny, nz;
+  size_t row_stride;
 };
 
-// Memory access of one population buffer pair, in elements: load(k, off)
-// reads population k at in-population offset off of the source, store(k, n,
-// v) writes population k of node n of the destination.
+// Memory access of one population buffer pair, in elements: load_at(k,
+// row, x) reads element x of population k in the x-row that starts at
+// element `row` (row index times NodeGeom::row_stride) of the source;
+// store_at writes the destination likewise.
 //
-// PtrAccess: plain pointers (kernel arguments, any size).
+// PtrAccess: plain pointers (kernel arguments, any size).  pop_stride is the
+// distance between populations of one row: P in the population-major
+// layout, nx in the row-major one.
 template <class S, bool NT>
 struct PtrAccess {
   const S *__restrict__ src;
   S *__restrict__ dst;
-  size_t pitch;  // population stride in elements
-  __device__ __forceinline__ S load(int k, unsigned off) const { return src[size_t(k) * pitch + off]; }
-  __device__ __forceinline__ void store(int k, unsigned n, S v) const {
-    store_elem<S, NT>(dst + size_t(k) * pitch + n, v);
-  }
+  size_t pop_stride;
   // Element x of the row that starts at element `row` of population k.  For
   // 2-byte storage, with the row uniform over the wave, the address is a
   // scalar 64-bit base plus a 32-bit lane byte offset (x * 2 < 2^32), so the
@@ -170,20 +172,20 @@ struct PtrAccess {
   // instructions as much as by HBM, run 1-2% faster.  The wider forms keep
   // the 64-bit vector address: they compute in double, already spill scalar
   // registers, and measured 0.3% slower with the scalar bases.
-  __device__ __forceinline__ S load_at(int k, unsigned row, unsigned x) const {
+  __device__ __forceinline__ S load_at(int k, size_t row, unsigned x) const {
     if constexpr (sizeof(S) == 2) {
-      const char *base = reinterpret_cast<const char *>(src + (size_t(k) * pitch + row));
+      const char *base = reinterpret_cast<const char *>(src + (size_t(k) * pop_stride + row));
       return *reinterpret_cast<const S *>(base + x * unsigned(sizeof(S)));
     } else {
-      return src[size_t(k) * pitch + (row + x)];
+      return src[size_t(k) * pop_stride + (row + x)];
     }
   }
-  __device__ __forceinline__ void store_at(int k, unsigned row, unsigned x, S v) const {
+  __device__ __forceinline__ void store_at(int k, size_t row, unsigned x, S v) const {
     if constexpr (sizeof(S) == 2) {
-      char *base = reinterpret_cast<char *>(dst + (size_t(k) * pitch + row));
+      char *base = reinterpret_cast<char *>(dst + (size_t(k) * pop_stride + row));
       store_elem<S, NT>(reinterpret_cast<S *>(base + x * unsigned(sizeof(S))), v);
     } else {
-      store_elem<S, NT>(dst + size_t(k) * pitch + (row + x), v);
+      store_elem<S, NT>(dst + size_t(k) * pop_stride + (row + x), v);
     }
   }
 };
@@ -232,15 +234,16 @@ struct BufAccess {
   __device__ __forceinline__ void store(int k, unsigned n, S v) const {
     buf_store_nt<S>(v, dst, n * unsigned(sizeof(S)), unsigned(k) * pop_bytes);
   }
-  __device__ __forceinline__ S load_at(int k, unsigned row, unsigned x) const { return load(k, row + x); }
+  // Rows here are population-major (row < 2^32: buffers below 4 GiB).
+  __device__ __forceinline__ S load_at(int k, size_t row, unsigned x) const { return load(k, unsigned(row) + x); }
   // As load_at, but where the value is not needed (skip) the lane's offset is
   // moved past the buffer's range: the load returns zero and reads no memory.
   static constexpr bool kSkipsLoads = true;
-  __device__ __forceinline__ S load_at_if(int k, unsigned row, unsigned x, bool skip) const {
-    const unsigned voff = skip ? 19u * pop_bytes : (row + x) * unsigned(sizeof(S));
+  __device__ __forceinline__ S load_at_if(int k, size_t row, unsigned x, bool skip) const {
+    const unsigned voff = skip ? 19u * pop_bytes : (unsigned(row) + x) * unsigned(sizeof(S));
     return buf_load<S>(src, voff, unsigned(k) * pop_bytes);
   }
-  __device__ __forceinline__ void store_at(int k, unsigned row, unsigned x, S v) const { store(k, row + x, v); }
+  __device__ __forceinline__ void store_at(int k, size_t row, unsigned x, S v) const { store(k, unsigned(row) + x, v); }
 };
 
 // Whether an access type can skip a load whose value is not needed
@@ -297,6 +300,8 @@ __device__ __forceinline__ void update_node(const Access &mem, const NodeGeom &g
   const unsigned xs[3] = {xp, unsigned(x), xm};
   S raw[19];
   const unsigned n = (unsigned(z) * ny + unsigned(y)) * nx + unsigned(x);
+  const size_t rs = g.row_stride;
+  const size_t row = size_t(unsigned(z) * ny + unsigned(y)) * rs;  // uniform when y and z are
   bool solid_node = false;
   unsigned gcode = 0u;
   if constexpr (EXT) {
@@ -309,14 +314,14 @@ __device__ __forceinline__ void update_node(const Access &mem, const NodeGeom &g
   if (EXT && solid_node) {
     // a solid node (or solid interior of a geometry) keeps its populations
 #pragma unroll
-    for (int k = 0; k < 19; ++k) raw[k] = mem.load(k, n);
+    for (int k = 0; k < 19; ++k) raw[k] = mem.load_at(k, row, unsigned(x));
   } else if (EXT && ext.solid) {
 #pragma unroll
     for (int k = 0; k < 19; ++k) {
-      const unsigned off = (yy[cy(k) + 1] + ny * zz[cz(k) + 1]) * nx + xs[cx(k) + 1];
+      const unsigned srow = yy[cy(k) + 1] + ny * zz[cz(k) + 1];
       // solid source: the node's own opposite population (mid-grid bounce-back)
-      const bool own = k != 18 && ext.solid[off] != 0;
-      raw[k] = mem.load(own ? opp(k) : k, own ? n : off);
+      const bool own = k != 18 && ext.solid[srow * nx + xs[cx(k) + 1]] != 0;
+      raw[k] = mem.load_at(own ? opp(k) : k, own ? row : size_t(srow) * rs, own ? unsigned(x) : xs[cx(k) + 1]);
     }
   } else {
     // A population entering from beyond a bounded face is unknown: the
@@ -332,11 +337,12 @@ __device__ __forceinline__ void update_node(const Access &mem, const NodeGeom &g
       for (int k = 0; k < 19; ++k) {
         const bool unk = (cx(k) > 0 && fx0) || (cx(k) < 0 && fx1) || (cy(k) > 0 && fy0) ||
                          (cy(k) < 0 && fy1) || (cz(k) > 0 && fz0) || (cz(k) < 0 && fz1);
-        raw[k] = mem.load_at_if(k, (yy[cy(k) + 1] + ny * zz[cz(k) + 1]) * nx, xs[cx(k) + 1], unk);
+        raw[k] = mem.load_at_if(k, size_t(yy[cy(k) + 1] + ny * zz[cz(k) + 1]) * rs, xs[cx(k) + 1], unk);
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < 19; ++k) raw[k] = mem.load_at(k, (yy[cy(k) + 1] + ny * zz[cz(k) + 1]) * nx, xs[cx(k) + 1]);
+      for (int k = 0; k < 19; ++k)
+        raw[k] = mem.load_at(k, size_t(yy[cy(k) + 1] + ny * zz[cz(k) + 1]) * rs, xs[cx(k) + 1]);
     }
   }
   if (!COPY && !solid_node) {
@@ -389,7 +395,6 @@ __device__ __forceinline__ void update_node(const Access &mem, const NodeGeom &g
 #pragma unroll
     for (int k = 0; k < 19; ++k) raw[k] = encode_form<F>(f[k], r0 + unsigned(k + 1) * 0x9e3779b9u);
   }
-  const unsigned row = (unsigned(z) * ny + unsigned(y)) * nx;  // uniform when y and z are
 #pragma unroll
   for (int k = 0; k < 19; ++k) mem.store_at(k, row, unsigned(x), raw[k]);
 }

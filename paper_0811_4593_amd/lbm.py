@@ -31,6 +31,7 @@ EXPORTS = (
     "lbm_set_solid_mask", "lbm_set_geometry", "lbm_classify_geometry", "lbm_set_rule_options", "lbm_set_body_force",
     "lbm_clear_bc", "lbm_step",
     "lbm_moments", "lbm_totals", "lbm_get_populations", "lbm_set_populations", "lbm_state_buffer",
+    "lbm_set_layout", "lbm_get_layout",
     "lbm_element_bytes", "lbm_population_pitch", "lbm_set_launch", "lbm_get_launch", "lbm_autotune", "lbm_get_step",
     "lbm_tune_placement", "lbm_probe",
     "lbm_destroy", "lbm_last_error",
@@ -42,6 +43,7 @@ EXPORTS = (
 LBM_JOB_QUEUED, LBM_JOB_RUNNING, LBM_JOB_DONE = 0, 1, 2
 LBM_RULE_NO_TRANSVERSE = 1
 LBM_XCD_NONE, LBM_XCD_SLABS, LBM_XCD_ROWS = 0, 1, 2  # sweep block placement on the XCDs
+LBM_LAYOUT_POPULATION_MAJOR, LBM_LAYOUT_ROW_MAJOR = 0, 1  # population layout of the device buffers
 
 
 class LbmJob(ctypes.Structure):
@@ -110,6 +112,8 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_get_populations.argtypes = [_vp, _dp]
     lib.lbm_set_populations.argtypes = [_vp, _dp]
     lib.lbm_state_buffer.argtypes = [_vp, ctypes.POINTER(_vp)]
+    lib.lbm_set_layout.argtypes = [_vp, st]
+    lib.lbm_get_layout.argtypes = [_vp, ctypes.POINTER(st)]
     lib.lbm_element_bytes.argtypes = [st]
     lib.lbm_element_bytes.restype = ctypes.c_size_t
     lib.lbm_population_pitch.argtypes = [ctypes.c_size_t]
@@ -305,6 +309,16 @@ def lbm_state_buffer(h) -> int:
     p = _vp()
     _check(load_library().lbm_state_buffer(h, ctypes.byref(p)))
     return p.value
+
+
+def lbm_set_layout(h, layout: int):
+    _check(load_library().lbm_set_layout(h, int(layout)))
+
+
+def lbm_get_layout(h) -> int:
+    v = ctypes.c_int()
+    _check(load_library().lbm_get_layout(h, ctypes.byref(v)))
+    return v.value
 
 
 def lbm_set_launch(h, block_x: int, nodes_per_thread: int, xcd_remap: int):

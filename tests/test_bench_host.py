@@ -51,6 +51,7 @@ def test_counter_ingest(tmp_path, monkeypatch):
         storage = "f32"
         nx, ny, nz = 64, 32, 16
         launch = "256,1,1"
+        layout = "rows"
         counters_command = "test"
 
     bench.ingest_counters(A)
@@ -59,3 +60,8 @@ def test_counter_ingest(tmp_path, monkeypatch):
     assert rec["fetch_scale"] == pytest.approx(2.0) and rec["write_scale"] == pytest.approx(1.0)
     assert rec["hbm_bytes_per_launch"] == pytest.approx(rec["algorithmic_bytes_per_launch"], rel=1e-12)
     assert rec["launch"] == [256, 1, 1] and rec["kernel_source_hash"] == bench.kernel_source_hash()
+    assert rec["layout"] == "rows"
+    # the figures are used only for the layout, launch and storage they were taken on
+    assert bench.measured_traffic([256, 1, 1], "f32", "rows") == rec["hbm_bytes_per_launch"]
+    assert bench.measured_traffic([256, 1, 1], "f32", "pop") is None
+    assert bench.measured_traffic([128, 1, 1], "f32", "rows") is None

@@ -326,16 +326,20 @@ def _sample_nodes(spec, rng, n_bulk=1500, n_face=40, n_edge=6):
 
 @pytest.mark.slow
 def test_full_size_roofline_duct_sampled_parity():
-    """The 1024x512x512 FP32 duct in the default launch shape that bench.py
-    times: one step from a perturbed state, ~1900 sampled nodes (every node
-    class) recomputed one by one by the oracle; then the exact boundary
-    velocities on every boundary node of the full lattice.  (bench.py also
-    tunes the buffer placement, which moves the state between allocations
-    without touching the arithmetic; that move is checked bit for bit in
-    test_gpu_step_runs.)"""
+    """The 1024x512x512 FP32 duct in the configuration bench.py times
+    (default launch shape, row-major layout): one step from a perturbed
+    state, ~1900 sampled nodes (every node class) recomputed one by one by
+    the oracle; then the exact boundary velocities on every boundary node of
+    the full lattice.  (The population-major layout gives the same bits:
+    test_gpu_layout compares the two at this size.)"""
     spec = workloads.roofline_duct()
     nx, ny, nz, N = spec.nx, spec.ny, spec.nz, spec.nodes
-    P = lbm.lbm_population_pitch(N)  # population k of node n is element k P + n
+    P = lbm.lbm_population_pitch(N)  # a buffer holds 19 P elements
+
+    def populations(buf):
+        # row-major: population k of node (x, y, z) is element k nx + 19 nx (y + ny z) + x
+        return buf[:19 * N].view(nz, ny, 19, nx).permute(2, 0, 1, 3)
+
     say(f"full-size duct {nx}x{ny}x{nz} fp32: allocating 2 x {19 * P * 4 / 1e9:.1f} GB")
     bufs = [torch.empty(19 * P, dtype=torch.float32, device="cuda") for _ in range(2)]
     stream = torch.cuda.current_stream()
@@ -344,14 +348,14 @@ def test_full_size_roofline_duct_sampled_parity():
     try:
         for face, v in spec.bc.items():
             lbm.lbm_set_velocity_bc(h, face, v)
+        lbm.lbm_set_layout(h, lbm.LBM_LAYOUT_ROW_MAJOR)
         lbm.lbm_step(h, 2)  # a few steps so boundary nodes carry non-trivial state
         cur = 0 if lbm.lbm_state_buffer(h) == bufs[0].data_ptr() else 1
         gen = torch.Generator(device="cuda").manual_seed(5)
+        pre = populations(bufs[cur])
         for k in range(19):  # perturb the stored deviations in place, one population at a time
-            seg = bufs[cur][k * P:k * P + N]
-            seg.add_(float(W[k]) * 0.04 * (torch.rand(N, device="cuda", generator=gen) - 0.5))
+            pre[k].add_(float(W[k]) * 0.04 * (torch.rand((nz, ny, nx), device="cuda", generator=gen) - 0.5))
         torch.cuda.synchronize()
-        pre = bufs[cur].view(19, P)[:, :N].unflatten(1, (nz, ny, nx))
         pts = _sample_nodes(spec, np.random.default_rng(11))
         say(f"  sampling {len(pts)} nodes")
         x, y, z = (torch.as_tensor(pts[:, i], device="cuda") for i in range(3))
@@ -367,7 +371,7 @@ def test_full_size_roofline_duct_sampled_parity():
         pulled[outside] = np.nan  # sources beyond a bounded face are unknown
         lbm.lbm_step(h, 1)
         torch.cuda.synchronize()
-        post = bufs[cur ^ 1].view(19, P)[:, :N].unflatten(1, (nz, ny, nx))
+        post = populations(bufs[cur ^ 1])
         assert lbm.lbm_state_buffer(h) == bufs[cur ^ 1].data_ptr()
         got = torch.stack([post[k, z, y, x] for k in range(19)], 1).double().cpu().numpy() + W[None, :]
         L = make_oracle(spec)

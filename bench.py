@@ -6,10 +6,11 @@ faces, on-site velocity inlet and outlet (0.04, 0.01, 0.01) on the x faces,
 tau = 0.8, FP32 storage), initial state at rest, synthetic.  A step is one
 launch of the fused sweep over all 2^28 nodes (pull streaming, boundary
 rules, BGK collision).  The populations are stored row-major (the 19
-populations of each x-row together; --layout pop: population-major, whose
-two buffers are then chosen by lbm_tune_placement from a pool of 6
-allocations, its trial steps real and untimed).  Then W untimed warm-up
-steps, then exactly K timed steps bracketed by device synchronisation.
+populations of each x-row together; --layout pop: population-major), and
+the lattice's two buffers are chosen by lbm_tune_placement from a pool of 6
+allocations (its trial steps are real, untimed steps; --placement 0 keeps
+the lattice's own).  Then W untimed warm-up steps, then exactly K timed
+steps bracketed by device synchronisation.
 
 Printed: one JSON line with MLUPS (the value), the roofline object for the
 sweep kernel (algorithmic bytes per launch / average launch duration measured
@@ -194,8 +195,9 @@ def form_precision(args):
             for face, v in spec.bc.items():
                 lbm.lbm_set_velocity_bc(h, face, v)
             lbm.lbm_set_layout(h, lbm.LBM_LAYOUT_ROW_MAJOR)
-            # launch shape picked on real steps; they count towards the run
+            # launch shape and buffer placement picked on real steps; they count towards the run
             shape = lbm.lbm_autotune(h, 4)
+            tried, ms0, ms1 = lbm.lbm_tune_placement(h, 6, 1)
             done = lbm.lbm_get_step(h)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -217,6 +219,7 @@ def form_precision(args):
         res[name] = {"MLUPS": round(N * (steps - done) / sec / 1e6, 1),
                      "GBs": round(N * (steps - done) / sec * 2 * 19 * lbm.lbm_element_bytes(st) / 1e9, 1),
                      "launch": list(shape), "layout": "row-major",
+                     "placement_ms_per_step": [round(ms0, 4), round(ms1, 4)],
                      "mass": mass, "momentum": [float(x) for x in mom],
                      "reductions": len(masses), "mass_first_last": [masses[0], masses[-1]]}
         print(f"precision form: {name} done in {sec:.1f} s", file=sys.stderr, flush=True)
@@ -311,10 +314,9 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch shape with lbm_autotune during the warm-up (default: the library's "
                          "default shape, the fastest measured on this workload)")
-    ap.add_argument("--placement", type=int, default=None,
-                    help="buffers in the pool of lbm_tune_placement before the warm-up (the population-major "
-                         "sweep's speed depends on where its two buffers lie; its trial steps are real, untimed "
-                         "steps); < 2: off; default 6 for --layout pop, off for rows (no gain measured)")
+    ap.add_argument("--placement", type=int, default=6,
+                    help="buffers in the pool of lbm_tune_placement before the warm-up (the sweep's speed depends "
+                         "on where its two buffers lie; its trial steps are real, untimed steps); < 2: off")
     ap.add_argument("--layout", default="rows", choices=["pop", "rows"],
                     help="population layout of the device buffers: population-major (k*P + n) or row-major "
                          "(the 19 populations of each x-row together)")
@@ -328,8 +330,6 @@ def main():
                     help="measure one of the systems forms instead of the roofline run (see form_* below)")
     ap.add_argument("--requests", type=int, default=40, help="serve form: requests in the timed trace")
     args = ap.parse_args()
-    if args.placement is None:
-        args.placement = 6 if args.layout == "pop" else 0
 
     if args.ingest_counters:
         ingest_counters(args)

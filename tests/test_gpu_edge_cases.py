@@ -79,8 +79,9 @@ def _sample(spec, rng, count=600):
 @pytest.mark.parametrize("storage,max_gaps", [(lbm.LBM_STORE_F16_DEV, 0.5), (lbm.LBM_STORE_F16_DEV_SR, 1.0)])
 def test_full_size_precision_duct_fp16_sampled(storage, max_gaps):
     """512 x 256 x 256 duct, FP16 form, in the configuration the precision
-    form times (row-major layout, launch shape from lbm_autotune): one step
-    after the trial steps from rest; sampled
+    form times (row-major layout, launch shape from lbm_autotune, buffers
+    from lbm_tune_placement): one step after those trial steps from rest;
+    sampled
     nodes are recomputed by the oracle from the decoded FP16 state; the new
     scaled deviations must be within max_gaps of the half grid of the
     oracle's."""
@@ -94,7 +95,8 @@ def test_full_size_precision_duct_fp16_sampled(storage, max_gaps):
         lbm.lbm_set_layout(h, lbm.LBM_LAYOUT_ROW_MAJOR)
         lbm.lbm_step(h, 4)
         shape = lbm.lbm_autotune(h, 2)
-        say(f"storage {storage}: row-major, autotuned {shape}")
+        tried, _, _ = lbm.lbm_tune_placement(h, 3, 1)
+        say(f"storage {storage}: row-major, autotuned {shape}, placement over {tried} buffers")
         host = np.empty((19, nz, ny, nx))
         lbm.lbm_get_populations(h, host)  # f = w + h 2^-8, exact decode
         pts = _sample(spec, np.random.default_rng(21))

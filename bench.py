@@ -82,8 +82,10 @@ def ingest_counters(args):
     storage = {"f32": lbm.LBM_STORE_F32, "f64": lbm.LBM_STORE_F64, "f16dev": lbm.LBM_STORE_F16_DEV,
                "f16sr": lbm.LBM_STORE_F16_DEV_SR}[args.storage]
     N = args.nx * args.ny * args.nz
-    # the probe copies the whole buffer, 19 populations of pitch P, in 16-byte units
-    copy_kib = (19 * lbm.lbm_population_pitch(N) * lbm.lbm_element_bytes(storage) // 16 * 16) / 1024.0
+    # the probe copies the whole buffer (its size in the layout), in 16-byte units
+    layout = {"pop": lbm.LBM_LAYOUT_POPULATION_MAJOR, "rows": lbm.LBM_LAYOUT_ROW_MAJOR}[args.layout]
+    buf_elems = lbm.lbm_buffer_elements(args.nx, args.ny, args.nz, storage, layout)
+    copy_kib = (buf_elems * lbm.lbm_element_bytes(storage) // 16 * 16) / 1024.0
 
     def pick(d, frag):
         ks = [k for k in d if frag in k]
@@ -405,8 +407,9 @@ def main():
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / args.probe_reps
             # the pull-pattern copy moves the 19 N elements of the nodes, the
-            # contiguous copy the whole buffer (19 P elements, in 16-byte units)
-            moved = 19 * N * ebytes if kind == 1 else 19 * lbm.lbm_population_pitch(N) * ebytes // 16 * 16
+            # contiguous copy the whole buffer (in 16-byte units)
+            moved = 19 * N * ebytes if kind == 1 else \
+                lbm.lbm_buffer_elements(spec.nx, spec.ny, spec.nz, storage, layout) * ebytes // 16 * 16
             probes[name] = round(2 * moved / (ms * 1e-3) / 1e9, 1)
     finally:
         lbm.lbm_destroy(h)

@@ -33,11 +33,12 @@
  *   population   k = i - 1, where i = 1..19 numbers the lattice vectors as the
  *                columns of the matrix M (Sec. II, eq_deffs); k = 18 is the
  *                rest population.  Host population arrays are structure-of-
- *                arrays, f[k*N + n] with N = nx*ny*nz.  Device buffers hold
- *                19*P elements, P = lbm_population_pitch(N), in one of two
- *                layouts (lbm_set_layout): population-major, element k*P + n
- *                (the default), or row-major, element k*nx + 19*nx*r + x for
- *                the x-row r = y + ny*z.
+ *                arrays, f[k*N + n] with N = nx*ny*nz.  Device buffers use
+ *                one of two layouts (lbm_set_layout): population-major,
+ *                element k*P + n with P = lbm_population_pitch(N) (the
+ *                default), or row-major, element k*R + 19*R*r + x for the
+ *                x-row r = y + ny*z, R = nx rounded up to a multiple of 128
+ *                bytes; lbm_buffer_elements gives a buffer's size.
  *   axes         every axis is periodic until a face of it gets a velocity
  *                or pressure BC; lbm_step then requires both faces of that
  *                axis to be set.
@@ -244,21 +245,32 @@ lbm_status lbm_state_buffer(const lbm_lattice *L, void **dev_ptr);
  * in both):
  *   LBM_LAYOUT_POPULATION_MAJOR  element k*P + n, P = lbm_population_pitch(N):
  *                                19 arrays of N nodes (the default);
- *   LBM_LAYOUT_ROW_MAJOR         element k*nx + 19*nx*r + x, r = y + ny*z:
- *                                the 19 populations of each x-row stored
- *                                next to each other.  A sweep then streams
- *                                through a few neighbouring regions of HBM
- *                                instead of 38 regions P elements apart; on
- *                                the MI355X this moves more bytes per second
- *                                and depends less on where the two buffers
- *                                lie.
+ *   LBM_LAYOUT_ROW_MAJOR         element k*R + 19*R*r + x, r = y + ny*z, with
+ *                                the row pitch R = nx rounded up to a
+ *                                multiple of 128 bytes (32 FP32, 16 FP64 or
+ *                                64 FP16 elements): the 19 populations of
+ *                                each x-row stored next to each other, every
+ *                                row on a cache-line boundary.  A sweep then
+ *                                streams through a few neighbouring regions
+ *                                of HBM instead of 38 regions P elements
+ *                                apart; on the MI355X this moves more bytes
+ *                                per second.
  * Every layout gives bitwise the same results.  lbm_set_layout moves the
  * state into the other buffer in the new layout (enqueued on the stream, so
- * lbm_state_buffer changes; caller-owned buffers are rewritten likewise).
- * Errors: LBM_ERR_ARG (unknown layout, NULL), LBM_ERR_HIP. */
+ * lbm_state_buffer changes).  When the row-major layout needs more than the
+ * buffers hold (padded rows), a lattice on library buffers gets a new,
+ * larger pair (the state is moved, the old pair freed; synchronizes); a
+ * lattice on caller-owned buffers gets LBM_ERR_STATE and keeps its layout.
+ * Errors: LBM_ERR_ARG (unknown layout, NULL), LBM_ERR_STATE, LBM_ERR_OOM,
+ * LBM_ERR_HIP. */
 enum { LBM_LAYOUT_POPULATION_MAJOR = 0, LBM_LAYOUT_ROW_MAJOR = 1 };
 lbm_status lbm_set_layout(lbm_lattice *L, int layout);
 lbm_status lbm_get_layout(const lbm_lattice *L, int *layout);
+
+/* Elements one population buffer needs for an nx*ny*nz lattice in a layout:
+ * 19*P population-major, 19*R*ny*nz row-major (R as above); multiply by
+ * lbm_element_bytes for bytes.  0 for invalid sizes, storage or layout. */
+size_t lbm_buffer_elements(int nx, int ny, int nz, lbm_storage storage, int layout);
 
 /* Bytes of one population element for a storage form (8, 4 or 2); 0 if the
  * storage value is invalid. */

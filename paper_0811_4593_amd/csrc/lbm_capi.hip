@@ -49,8 +49,9 @@ constexpr int kMaxPlacementBuffers = 8;          // pool size limit of lbm_tune_
 struct lbm_lattice {
   int nx, ny, nz;
   size_t N;      // nodes
-  size_t pitch;  // population stride in elements (N rounded up to 64); buffers hold 19 * pitch
-  int layout;    // lbm_layout of the state
+  size_t pitch;      // population stride in elements (N rounded up to 64)
+  size_t buf_elems;  // capacity of each of the two buffers, in elements (>= the layout's need)
+  int layout;        // LBM_LAYOUT_* of the state
   lbm::PopLayout lay;
   double tau;
   int storage;
@@ -80,6 +81,13 @@ extern "C" {
 const char *lbm_last_error(void) { return g_err; }
 
 size_t lbm_population_pitch(size_t nodes) { return lbm::population_pitch(nodes); }
+
+size_t lbm_buffer_elements(int nx, int ny, int nz, lbm_storage storage, int layout) {
+  const size_t esize = lbm_element_bytes(storage);
+  if (nx < 1 || ny < 1 || nz < 1 || esize == 0) return 0;
+  if (layout != LBM_LAYOUT_POPULATION_MAJOR && layout != LBM_LAYOUT_ROW_MAJOR) return 0;
+  return lbm::buffer_elements(layout, nx, ny, nz, esize);
+}
 
 size_t lbm_element_bytes(lbm_storage storage) {
   switch (storage) {
@@ -164,8 +172,9 @@ lbm_status lbm_create(int nx, int ny, int nz, double tau, double rho0, const dou
   L->esize = lbm_element_bytes(storage);
   L->stream = static_cast<hipStream_t>(hip_stream);
   L->owns = true;
+  L->buf_elems = 19 * L->pitch;
   default_launch(L);
-  const size_t bytes = 19 * L->pitch * L->esize;
+  const size_t bytes = L->buf_elems * L->esize;
   for (int i = 0; i < 2; ++i) {
     hipError_t e = hipMalloc(&L->buf[i], bytes);
     if (e != hipSuccess) {
@@ -203,6 +212,7 @@ lbm_status lbm_create_on_buffers(int nx, int ny, int nz, double tau, double rho0
   L->esize = lbm_element_bytes(storage);
   L->stream = static_cast<hipStream_t>(hip_stream);
   L->owns = false;
+  L->buf_elems = buf_bytes / L->esize;
   L->buf[0] = buf_a;
   L->buf[1] = buf_b;
   default_launch(L);
@@ -557,11 +567,39 @@ lbm_status lbm_set_layout(lbm_lattice *L, int layout) {
   if (layout != LBM_LAYOUT_POPULATION_MAJOR && layout != LBM_LAYOUT_ROW_MAJOR)
     return fail(LBM_ERR_ARG, "layout must be LBM_LAYOUT_POPULATION_MAJOR or LBM_LAYOUT_ROW_MAJOR (got %d)", layout);
   if (layout == L->layout) return LBM_OK;
-  const lbm::PopLayout to = layout == LBM_LAYOUT_ROW_MAJOR ? lbm::row_major(L->nx) : lbm::population_major(L->N, L->nx);
-  // the state moves into the other buffer in the new layout (both hold 19 * pitch >= 19 * N elements)
-  LBM_HIP(lbm::launch_relayout(int(L->esize), L->buf[L->cur], L->lay, L->buf[L->cur ^ 1], to, L->N, L->stream),
-          "relayout launch");
-  L->cur ^= 1;
+  const lbm::PopLayout to =
+      layout == LBM_LAYOUT_ROW_MAJOR ? lbm::row_major(L->nx, L->esize) : lbm::population_major(L->N, L->nx);
+  const size_t need = lbm::buffer_elements(layout, L->nx, L->ny, L->nz, L->esize);
+  if (need <= L->buf_elems) {
+    // the state moves into the other buffer in the new layout
+    LBM_HIP(lbm::launch_relayout(int(L->esize), L->buf[L->cur], L->lay, L->buf[L->cur ^ 1], to, L->N, L->stream),
+            "relayout launch");
+    L->cur ^= 1;
+  } else {
+    // padded rows need more room: a new pair of the library's own buffers
+    if (!L->owns)
+      return fail(LBM_ERR_STATE, "the row-major layout needs %zu bytes per buffer; the caller's buffers hold %zu "
+                                 "(lbm_buffer_elements gives the size)", need * L->esize, L->buf_elems * L->esize);
+    void *nb[2] = {nullptr, nullptr};
+    for (int i = 0; i < 2; ++i) {
+      if (hipMalloc(&nb[i], need * L->esize) != hipSuccess) {
+        (void)hipGetLastError();
+        for (int j = 0; j < i; ++j) (void)hipFree(nb[j]);
+        return fail(LBM_ERR_OOM, "hipMalloc of %zu bytes for the row-major layout failed", need * L->esize);
+      }
+    }
+    hipError_t e = lbm::launch_relayout(int(L->esize), L->buf[L->cur], L->lay, nb[0], to, L->N, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) {
+      for (int j = 0; j < 2; ++j) (void)hipFree(nb[j]);
+      return hip_fail(e, "relayout");
+    }
+    for (int j = 0; j < 2; ++j) (void)hipFree(L->buf[j]);
+    L->buf[0] = nb[0];
+    L->buf[1] = nb[1];
+    L->cur = 0;
+    L->buf_elems = need;
+  }
   L->layout = layout;
   L->lay = to;
   return LBM_OK;
@@ -678,7 +716,7 @@ lbm_status lbm_tune_placement(lbm_lattice *L, int max_buffers, int trial_steps, 
   if (trial_steps < 1) return fail(LBM_ERR_ARG, "trial_steps must be >= 1");
   lbm_status result = lbm_step(L, 0);  // the state checks of lbm_step
   if (result != LBM_OK) return result;
-  const size_t bytes = 19 * L->pitch * L->esize;
+  const size_t bytes = L->buf_elems * L->esize;
   // The pool: the state buffer, its partner, then new buffers while the device
   // keeps at least 1/8 of its memory (and 1 GiB) free.  All stay allocated
   // until the choice is made, so each new one lands on memory of its own.
@@ -774,7 +812,7 @@ lbm_status lbm_probe(lbm_lattice *L, int kind, int nrep) {
   void *dst = L->buf[L->cur ^ 1];
   const lbm::SweepConfig c = sweep_config(L);
   for (int r = 0; r < nrep; ++r) {
-    hipError_t e = kind == 0 ? lbm::launch_copy_probe(src, dst, 19 * L->pitch * L->esize & ~size_t(15), L->stream)
+    hipError_t e = kind == 0 ? lbm::launch_copy_probe(src, dst, L->buf_elems * L->esize & ~size_t(15), L->stream)
                              : lbm::launch_sweep(c, src, dst, true, L->stream);
     if (e != hipSuccess) return hip_fail(e, "probe launch");
   }

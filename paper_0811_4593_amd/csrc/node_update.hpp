@@ -227,7 +227,8 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_buffer(const void *p, unsi
 template <class S>
 struct BufAccess {
   __amdgpu_buffer_rsrc_t src, dst;
-  unsigned pop_bytes;  // population stride in bytes: pitch * sizeof(S)
+  unsigned pop_bytes;  // population stride in bytes (PopLayout::pop_stride * sizeof(S))
+  unsigned oob;        // a lane offset past the descriptors' range (their size in bytes)
   __device__ __forceinline__ S load(int k, unsigned off) const {
     return buf_load<S>(src, off * unsigned(sizeof(S)), unsigned(k) * pop_bytes);
   }
@@ -240,7 +241,7 @@ struct BufAccess {
   // moved past the buffer's range: the load returns zero and reads no memory.
   static constexpr bool kSkipsLoads = true;
   __device__ __forceinline__ S load_at_if(int k, size_t row, unsigned x, bool skip) const {
-    const unsigned voff = skip ? 19u * pop_bytes : (unsigned(row) + x) * unsigned(sizeof(S));
+    const unsigned voff = skip ? oob : (unsigned(row) + x) * unsigned(sizeof(S));
     return buf_load<S>(src, voff, unsigned(k) * pop_bytes);
   }
   __device__ __forceinline__ void store_at(int k, size_t row, unsigned x, S v) const { store(k, unsigned(row) + x, v); }

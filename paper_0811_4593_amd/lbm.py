@@ -31,7 +31,7 @@ EXPORTS = (
     "lbm_set_solid_mask", "lbm_set_geometry", "lbm_classify_geometry", "lbm_set_rule_options", "lbm_set_body_force",
     "lbm_clear_bc", "lbm_step",
     "lbm_moments", "lbm_totals", "lbm_get_populations", "lbm_set_populations", "lbm_state_buffer",
-    "lbm_set_layout", "lbm_get_layout",
+    "lbm_set_layout", "lbm_get_layout", "lbm_buffer_elements",
     "lbm_element_bytes", "lbm_population_pitch", "lbm_set_launch", "lbm_get_launch", "lbm_autotune", "lbm_get_step",
     "lbm_tune_placement", "lbm_probe",
     "lbm_destroy", "lbm_last_error",
@@ -114,6 +114,8 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_state_buffer.argtypes = [_vp, ctypes.POINTER(_vp)]
     lib.lbm_set_layout.argtypes = [_vp, st]
     lib.lbm_get_layout.argtypes = [_vp, ctypes.POINTER(st)]
+    lib.lbm_buffer_elements.argtypes = [st, st, st, st, st]
+    lib.lbm_buffer_elements.restype = ctypes.c_size_t
     lib.lbm_element_bytes.argtypes = [st]
     lib.lbm_element_bytes.restype = ctypes.c_size_t
     lib.lbm_population_pitch.argtypes = [ctypes.c_size_t]
@@ -143,7 +145,8 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_batch_destroy.argtypes = [_vp]
     lib.lbm_batch_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("lbm_element_bytes", "lbm_population_pitch", "lbm_destroy", "lbm_last_error",
+        if name not in ("lbm_element_bytes", "lbm_population_pitch", "lbm_buffer_elements", "lbm_destroy",
+                        "lbm_last_error",
                         "lbm_batch_destroy"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -313,6 +316,10 @@ def lbm_state_buffer(h) -> int:
 
 def lbm_set_layout(h, layout: int):
     _check(load_library().lbm_set_layout(h, int(layout)))
+
+
+def lbm_buffer_elements(nx: int, ny: int, nz: int, storage: int, layout: int) -> int:
+    return int(load_library().lbm_buffer_elements(int(nx), int(ny), int(nz), int(storage), int(layout)))
 
 
 def lbm_get_layout(h) -> int:

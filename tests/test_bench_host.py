@@ -37,7 +37,7 @@ def test_counter_ingest(tmp_path, monkeypatch):
     N = nx * ny * nz
     known_kib = 19 * N * 4 / 1024.0  # the sweep's algorithmic reads (and writes)
     from paper_0811_4593_amd import lbm
-    copy_kib = 19 * lbm.lbm_population_pitch(N) * 4 / 1024.0  # the copy probe moves the whole buffer
+    copy_kib = lbm.lbm_buffer_elements(nx, ny, nz, lbm.LBM_STORE_F32, lbm.LBM_LAYOUT_ROW_MAJOR) * 4 / 1024.0  # the whole buffer
     sweep = "void lbm::sweep_kernel<lbm::FormF32, 256, 1, true, false, false>(float const*, float*, args)"
     pull = "void lbm::sweep_kernel<lbm::FormF32, 256, 1, true, true, false>(float const*, float*, args)"
     copy = "lbm::copy_probe_kernel(uint4 const*, uint4*, unsigned long)"

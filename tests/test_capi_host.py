@@ -112,6 +112,21 @@ def test_binding_refuses_to_run_without_library(tmp_path):
         m._lib = saved
 
 
+def test_buffer_elements(lbm):
+    F64, F32, F16 = lbm.LBM_STORE_F64, lbm.LBM_STORE_F32, lbm.LBM_STORE_F16_DEV
+    POP, ROWS = lbm.LBM_LAYOUT_POPULATION_MAJOR, lbm.LBM_LAYOUT_ROW_MAJOR
+    assert lbm.lbm_buffer_elements(37, 21, 13, F32, POP) == 19 * lbm.lbm_population_pitch(37 * 21 * 13)
+    # row-major rows padded to 128 bytes: 32 FP32, 16 FP64, 64 FP16 elements
+    assert lbm.lbm_buffer_elements(37, 21, 13, F32, ROWS) == 19 * 64 * 21 * 13
+    assert lbm.lbm_buffer_elements(37, 21, 13, F64, ROWS) == 19 * 48 * 21 * 13
+    assert lbm.lbm_buffer_elements(37, 21, 13, F16, ROWS) == 19 * 64 * 21 * 13
+    assert lbm.lbm_buffer_elements(1024, 512, 512, F32, ROWS) == 19 * 1024 * 512 * 512
+    assert lbm.lbm_buffer_elements(512, 256, 256, F16, ROWS) == 19 * 512 * 256 * 256
+    assert lbm.lbm_buffer_elements(0, 4, 4, F32, ROWS) == 0
+    assert lbm.lbm_buffer_elements(4, 4, 4, 9, ROWS) == 0
+    assert lbm.lbm_buffer_elements(4, 4, 4, F32, 2) == 0
+
+
 def test_population_pitch(lbm):
     assert lbm.lbm_population_pitch(64) == 64
     assert lbm.lbm_population_pitch(65) == 128

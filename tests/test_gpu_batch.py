@@ -36,6 +36,11 @@ MIX = [
     (workloads.all_classes_lattices()[2], "f32"),
     (workloads.duct(21, 11, 13, (0.01, 0.0, 0.02), 1.0), "f64"),
     (workloads.duct(25, 14, 10, (0.035, 0.01, -0.01), 0.9), "f16sr"),
+    # rows of whole 128-byte lines: these jobs are stored row-major
+    (workloads.duct(32, 10, 7, (0.03, 0.01, 0.005), 0.85), "f32"),
+    (workloads.duct(64, 6, 5, (0.02, -0.01, 0.01), 0.75), "f16dev"),
+    (workloads.duct(16, 9, 8, (0.04, 0.0, -0.01), 1.1), "f64"),
+    (workloads.duct(64, 7, 6, (0.025, 0.01, 0.01), 0.95), "f16sr"),
 ]
 
 

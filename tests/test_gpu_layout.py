@@ -176,8 +176,8 @@ def test_row_major_fp64_step_parity_with_oracle():
 
 
 def test_layout_round_trip_and_errors():
-    """pop -> rows -> pop restores the state bit for bit and moves it between
-    the two buffers; an unknown layout is rejected and changes nothing."""
+    """pop -> rows -> pop restores the state bit for bit, each switch moving
+    it to another buffer; an unknown layout is rejected and changes nothing."""
     spec = workloads.duct(19, 7, 6)
     h = lbm.lbm_create(spec.nx, spec.ny, spec.nz, spec.tau, 1.0, None, lbm.LBM_STORE_F16_DEV,
                        torch.cuda.current_stream())
@@ -189,11 +189,13 @@ def test_layout_round_trip_and_errors():
         lbm.lbm_get_populations(h, before)
         b0 = lbm.lbm_state_buffer(h)
         assert lbm.lbm_get_layout(h) == POP
-        lbm.lbm_set_layout(h, ROWS)
-        assert lbm.lbm_state_buffer(h) != b0
+        lbm.lbm_set_layout(h, ROWS)  # 19-wide FP16 rows pad to 64: a larger pair
+        b1 = lbm.lbm_state_buffer(h)
+        assert b1 != b0
         lbm.lbm_set_layout(h, ROWS)  # no-op
-        lbm.lbm_set_layout(h, POP)
-        assert lbm.lbm_state_buffer(h) == b0
+        assert lbm.lbm_state_buffer(h) == b1
+        lbm.lbm_set_layout(h, POP)   # into the pair's other buffer
+        assert lbm.lbm_state_buffer(h) != b1
         after = np.empty_like(before)
         lbm.lbm_get_populations(h, after)
         np.testing.assert_array_equal(after, before)
@@ -201,6 +203,64 @@ def test_layout_round_trip_and_errors():
             lbm.lbm_set_layout(h, 2)
         assert e.value.status == lbm.LBM_ERR_ARG
         assert lbm.lbm_get_layout(h) == POP
+    finally:
+        lbm.lbm_destroy(h)
+
+
+def test_caller_owned_buffers_must_hold_the_padded_rows():
+    """37-wide rows pad to 64 FP32 elements: caller buffers sized for the
+    population-major layout are refused (layout unchanged), buffers of
+    lbm_buffer_elements bytes work and give the same bits; a lattice on the
+    library's buffers gets a larger pair."""
+    spec = workloads.duct(37, 9, 7)
+    nx, ny, nz, N = spec.nx, spec.ny, spec.nz, spec.nodes
+    stream = torch.cuda.current_stream()
+    f0 = _start(spec, seed=12)
+    ref = _run(spec, lbm.LBM_STORE_F32, POP, 6, f0)
+    small = [torch.empty(19 * lbm.lbm_population_pitch(N), dtype=torch.float32, device="cuda") for _ in range(2)]
+    need = lbm.lbm_buffer_elements(nx, ny, nz, lbm.LBM_STORE_F32, ROWS)
+    assert need == 19 * 64 * ny * nz > small[0].numel()
+    big = [torch.empty(need, dtype=torch.float32, device="cuda") for _ in range(2)]
+    for bufs, ok in ((small, False), (big, True)):
+        h = lbm.lbm_create_on_buffers(nx, ny, nz, spec.tau, 1.0, None, lbm.LBM_STORE_F32, stream,
+                                      bufs[0], bufs[1], bufs[0].numel() * 4)
+        try:
+            for face, v in spec.bc.items():
+                lbm.lbm_set_velocity_bc(h, face, v)
+            lbm.lbm_set_populations(h, f0)
+            if not ok:
+                with pytest.raises(lbm.LBMError) as e:
+                    lbm.lbm_set_layout(h, ROWS)
+                assert e.value.status == lbm.LBM_ERR_STATE
+                assert lbm.lbm_get_layout(h) == POP
+                continue
+            lbm.lbm_set_layout(h, ROWS)
+            assert lbm.lbm_state_buffer(h) in (bufs[0].data_ptr(), bufs[1].data_ptr())
+            lbm.lbm_step(h, 6)
+            f = np.empty((19, nz, ny, nx))
+            lbm.lbm_get_populations(h, f)
+            np.testing.assert_array_equal(f, ref[0])
+            # the device state as documented: element k R + 19 R r + x, R = 64
+            cur = bufs[0] if lbm.lbm_state_buffer(h) == bufs[0].data_ptr() else bufs[1]
+            dev = cur.view(nz, ny, 19, 64)[..., :nx].permute(2, 0, 1, 3).double().cpu().numpy()
+            W = np.array([2] * 6 + [1] * 12 + [12]) / 36.0
+            np.testing.assert_array_equal(dev + W[:, None, None, None], f)
+        finally:
+            lbm.lbm_destroy(h)
+    h = lbm.lbm_create(nx, ny, nz, spec.tau, 1.0, None, lbm.LBM_STORE_F32, stream)
+    try:
+        for face, v in spec.bc.items():
+            lbm.lbm_set_velocity_bc(h, face, v)
+        lbm.lbm_set_populations(h, f0)
+        old = lbm.lbm_state_buffer(h)
+        lbm.lbm_set_layout(h, ROWS)  # the library's pair is replaced by a larger one
+        assert lbm.lbm_get_layout(h) == ROWS and lbm.lbm_state_buffer(h) != old
+        lbm.lbm_set_layout(h, POP)   # fits in the larger pair
+        lbm.lbm_set_layout(h, ROWS)
+        lbm.lbm_step(h, 6)
+        f = np.empty((19, nz, ny, nx))
+        lbm.lbm_get_populations(h, f)
+        np.testing.assert_array_equal(f, ref[0])
     finally:
         lbm.lbm_destroy(h)
 
@@ -213,6 +273,7 @@ def test_full_size_duct_row_major_equals_population_major_in_device_memory():
     spec = workloads.roofline_duct()
     nx, ny, nz, N = spec.nx, spec.ny, spec.nz, spec.nodes
     P = lbm.lbm_population_pitch(N)
+    assert lbm.lbm_buffer_elements(nx, ny, nz, lbm.LBM_STORE_F32, ROWS) == 19 * N  # 1024-wide rows: no padding
     say(f"full-size duct {nx}x{ny}x{nz} fp32, both layouts: allocating 4 x {19 * P * 4 / 1e9:.1f} GB")
     stream = torch.cuda.current_stream()
     states = {}

@@ -335,6 +335,7 @@ def test_full_size_roofline_duct_sampled_parity():
     spec = workloads.roofline_duct()
     nx, ny, nz, N = spec.nx, spec.ny, spec.nz, spec.nodes
     P = lbm.lbm_population_pitch(N)  # a buffer holds 19 P elements
+    assert lbm.lbm_buffer_elements(nx, ny, nz, lbm.LBM_STORE_F32, lbm.LBM_LAYOUT_ROW_MAJOR) == 19 * N  # R = nx
 
     def populations(buf):
         # row-major: population k of node (x, y, z) is element k nx + 19 nx (y + ny z) + x

@@ -91,10 +91,12 @@ def _host_array(n):
 
 
 def run_plain(spec, storage="f32", steps=2000, stream=None, launch=None):
-    """One lattice with plain lbm_step launches; returns (seconds, rho, u)."""
+    """One lattice with plain lbm_step launches in the row-major layout (the
+    faster one for a single lattice); returns (seconds, rho, u)."""
     h = lbm.lbm_create(spec.nx, spec.ny, spec.nz, spec.tau, spec.rho0, None, STORAGE[storage], stream)
     try:
         apply_bc(h, spec)
+        lbm.lbm_set_layout(h, lbm.LBM_LAYOUT_ROW_MAJOR)
         if launch:
             lbm.lbm_set_launch(h, *launch)
         rho = _host_array(spec.nodes)

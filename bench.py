@@ -278,7 +278,8 @@ def form_serve(args):
     free, total = torch.cuda.mem_get_info()
     budget = int(min(free * 0.8, 200e9))
     calib = workloads.serving_trace(count=12, rate=1e9, seed=1)
-    rep_c = serving.serve_trace(calib, budget, chunk=100, tol=1e-6, max_steps=20000, max_jobs=512)
+    rep_c = serving.serve_trace(calib, budget, chunk=100, tol=1e-6, max_steps=20000, max_jobs=512,
+                                fill_nodes=args.serve_fill)
     sat = rep_c.solves_per_s
     print(f"serve form: calibration {rep_c.summary()}", file=sys.stderr, flush=True)
     rate = 0.7 * sat
@@ -290,12 +291,13 @@ def form_serve(args):
         return report
 
     rep = serving.serve_trace(trace, budget, chunk=100, tol=1e-6, max_steps=20000, max_jobs=512,
-                              progress=progress("served"))
+                              fill_nodes=args.serve_fill, progress=progress("served"))
     print(f"serve form: served {rep.summary()}", file=sys.stderr, flush=True)
     base = serving.replay_one_at_a_time(trace, rep.steps, progress=progress("one at a time"))
     print(f"serve form: one-at-a-time {base.summary()}", file=sys.stderr, flush=True)
     nodes = [r.spec.nodes for r in trace]
-    return {"form": "serve", "requests": len(trace), "rate_per_s": round(rate, 4),
+    return {"form": "serve", "policy": f"shortest remaining work first, at least {args.serve_fill} nodes per chunk",
+            "requests": len(trace), "rate_per_s": round(rate, 4),
             "calibration_solves_per_s": round(sat, 4), "budget_bytes": budget,
             "mean_nodes": float(np.mean(nodes)), "storage_f16_share": float(np.mean([r.storage == "f16sr" for r in trace])),
             "served": rep.summary(), "one_at_a_time": base.summary(),
@@ -331,6 +333,8 @@ def main():
     ap.add_argument("--form", choices=["precision", "batch", "serve"], default=None,
                     help="measure one of the systems forms instead of the roofline run (see form_* below)")
     ap.add_argument("--requests", type=int, default=40, help="serve form: requests in the timed trace")
+    ap.add_argument("--serve-fill", type=int, default=0,
+                    help="serve form: nodes a chunk steps at least (shortest remaining work first; 0: one job)")
     args = ap.parse_args()
 
     if args.ingest_counters:

@@ -425,6 +425,21 @@ lbm_status lbm_batch_result(lbm_batch *B, int job_id, double *rho, double *u);
  * tile_nodes nodes per tile (>= 256), grid_blocks persistent blocks (0: 8 per
  * compute unit).  Any shape gives the same results. */
 lbm_status lbm_batch_set_shape(lbm_batch *B, int block_x, int tile_nodes, int grid_blocks);
+
+/* Which resident jobs a chunk steps:
+ *   LBM_BATCH_LOCKSTEP        all of them (the default): every resident job
+ *                             advances chunk_steps steps per chunk;
+ *   LBM_BATCH_SHORTEST_FIRST  the jobs with the least remaining work (nodes
+ *                             times the steps left to max_steps) until at
+ *                             least fill_nodes nodes are chosen, plus any job
+ *                             left out for 50 chunks in a row.  Small jobs
+ *                             then step at their own pace instead of a large
+ *                             co-resident job's; the others wait, resident.
+ * A job's results do not depend on the policy (only when its steps run).
+ * lbm_batch_autotune steps every resident job whatever the policy.
+ * Errors: LBM_ERR_ARG (NULL, unknown policy). */
+enum { LBM_BATCH_LOCKSTEP = 0, LBM_BATCH_SHORTEST_FIRST = 1 };
+lbm_status lbm_batch_set_policy(lbm_batch *B, int policy, size_t fill_nodes);
 lbm_status lbm_batch_get_shape(const lbm_batch *B, int *block_x, int *tile_nodes, int *grid_blocks);
 
 /* Admit what fits, then time trial_steps (even) steps of the resident jobs

@@ -367,7 +367,8 @@ struct Job {
   int steps = 0;
   double delta = INFINITY;
   int converged = 0;
-  int waited = 0;  // chunks spent at the head of the queue without fitting
+  int waited = 0;   // chunks spent at the head of the queue without fitting
+  int skipped = 0;  // consecutive chunks resident but not stepped
   HostResult result;  // moments at retirement: rho [N], then u [3][N]
 };
 
@@ -409,6 +410,9 @@ struct lbm_batch {
   std::vector<unsigned> h_delta;
   double *d_stage = nullptr;
   std::map<long long, hipGraphExec_t> graphs;
+  int policy = LBM_BATCH_LOCKSTEP;  // which resident jobs a chunk steps
+  size_t fill_nodes = 0;            // LBM_BATCH_SHORTEST_FIRST: nodes a chunk steps at least
+  std::vector<char> run_slot;       // slot -> stepped by the current chunk
 };
 
 namespace {
@@ -444,7 +448,7 @@ lbm_status rebuild_tiles(lbm_batch *B) {
   const unsigned tn = unsigned(B->shape.tile_nodes);
   for (int slot = 0; slot < B->max_jobs; ++slot) {
     const int id = B->slot_job[slot];
-    if (id < 0) continue;
+    if (id < 0 || !B->run_slot[slot]) continue;
     const Job &J = B->jobs[id];
     const unsigned S = unsigned(size_t(B->h_lats[slot].slot_row) * J.spec.ny * J.spec.nz);  // slots
     for (unsigned n0 = 0; n0 < S; n0 += tn) B->h_tiles[J.spec.storage].push_back({slot, n0, std::min(S, n0 + tn)});
@@ -615,6 +619,50 @@ lbm_status admit(lbm_batch *B) {
   return LBM_OK;
 }
 
+// Choose the resident jobs the next chunk steps; the tile list is rebuilt
+// when the choice changes.  Lockstep: all of them.  Shortest first: every
+// job skipped for kMaxSkipped chunks in a row, then the others in order of
+// remaining work (nodes x steps left to max_steps, ties by slot) until at
+// least fill_nodes nodes are chosen -- small jobs then run at their own step
+// time instead of a large co-resident job's, and a large job waits, but not
+// for ever.
+constexpr int kMaxSkipped = 50;
+void select_jobs(lbm_batch *B, bool all) {
+  std::vector<char> next(size_t(B->max_jobs), 0);
+  if (all || B->policy == LBM_BATCH_LOCKSTEP) {
+    for (int slot = 0; slot < B->max_jobs; ++slot) next[slot] = B->slot_job[slot] >= 0;
+  } else {
+    std::vector<std::pair<double, int>> order;
+    for (int slot = 0; slot < B->max_jobs; ++slot) {
+      const int id = B->slot_job[slot];
+      if (id < 0) continue;
+      const Job &J = B->jobs[id];
+      const double nodes = double(J.spec.nx) * J.spec.ny * J.spec.nz;
+      order.push_back({nodes * double(std::max(0, J.spec.max_steps - J.steps)), slot});
+    }
+    std::sort(order.begin(), order.end());
+    double chosen = 0.0;
+    for (const auto &o : order) {
+      const Job &J = B->jobs[B->slot_job[o.second]];
+      if (J.skipped >= kMaxSkipped) {
+        next[o.second] = 1;
+        chosen += double(J.spec.nx) * J.spec.ny * J.spec.nz;
+      }
+    }
+    for (const auto &o : order) {
+      if (chosen > 0.0 && chosen >= double(B->fill_nodes)) break;
+      if (next[o.second]) continue;
+      const Job &J = B->jobs[B->slot_job[o.second]];
+      next[o.second] = 1;
+      chosen += double(J.spec.nx) * J.spec.ny * J.spec.nz;
+    }
+  }
+  if (next != B->run_slot) {
+    B->run_slot.swap(next);
+    B->tiles_dirty = true;
+  }
+}
+
 int count_active(const lbm_batch *B) {
   int n = 0;
   for (int id : B->slot_job) n += id >= 0;
@@ -682,6 +730,7 @@ lbm_status lbm_batch_create(size_t hbm_budget_bytes, int chunk_steps, int max_jo
   // partial tile per job.
   B->tile_cap = cap / 76 / kMinTileNodes + size_t(max_jobs) + 1;
   B->slot_job.assign(max_jobs, -1);
+  B->run_slot.assign(max_jobs, 0);
   B->h_lats.assign(max_jobs, lbm::BatchLat());
   std::memset(B->h_lats.data(), 0, B->h_lats.size() * sizeof(lbm::BatchLat));
   B->h_delta.assign(max_jobs, 0u);
@@ -776,6 +825,7 @@ lbm_status lbm_batch_run_chunk(lbm_batch *B, int *n_active, int *n_queued) {
   if (st != LBM_OK) return st;
   const int active = count_active(B);
   if (active > 0) {
+    select_jobs(B, false);
     st = B->tiles_dirty ? rebuild_tiles(B) : upload_lats(B);
     if (st != LBM_OK) return st;
     st = run_graph_chunk(B);
@@ -798,6 +848,11 @@ lbm_status lbm_batch_run_chunk(lbm_batch *B, int *n_active, int *n_queued) {
       const int id = B->slot_job[slot];
       if (id < 0) continue;
       Job &J = B->jobs[id];
+      if (!B->run_slot[slot]) {  // not stepped by this chunk
+        ++J.skipped;
+        continue;
+      }
+      J.skipped = 0;
       J.steps += B->chunk_steps;
       float d;
       std::memcpy(&d, &B->h_delta[slot], sizeof(d));
@@ -852,6 +907,15 @@ lbm_status lbm_batch_set_shape(lbm_batch *B, int block_x, int tile_nodes, int gr
   return LBM_OK;
 }
 
+lbm_status lbm_batch_set_policy(lbm_batch *B, int policy, size_t fill_nodes) {
+  if (!B) return bfail(LBM_ERR_ARG, "NULL handle");
+  if (policy != LBM_BATCH_LOCKSTEP && policy != LBM_BATCH_SHORTEST_FIRST)
+    return bfail(LBM_ERR_ARG, "policy must be LBM_BATCH_LOCKSTEP or LBM_BATCH_SHORTEST_FIRST (got %d)", policy);
+  B->policy = policy;
+  B->fill_nodes = fill_nodes;
+  return LBM_OK;
+}
+
 lbm_status lbm_batch_get_shape(const lbm_batch *B, int *block_x, int *tile_nodes, int *grid_blocks) {
   if (!B || !block_x || !tile_nodes || !grid_blocks) return bfail(LBM_ERR_ARG, "NULL argument");
   *block_x = B->shape.block_x;
@@ -866,6 +930,7 @@ lbm_status lbm_batch_autotune(lbm_batch *B, int trial_steps, int *block_x, int *
   lbm_status st = admit(B);
   if (st != LBM_OK) return st;
   if (count_active(B) == 0) return bfail(LBM_ERR_STATE, "no resident job to tune on");
+  select_jobs(B, true);  // trial steps are steps of every resident job
   const long long key = tune_key(B);
   Shape cached_shape;
   bool have_cached = false;

@@ -36,11 +36,12 @@ EXPORTS = (
     "lbm_tune_placement", "lbm_probe",
     "lbm_destroy", "lbm_last_error",
     "lbm_job_bytes", "lbm_batch_create", "lbm_batch_submit", "lbm_batch_run_chunk", "lbm_batch_poll",
-    "lbm_batch_result", "lbm_batch_set_shape", "lbm_batch_get_shape", "lbm_batch_autotune",
+    "lbm_batch_result", "lbm_batch_set_shape", "lbm_batch_get_shape", "lbm_batch_autotune", "lbm_batch_set_policy",
     "lbm_batch_memory", "lbm_batch_destroy",
 )
 
 LBM_JOB_QUEUED, LBM_JOB_RUNNING, LBM_JOB_DONE = 0, 1, 2
+LBM_BATCH_LOCKSTEP, LBM_BATCH_SHORTEST_FIRST = 0, 1
 LBM_RULE_NO_TRANSVERSE = 1
 LBM_XCD_NONE, LBM_XCD_SLABS, LBM_XCD_ROWS = 0, 1, 2  # sweep block placement on the XCDs
 LBM_LAYOUT_POPULATION_MAJOR, LBM_LAYOUT_ROW_MAJOR = 0, 1  # population layout of the device buffers
@@ -139,6 +140,7 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_batch_poll.argtypes = [_vp, st, ctypes.POINTER(LbmJobStatus)]
     lib.lbm_batch_result.argtypes = [_vp, st, _vp, _vp]
     lib.lbm_batch_set_shape.argtypes = [_vp, st, st, st]
+    lib.lbm_batch_set_policy.argtypes = [_vp, st, ctypes.c_size_t]
     lib.lbm_batch_get_shape.argtypes = [_vp, ip, ip, ip]
     lib.lbm_batch_autotune.argtypes = [_vp, st, ip, ip, ip]
     lib.lbm_batch_memory.argtypes = [_vp, szp, szp]
@@ -447,6 +449,10 @@ def lbm_batch_result(b, job_id: int, nodes):
 
 def lbm_batch_set_shape(b, block_x: int, tile_nodes: int, grid_blocks: int = 0):
     _check(load_library().lbm_batch_set_shape(b, int(block_x), int(tile_nodes), int(grid_blocks)))
+
+
+def lbm_batch_set_policy(b, policy: int, fill_nodes: int = 0):
+    _check(load_library().lbm_batch_set_policy(b, int(policy), int(fill_nodes)))
 
 
 def lbm_batch_get_shape(b):

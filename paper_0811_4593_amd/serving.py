@@ -132,15 +132,19 @@ class ServeReport:
 
 
 def serve_trace(trace, budget_bytes, chunk=100, tol=1e-6, max_steps=20000, max_jobs=256, shape=None,
-                keep_results=(), stream=None, progress=None):
+                keep_results=(), stream=None, progress=None, policy=lbm.LBM_BATCH_SHORTEST_FIRST,
+                fill_nodes=0):
     """Replay `trace` (workloads.Request list, sorted by arrival) in real time:
     each request is submitted at its arrival time; between submissions the
     batch runs chunks, admitting queued requests as slots and memory free up
-    (continuous batching).  Latency = completion time - arrival time.
-    progress(done, total), if given, is called after every completion."""
+    (continuous batching); each chunk steps the resident requests `policy`
+    picks (shortest remaining work first by default, at least fill_nodes
+    nodes).  Latency = completion time - arrival time.  progress(done,
+    total), if given, is called after every completion."""
     b = lbm.lbm_batch_create(budget_bytes, chunk, max_jobs, stream)
     rep = ServeReport()
     try:
+        lbm.lbm_batch_set_policy(b, policy, fill_nodes)
         if shape:
             lbm.lbm_batch_set_shape(b, *shape)
         nreq = len(trace)

@@ -93,6 +93,7 @@ def test_null_handle_calls_fail_cleanly(lbm):
     assert lib.lbm_clear_bc(None, 0) == lbm.LBM_ERR_ARG
     assert lib.lbm_set_launch(None, 256, 1, 1) == lbm.LBM_ERR_ARG
     assert lib.lbm_set_layout(None, lbm.LBM_LAYOUT_ROW_MAJOR) == lbm.LBM_ERR_ARG
+    assert lib.lbm_batch_set_policy(None, lbm.LBM_BATCH_SHORTEST_FIRST, 0) == lbm.LBM_ERR_ARG
     assert lib.lbm_get_layout(None, None) == lbm.LBM_ERR_ARG
     assert lib.lbm_probe(None, 0, 1) == lbm.LBM_ERR_ARG
     assert lib.lbm_totals(None, None, None) == lbm.LBM_ERR_ARG

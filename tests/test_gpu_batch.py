@@ -297,3 +297,70 @@ def test_result_of_an_unfinished_job_is_refused():
         assert e.value.status == lbm.LBM_ERR_STATE
     finally:
         lbm.lbm_batch_destroy(b)  # destroying a batch with a resident job is fine
+
+
+def test_shortest_first_policy_order_and_results():
+    """LBM_BATCH_SHORTEST_FIRST with fill_nodes 0 steps one job per chunk, the
+    one with the least remaining work: the two small jobs finish before the
+    large one takes a step; every result equals the lattice run alone."""
+    big = workloads.duct(48, 24, 20, (0.03, 0.01, 0.0), 0.8)
+    small = [workloads.duct(10, 8, 6, (0.02, 0.0, 0.01), 0.9), workloads.duct(12, 6, 7, (0.01, 0.01, 0.0), 1.1)]
+    b = lbm.lbm_batch_create(256 << 20, 10, 8)
+    try:
+        lbm.lbm_batch_set_policy(b, lbm.LBM_BATCH_SHORTEST_FIRST, 0)
+        jb = lbm.lbm_batch_submit(b, serving.job_for(big, "f32", 0.0, 60))
+        js = [lbm.lbm_batch_submit(b, serving.job_for(s, "f16sr", 0.0, 40)) for s in small]
+        small_done_first = None
+        total_before = 0
+        while True:
+            active, queued = lbm.lbm_batch_run_chunk(b)
+            big_steps = lbm.lbm_batch_poll(b, jb).steps
+            ss = [lbm.lbm_batch_poll(b, j) for j in js]
+            total = big_steps + sum(st.steps for st in ss)
+            assert total - total_before == 10  # one job per chunk, one chunk of steps
+            total_before = total
+            if small_done_first is None and all(st.state == lbm.LBM_JOB_DONE for st in ss):
+                small_done_first = big_steps == 0
+            if active == 0 and queued == 0:
+                break
+        assert small_done_first, "the large job stepped before the small ones were done"
+        for jid, spec, st, steps in [(jb, big, "f32", 60)] + [(j, s, "f16sr", 40) for j, s in zip(js, small)]:
+            assert lbm.lbm_batch_poll(b, jid).steps == steps
+            rho_b, u_b = lbm.lbm_batch_result(b, jid, spec.nodes)
+            _, rho_p, u_p = serving.run_plain(spec, st, steps)
+            np.testing.assert_array_equal(rho_b, rho_p)
+            np.testing.assert_array_equal(u_b, u_p)
+    finally:
+        lbm.lbm_batch_destroy(b)
+
+
+def test_shortest_first_does_not_starve_a_large_job():
+    """A large job left out for 50 chunks in a row is stepped anyway."""
+    big = workloads.duct(40, 20, 16)
+    small = workloads.duct(8, 8, 8)
+    b = lbm.lbm_batch_create(256 << 20, 10, 4)
+    try:
+        lbm.lbm_batch_set_policy(b, lbm.LBM_BATCH_SHORTEST_FIRST, 0)
+        jb = lbm.lbm_batch_submit(b, serving.job_for(big, "f32", 0.0, 20))
+        js = lbm.lbm_batch_submit(b, serving.job_for(small, "f32", 0.0, 2000))
+        for chunk in range(52):
+            lbm.lbm_batch_run_chunk(b)
+        assert lbm.lbm_batch_poll(b, jb).steps >= 10  # stepped after 50 skipped chunks
+        assert lbm.lbm_batch_poll(b, js).steps >= 500
+        while True:
+            active, queued = lbm.lbm_batch_run_chunk(b)
+            if active == 0 and queued == 0:
+                break
+        assert lbm.lbm_batch_poll(b, jb).steps == 20 and lbm.lbm_batch_poll(b, js).steps == 2000
+    finally:
+        lbm.lbm_batch_destroy(b)
+
+
+def test_batch_policy_rejects_unknown_values():
+    b = lbm.lbm_batch_create(16 << 20, 10, 2)
+    try:
+        with pytest.raises(lbm.LBMError) as e:
+            lbm.lbm_batch_set_policy(b, 7, 0)
+        assert e.value.status == lbm.LBM_ERR_ARG
+    finally:
+        lbm.lbm_batch_destroy(b)

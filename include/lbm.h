@@ -436,6 +436,10 @@ lbm_status lbm_batch_set_shape(lbm_batch *B, int block_x, int tile_nodes, int gr
  *                             then step at their own pace instead of a large
  *                             co-resident job's; the others wait, resident.
  * A job's results do not depend on the policy (only when its steps run).
+ * Set the policy before submitting: with LBM_BATCH_SHORTEST_FIRST and
+ * fill_nodes 0, jobs submitted afterwards are stored row-major with padded
+ * rows and a chunk that steps a single row-major job runs the single-lattice
+ * sweep on it.  lbm_job_bytes gives the bytes of the lockstep layout.
  * lbm_batch_autotune steps every resident job whatever the policy.
  * Errors: LBM_ERR_ARG (NULL, unknown policy). */
 enum { LBM_BATCH_LOCKSTEP = 0, LBM_BATCH_SHORTEST_FIRST = 1 };

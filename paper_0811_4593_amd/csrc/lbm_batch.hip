@@ -22,6 +22,7 @@
 
 #include "../../include/lbm.h"
 #include "lbm_internal.hpp"
+#include "lbm_launch_defaults.hpp"
 #include "node_update.hpp"
 
 namespace lbm {
@@ -245,13 +246,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 int batch_layout_kind(int nx, size_t esize) {
   return (size_t(nx) * esize) % 128 == 0 ? LBM_LAYOUT_ROW_MAJOR : LBM_LAYOUT_POPULATION_MAJOR;
 }
-lbm::PopLayout batch_layout(size_t nodes, int nx, size_t esize) {
-  return batch_layout_kind(nx, esize) == LBM_LAYOUT_ROW_MAJOR ? lbm::row_major(nx, esize)
-                                                              : lbm::population_major(nodes, nx);
-}
-size_t batch_buffer_elements(const lbm_job &j) {
-  const size_t esize = lbm_element_bytes(j.storage);
-  return lbm::buffer_elements(batch_layout_kind(j.nx, esize), j.nx, j.ny, j.nz, esize);
+lbm::PopLayout layout_of(int kind, size_t nodes, int nx, size_t esize) {
+  return kind == LBM_LAYOUT_ROW_MAJOR ? lbm::row_major(nx, esize) : lbm::population_major(nodes, nx);
 }
 
 // First-fit allocator over one device allocation; free blocks are kept
@@ -303,9 +299,11 @@ class Pool {
   std::map<size_t, size_t> free_;
 };
 
-size_t job_bytes(const lbm_job &j) {
+size_t job_bytes(const lbm_job &j, int layout) {
   const size_t N = size_t(j.nx) * j.ny * j.nz;
-  return 2 * align_up(batch_buffer_elements(j) * lbm_element_bytes(j.storage)) + align_up(3 * N * sizeof(float));
+  const size_t esize = lbm_element_bytes(j.storage);
+  return 2 * align_up(lbm::buffer_elements(layout, j.nx, j.ny, j.nz, esize) * esize) +
+         align_up(3 * N * sizeof(float));
 }
 
 // Host memory for a retired job's moments, rho [N] then u [3][N].  Pinned
@@ -369,6 +367,8 @@ struct Job {
   int converged = 0;
   int waited = 0;   // chunks spent at the head of the queue without fitting
   int skipped = 0;  // consecutive chunks resident but not stepped
+  int layout = LBM_LAYOUT_POPULATION_MAJOR;  // chosen at submission
+  lbm::SweepConfig cfg{};                    // single-lattice sweep of the job (set at admission)
   HostResult result;  // moments at retirement: rho [N], then u [3][N]
 };
 
@@ -485,6 +485,20 @@ lbm_status launch_steps(lbm_batch *B, int nsteps, int first) {
   return LBM_OK;
 }
 
+// A chunk that steps a single job: plain launches of the single-lattice
+// sweep on the job's buffers (row-aligned blocks; bitwise the batch sweep's
+// results), one per step, each with the job's own step index.
+lbm_status run_solo_chunk(lbm_batch *B, int slot) {
+  const Job &J = B->jobs[B->slot_job[slot]];
+  const lbm::BatchLat &L = B->h_lats[slot];
+  lbm::SweepConfig c = J.cfg;
+  for (int s = 0; s < B->chunk_steps; ++s) {
+    c.step = unsigned(J.steps + s);
+    LBM_BHIP(lbm::launch_sweep(c, L.buf[s & 1], L.buf[(s & 1) ^ 1], false, B->stream), "sweep launch");
+  }
+  return LBM_OK;
+}
+
 lbm_status run_graph_chunk(lbm_batch *B) {
   const unsigned mask = present_mask(B);
   if (!mask) return LBM_OK;
@@ -530,7 +544,8 @@ lbm_status retire(lbm_batch *B, int id) {
   for (size_t n0 = 0; n0 < N; n0 += kStageNodes) {
     const size_t cnt = std::min(kStageNodes, N - n0);
     double *dr = B->d_stage, *du = B->d_stage + cnt;
-    LBM_BHIP(lbm::launch_moments(J.spec.storage, f, batch_layout(N, J.spec.nx, lbm_element_bytes(J.spec.storage)), n0, cnt, dr, du, nullptr, 1024, B->stream),
+    LBM_BHIP(lbm::launch_moments(J.spec.storage, f, layout_of(J.layout, N, J.spec.nx, lbm_element_bytes(J.spec.storage)),
+                                 n0, cnt, dr, du, nullptr, 1024, B->stream),
              "moments");
     LBM_BHIP(hipMemcpyAsync(rho_h + n0, dr, cnt * sizeof(double), hipMemcpyDeviceToHost, B->stream), "copy");
     for (int a = 0; a < 3; ++a)
@@ -572,7 +587,8 @@ lbm_status admit(lbm_batch *B) {
       continue;
     }
     const size_t N = size_t(J.spec.nx) * J.spec.ny * J.spec.nz;
-    const size_t elems = batch_buffer_elements(J.spec);
+    const size_t esize = lbm_element_bytes(J.spec.storage);
+    const size_t elems = lbm::buffer_elements(J.layout, J.spec.nx, J.spec.ny, J.spec.nz, esize);
     const size_t pop_bytes = align_up(elems * lbm_element_bytes(J.spec.storage));
     lbm::BatchLat L;
     std::memset(&L, 0, sizeof(L));
@@ -584,12 +600,11 @@ lbm_status admit(lbm_batch *B) {
     L.nz = unsigned(J.spec.nz);
     L.N = unsigned(N);
     L.buf_elems = unsigned(elems);
-    const lbm::PopLayout lay = batch_layout(N, J.spec.nx, lbm_element_bytes(J.spec.storage));
+    const lbm::PopLayout lay = layout_of(J.layout, N, J.spec.nx, esize);
     L.pop_stride = unsigned(lay.pop_stride);
     L.row_stride = unsigned(lay.row_stride);
-    L.slot_row = batch_layout_kind(J.spec.nx, lbm_element_bytes(J.spec.storage)) == LBM_LAYOUT_ROW_MAJOR
-                     ? unsigned(lay.pop_stride)  // the padded row pitch
-                     : unsigned(J.spec.nx);
+    L.slot_row = J.layout == LBM_LAYOUT_ROW_MAJOR ? unsigned(lay.pop_stride)  // the padded row pitch
+                                                  : unsigned(J.spec.nx);
     L.bc_mask = J.spec.bc_mask;
     L.p_mask = J.spec.pressure_mask;
     L.omega = 1.0 / J.spec.tau;
@@ -603,6 +618,23 @@ lbm_status admit(lbm_batch *B) {
     }
     for (int d = 0; d < 3; ++d) L.tau_f[d] = J.spec.tau * J.spec.force[d];
     L.inv_uref = 1.0 / J.spec.u_ref;
+    // the same lattice as a single-lattice sweep (a chunk that steps this job alone)
+    lbm::SweepConfig &c = J.cfg;
+    c = lbm::SweepConfig{};
+    c.storage = J.spec.storage;
+    c.nx = J.spec.nx;
+    c.ny = J.spec.ny;
+    c.nz = J.spec.nz;
+    c.layout = lay;
+    c.tau = J.spec.tau;
+    c.bc_mask = L.bc_mask;
+    c.p_mask = L.p_mask;
+    std::memcpy(c.v, L.v, sizeof(c.v));
+    std::memcpy(c.rho_p, L.rho_p, sizeof(c.rho_p));
+    for (int d = 0; d < 3; ++d) c.force[d] = J.spec.force[d];
+    c.block_x = lbm::default_block_x(J.spec.nx);
+    c.nodes_per_thread = 1;
+    c.xcd_remap = LBM_XCD_SLABS;
     B->h_lats[slot] = L;
     B->slot_job[slot] = *it;
     const double zero[3] = {0.0, 0.0, 0.0};
@@ -688,7 +720,7 @@ extern "C" {
 lbm_status lbm_job_bytes(const lbm_job *job, size_t *bytes) {
   if (!job || !bytes) return bfail(LBM_ERR_ARG, "NULL argument");
   if (lbm_element_bytes(job->storage) == 0) return bfail(LBM_ERR_ARG, "invalid storage");
-  *bytes = job_bytes(*job);
+  *bytes = job_bytes(*job, batch_layout_kind(job->nx, lbm_element_bytes(job->storage)));
   return LBM_OK;
 }
 
@@ -809,7 +841,13 @@ lbm_status lbm_batch_submit(lbm_batch *B, const lbm_job *job, int *job_id) {
   }
   Job J;
   J.spec = j;
-  J.bytes = job_bytes(j);
+  // The layout is fixed here: row-major with padded rows when every chunk
+  // steps one job through the single-lattice sweep (shortest first, fill 0),
+  // else row-major only for rows of whole 128-byte lines.
+  J.layout = B->policy == LBM_BATCH_SHORTEST_FIRST && B->fill_nodes == 0
+                 ? LBM_LAYOUT_ROW_MAJOR
+                 : batch_layout_kind(j.nx, lbm_element_bytes(j.storage));
+  J.bytes = job_bytes(j, J.layout);
   if (J.bytes > B->pool.capacity())
     return bfail(LBM_ERR_OOM, "job needs %zu bytes, more than the whole budget (%zu)", J.bytes, B->pool.capacity());
   const int id = B->next_id++;
@@ -828,7 +866,16 @@ lbm_status lbm_batch_run_chunk(lbm_batch *B, int *n_active, int *n_queued) {
     select_jobs(B, false);
     st = B->tiles_dirty ? rebuild_tiles(B) : upload_lats(B);
     if (st != LBM_OK) return st;
-    st = run_graph_chunk(B);
+    int stepped = 0, only = -1;
+    for (int slot = 0; slot < B->max_jobs; ++slot)
+      if (B->slot_job[slot] >= 0 && B->run_slot[slot]) {
+        ++stepped;
+        only = slot;
+      }
+    // one row-major job alone: the single-lattice sweep (population-major
+    // rows that are not whole lines run faster in the batch's flat walk)
+    const bool solo = stepped == 1 && B->jobs[B->slot_job[only]].layout == LBM_LAYOUT_ROW_MAJOR;
+    st = solo ? run_solo_chunk(B, only) : run_graph_chunk(B);
     if (st != LBM_OK) return st;
     // (a fill kernel rather than a memset node: the convergence maxima are
     // the bit patterns of non-negative floats, and 0.0f is all zero bits)

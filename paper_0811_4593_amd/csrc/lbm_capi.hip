@@ -11,6 +11,7 @@
 
 #include "../../include/lbm.h"
 #include "lbm_internal.hpp"
+#include "lbm_launch_defaults.hpp"
 
 namespace {
 
@@ -113,26 +114,10 @@ static lbm_status validate_create(int nx, int ny, int nz, double tau, double rho
 }
 
 static void default_launch(lbm_lattice *L) {
-  // One node per thread, each XCD on its own eighth of the lattice; the
-  // widest block (256 threads is the fastest shape measured on the
-  // 1024 x 512 x 512 duct) whose row segments leave at most 1/16 of the
-  // lanes idle, else the one that leaves the fewest (a 300-node row takes
-  // 64-thread blocks: 20 idle lanes in 320 instead of 212 in 512).
-  // lbm_set_launch and lbm_autotune override it.
-  int best = 0;
-  long best_lanes = 0;
-  for (int bx : {256, 128, 64}) {
-    const long lanes = (long(L->nx) + bx - 1) / bx * bx;
-    if (16 * (lanes - L->nx) <= lanes) {
-      best = bx;
-      break;
-    }
-    if (best == 0 || lanes < best_lanes) {
-      best = bx;
-      best_lanes = lanes;
-    }
-  }
-  L->block_x = best;
+  // One node per thread, each XCD on its own eighth of the lattice, the
+  // block width by row length (256 threads is the fastest shape measured on
+  // the 1024 x 512 x 512 duct).  lbm_set_launch and lbm_autotune override it.
+  L->block_x = lbm::default_block_x(L->nx);
   L->npt = 1;
   L->xcd = LBM_XCD_SLABS;
 }

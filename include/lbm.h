@@ -34,11 +34,13 @@
  *                columns of the matrix M (Sec. II, eq_deffs); k = 18 is the
  *                rest population.  Host population arrays are structure-of-
  *                arrays, f[k*N + n] with N = nx*ny*nz.  Device buffers use
- *                one of two layouts (lbm_set_layout): population-major,
- *                element k*P + n with P = lbm_population_pitch(N) (the
- *                default), or row-major, element k*R + 19*R*r + x for the
- *                x-row r = y + ny*z, R = nx rounded up to a multiple of 128
- *                bytes; lbm_buffer_elements gives a buffer's size.
+ *                one of two layouts (lbm_set_layout): row-major, element
+ *                k*R + 19*R*r + x for the x-row r = y + ny*z, R = nx rounded
+ *                up to a multiple of 128 bytes (the start of lbm_create), or
+ *                population-major, element k*P + n with
+ *                P = lbm_population_pitch(N) (the start of
+ *                lbm_create_on_buffers); lbm_buffer_elements gives a
+ *                buffer's size.
  *   axes         every axis is periodic until a face of it gets a velocity
  *                or pressure BC; lbm_step then requires both faces of that
  *                axis to be set.
@@ -99,7 +101,8 @@ typedef enum { LBM_X0 = 0, LBM_X1 = 1, LBM_Y0 = 2, LBM_Y1 = 3, LBM_Z0 = 4, LBM_Z
 /* Create a lattice of nx*ny*nz nodes (each >= 1, N < 2^31) with relaxation
  * time tau > 1/2, all axes periodic, every node at f^eq(rho0, u0)
  * (eq_feq).  rho0 > 0; u0 may be NULL (rest).  hip_stream is a hipStream_t
- * or NULL.  On success *out receives the handle.
+ * or NULL.  On success *out receives the handle.  The library allocates two
+ * buffers that hold either layout and starts row-major (lbm_set_layout).
  * Errors: LBM_ERR_ARG (sizes, tau, rho0, storage, out == NULL),
  * LBM_ERR_OOM, LBM_ERR_HIP. */
 lbm_status lbm_create(int nx, int ny, int nz, double tau, double rho0, const double u0[3],
@@ -244,7 +247,8 @@ lbm_status lbm_state_buffer(const lbm_lattice *L, void **dev_ptr);
  * lbm_get_populations / lbm_set_populations and every result are the same
  * in both):
  *   LBM_LAYOUT_POPULATION_MAJOR  element k*P + n, P = lbm_population_pitch(N):
- *                                19 arrays of N nodes (the default);
+ *                                19 arrays of N nodes (the start of a
+ *                                lattice on caller-owned buffers);
  *   LBM_LAYOUT_ROW_MAJOR         element k*R + 19*R*r + x, r = y + ny*z, with
  *                                the row pitch R = nx rounded up to a
  *                                multiple of 128 bytes (32 FP32, 16 FP64 or
@@ -254,15 +258,13 @@ lbm_status lbm_state_buffer(const lbm_lattice *L, void **dev_ptr);
  *                                streams through a few neighbouring regions
  *                                of HBM instead of 38 regions P elements
  *                                apart; on the MI355X this moves more bytes
- *                                per second.
+ *                                per second (the start of lbm_create).
  * Every layout gives bitwise the same results.  lbm_set_layout moves the
  * state into the other buffer in the new layout (enqueued on the stream, so
- * lbm_state_buffer changes).  When the row-major layout needs more than the
- * buffers hold (padded rows), a lattice on library buffers gets a new,
- * larger pair (the state is moved, the old pair freed; synchronizes); a
- * lattice on caller-owned buffers gets LBM_ERR_STATE and keeps its layout.
- * Errors: LBM_ERR_ARG (unknown layout, NULL), LBM_ERR_STATE, LBM_ERR_OOM,
- * LBM_ERR_HIP. */
+ * lbm_state_buffer changes).  The library's buffers hold either layout;
+ * caller-owned buffers smaller than the row-major layout needs (padded rows,
+ * lbm_buffer_elements) give LBM_ERR_STATE and the lattice keeps its layout.
+ * Errors: LBM_ERR_ARG (unknown layout, NULL), LBM_ERR_STATE, LBM_ERR_HIP. */
 enum { LBM_LAYOUT_POPULATION_MAJOR = 0, LBM_LAYOUT_ROW_MAJOR = 1 };
 lbm_status lbm_set_layout(lbm_lattice *L, int layout);
 lbm_status lbm_get_layout(const lbm_lattice *L, int *layout);

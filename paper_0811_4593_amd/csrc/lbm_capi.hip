@@ -2,6 +2,7 @@
 // argument and state validation, and the launches on the handle's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -150,14 +151,16 @@ lbm_status lbm_create(int nx, int ny, int nz, double tau, double rho0, const dou
   L->nz = nz;
   L->N = size_t(nx) * ny * nz;
   L->pitch = lbm::population_pitch(L->N);
-  L->layout = LBM_LAYOUT_POPULATION_MAJOR;
-  L->lay = lbm::population_major(L->N, nx);
   L->tau = tau;
   L->storage = int(storage);
   L->esize = lbm_element_bytes(storage);
   L->stream = static_cast<hipStream_t>(hip_stream);
   L->owns = true;
-  L->buf_elems = 19 * L->pitch;
+  // The library's buffers start row-major (rows padded to cache lines, the
+  // faster layout for the sweep) and hold either layout.
+  L->layout = LBM_LAYOUT_ROW_MAJOR;
+  L->lay = lbm::row_major(nx, L->esize);
+  L->buf_elems = std::max(19 * L->pitch, lbm::buffer_elements(LBM_LAYOUT_ROW_MAJOR, nx, ny, nz, L->esize));
   default_launch(L);
   const size_t bytes = L->buf_elems * L->esize;
   for (int i = 0; i < 2; ++i) {
@@ -190,7 +193,7 @@ lbm_status lbm_create_on_buffers(int nx, int ny, int nz, double tau, double rho0
   L->nz = nz;
   L->N = size_t(nx) * ny * nz;
   L->pitch = lbm::population_pitch(L->N);
-  L->layout = LBM_LAYOUT_POPULATION_MAJOR;
+  L->layout = LBM_LAYOUT_POPULATION_MAJOR;  // the caller's buffers: k*P + n until lbm_set_layout
   L->lay = lbm::population_major(L->N, nx);
   L->tau = tau;
   L->storage = int(storage);
@@ -555,36 +558,13 @@ lbm_status lbm_set_layout(lbm_lattice *L, int layout) {
   const lbm::PopLayout to =
       layout == LBM_LAYOUT_ROW_MAJOR ? lbm::row_major(L->nx, L->esize) : lbm::population_major(L->N, L->nx);
   const size_t need = lbm::buffer_elements(layout, L->nx, L->ny, L->nz, L->esize);
-  if (need <= L->buf_elems) {
-    // the state moves into the other buffer in the new layout
-    LBM_HIP(lbm::launch_relayout(int(L->esize), L->buf[L->cur], L->lay, L->buf[L->cur ^ 1], to, L->N, L->stream),
-            "relayout launch");
-    L->cur ^= 1;
-  } else {
-    // padded rows need more room: a new pair of the library's own buffers
-    if (!L->owns)
-      return fail(LBM_ERR_STATE, "the row-major layout needs %zu bytes per buffer; the caller's buffers hold %zu "
-                                 "(lbm_buffer_elements gives the size)", need * L->esize, L->buf_elems * L->esize);
-    void *nb[2] = {nullptr, nullptr};
-    for (int i = 0; i < 2; ++i) {
-      if (hipMalloc(&nb[i], need * L->esize) != hipSuccess) {
-        (void)hipGetLastError();
-        for (int j = 0; j < i; ++j) (void)hipFree(nb[j]);
-        return fail(LBM_ERR_OOM, "hipMalloc of %zu bytes for the row-major layout failed", need * L->esize);
-      }
-    }
-    hipError_t e = lbm::launch_relayout(int(L->esize), L->buf[L->cur], L->lay, nb[0], to, L->N, L->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
-    if (e != hipSuccess) {
-      for (int j = 0; j < 2; ++j) (void)hipFree(nb[j]);
-      return hip_fail(e, "relayout");
-    }
-    for (int j = 0; j < 2; ++j) (void)hipFree(L->buf[j]);
-    L->buf[0] = nb[0];
-    L->buf[1] = nb[1];
-    L->cur = 0;
-    L->buf_elems = need;
-  }
+  if (need > L->buf_elems)  // only caller-owned buffers can be too small: the library's hold either layout
+    return fail(LBM_ERR_STATE, "the row-major layout needs %zu bytes per buffer; the caller's buffers hold %zu "
+                               "(lbm_buffer_elements gives the size)", need * L->esize, L->buf_elems * L->esize);
+  // the state moves into the other buffer in the new layout
+  LBM_HIP(lbm::launch_relayout(int(L->esize), L->buf[L->cur], L->lay, L->buf[L->cur ^ 1], to, L->N, L->stream),
+          "relayout launch");
+  L->cur ^= 1;
   L->layout = layout;
   L->lay = to;
   return LBM_OK;

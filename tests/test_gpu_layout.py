@@ -176,33 +176,37 @@ def test_row_major_fp64_step_parity_with_oracle():
 
 
 def test_layout_round_trip_and_errors():
-    """pop -> rows -> pop restores the state bit for bit, each switch moving
-    it to another buffer; an unknown layout is rejected and changes nothing."""
+    """A lattice of lbm_create starts row-major; rows -> pop -> rows restores
+    the state bit for bit, each switch moving it to the pair's other buffer
+    (the library's pair holds either layout); an unknown layout is rejected
+    and changes nothing."""
     spec = workloads.duct(19, 7, 6)
     h = lbm.lbm_create(spec.nx, spec.ny, spec.nz, spec.tau, 1.0, None, lbm.LBM_STORE_F16_DEV,
                        torch.cuda.current_stream())
     try:
         for face, v in spec.bc.items():
             lbm.lbm_set_velocity_bc(h, face, v)
+        assert lbm.lbm_get_layout(h) == ROWS
         lbm.lbm_step(h, 5)
         before = np.empty((19, spec.nz, spec.ny, spec.nx))
         lbm.lbm_get_populations(h, before)
         b0 = lbm.lbm_state_buffer(h)
-        assert lbm.lbm_get_layout(h) == POP
-        lbm.lbm_set_layout(h, ROWS)  # 19-wide FP16 rows pad to 64: a larger pair
-        b1 = lbm.lbm_state_buffer(h)
-        assert b1 != b0
         lbm.lbm_set_layout(h, ROWS)  # no-op
-        assert lbm.lbm_state_buffer(h) == b1
-        lbm.lbm_set_layout(h, POP)   # into the pair's other buffer
-        assert lbm.lbm_state_buffer(h) != b1
+        assert lbm.lbm_state_buffer(h) == b0
+        lbm.lbm_set_layout(h, POP)
+        assert lbm.lbm_state_buffer(h) != b0 and lbm.lbm_get_layout(h) == POP
+        mid = np.empty_like(before)
+        lbm.lbm_get_populations(h, mid)
+        np.testing.assert_array_equal(mid, before)
+        lbm.lbm_set_layout(h, ROWS)
+        assert lbm.lbm_state_buffer(h) == b0
         after = np.empty_like(before)
         lbm.lbm_get_populations(h, after)
         np.testing.assert_array_equal(after, before)
         with pytest.raises(lbm.LBMError) as e:
             lbm.lbm_set_layout(h, 2)
         assert e.value.status == lbm.LBM_ERR_ARG
-        assert lbm.lbm_get_layout(h) == POP
+        assert lbm.lbm_get_layout(h) == ROWS
     finally:
         lbm.lbm_destroy(h)
 
@@ -211,7 +215,7 @@ def test_caller_owned_buffers_must_hold_the_padded_rows():
     """37-wide rows pad to 64 FP32 elements: caller buffers sized for the
     population-major layout are refused (layout unchanged), buffers of
     lbm_buffer_elements bytes work and give the same bits; a lattice on the
-    library's buffers gets a larger pair."""
+    library's buffers holds both layouts."""
     spec = workloads.duct(37, 9, 7)
     nx, ny, nz, N = spec.nx, spec.ny, spec.nz, spec.nodes
     stream = torch.cuda.current_stream()
@@ -252,10 +256,8 @@ def test_caller_owned_buffers_must_hold_the_padded_rows():
         for face, v in spec.bc.items():
             lbm.lbm_set_velocity_bc(h, face, v)
         lbm.lbm_set_populations(h, f0)
-        old = lbm.lbm_state_buffer(h)
-        lbm.lbm_set_layout(h, ROWS)  # the library's pair is replaced by a larger one
-        assert lbm.lbm_get_layout(h) == ROWS and lbm.lbm_state_buffer(h) != old
-        lbm.lbm_set_layout(h, POP)   # fits in the larger pair
+        assert lbm.lbm_get_layout(h) == ROWS  # the library's pair holds the padded rows from the start
+        lbm.lbm_set_layout(h, POP)
         lbm.lbm_set_layout(h, ROWS)
         lbm.lbm_step(h, 6)
         f = np.empty((19, nz, ny, nx))

@@ -57,8 +57,9 @@ struct BatchTile {
 
 // One step of every lattice of storage form F listed in `tiles`.  Blocks take
 // tiles round-robin; each lane updates the nodes of slots n0 + t, n0 + t + BX,
-// ... of its block's tile (padding slots of row-major lattices stay idle, so
-// that the waves of a row start on cache lines as the rows do).  `s` is the index of the step within the launch sequence: it
+// ... of its block's tile (the padding slots of a row-major lattice with
+// padded rows stay idle, so that its rows' waves start on cache lines as the
+// rows do).  `s` is the index of the step within the launch sequence: it
 // selects source and destination buffer (parity) and, with the lattice's
 // step_base, the step key.
 template <class F, int BX>
@@ -589,12 +590,12 @@ lbm_status admit(lbm_batch *B) {
     const size_t N = size_t(J.spec.nx) * J.spec.ny * J.spec.nz;
     const size_t esize = lbm_element_bytes(J.spec.storage);
     const size_t elems = lbm::buffer_elements(J.layout, J.spec.nx, J.spec.ny, J.spec.nz, esize);
-    const size_t pop_bytes = align_up(elems * lbm_element_bytes(J.spec.storage));
+    const size_t buf_bytes = align_up(elems * esize);
     lbm::BatchLat L;
     std::memset(&L, 0, sizeof(L));
     L.buf[0] = B->pool_base + off;
-    L.buf[1] = B->pool_base + off + pop_bytes;
-    L.snap = reinterpret_cast<float *>(B->pool_base + off + 2 * pop_bytes);
+    L.buf[1] = B->pool_base + off + buf_bytes;
+    L.snap = reinterpret_cast<float *>(B->pool_base + off + 2 * buf_bytes);
     L.nx = unsigned(J.spec.nx);
     L.ny = unsigned(J.spec.ny);
     L.nz = unsigned(J.spec.nz);

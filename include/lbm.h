@@ -110,9 +110,10 @@ lbm_status lbm_create(int nx, int ny, int nz, double tau, double rho0, const dou
 
 /* As lbm_create, on two caller-owned device buffers of buf_bytes bytes each
  * (at least 19*P*element size with P = lbm_population_pitch(N), 256-byte
- * aligned).  The library never frees
- * them.  Errors as lbm_create; LBM_ERR_ARG if a buffer is NULL, too small or
- * misaligned. */
+ * aligned), starting population-major; lbm_set_layout to the row-major
+ * layout needs lbm_buffer_elements(..., LBM_LAYOUT_ROW_MAJOR) elements per
+ * buffer.  The library never frees them.  Errors as lbm_create; LBM_ERR_ARG
+ * if a buffer is NULL, too small or misaligned. */
 lbm_status lbm_create_on_buffers(int nx, int ny, int nz, double tau, double rho0, const double u0[3],
                                  lbm_storage storage, void *hip_stream, void *buf_a, void *buf_b,
                                  size_t buf_bytes, lbm_lattice **out);

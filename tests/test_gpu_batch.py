@@ -364,3 +364,43 @@ def test_batch_policy_rejects_unknown_values():
         assert e.value.status == lbm.LBM_ERR_ARG
     finally:
         lbm.lbm_batch_destroy(b)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f16dev", "f32", "f16sr"])
+def test_single_sweep_chunks_every_storage_form(storage):
+    """Shortest first with one job per chunk stores jobs row-major with padded
+    rows (37 wide: 48 FP64, 64 FP32/FP16 elements) and steps each chunk's job
+    with the single-lattice sweep; a duct with velocity faces and a forced
+    channel still equal the lattices run alone, bit for bit."""
+    duct = workloads.duct(37, 9, 8, (0.03, 0.01, -0.01), 0.85)
+    chan = workloads.LatticeSpec(21, 10, 9, 1.0, {4: (0.0, 0.0, 0.0), 5: (0.0, 0.0, 0.0)}, name="forced_channel")
+    b = lbm.lbm_batch_create(256 << 20, 10, 4)
+    try:
+        lbm.lbm_batch_set_policy(b, lbm.LBM_BATCH_SHORTEST_FIRST, 0)
+        j1 = lbm.lbm_batch_submit(b, serving.job_for(duct, storage, 0.0, 30))
+        job = serving.job_for(chan, storage, 0.0, 40)
+        job.force[0], job.force[1] = 1e-5, 2e-6
+        j2 = lbm.lbm_batch_submit(b, job)
+        while True:
+            active, queued = lbm.lbm_batch_run_chunk(b)
+            if active == 0 and queued == 0:
+                break
+        rho_b, u_b = lbm.lbm_batch_result(b, j1, duct.nodes)
+        _, rho_p, u_p = serving.run_plain(duct, storage, 30)
+        np.testing.assert_array_equal(rho_b, rho_p)
+        np.testing.assert_array_equal(u_b, u_p)
+        rho_c, u_c = lbm.lbm_batch_result(b, j2, chan.nodes)
+        h = lbm.lbm_create(chan.nx, chan.ny, chan.nz, chan.tau, 1.0, None, serving.STORAGE[storage],
+                           torch.cuda.current_stream())
+        try:
+            serving.apply_bc(h, chan)
+            lbm.lbm_set_body_force(h, (1e-5, 2e-6, 0.0))
+            lbm.lbm_step(h, 40)
+            rho, u = np.empty(chan.nodes), np.empty(3 * chan.nodes)
+            lbm.lbm_moments(h, rho, u)
+        finally:
+            lbm.lbm_destroy(h)
+        np.testing.assert_array_equal(rho_c, rho)
+        np.testing.assert_array_equal(u_c, u)
+    finally:
+        lbm.lbm_batch_destroy(b)

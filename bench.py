@@ -7,7 +7,7 @@ tau = 0.8, FP32 storage), initial state at rest, synthetic.  A step is one
 launch of the fused sweep over all 2^28 nodes (pull streaming, boundary
 rules, BGK collision).  The populations are stored row-major (the 19
 populations of each x-row together; --layout pop: population-major), and
-the lattice's two buffers are chosen by lbm_tune_placement from a pool of 6
+the lattice's two buffers are chosen by lbm_tune_placement from a pool of 8
 allocations (its trial steps are real, untimed steps; --placement 0 keeps
 the lattice's own).  Then W untimed warm-up steps, then exactly K timed
 steps bracketed by device synchronisation.
@@ -318,7 +318,7 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch shape with lbm_autotune during the warm-up (default: the library's "
                          "default shape, the fastest measured on this workload)")
-    ap.add_argument("--placement", type=int, default=6,
+    ap.add_argument("--placement", type=int, default=8,
                     help="buffers in the pool of lbm_tune_placement before the warm-up (the sweep's speed depends "
                          "on where its two buffers lie; its trial steps are real, untimed steps); < 2: off")
     ap.add_argument("--layout", default="rows", choices=["pop", "rows"],

@@ -158,8 +158,9 @@ lbm_status lbm_set_velocity_field(lbm_lattice *L, lbm_face face, const double *v
  * between the two nodes); solid nodes keep their populations unchanged.  A
  * solid node on a bounded face takes no boundary rule.  solid = NULL removes
  * the mask.  Lattices with a mask or a face velocity field are advanced by
- * the extended sweep (one node per thread, the mask read as 1 byte per node
- * and its neighbours, mostly from cache).  Errors: LBM_ERR_ARG, LBM_ERR_OOM,
+ * the extended sweep (one node per thread; the mask is turned on the host
+ * into one 4-byte word per node holding the node's own flag and those of its
+ * 18 sources, read once per node).  Errors: LBM_ERR_ARG, LBM_ERR_OOM,
  * LBM_ERR_HIP. */
 lbm_status lbm_set_solid_mask(lbm_lattice *L, const unsigned char *solid);
 

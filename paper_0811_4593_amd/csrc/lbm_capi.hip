@@ -68,7 +68,7 @@ struct lbm_lattice {
   double rho_p[6];
   double force[3];
   unsigned rule_flags;
-  unsigned char *d_solid;  // [N] solid flags on the device, or nullptr
+  unsigned *d_solid;       // [N] solid words on the device (NodeExt), or nullptr
   double *d_face_v[6];     // per-node face velocities on the device, or nullptr
   unsigned *d_geo;         // complex-geometry node codes on the device, or nullptr
   int block_x, npt, xcd;
@@ -338,16 +338,32 @@ lbm_status lbm_set_solid_mask(lbm_lattice *L, const unsigned char *solid) {
     return LBM_OK;
   }
   if (!L->d_solid) {
-    hipError_t e = hipMalloc(&L->d_solid, L->N);
+    hipError_t e = hipMalloc(&L->d_solid, L->N * sizeof(unsigned));
     if (e != hipSuccess) {
       L->d_solid = nullptr;
       return fail(LBM_ERR_OOM, "hipMalloc of the solid mask failed: %s", hipGetErrorString(e));
     }
   }
-  // Flags are stored as 0 / 1 whatever non-zero value the caller used.
-  std::vector<unsigned char> flags(solid, solid + L->N);
-  for (auto &c : flags) c = c ? 1 : 0;
-  hipError_t e = hipMemcpyAsync(L->d_solid, flags.data(), L->N, hipMemcpyHostToDevice, L->stream);
+  // One word per node: which of its 18 moving populations stream in from a
+  // solid node (source at -c_k, periodic wrap, as the sweep's gather), and
+  // whether it is solid itself (any non-zero flag counts).
+  const int nx = L->nx, ny = L->ny, nz = L->nz;
+  std::vector<unsigned> words(L->N);
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const size_t n = size_t(x) + size_t(nx) * (size_t(y) + size_t(ny) * size_t(z));
+        unsigned w = solid[n] ? (1u << lbm::kSolidSelfBit) : 0u;
+        for (int k = 0; k < 18; ++k) {
+          int xs = x - lbm::cx(k), ys = y - lbm::cy(k), zs = z - lbm::cz(k);
+          xs += xs < 0 ? nx : (xs >= nx ? -nx : 0);
+          ys += ys < 0 ? ny : (ys >= ny ? -ny : 0);
+          zs += zs < 0 ? nz : (zs >= nz ? -nz : 0);
+          if (solid[size_t(xs) + size_t(nx) * (size_t(ys) + size_t(ny) * size_t(zs))]) w |= 1u << k;
+        }
+        words[n] = w;
+      }
+  hipError_t e = hipMemcpyAsync(L->d_solid, words.data(), L->N * sizeof(unsigned), hipMemcpyHostToDevice, L->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
   if (e != hipSuccess) return hip_fail(e, "solid mask upload");
   return LBM_OK;

@@ -70,7 +70,7 @@ struct SweepConfig {
   double rho_p[6];   // prescribed densities of the pressure faces
   double force[3];   // body force
   unsigned rule_flags;               // kRuleNoTransverse
-  const unsigned char *solid;        // device [N] solid flags, or nullptr
+  const unsigned *solid;             // device [N] solid words (NodeExt), or nullptr
   const double *face_v[6];           // device per-node face velocities, or nullptr
   const unsigned *geo_code;          // device complex-geometry node codes, or nullptr
   int block_x;

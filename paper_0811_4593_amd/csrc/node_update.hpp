@@ -263,12 +263,18 @@ __host__ __device__ constexpr bool skips_loads() { return SkipsLoads<Access>::va
 // Optional per-node data of the extended sweep: solid nodes (mid-grid
 // bounce-back, Sec. III) and per-node velocities of velocity faces.
 struct NodeExt {
-  const unsigned char *solid;  // [N] 1 = solid node, or nullptr
+  const unsigned *solid;       // [N] solid words (solid_word), or nullptr
   const double *face_v[6];     // [n_face][3] per face, or nullptr; face node
                                // order: x faces y + ny z, y faces x + nx z,
                                // z faces x + nx y
   const unsigned *code;        // [N] complex-geometry node codes, or nullptr
 };
+
+// Solid word of a node of a lattice with a solid mask (built on the host):
+// bit k (k < 18) set when the source of population k, the node at -c_k
+// (periodic wrap), is solid; bit 18 set when the node itself is solid.  One
+// 4-byte read per node instead of the flags of its 19 sources.
+constexpr unsigned kSolidSelfBit = 18u;
 
 // Complex-geometry node code (built on the host from the node types):
 // bits 0-17 the unknown populations U, bits 18-23 the wall planes as a face
@@ -304,9 +310,12 @@ __device__ __forceinline__ void update_node(const Access &mem, const NodeGeom &g
   const size_t rs = g.row_stride;
   const size_t row = size_t(unsigned(z) * ny + unsigned(y)) * rs;  // uniform when y and z are
   bool solid_node = false;
-  unsigned gcode = 0u;
+  unsigned gcode = 0u, sword = 0u;
   if constexpr (EXT) {
-    if (ext.solid) solid_node = ext.solid[n] != 0;
+    if (ext.solid) {
+      sword = ext.solid[n];
+      solid_node = (sword >> kSolidSelfBit) & 1u;
+    }
     if (ext.code) {
       gcode = ext.code[n];
       solid_node = (gcode >> 24) == kGeoSolid;
@@ -321,7 +330,7 @@ __device__ __forceinline__ void update_node(const Access &mem, const NodeGeom &g
     for (int k = 0; k < 19; ++k) {
       const unsigned srow = yy[cy(k) + 1] + ny * zz[cz(k) + 1];
       // solid source: the node's own opposite population (mid-grid bounce-back)
-      const bool own = k != 18 && ext.solid[srow * nx + xs[cx(k) + 1]] != 0;
+      const bool own = k != 18 && ((sword >> k) & 1u);
       raw[k] = mem.load_at(own ? opp(k) : k, own ? row : size_t(srow) * rs, own ? unsigned(x) : xs[cx(k) + 1]);
     }
   } else {

@@ -162,7 +162,7 @@ def cpu_baseline(spec_full, budget_s: float):
     for _ in range(2000):
         fc = Lc.step(fc, nthreads=threads)
     el_c = time.perf_counter() - t0
-    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": threads, "cpu_model": cpu_model(), "kind": "oracle",
             "single_thread_value": round(mlups1, 3), "couette_16x16x32_2000_steps_s": round(el_c, 3),
             "sample": f"duct {s.nx}x{s.ny}x{s.nz} (same boundary set-up, 1/64 of the nodes), FP64, "
                       f"{steps} steps in {el:.1f} s on {threads} threads; effective {mlups * 304 / 1e3:.2f} GB/s "
@@ -174,7 +174,19 @@ def _device_rel_l2(u, ref):
     return float(torch.linalg.vector_norm(u - ref) / torch.linalg.vector_norm(ref))
 
 
-def form_precision(args):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def form_precision(args, steps=20000):
     """Storage precision on the 512x256x256 duct: FP16 scaled deviations (FP32
     arithmetic) and FP32 storage against the FP64 form (the GPU FP64 path is
     parity-pinned to the CPU oracle at 1e-12 per step) after the same number of
@@ -186,7 +198,6 @@ def form_precision(args):
     from paper_0811_4593_amd import lbm, workloads
 
     spec = workloads.precision_duct()
-    steps = args.steps if args.steps != 500 else 20000
     N = spec.nodes
     res, fields = {}, {}
     for name, st in (("f64", lbm.LBM_STORE_F64), ("f32", lbm.LBM_STORE_F32), ("f16dev", lbm.LBM_STORE_F16_DEV),
@@ -233,7 +244,7 @@ def form_precision(args):
             "f16sr_over_f32_MLUPS": round(res["f16sr"]["MLUPS"] / res["f32"]["MLUPS"], 3)}
 
 
-def form_batch(args):
+def form_batch(args, steps=2000):
     """64 seeded uneven ducts (Nx ~ U{32..256}, Ny, Nz ~ U{16..128}, oblique
     inflow |u| ~ U[0.01, 0.05], tau ~ U[0.6, 1.5], FP32) in one batch:
     autotuned shape, 100-step graph chunks, 2000 steps each; against the same
@@ -241,7 +252,6 @@ def form_batch(args):
     from paper_0811_4593_amd import serving, workloads
 
     specs = workloads.batch_ducts(64, seed=0)
-    steps = args.steps if args.steps != 500 else 2000
     run = serving.run_batch(specs, "f32", steps=steps, chunk=100, autotune=True, keep_results=True)
     print(f"batch form: batched run {run.seconds:.2f} s", file=sys.stderr, flush=True)
     seq_s, worst = 0.0, 0.0
@@ -260,10 +270,10 @@ def form_batch(args):
             "sequential_plain": {"seconds": round(seq_s, 3), "MLUPS": round(seq_updates / seq_s / 1e6, 1),
                                  "solves_per_s": round(len(specs) / seq_s, 2)},
             "speedup": round(seq_s / run.seconds, 2),
-            "max_rel_L2_u_batched_vs_plain": worst}
+            "max_rel_L2_u_batched_vs_plain": worst, "bitwise_equal_to_plain": worst == 0.0}
 
 
-def form_serve(args):
+def form_serve(args, requests=40):
     """Serving: seeded Poisson arrivals of cubic ducts, N log-uniform in
     [16, 256], oblique inflow |u| ~ U[0.01, 0.05], tau ~ U[0.6, 1.5], FP16 or
     FP32 per request, each run until the relative velocity change over 100
@@ -279,11 +289,11 @@ def form_serve(args):
     budget = int(min(free * 0.8, 200e9))
     calib = workloads.serving_trace(count=12, rate=1e9, seed=1)
     rep_c = serving.serve_trace(calib, budget, chunk=100, tol=1e-6, max_steps=20000, max_jobs=512,
-                                fill_nodes=args.serve_fill)
+                                fill_nodes=args.serve_fill, lanes=args.serve_lanes)
     sat = rep_c.solves_per_s
     print(f"serve form: calibration {rep_c.summary()}", file=sys.stderr, flush=True)
     rate = 0.7 * sat
-    trace = workloads.serving_trace(count=args.requests, rate=rate, seed=1)
+    trace = workloads.serving_trace(count=requests, rate=rate, seed=1)
     def progress(what):
         def report(done, total):
             if done % 10 == 0 or done == total:
@@ -291,16 +301,20 @@ def form_serve(args):
         return report
 
     rep = serving.serve_trace(trace, budget, chunk=100, tol=1e-6, max_steps=20000, max_jobs=512,
-                              fill_nodes=args.serve_fill, progress=progress("served"))
+                              fill_nodes=args.serve_fill, lanes=args.serve_lanes, progress=progress("served"))
     print(f"serve form: served {rep.summary()}", file=sys.stderr, flush=True)
     base = serving.replay_one_at_a_time(trace, rep.steps, progress=progress("one at a time"))
     print(f"serve form: one-at-a-time {base.summary()}", file=sys.stderr, flush=True)
     nodes = [r.spec.nodes for r in trace]
-    return {"form": "serve", "policy": f"shortest remaining work first, at least {args.serve_fill} nodes per chunk",
+    sv, oa = rep.summary(), base.summary()
+    return {"form": "serve", "policy": f"{args.serve_lanes} lanes, shortest remaining work first, requests below "
+                                       f"{args.serve_fill} nodes share launches up to {args.serve_fill} nodes",
             "requests": len(trace), "rate_per_s": round(rate, 4),
             "calibration_solves_per_s": round(sat, 4), "budget_bytes": budget,
             "mean_nodes": float(np.mean(nodes)), "storage_f16_share": float(np.mean([r.storage == "f16sr" for r in trace])),
-            "served": rep.summary(), "one_at_a_time": base.summary(),
+            "served": sv, "one_at_a_time": oa,
+            "p50_served_over_one_at_a_time": round(sv["p50_s"] / oa["p50_s"], 3),
+            "p99_served_over_one_at_a_time": round(sv["p99_s"] / oa["p99_s"], 3),
             "steps_mean": float(np.mean(rep.steps)), "converged": int(sum(rep.converged))}
 
 
@@ -332,9 +346,21 @@ def main():
     ap.add_argument("--counters-command", default="", help="the rocprofv3 command lines, for the record")
     ap.add_argument("--form", choices=["precision", "batch", "serve"], default=None,
                     help="measure one of the systems forms instead of the roofline run (see form_* below)")
-    ap.add_argument("--requests", type=int, default=40, help="serve form: requests in the timed trace")
+    ap.add_argument("--requests", type=int, default=40, help="--form serve: requests in the timed trace")
+    ap.add_argument("--precision-steps", type=int, default=20000,
+                    help="precision leg: steps of the 512x256x256 duct in every storage form (not --steps)")
+    ap.add_argument("--batch-steps", type=int, default=2000, help="batch leg: steps of each of the 64 ducts")
+    ap.add_argument("--serve-requests", type=int, default=20,
+                    help="serving leg of the default run: requests of the seeded trace (bounded so that the "
+                         "whole run stays within a few minutes; --form serve --requests N for longer traces)")
+    ap.add_argument("--legs", default="precision,batch,serve",
+                    help="systems forms measured after the roofline run and reported under 'forms' "
+                         "(comma list of precision, batch, serve; empty: none)")
     ap.add_argument("--serve-fill", type=int, default=0,
-                    help="serve form: nodes a chunk steps at least (shortest remaining work first; 0: one job)")
+                    help="serve form: requests below this many nodes share their lane's launches up to it "
+                         "(shortest remaining work first; 0: one request per lane)")
+    ap.add_argument("--serve-lanes", type=int, default=4,
+                    help="serve form: lanes (concurrent chunk streams) of the batch runtime")
     args = ap.parse_args()
 
     if args.ingest_counters:
@@ -344,7 +370,12 @@ def main():
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
-        out = {"precision": form_precision, "batch": form_batch, "serve": form_serve}[args.form](args)
+        if args.form == "precision":
+            out = form_precision(args, args.precision_steps)
+        elif args.form == "batch":
+            out = form_batch(args, args.batch_steps)
+        else:
+            out = form_serve(args, args.requests)
         print(json.dumps(out), flush=True)
         return
 
@@ -465,7 +496,52 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)
+    legs = [x for x in args.legs.split(",") if x]
+    if legs:
+        out["forms"] = run_legs(args, legs)
     print(json.dumps(out), flush=True)
+
+
+def run_legs(args, legs):
+    """The systems forms beside the roofline run, each with its configured
+    size (independent of --steps): the storage-precision gate on the
+    512x256x256 duct (20000 steps), the 64-duct batch (2000 steps each) and a
+    bounded serving trace.  A leg that fails reports its error instead of
+    ending the run."""
+    import torch
+
+    forms = {}
+    for leg in legs:
+        t0 = time.perf_counter()
+        try:
+            if leg == "precision":
+                r = form_precision(args, args.precision_steps)
+                res = r["results"]
+                forms[leg] = {
+                    "workload": r["workload"], "steps": r["steps"],
+                    "MLUPS": {k: v["MLUPS"] for k, v in res.items()},
+                    "rel_L2_u_vs_f64": {k: res[k]["rel_L2_u_vs_f64"] for k in ("f32", "f16dev", "f16sr")},
+                    "gate": {"f32_le_1e-5": res["f32"]["rel_L2_u_vs_f64"] <= 1e-5,
+                             "f16sr_le_1e-3": res["f16sr"]["rel_L2_u_vs_f64"] <= 1e-3,
+                             "f16dev_le_1e-3": res["f16dev"]["rel_L2_u_vs_f64"] <= 1e-3},
+                    "f16sr_over_f32_MLUPS": r["f16sr_over_f32_MLUPS"],
+                    "f16_over_f32_MLUPS": r["f16_over_f32_MLUPS"]}
+            elif leg == "batch":
+                r = form_batch(args, args.batch_steps)
+                forms[leg] = {k: r[k] for k in ("lattices", "nodes", "steps_each", "shape", "batched",
+                                                 "sequential_plain", "speedup", "bitwise_equal_to_plain")}
+                forms[leg]["batched"]["GBs"] = round(r["batched"]["MLUPS"] * 152 / 1e3, 1)
+            elif leg == "serve":
+                r = form_serve(args, args.serve_requests)
+                forms[leg] = r
+            else:
+                forms[leg] = {"error": "unknown leg"}
+        except Exception as e:  # reported, not fatal: the roofline line above stands on its own
+            forms[leg] = {"error": f"{type(e).__name__}: {e}"}
+        forms.setdefault(leg, {})["leg_seconds"] = round(time.perf_counter() - t0, 1)
+        print(f"leg {leg} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    return forms
 
 
 if __name__ == "__main__":

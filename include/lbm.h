@@ -54,12 +54,20 @@
  *   LBM_STORE_F32      d_k in float,  arithmetic in double
  *   LBM_STORE_F16_DEV  d_k as half-precision scaled deviations
  *                      h_k = RNE(d_k * 2^8), decoded d_k = h_k * 2^-8,
- *                      arithmetic in float
+ *                      arithmetic in float.  Limit: near a steady state
+ *                      round-to-nearest rounds every node the same way at
+ *                      every step, which acts as a constant forcing; on the
+ *                      512 x 256 x 256 duct after 20000 steps the velocity
+ *                      field is 1.95e-3 (relative L2) from the FP64 form,
+ *                      over a 1e-3 bound.  Use LBM_STORE_F16_DEV_SR for
+ *                      long runs to steady state.
  *   LBM_STORE_F16_DEV_SR  as LBM_STORE_F16_DEV, but each step rounds
  *                      d_k * 2^8 stochastically to one of its two neighbouring
  *                      half values, unbiased; the random bits are a hash of
  *                      (step index, node, population), so results are
- *                      reproducible and the same alone or in a batch
+ *                      reproducible and the same alone or in a batch.  The
+ *                      16-bit form for steady states: 2.2e-4 relative L2 on
+ *                      the same run
  *
  * Errors: every call returns an lbm_status and never aborts.  On failure
  * lbm_last_error() returns a message for the calling thread.  Calls on one
@@ -347,6 +355,9 @@ lbm_status lbm_tune_placement(lbm_lattice *L, int max_buffers, int trial_steps, 
  * Enqueues nrep launches.  Errors: LBM_ERR_ARG, LBM_ERR_HIP. */
 lbm_status lbm_probe(lbm_lattice *L, int kind, int nrep);
 
+/* Lattice size as given at creation.  Errors: LBM_ERR_ARG (NULL). */
+lbm_status lbm_get_size(const lbm_lattice *L, int *nx, int *ny, int *nz);
+
 /* Release the handle and the buffers it allocated.  NULL is a no-op. */
 void lbm_destroy(lbm_lattice *L);
 
@@ -389,10 +400,11 @@ typedef struct {
 typedef enum { LBM_JOB_QUEUED = 0, LBM_JOB_RUNNING = 1, LBM_JOB_DONE = 2 } lbm_job_state;
 
 typedef struct {
-  int state;      /* lbm_job_state */
-  int steps;      /* steps taken (a multiple of 2; chunks and autotune trials) */
-  double delta;   /* convergence measure at the last check (inf before the first) */
-  int converged;  /* 1 if it stopped on delta < tol */
+  int state;        /* lbm_job_state */
+  int steps;        /* steps taken (a multiple of 2; chunks and autotune trials) */
+  double delta;     /* convergence measure at the last check (inf before the first) */
+  int converged;    /* 1 if it stopped on delta < tol */
+  long long nodes;  /* nx*ny*nz: the length of the rho array of lbm_batch_result */
 } lbm_job_status;
 
 /* Device bytes a job occupies while resident: two population buffers and a
@@ -411,10 +423,17 @@ lbm_status lbm_batch_create(size_t hbm_budget_bytes, int chunk_steps, int max_jo
  * LBM_ERR_OOM (the job alone exceeds the budget). */
 lbm_status lbm_batch_submit(lbm_batch *B, const lbm_job *job, int *job_id);
 
-/* Admit queued jobs that fit, run one chunk of steps on every resident job,
- * evaluate delta and retire finished jobs.  Blocks until the chunk is done.
- * n_active / n_queued (may be NULL) receive the counts after the chunk.
- * Errors: LBM_ERR_ARG, LBM_ERR_HIP, LBM_ERR_OOM (staging buffer). */
+/* Admit queued jobs that fit; on every idle lane (lbm_batch_set_lanes) start
+ * a chunk of chunk_steps steps of the resident jobs the policy gives it (jobs
+ * in flight on another lane are not eligible); block until at least one
+ * lane's chunk has completed; for each completed chunk evaluate delta and
+ * retire the finished jobs (their moments are on the host when the call
+ * returns).  Chunks of other lanes may still be running on the device when
+ * the call returns: the next call starts new chunks beside them.  With one
+ * lane (the default) a call runs exactly one chunk.  n_active / n_queued (may
+ * be NULL) receive the resident and queued counts at return.
+ * Errors: LBM_ERR_ARG, LBM_ERR_HIP, LBM_ERR_OOM (host memory for results,
+ * tile tables). */
 lbm_status lbm_batch_run_chunk(lbm_batch *B, int *n_active, int *n_queued);
 
 /* Status of a job.  Errors: LBM_ERR_ARG (unknown id). */
@@ -430,21 +449,25 @@ lbm_status lbm_batch_result(lbm_batch *B, int job_id, double *rho, double *u);
  * compute unit).  Any shape gives the same results. */
 lbm_status lbm_batch_set_shape(lbm_batch *B, int block_x, int tile_nodes, int grid_blocks);
 
-/* Which resident jobs a chunk steps:
+/* Which resident jobs a chunk steps (with one lane; lbm_batch_set_lanes
+ * gives the rule for several):
  *   LBM_BATCH_LOCKSTEP        all of them (the default): every resident job
  *                             advances chunk_steps steps per chunk;
- *   LBM_BATCH_SHORTEST_FIRST  the jobs with the least remaining work (nodes
- *                             times the steps left to max_steps) until at
- *                             least fill_nodes nodes are chosen, plus any job
- *                             left out for 50 chunks in a row.  Small jobs
- *                             then step at their own pace instead of a large
- *                             co-resident job's; the others wait, resident.
+ *   LBM_BATCH_SHORTEST_FIRST  the job with the least remaining work (nodes
+ *                             times the steps left to max_steps) and, if it
+ *                             has fewer than fill_nodes nodes, the next ones
+ *                             below fill_nodes until at least fill_nodes
+ *                             nodes are chosen; every job left out for 50
+ *                             scheduling rounds in a row is added.  Small
+ *                             jobs then step at their own pace instead of a
+ *                             large co-resident job's; the others wait,
+ *                             resident.
  * A job's results do not depend on the policy (only when its steps run).
- * Set the policy before submitting: with LBM_BATCH_SHORTEST_FIRST and
- * fill_nodes 0, jobs submitted afterwards are stored row-major with padded
- * rows and a chunk that steps a single row-major job runs the single-lattice
- * sweep on it.  lbm_job_bytes gives the bytes of the lockstep layout.
- * lbm_batch_autotune steps every resident job whatever the policy.
+ * Set the policy before submitting: with LBM_BATCH_SHORTEST_FIRST, jobs of
+ * at least fill_nodes nodes submitted afterwards are stored row-major with
+ * padded rows, and a chunk that steps a single row-major job runs the
+ * single-lattice sweep on it.  lbm_job_bytes gives the bytes of the lockstep
+ * layout.  lbm_batch_autotune steps every resident job whatever the policy.
  * Errors: LBM_ERR_ARG (NULL, unknown policy). */
 enum { LBM_BATCH_LOCKSTEP = 0, LBM_BATCH_SHORTEST_FIRST = 1 };
 lbm_status lbm_batch_set_policy(lbm_batch *B, int policy, size_t fill_nodes);
@@ -461,6 +484,42 @@ lbm_status lbm_batch_autotune(lbm_batch *B, int trial_steps, int *block_x, int *
 
 /* Bytes of the pool in use and in total.  Errors: LBM_ERR_ARG. */
 lbm_status lbm_batch_memory(const lbm_batch *B, size_t *used, size_t *capacity);
+
+/* Lanes: independent streams of one batch that run chunks at the same time
+ * on the device, all sharing the batch's HBM pool.  A lane's chunk steps its
+ * group of jobs (one launch sequence: the multi-lattice sweep, or the
+ * single-lattice sweep for one row-major job); groups are formed from the
+ * jobs not in flight whenever a lane is idle:
+ *   LBM_BATCH_LOCKSTEP        every such job, spread over the idle lanes
+ *                             (largest first, each to the lane with the
+ *                             fewest nodes so far);
+ *   LBM_BATCH_SHORTEST_FIRST  in order of remaining work, one job per idle
+ *                             lane; a job below fill_nodes nodes takes
+ *                             further jobs below fill_nodes into its lane's
+ *                             launch until it holds fill_nodes nodes.
+ * So a request that arrives while others are on the GPU starts at once on
+ * an idle lane, and its steps overlap theirs on the device, instead of
+ * waiting for them.  1 <= lanes <= 8 (1: the default, one chunk at a time;
+ * lane 0 runs on the batch's stream, the others on streams the batch
+ * creates, all at the default priority).  Each lane holds a small
+ * descriptor table and page-locked staging.  Results do not depend on the
+ * lanes.  Errors: LBM_ERR_ARG (NULL, out of range), LBM_ERR_STATE (a chunk
+ * in flight), LBM_ERR_OOM, LBM_ERR_HIP. */
+lbm_status lbm_batch_set_lanes(lbm_batch *B, int lanes);
+
+/* What the batch has run so far (counts since creation). */
+typedef struct {
+  int lanes;                   /* lanes configured now */
+  long long chunks;            /* chunks started (on any lane) */
+  long long job_chunks;        /* sum over chunks of the jobs each stepped */
+  long long multi_job_chunks;  /* chunks whose launches stepped two or more jobs */
+  int max_jobs_in_chunk;       /* most jobs one chunk stepped */
+  long long overlapped_chunks; /* chunks started while another lane's chunk was still running on the device */
+  int max_lanes_running;       /* most lanes with a chunk running on the device at one chunk start */
+} lbm_batch_stats;
+
+/* Copy the counts into *stats.  Errors: LBM_ERR_ARG (NULL). */
+lbm_status lbm_batch_get_stats(const lbm_batch *B, lbm_batch_stats *stats);
 
 /* Release the batch, its pool and every job.  NULL is a no-op. */
 void lbm_batch_destroy(lbm_batch *B);

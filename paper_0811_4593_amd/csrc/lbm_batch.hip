@@ -18,6 +18,7 @@
 #include <map>
 #include <new>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "../../include/lbm.h"
@@ -232,7 +233,8 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr int kNumStorage = 4;
 constexpr int kMinTileNodes = 256;
-constexpr size_t kStageNodes = size_t(1) << 22;
+constexpr int kMaxLanes = 8;
+constexpr size_t kResultCacheBytes = size_t(4) << 30;  // page-locked result blocks kept for reuse
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -307,36 +309,37 @@ size_t job_bytes(const lbm_job &j, int layout) {
          align_up(3 * N * sizeof(float));
 }
 
-// Host memory for a retired job's moments, rho [N] then u [3][N].  Pinned
-// (page-locked) when the runtime grants it: a device-to-host copy into fresh
-// pageable memory runs at about 4 GB/s on this host, page faults included,
-// into a fresh pinned allocation at about 40 GB/s.  Pageable otherwise.
-class HostResult {
+// Host memory block, page-locked when the runtime grants it (a
+// device-to-host copy into fresh pageable memory runs at about 4 GB/s on this
+// host, page faults included, into page-locked memory at about 40 GB/s),
+// pageable otherwise.
+class HostBlock {
  public:
-  HostResult() = default;
-  HostResult(const HostResult &) = delete;
-  HostResult &operator=(const HostResult &) = delete;
-  HostResult(HostResult &&o) noexcept : p_(o.p_), n_(o.n_), pinned_(o.pinned_) { o.p_ = nullptr, o.n_ = 0; }
-  HostResult &operator=(HostResult &&o) noexcept {
+  HostBlock() = default;
+  HostBlock(const HostBlock &) = delete;
+  HostBlock &operator=(const HostBlock &) = delete;
+  HostBlock(HostBlock &&o) noexcept : p_(o.p_), bytes_(o.bytes_), pinned_(o.pinned_) { o.p_ = nullptr, o.bytes_ = 0; }
+  HostBlock &operator=(HostBlock &&o) noexcept {
     if (this != &o) {
       release();
-      p_ = o.p_, n_ = o.n_, pinned_ = o.pinned_;
-      o.p_ = nullptr, o.n_ = 0;
+      p_ = o.p_, bytes_ = o.bytes_, pinned_ = o.pinned_;
+      o.p_ = nullptr, o.bytes_ = 0;
     }
     return *this;
   }
-  ~HostResult() { release(); }
-  bool allocate(size_t count) {
+  ~HostBlock() { release(); }
+  bool allocate(size_t bytes, bool need_pinned = false) {
     release();
     void *p = nullptr;
-    pinned_ = hipHostMalloc(&p, count * sizeof(double), hipHostMallocDefault) == hipSuccess;
+    pinned_ = hipHostMalloc(&p, bytes, hipHostMallocDefault) == hipSuccess;
     if (!pinned_) {
       (void)hipGetLastError();
-      p = new (std::nothrow) double[count];
+      if (need_pinned) return false;
+      p = ::operator new(bytes, std::nothrow);
       if (!p) return false;
     }
-    p_ = static_cast<double *>(p);
-    n_ = count;
+    p_ = p;
+    bytes_ = bytes;
     return true;
   }
   void release() {
@@ -344,33 +347,38 @@ class HostResult {
       if (pinned_)
         (void)hipHostFree(p_);
       else
-        delete[] p_;
+        ::operator delete(p_);
     }
     p_ = nullptr;
-    n_ = 0;
+    bytes_ = 0;
   }
-  double *data() const { return p_; }
-  size_t size() const { return n_; }
+  template <class T>
+  T *as() const {
+    return static_cast<T *>(p_);
+  }
+  size_t bytes() const { return bytes_; }
 
  private:
-  double *p_ = nullptr;
-  size_t n_ = 0;
+  void *p_ = nullptr;
+  size_t bytes_ = 0;
   bool pinned_ = false;
 };
 
 struct Job {
   lbm_job spec;
+  size_t nodes = 0;
   int state = LBM_JOB_QUEUED;
   int slot = -1;
+  int lane = -1;  // lane whose chunk in flight steps this job, or -1
   size_t off = 0, bytes = 0;
   int steps = 0;
   double delta = INFINITY;
   int converged = 0;
   int waited = 0;   // chunks spent at the head of the queue without fitting
-  int skipped = 0;  // consecutive chunks resident but not stepped
+  int skipped = 0;  // consecutive scheduling rounds resident, idle and not stepped
   int layout = LBM_LAYOUT_POPULATION_MAJOR;  // chosen at submission
   lbm::SweepConfig cfg{};                    // single-lattice sweep of the job (set at admission)
-  HostResult result;  // moments at retirement: rho [N], then u [3][N]
+  HostBlock result;  // moments at retirement: rho [N], then u [3][N], in double
 };
 
 struct Shape {
@@ -383,90 +391,179 @@ struct Shape {
 std::map<long long, Shape> g_tuned;
 std::mutex g_tuned_mutex;
 
+// One lane: a stream with its own descriptor and tile tables, so that the
+// chunks of different lanes run on the device at the same time.  Host-side
+// staging of the tables and of the convergence maxima is page-locked; it is
+// written only while the lane is idle (its previous chunk, including these
+// copies, has completed).
+struct Lane {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  hipEvent_t done = nullptr;
+  bool busy = false;
+  std::vector<int> slots;  // slots the chunk in flight steps
+  lbm::BatchLat *d_lats = nullptr;
+  unsigned *d_delta = nullptr;
+  int *d_ntiles = nullptr;
+  lbm::BatchTile *d_tiles[kNumStorage] = {nullptr, nullptr, nullptr, nullptr};
+  size_t tile_cap[kNumStorage] = {0, 0, 0, 0};
+  HostBlock h_lats, h_delta, h_ntiles, h_tiles[kNumStorage];
+  int ntiles[kNumStorage] = {0, 0, 0, 0};
+  // Jobs (slot, job id) the tile tables describe: a slot reused by a later
+  // job has other extents, so the tables follow the job ids, not the slots.
+  std::vector<std::pair<int, int>> table_jobs;
+  int table_tile_nodes = 0;
+  std::map<long long, hipGraphExec_t> graphs;
+};
+
 }  // namespace
 
 struct lbm_batch {
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
+  hipStream_t user_stream = nullptr;
   int num_cu = 256;
   char *pool_base = nullptr;
   Pool pool;
   int chunk_steps = 100;
   int max_jobs = 0;
   Shape shape;
-  bool tiles_dirty = true;
   std::map<int, Job> jobs;
   std::deque<int> queue;
-  std::vector<int> slot_job;  // slot -> job id (-1 free)
+  std::vector<int> slot_job;           // slot -> job id (-1 free)
+  std::vector<lbm::BatchLat> lat;      // slot -> descriptor (step_base set at upload)
   int next_id = 1;
-  // device tables
-  lbm::BatchLat *d_lats = nullptr;
-  lbm::BatchTile *d_tiles[kNumStorage] = {nullptr, nullptr, nullptr, nullptr};
-  int *d_ntiles = nullptr;
-  unsigned *d_delta = nullptr;
-  size_t tile_cap = 0;
-  std::vector<lbm::BatchLat> h_lats;
-  std::vector<lbm::BatchTile> h_tiles[kNumStorage];
-  int h_ntiles[kNumStorage] = {0, 0, 0, 0};
-  std::vector<unsigned> h_delta;
-  double *d_stage = nullptr;
-  std::map<long long, hipGraphExec_t> graphs;
   int policy = LBM_BATCH_LOCKSTEP;  // which resident jobs a chunk steps
   size_t fill_nodes = 0;            // LBM_BATCH_SHORTEST_FIRST: nodes a chunk steps at least
-  std::vector<char> run_slot;       // slot -> stepped by the current chunk
+  std::vector<Lane> lanes;
+  std::vector<HostBlock> result_cache;  // released result blocks, reused by later retirements
+  size_t result_cache_bytes = 0;
+  lbm_batch_stats stats{};
+  // Admitted jobs are initialised on a stream of their own, so that a new
+  // job does not wait behind a chunk in flight; every chunk waits for the
+  // initialisations enqueued before it.
+  hipStream_t init_stream = nullptr;
+  hipEvent_t init_done = nullptr;
+  bool init_recorded = false;
 };
 
 namespace {
 
-unsigned present_mask(const lbm_batch *B) {
-  unsigned m = 0;
+void drop_graphs(Lane &ln) {
+  for (auto &kv : ln.graphs) (void)hipGraphExecDestroy(kv.second);
+  ln.graphs.clear();
+}
+
+void free_lane(Lane &ln) {
+  if (ln.stream) (void)hipStreamSynchronize(ln.stream);
+  drop_graphs(ln);
+  if (ln.d_lats) (void)hipFree(ln.d_lats);
+  if (ln.d_delta) (void)hipFree(ln.d_delta);
+  if (ln.d_ntiles) (void)hipFree(ln.d_ntiles);
   for (int s = 0; s < kNumStorage; ++s)
-    if (B->h_ntiles[s] > 0) m |= 1u << s;
-  return m;
+    if (ln.d_tiles[s]) (void)hipFree(ln.d_tiles[s]);
+  if (ln.done) (void)hipEventDestroy(ln.done);
+  if (ln.own_stream && ln.stream) (void)hipStreamDestroy(ln.stream);
+  ln = Lane();
 }
 
-void drop_graphs(lbm_batch *B) {
-  for (auto &kv : B->graphs) (void)hipGraphExecDestroy(kv.second);
-  B->graphs.clear();
-}
-
-// Refresh every resident lattice's step_base and upload the descriptors.
-lbm_status upload_lats(lbm_batch *B) {
-  for (int slot = 0; slot < B->max_jobs; ++slot) {
-    const int id = B->slot_job[slot];
-    if (id >= 0) B->h_lats[slot].step_base = unsigned(B->jobs[id].steps);
+lbm_status init_lane(lbm_batch *B, Lane &ln, hipStream_t given) {
+  if (given) {
+    ln.stream = given;
+  } else {
+    // Graph capture needs a stream other than the null stream; every stream
+    // keeps the default priority.
+    LBM_BHIP(hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking), "stream creation");
+    ln.own_stream = true;
   }
-  LBM_BHIP(hipMemcpyAsync(B->d_lats, B->h_lats.data(), B->h_lats.size() * sizeof(lbm::BatchLat),
-                          hipMemcpyHostToDevice, B->stream),
-           "upload lattices");
-  // The host vector must stay untouched until the copy has run.
-  LBM_BHIP(hipStreamSynchronize(B->stream), "upload");
+  LBM_BHIP(hipEventCreateWithFlags(&ln.done, hipEventDisableTiming), "event creation");
+  const size_t mj = size_t(B->max_jobs);
+  bool ok = hipMalloc(&ln.d_lats, sizeof(lbm::BatchLat) * mj) == hipSuccess &&
+            hipMalloc(&ln.d_delta, sizeof(unsigned) * mj) == hipSuccess &&
+            hipMalloc(&ln.d_ntiles, sizeof(int) * kNumStorage) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    return bfail(LBM_ERR_OOM, "device tables of a lane could not be allocated");
+  }
+  if (!ln.h_lats.allocate(sizeof(lbm::BatchLat) * mj, true) || !ln.h_delta.allocate(sizeof(unsigned) * mj, true) ||
+      !ln.h_ntiles.allocate(sizeof(int) * kNumStorage, true))
+    return bfail(LBM_ERR_OOM, "page-locked staging of a lane could not be allocated");
+  std::memset(ln.h_lats.as<void>(), 0, ln.h_lats.bytes());
   return LBM_OK;
 }
 
-lbm_status rebuild_tiles(lbm_batch *B) {
-  for (int s = 0; s < kNumStorage; ++s) B->h_tiles[s].clear();
-  const unsigned tn = unsigned(B->shape.tile_nodes);
-  for (int slot = 0; slot < B->max_jobs; ++slot) {
-    const int id = B->slot_job[slot];
-    if (id < 0 || !B->run_slot[slot]) continue;
-    const Job &J = B->jobs[id];
-    const unsigned S = unsigned(size_t(B->h_lats[slot].slot_row) * J.spec.ny * J.spec.nz);  // slots
-    for (unsigned n0 = 0; n0 < S; n0 += tn) B->h_tiles[J.spec.storage].push_back({slot, n0, std::min(S, n0 + tn)});
+// Room for n tiles of storage form s in a lane's tables.  A new device
+// table invalidates the lane's captured graphs (their launches hold the old
+// address).  Only called while the lane is idle.
+lbm_status ensure_tiles(Lane &ln, int s, size_t n) {
+  if (n <= ln.tile_cap[s]) return LBM_OK;
+  size_t cap = std::max<size_t>(n, 2 * ln.tile_cap[s]);
+  cap = std::max<size_t>(cap, 1024);
+  drop_graphs(ln);
+  if (ln.d_tiles[s]) (void)hipFree(ln.d_tiles[s]);
+  ln.d_tiles[s] = nullptr;
+  ln.tile_cap[s] = 0;
+  if (hipMalloc(&ln.d_tiles[s], sizeof(lbm::BatchTile) * cap) != hipSuccess) {
+    (void)hipGetLastError();
+    ln.d_tiles[s] = nullptr;
+    return bfail(LBM_ERR_OOM, "tile table of %zu entries could not be allocated", cap);
   }
-  for (int s = 0; s < kNumStorage; ++s) {
-    if (B->h_tiles[s].size() > B->tile_cap) return bfail(LBM_ERR_STATE, "tile list exceeds its capacity");
-    B->h_ntiles[s] = int(B->h_tiles[s].size());
-    if (!B->h_tiles[s].empty())
-      LBM_BHIP(hipMemcpyAsync(B->d_tiles[s], B->h_tiles[s].data(), B->h_tiles[s].size() * sizeof(lbm::BatchTile),
-                              hipMemcpyHostToDevice, B->stream),
-               "upload tiles");
+  if (!ln.h_tiles[s].allocate(sizeof(lbm::BatchTile) * cap, true))
+    return bfail(LBM_ERR_OOM, "page-locked tile staging of %zu entries could not be allocated", cap);
+  ln.tile_cap[s] = cap;
+  return LBM_OK;
+}
+
+unsigned present_mask(const Lane &ln) {
+  unsigned m = 0;
+  for (int s = 0; s < kNumStorage; ++s)
+    if (ln.ntiles[s] > 0) m |= 1u << s;
+  return m;
+}
+
+// Tables of a lane for the jobs in `slots`: the descriptors (with the step
+// counts as step_base) always, the tile lists when the job set or the tile
+// size changed.  Asynchronous copies from page-locked staging on the lane's
+// stream; the lane is idle.
+lbm_status upload_tables(lbm_batch *B, Lane &ln, const std::vector<int> &slots) {
+  std::vector<std::pair<int, int>> jobs;
+  for (int slot : slots) jobs.push_back({slot, B->slot_job[slot]});
+  if (jobs != ln.table_jobs || ln.table_tile_nodes != B->shape.tile_nodes) {
+    std::vector<lbm::BatchTile> tiles[kNumStorage];
+    const unsigned tn = unsigned(B->shape.tile_nodes);
+    for (int slot : slots) {
+      const Job &J = B->jobs.at(B->slot_job[slot]);
+      const unsigned S = unsigned(size_t(B->lat[slot].slot_row) * J.spec.ny * J.spec.nz);  // slots of the job
+      for (unsigned n0 = 0; n0 < S; n0 += tn) tiles[J.spec.storage].push_back({slot, n0, std::min(S, n0 + tn)});
+    }
+    for (int s = 0; s < kNumStorage; ++s) {
+      lbm_status st = ensure_tiles(ln, s, tiles[s].size());
+      if (st != LBM_OK) return st;
+      ln.ntiles[s] = int(tiles[s].size());
+      if (!tiles[s].empty()) {
+        std::memcpy(ln.h_tiles[s].as<void>(), tiles[s].data(), tiles[s].size() * sizeof(lbm::BatchTile));
+        LBM_BHIP(hipMemcpyAsync(ln.d_tiles[s], ln.h_tiles[s].as<void>(), tiles[s].size() * sizeof(lbm::BatchTile),
+                                hipMemcpyHostToDevice, ln.stream),
+                 "upload tiles");
+      }
+      ln.h_ntiles.as<int>()[s] = ln.ntiles[s];
+    }
+    LBM_BHIP(hipMemcpyAsync(ln.d_ntiles, ln.h_ntiles.as<void>(), sizeof(int) * kNumStorage, hipMemcpyHostToDevice,
+                            ln.stream),
+             "upload tile counts");
+    ln.table_jobs = jobs;
+    ln.table_tile_nodes = B->shape.tile_nodes;
   }
-  LBM_BHIP(hipMemcpyAsync(B->d_ntiles, B->h_ntiles, sizeof(B->h_ntiles), hipMemcpyHostToDevice, B->stream),
-           "upload tile counts");
-  lbm_status st = upload_lats(B);
-  if (st != LBM_OK) return st;
-  B->tiles_dirty = false;
+  lbm::BatchLat *h = ln.h_lats.as<lbm::BatchLat>();
+  int lo = B->max_jobs, hi = -1;
+  for (int slot : slots) {
+    h[slot] = B->lat[slot];
+    h[slot].step_base = unsigned(B->jobs.at(B->slot_job[slot]).steps);
+    lo = std::min(lo, slot);
+    hi = std::max(hi, slot);
+  }
+  if (hi >= lo)
+    LBM_BHIP(hipMemcpyAsync(ln.d_lats + lo, h + lo, sizeof(lbm::BatchLat) * size_t(hi - lo + 1),
+                            hipMemcpyHostToDevice, ln.stream),
+             "upload lattices");
   return LBM_OK;
 }
 
@@ -475,13 +572,13 @@ int grid_of(const lbm_batch *B) { return B->shape.grid > 0 ? B->shape.grid : 8 *
 // Enqueue nsteps steps with indices first..first+nsteps-1 of a sequence that
 // starts at each lattice's step_base (first and nsteps even keep the state in
 // buf[0] at the end).
-lbm_status launch_steps(lbm_batch *B, int nsteps, int first) {
+lbm_status launch_steps(lbm_batch *B, Lane &ln, int nsteps, int first) {
   const int grid = grid_of(B);
   for (int st = first; st < first + nsteps; ++st)
     for (int s = 0; s < kNumStorage; ++s)
-      if (B->h_ntiles[s] > 0)
-        LBM_BHIP(lbm::launch_batch_sweep(s, B->shape.block_x, B->d_lats, B->d_tiles[s], B->d_ntiles + s, st, grid,
-                                         B->stream),
+      if (ln.ntiles[s] > 0)
+        LBM_BHIP(lbm::launch_batch_sweep(s, B->shape.block_x, ln.d_lats, ln.d_tiles[s], ln.d_ntiles + s, st, grid,
+                                         ln.stream),
                  "batch sweep launch");
   return LBM_OK;
 }
@@ -489,78 +586,87 @@ lbm_status launch_steps(lbm_batch *B, int nsteps, int first) {
 // A chunk that steps a single job: plain launches of the single-lattice
 // sweep on the job's buffers (row-aligned blocks; bitwise the batch sweep's
 // results), one per step, each with the job's own step index.
-lbm_status run_solo_chunk(lbm_batch *B, int slot) {
-  const Job &J = B->jobs[B->slot_job[slot]];
-  const lbm::BatchLat &L = B->h_lats[slot];
+lbm_status run_solo_chunk(lbm_batch *B, Lane &ln, int slot) {
+  const Job &J = B->jobs.at(B->slot_job[slot]);
+  const lbm::BatchLat &L = B->lat[slot];
   lbm::SweepConfig c = J.cfg;
   for (int s = 0; s < B->chunk_steps; ++s) {
     c.step = unsigned(J.steps + s);
-    LBM_BHIP(lbm::launch_sweep(c, L.buf[s & 1], L.buf[(s & 1) ^ 1], false, B->stream), "sweep launch");
+    LBM_BHIP(lbm::launch_sweep(c, L.buf[s & 1], L.buf[(s & 1) ^ 1], false, ln.stream), "sweep launch");
   }
   return LBM_OK;
 }
 
-lbm_status run_graph_chunk(lbm_batch *B) {
-  const unsigned mask = present_mask(B);
+lbm_status run_graph_chunk(lbm_batch *B, Lane &ln) {
+  const unsigned mask = present_mask(ln);
   if (!mask) return LBM_OK;
   const long long key = (long long)mask | ((long long)B->chunk_steps << 8) | ((long long)B->shape.block_x << 24) |
                         ((long long)grid_of(B) << 36);
-  auto it = B->graphs.find(key);
-  if (it == B->graphs.end()) {
+  auto it = ln.graphs.find(key);
+  if (it == ln.graphs.end()) {
     hipGraph_t graph;
-    LBM_BHIP(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal), "begin capture");
-    lbm_status st = launch_steps(B, B->chunk_steps, 0);
-    hipError_t e = hipStreamEndCapture(B->stream, &graph);
+    LBM_BHIP(hipStreamBeginCapture(ln.stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    lbm_status st = launch_steps(B, ln, B->chunk_steps, 0);
+    hipError_t e = hipStreamEndCapture(ln.stream, &graph);
     if (st != LBM_OK) return st;
     if (e != hipSuccess) return bfail(LBM_ERR_HIP, "end capture: %s", hipGetErrorString(e));
     hipGraphExec_t exec;
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return bfail(LBM_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
-    it = B->graphs.emplace(key, exec).first;
+    it = ln.graphs.emplace(key, exec).first;
   }
-  LBM_BHIP(hipGraphLaunch(it->second, B->stream), "graph launch");
+  LBM_BHIP(hipGraphLaunch(it->second, ln.stream), "graph launch");
   return LBM_OK;
 }
 
-lbm_status ensure_stage(lbm_batch *B) {
-  if (B->d_stage) return LBM_OK;
-  hipError_t e = hipMalloc(&B->d_stage, sizeof(double) * 4 * kStageNodes);
-  if (e != hipSuccess) {
-    B->d_stage = nullptr;
-    return bfail(LBM_ERR_OOM, "staging buffer: %s", hipGetErrorString(e));
+// Host block for a retiring job's moments: a cached block large enough, else
+// a new one.
+bool take_result_block(lbm_batch *B, HostBlock &out, size_t bytes) {
+  int best = -1;
+  for (int i = 0; i < int(B->result_cache.size()); ++i)
+    if (B->result_cache[i].bytes() >= bytes &&
+        (best < 0 || B->result_cache[i].bytes() < B->result_cache[best].bytes()))
+      best = i;
+  if (best >= 0) {
+    B->result_cache_bytes -= B->result_cache[best].bytes();
+    out = std::move(B->result_cache[best]);
+    B->result_cache.erase(B->result_cache.begin() + best);
+    return true;
   }
-  return LBM_OK;
+  return out.allocate(bytes);
 }
 
-// Moments of a finished job into host memory, then release its device memory.
-lbm_status retire(lbm_batch *B, int id) {
-  Job &J = B->jobs[id];
-  lbm_status st = ensure_stage(B);
-  if (st != LBM_OK) return st;
-  const size_t N = size_t(J.spec.nx) * J.spec.ny * J.spec.nz;
-  if (!J.result.allocate(4 * N)) return bfail(LBM_ERR_OOM, "host memory for the moments of job %d", id);
-  double *rho_h = J.result.data(), *u_h = J.result.data() + N;
-  const void *f = B->h_lats[J.slot].buf[0];
-  for (size_t n0 = 0; n0 < N; n0 += kStageNodes) {
-    const size_t cnt = std::min(kStageNodes, N - n0);
-    double *dr = B->d_stage, *du = B->d_stage + cnt;
-    LBM_BHIP(lbm::launch_moments(J.spec.storage, f, layout_of(J.layout, N, J.spec.nx, lbm_element_bytes(J.spec.storage)),
-                                 n0, cnt, dr, du, nullptr, 1024, B->stream),
-             "moments");
-    LBM_BHIP(hipMemcpyAsync(rho_h + n0, dr, cnt * sizeof(double), hipMemcpyDeviceToHost, B->stream), "copy");
-    for (int a = 0; a < 3; ++a)
-      LBM_BHIP(hipMemcpyAsync(u_h + a * N + n0, du + a * cnt, cnt * sizeof(double), hipMemcpyDeviceToHost,
-                              B->stream),
-               "copy");
-    LBM_BHIP(hipStreamSynchronize(B->stream), "moments");
-  }
+void give_back_result_block(lbm_batch *B, HostBlock &&blk) {
+  if (!blk.bytes()) return;
+  if (B->result_cache_bytes + blk.bytes() > kResultCacheBytes) return;  // freed with blk
+  B->result_cache_bytes += blk.bytes();
+  B->result_cache.push_back(std::move(blk));
+}
+
+// Moments of a finished job into host memory, then release its device
+// memory.  The moments are written in double (rho [N], then u [3][N]) into
+// the job's idle population buffer (it holds at least 38 N bytes), then
+// copied to the host.  Synchronizes the lane's stream.
+lbm_status retire(lbm_batch *B, int id, Lane &ln) {
+  Job &J = B->jobs.at(id);
+  const size_t N = J.nodes;
+  if (!take_result_block(B, J.result, 4 * N * sizeof(double)))
+    return bfail(LBM_ERR_OOM, "host memory for the moments of job %d", id);
+  const lbm::BatchLat &L = B->lat[J.slot];
+  double *scratch = static_cast<double *>(L.buf[1]);
+  LBM_BHIP(lbm::launch_moments(J.spec.storage, L.buf[0],
+                               layout_of(J.layout, N, J.spec.nx, lbm_element_bytes(J.spec.storage)), 0, N, scratch,
+                               scratch + N, nullptr, 1024, ln.stream),
+           "moments");
+  LBM_BHIP(hipMemcpyAsync(J.result.as<void>(), scratch, 4 * N * sizeof(double), hipMemcpyDeviceToHost, ln.stream),
+           "copy moments");
+  LBM_BHIP(hipStreamSynchronize(ln.stream), "moments");
   B->pool.release(J.off, J.bytes);
   B->slot_job[J.slot] = -1;
-  std::memset(&B->h_lats[J.slot], 0, sizeof(lbm::BatchLat));
+  std::memset(&B->lat[J.slot], 0, sizeof(lbm::BatchLat));
   J.slot = -1;
   J.state = LBM_JOB_DONE;
-  B->tiles_dirty = true;
   return LBM_OK;
 }
 
@@ -570,7 +676,7 @@ lbm_status retire(lbm_batch *B, int id) {
 lbm_status admit(lbm_batch *B) {
   bool head_blocked = false;
   for (auto it = B->queue.begin(); it != B->queue.end();) {
-    Job &J = B->jobs[*it];
+    Job &J = B->jobs.at(*it);
     int slot = -1;
     for (int s = 0; s < B->max_jobs; ++s)
       if (B->slot_job[s] < 0) {
@@ -587,7 +693,7 @@ lbm_status admit(lbm_batch *B) {
       ++it;
       continue;
     }
-    const size_t N = size_t(J.spec.nx) * J.spec.ny * J.spec.nz;
+    const size_t N = J.nodes;
     const size_t esize = lbm_element_bytes(J.spec.storage);
     const size_t elems = lbm::buffer_elements(J.layout, J.spec.nx, J.spec.ny, J.spec.nz, esize);
     const size_t buf_bytes = align_up(elems * esize);
@@ -636,63 +742,214 @@ lbm_status admit(lbm_batch *B) {
     c.block_x = lbm::default_block_x(J.spec.nx);
     c.nodes_per_thread = 1;
     c.xcd_remap = LBM_XCD_SLABS;
-    B->h_lats[slot] = L;
+    B->lat[slot] = L;
     B->slot_job[slot] = *it;
     const double zero[3] = {0.0, 0.0, 0.0};
-    LBM_BHIP(lbm::launch_init(J.spec.storage, L.buf[0], N, lay, J.spec.rho0, zero, B->stream), "init launch");
+    LBM_BHIP(lbm::launch_init(J.spec.storage, L.buf[0], N, lay, J.spec.rho0, zero, B->init_stream), "init launch");
     const size_t n3 = 3 * N;
-    lbm::fill_float_kernel<<<dim3(unsigned((n3 + 255) / 256)), dim3(256), 0, B->stream>>>(L.snap, n3, 0.0f);
+    lbm::fill_float_kernel<<<dim3(unsigned((n3 + 255) / 256)), dim3(256), 0, B->init_stream>>>(L.snap, n3, 0.0f);
     LBM_BHIP(hipGetLastError(), "snapshot fill");
+    LBM_BHIP(hipEventRecord(B->init_done, B->init_stream), "event");
+    B->init_recorded = true;
     J.off = off;
     J.slot = slot;
     J.state = LBM_JOB_RUNNING;
-    B->tiles_dirty = true;
     it = B->queue.erase(it);
   }
   return LBM_OK;
 }
 
-// Choose the resident jobs the next chunk steps; the tile list is rebuilt
-// when the choice changes.  Lockstep: all of them.  Shortest first: every
-// job skipped for kMaxSkipped chunks in a row, then the others in order of
-// remaining work (nodes x steps left to max_steps, ties by slot) until at
-// least fill_nodes nodes are chosen -- small jobs then run at their own step
-// time instead of a large co-resident job's, and a large job waits, but not
-// for ever.
+double job_nodes(const Job &J) { return double(J.nodes); }
+
+// Resident jobs not in flight, grouped for the idle lanes.
+//   Lockstep: all of them; with several idle lanes, each job (largest first)
+//   goes to the lane with the fewest nodes so far.
+//   Shortest first: jobs left out for kMaxSkipped rounds, then the others in
+//   order of remaining work (nodes x steps left to max_steps, ties by slot).
+//   Each idle lane takes the next job; a job below fill_nodes nodes takes
+//   further jobs below fill_nodes with it until the lane holds fill_nodes
+//   nodes.  The rest wait, resident.  Small jobs then step at their own pace
+//   instead of a large co-resident job's, and a large job waits, but not for
+//   ever.
 constexpr int kMaxSkipped = 50;
-void select_jobs(lbm_batch *B, bool all) {
-  std::vector<char> next(size_t(B->max_jobs), 0);
-  if (all || B->policy == LBM_BATCH_LOCKSTEP) {
-    for (int slot = 0; slot < B->max_jobs; ++slot) next[slot] = B->slot_job[slot] >= 0;
+std::vector<std::pair<int, std::vector<int>>> plan_chunks(lbm_batch *B) {
+  std::vector<int> idle;
+  for (int l = 0; l < int(B->lanes.size()); ++l)
+    if (!B->lanes[l].busy) idle.push_back(l);
+  std::vector<int> cand;
+  for (int slot = 0; slot < B->max_jobs; ++slot) {
+    const int id = B->slot_job[slot];
+    if (id >= 0 && B->jobs.at(id).lane < 0) cand.push_back(slot);
+  }
+  std::vector<std::pair<int, std::vector<int>>> plan;
+  if (idle.empty() || cand.empty()) return plan;
+  for (int l : idle) plan.push_back({l, {}});
+  auto job_at = [&](int slot) -> Job & { return B->jobs.at(B->slot_job[slot]); };
+  if (B->policy == LBM_BATCH_LOCKSTEP) {
+    std::vector<int> order = cand;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return job_nodes(job_at(a)) > job_nodes(job_at(b)); });
+    std::vector<double> load(plan.size(), 0.0);
+    for (int slot : order) {
+      const size_t g = size_t(std::min_element(load.begin(), load.end()) - load.begin());
+      plan[g].second.push_back(slot);
+      load[g] += job_nodes(job_at(slot));
+    }
   } else {
-    std::vector<std::pair<double, int>> order;
-    for (int slot = 0; slot < B->max_jobs; ++slot) {
-      const int id = B->slot_job[slot];
-      if (id < 0) continue;
-      const Job &J = B->jobs[id];
-      const double nodes = double(J.spec.nx) * J.spec.ny * J.spec.nz;
-      order.push_back({nodes * double(std::max(0, J.spec.max_steps - J.steps)), slot});
+    std::vector<std::pair<std::pair<int, double>, int>> order;  // ((not forced, work), slot)
+    for (int slot : cand) {
+      const Job &J = job_at(slot);
+      const double work = job_nodes(J) * double(std::max(0, J.spec.max_steps - J.steps));
+      order.push_back({{J.skipped >= kMaxSkipped ? 0 : 1, work}, slot});
     }
     std::sort(order.begin(), order.end());
-    double chosen = 0.0;
-    for (const auto &o : order) {
-      const Job &J = B->jobs[B->slot_job[o.second]];
-      if (J.skipped >= kMaxSkipped) {
-        next[o.second] = 1;
-        chosen += double(J.spec.nx) * J.spec.ny * J.spec.nz;
+    const double fill = double(B->fill_nodes);
+    size_t next = 0;
+    for (size_t g = 0; g < plan.size() && next < order.size(); ++g) {
+      std::vector<int> &grp = plan[g].second;
+      double nodes = 0.0;
+      // jobs left out too long all go into the first group
+      while (g == 0 && next < order.size() && order[next].first.first == 0) {
+        grp.push_back(order[next].second);
+        nodes += job_nodes(job_at(order[next].second));
+        ++next;
+      }
+      if (grp.empty()) {
+        grp.push_back(order[next].second);
+        nodes = job_nodes(job_at(order[next].second));
+        ++next;
+        if (nodes >= fill) continue;
+      }
+      while (next < order.size() && nodes < fill && job_nodes(job_at(order[next].second)) < fill) {
+        grp.push_back(order[next].second);
+        nodes += job_nodes(job_at(order[next].second));
+        ++next;
       }
     }
-    for (const auto &o : order) {
-      if (chosen > 0.0 && chosen >= double(B->fill_nodes)) break;
-      if (next[o.second]) continue;
-      const Job &J = B->jobs[B->slot_job[o.second]];
-      next[o.second] = 1;
-      chosen += double(J.spec.nx) * J.spec.ny * J.spec.nz;
+  }
+  std::vector<char> picked(size_t(B->max_jobs), 0);
+  for (auto &p : plan) {
+    std::sort(p.second.begin(), p.second.end());
+    for (int slot : p.second) picked[slot] = 1;
+  }
+  for (int slot : cand) {
+    Job &J = job_at(slot);
+    J.skipped = picked[slot] ? 0 : J.skipped + 1;
+  }
+  plan.erase(std::remove_if(plan.begin(), plan.end(), [](const auto &p) { return p.second.empty(); }), plan.end());
+  return plan;
+}
+
+// Enqueue one chunk of the jobs in `slots` on a lane: the steps, then the
+// convergence measure and its copy to the host, then the lane's event.
+lbm_status start_chunk(lbm_batch *B, int l, const std::vector<int> &slots) {
+  Lane &ln = B->lanes[l];
+  int running = 0;
+  for (size_t o = 0; o < B->lanes.size(); ++o) {
+    if (int(o) == l || !B->lanes[o].busy) continue;
+    const hipError_t q = hipEventQuery(B->lanes[o].done);
+    if (q == hipErrorNotReady)
+      ++running;
+    else if (q != hipSuccess)
+      return bfail(LBM_ERR_HIP, "event query: %s", hipGetErrorString(q));
+  }
+  if (B->init_recorded) LBM_BHIP(hipStreamWaitEvent(ln.stream, B->init_done, 0), "wait for initialisation");
+  lbm_status st = upload_tables(B, ln, slots);
+  if (st != LBM_OK) return st;
+  // one row-major job alone: the single-lattice sweep (population-major
+  // rows that are not whole lines run faster in the batch's flat walk)
+  const bool solo = slots.size() == 1 && B->jobs.at(B->slot_job[slots[0]]).layout == LBM_LAYOUT_ROW_MAJOR;
+  st = solo ? run_solo_chunk(B, ln, slots[0]) : run_graph_chunk(B, ln);
+  if (st != LBM_OK) return st;
+  // (a fill kernel rather than a memset node: the convergence maxima are
+  // the bit patterns of non-negative floats, and 0.0f is all zero bits)
+  lbm::fill_float_kernel<<<dim3(unsigned((B->max_jobs + 255) / 256)), dim3(256), 0, ln.stream>>>(
+      reinterpret_cast<float *>(ln.d_delta), size_t(B->max_jobs), 0.0f);
+  LBM_BHIP(hipGetLastError(), "reset deltas");
+  for (int s = 0; s < kNumStorage; ++s)
+    if (ln.ntiles[s] > 0)
+      LBM_BHIP(lbm::launch_batch_delta(s, ln.d_lats, ln.d_tiles[s], ln.d_ntiles + s, ln.d_delta, 4 * B->num_cu,
+                                       ln.stream),
+               "delta launch");
+  LBM_BHIP(hipMemcpyAsync(ln.h_delta.as<void>(), ln.d_delta, sizeof(unsigned) * B->max_jobs, hipMemcpyDeviceToHost,
+                          ln.stream),
+           "copy deltas");
+  LBM_BHIP(hipEventRecord(ln.done, ln.stream), "event");
+  ln.busy = true;
+  ln.slots = slots;
+  for (int slot : slots) B->jobs.at(B->slot_job[slot]).lane = l;
+  lbm_batch_stats &S = B->stats;
+  ++S.chunks;
+  S.job_chunks += (long long)slots.size();
+  if (slots.size() >= 2) ++S.multi_job_chunks;
+  S.max_jobs_in_chunk = std::max(S.max_jobs_in_chunk, int(slots.size()));
+  if (running > 0) ++S.overlapped_chunks;
+  S.max_lanes_running = std::max(S.max_lanes_running, running + 1);
+  return LBM_OK;
+}
+
+// Results of a lane's completed chunk: step counts, convergence, retirement.
+lbm_status finish_chunk(lbm_batch *B, int l) {
+  Lane &ln = B->lanes[l];
+  ln.busy = false;
+  const unsigned *hd = ln.h_delta.as<unsigned>();
+  for (int slot : ln.slots) {
+    const int id = B->slot_job[slot];
+    Job &J = B->jobs.at(id);
+    J.lane = -1;
+    J.steps += B->chunk_steps;
+    float d;
+    std::memcpy(&d, &hd[slot], sizeof(d));
+    J.delta = d;
+    const bool conv = J.spec.tol > 0.0 && J.delta < J.spec.tol;
+    if (conv || J.steps >= J.spec.max_steps) {
+      J.converged = conv ? 1 : 0;
+      lbm_status st = retire(B, id, ln);
+      if (st != LBM_OK) return st;
     }
   }
-  if (next != B->run_slot) {
-    B->run_slot.swap(next);
-    B->tiles_dirty = true;
+  ln.slots.clear();
+  return LBM_OK;
+}
+
+// Block until at least one busy lane has completed its chunk; process every
+// completed one.
+lbm_status wait_and_finish(lbm_batch *B) {
+  std::vector<int> busy;
+  for (int l = 0; l < int(B->lanes.size()); ++l)
+    if (B->lanes[l].busy) busy.push_back(l);
+  if (busy.empty()) return LBM_OK;
+  std::vector<int> ready;
+  if (busy.size() == 1) {
+    LBM_BHIP(hipEventSynchronize(B->lanes[busy[0]].done), "chunk");
+    ready = busy;
+  } else {
+    for (;;) {
+      for (int l : busy) {
+        const hipError_t q = hipEventQuery(B->lanes[l].done);
+        if (q == hipSuccess)
+          ready.push_back(l);
+        else if (q != hipErrorNotReady)
+          return bfail(LBM_ERR_HIP, "chunk: %s", hipGetErrorString(q));
+      }
+      if (!ready.empty()) break;
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+  }
+  for (int l : ready) {
+    lbm_status st = finish_chunk(B, l);
+    if (st != LBM_OK) return st;
+  }
+  return LBM_OK;
+}
+
+lbm_status drain(lbm_batch *B) {
+  for (;;) {
+    bool any = false;
+    for (const Lane &ln : B->lanes) any = any || ln.busy;
+    if (!any) return LBM_OK;
+    lbm_status st = wait_and_finish(B);
+    if (st != LBM_OK) return st;
   }
 }
 
@@ -702,16 +959,13 @@ int count_active(const lbm_batch *B) {
   return n;
 }
 
-long long tune_key(const lbm_batch *B) {
+long long tune_key(const lbm_batch *B, const Lane &ln) {
   size_t nodes = 0;
   for (int id : B->slot_job)
-    if (id >= 0) {
-      const Job &J = B->jobs.at(id);
-      nodes += size_t(J.spec.nx) * J.spec.ny * J.spec.nz;
-    }
+    if (id >= 0) nodes += B->jobs.at(id).nodes;
   int lg = 0;
   while ((size_t(1) << lg) < nodes) ++lg;
-  return (long long)present_mask(B) | ((long long)lg << 4);
+  return (long long)present_mask(ln) | ((long long)lg << 4);
 }
 
 }  // namespace
@@ -736,19 +990,22 @@ lbm_status lbm_batch_create(size_t hbm_budget_bytes, int chunk_steps, int max_jo
   if (!B) return bfail(LBM_ERR_OOM, "host allocation failed");
   B->chunk_steps = chunk_steps;
   B->max_jobs = max_jobs;
+  B->user_stream = static_cast<hipStream_t>(hip_stream);
   int dev = 0;
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
     B->num_cu = prop.multiProcessorCount;
-  if (hip_stream) {
-    B->stream = static_cast<hipStream_t>(hip_stream);
-  } else {
-    // Graph capture needs a stream other than the null stream.
-    if (hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking) != hipSuccess) {
-      delete B;
-      return bfail(LBM_ERR_HIP, "stream creation failed");
-    }
-    B->own_stream = true;
+  B->stats.lanes = 1;
+  B->lanes.resize(1);
+  lbm_status st = init_lane(B, B->lanes[0], B->user_stream);
+  if (st == LBM_OK && (hipStreamCreateWithFlags(&B->init_stream, hipStreamNonBlocking) != hipSuccess ||
+                       hipEventCreateWithFlags(&B->init_done, hipEventDisableTiming) != hipSuccess)) {
+    (void)hipGetLastError();
+    st = bfail(LBM_ERR_HIP, "stream or event creation failed");
+  }
+  if (st != LBM_OK) {
+    lbm_batch_destroy(B);
+    return st;
   }
   const size_t cap = hbm_budget_bytes / kAlign * kAlign;
   hipError_t e = hipMalloc(&B->pool_base, cap);
@@ -758,42 +1015,45 @@ lbm_status lbm_batch_create(size_t hbm_budget_bytes, int chunk_steps, int max_jo
     return bfail(LBM_ERR_OOM, "hipMalloc of the %zu-byte pool failed: %s", cap, hipGetErrorString(e));
   }
   B->pool.reset(cap);
-  // Tile capacity: the most slots the pool can hold (at least 76 B per FP16
-  // slot: two buffers of 19 elements), cut into the smallest tiles, plus one
-  // partial tile per job.
-  B->tile_cap = cap / 76 / kMinTileNodes + size_t(max_jobs) + 1;
   B->slot_job.assign(max_jobs, -1);
-  B->run_slot.assign(max_jobs, 0);
-  B->h_lats.assign(max_jobs, lbm::BatchLat());
-  std::memset(B->h_lats.data(), 0, B->h_lats.size() * sizeof(lbm::BatchLat));
-  B->h_delta.assign(max_jobs, 0u);
-  bool ok = hipMalloc(&B->d_lats, sizeof(lbm::BatchLat) * max_jobs) == hipSuccess &&
-            hipMalloc(&B->d_ntiles, sizeof(int) * kNumStorage) == hipSuccess &&
-            hipMalloc(&B->d_delta, sizeof(unsigned) * max_jobs) == hipSuccess;
-  for (int s = 0; s < kNumStorage && ok; ++s)
-    ok = hipMalloc(&B->d_tiles[s], sizeof(lbm::BatchTile) * B->tile_cap) == hipSuccess;
-  if (!ok) {
-    (void)hipGetLastError();
-    lbm_batch_destroy(B);
-    return bfail(LBM_ERR_OOM, "device tables could not be allocated");
-  }
+  B->lat.assign(max_jobs, lbm::BatchLat());
+  std::memset(B->lat.data(), 0, B->lat.size() * sizeof(lbm::BatchLat));
   *out = B;
   return LBM_OK;
 }
 
 void lbm_batch_destroy(lbm_batch *B) {
   if (!B) return;
-  if (B->stream) (void)hipStreamSynchronize(B->stream);
-  drop_graphs(B);
+  for (Lane &ln : B->lanes) free_lane(ln);
+  if (B->init_stream) (void)hipStreamSynchronize(B->init_stream);
+  if (B->init_done) (void)hipEventDestroy(B->init_done);
+  if (B->init_stream) (void)hipStreamDestroy(B->init_stream);
   if (B->pool_base) (void)hipFree(B->pool_base);
-  if (B->d_lats) (void)hipFree(B->d_lats);
-  for (int s = 0; s < kNumStorage; ++s)
-    if (B->d_tiles[s]) (void)hipFree(B->d_tiles[s]);
-  if (B->d_ntiles) (void)hipFree(B->d_ntiles);
-  if (B->d_delta) (void)hipFree(B->d_delta);
-  if (B->d_stage) (void)hipFree(B->d_stage);
-  if (B->own_stream) (void)hipStreamDestroy(B->stream);
   delete B;
+}
+
+lbm_status lbm_batch_set_lanes(lbm_batch *B, int lanes) {
+  if (!B) return bfail(LBM_ERR_ARG, "NULL handle");
+  if (lanes < 1 || lanes > kMaxLanes) return bfail(LBM_ERR_ARG, "lanes must be in [1, %d] (got %d)", kMaxLanes, lanes);
+  for (const Lane &ln : B->lanes)
+    if (ln.busy) return bfail(LBM_ERR_STATE, "a chunk is in flight");
+  for (int id : B->slot_job)
+    if (id >= 0 && B->jobs.at(id).lane >= 0) return bfail(LBM_ERR_STATE, "a chunk is in flight");
+  while (int(B->lanes.size()) > lanes) {
+    free_lane(B->lanes.back());
+    B->lanes.pop_back();
+  }
+  while (int(B->lanes.size()) < lanes) {
+    B->lanes.emplace_back();
+    lbm_status st = init_lane(B, B->lanes.back(), nullptr);
+    if (st != LBM_OK) {
+      free_lane(B->lanes.back());
+      B->lanes.pop_back();
+      return st;
+    }
+  }
+  B->stats.lanes = lanes;
+  return LBM_OK;
 }
 
 lbm_status lbm_batch_submit(lbm_batch *B, const lbm_job *job, int *job_id) {
@@ -842,10 +1102,12 @@ lbm_status lbm_batch_submit(lbm_batch *B, const lbm_job *job, int *job_id) {
   }
   Job J;
   J.spec = j;
-  // The layout is fixed here: row-major with padded rows when every chunk
-  // steps one job through the single-lattice sweep (shortest first, fill 0),
-  // else row-major only for rows of whole 128-byte lines.
-  J.layout = B->policy == LBM_BATCH_SHORTEST_FIRST && B->fill_nodes == 0
+  J.nodes = size_t(j.nx) * j.ny * j.nz;
+  // The layout is fixed here: row-major with padded rows for a job that
+  // every chunk steps alone through the single-lattice sweep (shortest
+  // first, at least fill_nodes nodes), else row-major only for rows of whole
+  // 128-byte lines.
+  J.layout = B->policy == LBM_BATCH_SHORTEST_FIRST && double(J.nodes) >= double(B->fill_nodes)
                  ? LBM_LAYOUT_ROW_MAJOR
                  : batch_layout_kind(j.nx, lbm_element_bytes(j.storage));
   J.bytes = job_bytes(j, J.layout);
@@ -862,57 +1124,12 @@ lbm_status lbm_batch_run_chunk(lbm_batch *B, int *n_active, int *n_queued) {
   if (!B) return bfail(LBM_ERR_ARG, "NULL handle");
   lbm_status st = admit(B);
   if (st != LBM_OK) return st;
-  const int active = count_active(B);
-  if (active > 0) {
-    select_jobs(B, false);
-    st = B->tiles_dirty ? rebuild_tiles(B) : upload_lats(B);
+  for (const auto &p : plan_chunks(B)) {
+    st = start_chunk(B, p.first, p.second);
     if (st != LBM_OK) return st;
-    int stepped = 0, only = -1;
-    for (int slot = 0; slot < B->max_jobs; ++slot)
-      if (B->slot_job[slot] >= 0 && B->run_slot[slot]) {
-        ++stepped;
-        only = slot;
-      }
-    // one row-major job alone: the single-lattice sweep (population-major
-    // rows that are not whole lines run faster in the batch's flat walk)
-    const bool solo = stepped == 1 && B->jobs[B->slot_job[only]].layout == LBM_LAYOUT_ROW_MAJOR;
-    st = solo ? run_solo_chunk(B, only) : run_graph_chunk(B);
-    if (st != LBM_OK) return st;
-    // (a fill kernel rather than a memset node: the convergence maxima are
-    // the bit patterns of non-negative floats, and 0.0f is all zero bits)
-    lbm::fill_float_kernel<<<dim3(unsigned((B->max_jobs + 255) / 256)), dim3(256), 0, B->stream>>>(
-        reinterpret_cast<float *>(B->d_delta), size_t(B->max_jobs), 0.0f);
-    LBM_BHIP(hipGetLastError(), "reset deltas");
-    for (int s = 0; s < kNumStorage; ++s)
-      if (B->h_ntiles[s] > 0)
-        LBM_BHIP(lbm::launch_batch_delta(s, B->d_lats, B->d_tiles[s], B->d_ntiles + s, B->d_delta, 4 * B->num_cu,
-                                         B->stream),
-                 "delta launch");
-    LBM_BHIP(hipMemcpyAsync(B->h_delta.data(), B->d_delta, sizeof(unsigned) * B->max_jobs, hipMemcpyDeviceToHost,
-                            B->stream),
-             "copy deltas");
-    LBM_BHIP(hipStreamSynchronize(B->stream), "chunk");
-    for (int slot = 0; slot < B->max_jobs; ++slot) {
-      const int id = B->slot_job[slot];
-      if (id < 0) continue;
-      Job &J = B->jobs[id];
-      if (!B->run_slot[slot]) {  // not stepped by this chunk
-        ++J.skipped;
-        continue;
-      }
-      J.skipped = 0;
-      J.steps += B->chunk_steps;
-      float d;
-      std::memcpy(&d, &B->h_delta[slot], sizeof(d));
-      J.delta = d;
-      const bool conv = J.spec.tol > 0.0 && J.delta < J.spec.tol;
-      if (conv || J.steps >= J.spec.max_steps) {
-        J.converged = conv ? 1 : 0;
-        st = retire(B, id);
-        if (st != LBM_OK) return st;
-      }
-    }
   }
+  st = wait_and_finish(B);
+  if (st != LBM_OK) return st;
   if (n_active) *n_active = count_active(B);
   if (n_queued) *n_queued = int(B->queue.size());
   return LBM_OK;
@@ -926,6 +1143,7 @@ lbm_status lbm_batch_poll(lbm_batch *B, int job_id, lbm_job_status *st) {
   st->steps = it->second.steps;
   st->delta = it->second.delta;
   st->converged = it->second.converged;
+  st->nodes = (long long)it->second.nodes;
   return LBM_OK;
 }
 
@@ -934,11 +1152,12 @@ lbm_status lbm_batch_result(lbm_batch *B, int job_id, double *rho, double *u) {
   auto it = B->jobs.find(job_id);
   if (it == B->jobs.end()) return bfail(LBM_ERR_ARG, "unknown job %d", job_id);
   if (it->second.state != LBM_JOB_DONE) return bfail(LBM_ERR_STATE, "job %d is not finished", job_id);
-  const HostResult &r = it->second.result;
-  const size_t N = r.size() / 4;
-  if (rho) std::memcpy(rho, r.data(), N * sizeof(double));
-  if (u) std::memcpy(u, r.data() + N, 3 * N * sizeof(double));
-  B->jobs.erase(it);  // frees the host copy
+  const size_t N = it->second.nodes;
+  const double *r = it->second.result.as<double>();
+  if (rho) std::memcpy(rho, r, N * sizeof(double));
+  if (u) std::memcpy(u, r + N, 3 * N * sizeof(double));
+  give_back_result_block(B, std::move(it->second.result));
+  B->jobs.erase(it);
   return LBM_OK;
 }
 
@@ -947,8 +1166,10 @@ lbm_status lbm_batch_set_shape(lbm_batch *B, int block_x, int tile_nodes, int gr
   if (block_x != 128 && block_x != 256) return bfail(LBM_ERR_ARG, "block_x must be 128 or 256");
   if (tile_nodes < kMinTileNodes) return bfail(LBM_ERR_ARG, "tile_nodes must be >= %d", kMinTileNodes);
   if (grid_blocks < 0 || grid_blocks > (1 << 20)) return bfail(LBM_ERR_ARG, "grid_blocks out of range");
-  if (B->shape.tile_nodes != tile_nodes) B->tiles_dirty = true;
-  if (B->shape.block_x != block_x || B->shape.grid != grid_blocks) drop_graphs(B);
+  for (const Lane &ln : B->lanes)
+    if (ln.busy) return bfail(LBM_ERR_STATE, "a chunk is in flight");
+  if (B->shape.block_x != block_x || B->shape.grid != grid_blocks)
+    for (Lane &ln : B->lanes) drop_graphs(ln);
   B->shape.block_x = block_x;
   B->shape.tile_nodes = tile_nodes;
   B->shape.grid = grid_blocks;
@@ -975,11 +1196,20 @@ lbm_status lbm_batch_get_shape(const lbm_batch *B, int *block_x, int *tile_nodes
 lbm_status lbm_batch_autotune(lbm_batch *B, int trial_steps, int *block_x, int *tile_nodes, int *grid_blocks) {
   if (!B) return bfail(LBM_ERR_ARG, "NULL handle");
   if (trial_steps < 2 || trial_steps % 2) return bfail(LBM_ERR_ARG, "trial_steps must be even and >= 2");
-  lbm_status st = admit(B);
+  lbm_status st = drain(B);
+  if (st != LBM_OK) return st;
+  st = admit(B);
   if (st != LBM_OK) return st;
   if (count_active(B) == 0) return bfail(LBM_ERR_STATE, "no resident job to tune on");
-  select_jobs(B, true);  // trial steps are steps of every resident job
-  const long long key = tune_key(B);
+  // trial steps are steps of every resident job, on lane 0
+  Lane &ln = B->lanes[0];
+  if (B->init_recorded) LBM_BHIP(hipStreamWaitEvent(ln.stream, B->init_done, 0), "wait for initialisation");
+  std::vector<int> all;
+  for (int slot = 0; slot < B->max_jobs; ++slot)
+    if (B->slot_job[slot] >= 0) all.push_back(slot);
+  st = upload_tables(B, ln, all);
+  if (st != LBM_OK) return st;
+  const long long key = tune_key(B, ln);
   Shape cached_shape;
   bool have_cached = false;
   {
@@ -1004,11 +1234,11 @@ lbm_status lbm_batch_autotune(lbm_batch *B, int trial_steps, int *block_x, int *
       for (int tn : {1024, 4096, 16384})
         for (int gm : {4, 8, 16}) {
           st = lbm_batch_set_shape(B, bx, tn, gm * B->num_cu);
-          if (st == LBM_OK) st = B->tiles_dirty ? rebuild_tiles(B) : upload_lats(B);
-          if (st == LBM_OK) st = launch_steps(B, 2, 0);  // warm-up
-          hipError_t e = st == LBM_OK ? hipEventRecord(e0, B->stream) : hipSuccess;
-          if (st == LBM_OK && e == hipSuccess) st = launch_steps(B, trial_steps, 2);
-          if (st == LBM_OK && e == hipSuccess) e = hipEventRecord(e1, B->stream);
+          if (st == LBM_OK) st = upload_tables(B, ln, all);
+          if (st == LBM_OK) st = launch_steps(B, ln, 2, 0);  // warm-up
+          hipError_t e = st == LBM_OK ? hipEventRecord(e0, ln.stream) : hipSuccess;
+          if (st == LBM_OK && e == hipSuccess) st = launch_steps(B, ln, trial_steps, 2);
+          if (st == LBM_OK && e == hipSuccess) e = hipEventRecord(e1, ln.stream);
           if (st == LBM_OK && e == hipSuccess) e = hipEventSynchronize(e1);
           float ms = 0.f;
           if (st == LBM_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
@@ -1017,8 +1247,7 @@ lbm_status lbm_batch_autotune(lbm_batch *B, int trial_steps, int *block_x, int *
             (void)hipEventDestroy(e1);
             return st != LBM_OK ? st : bfail(LBM_ERR_HIP, "autotune timing: %s", hipGetErrorString(e));
           }
-          for (int id : B->slot_job)
-            if (id >= 0) B->jobs[id].steps += 2 + trial_steps;
+          for (int slot : all) B->jobs.at(B->slot_job[slot]).steps += 2 + trial_steps;
           if (ms < best_ms) {
             best_ms = ms;
             best = B->shape;
@@ -1033,10 +1262,6 @@ lbm_status lbm_batch_autotune(lbm_batch *B, int trial_steps, int *block_x, int *
     st = lbm_batch_set_shape(B, best.block_x, best.tile_nodes, best.grid);
   }
   if (st != LBM_OK) return st;
-  if (B->tiles_dirty) {
-    st = rebuild_tiles(B);
-    if (st != LBM_OK) return st;
-  }
   if (block_x) *block_x = B->shape.block_x;
   if (tile_nodes) *tile_nodes = B->shape.tile_nodes;
   if (grid_blocks) *grid_blocks = grid_of(B);
@@ -1047,6 +1272,12 @@ lbm_status lbm_batch_memory(const lbm_batch *B, size_t *used, size_t *capacity) 
   if (!B || !used || !capacity) return bfail(LBM_ERR_ARG, "NULL argument");
   *used = B->pool.used();
   *capacity = B->pool.capacity();
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_get_stats(const lbm_batch *B, lbm_batch_stats *stats) {
+  if (!B || !stats) return bfail(LBM_ERR_ARG, "NULL argument");
+  *stats = B->stats;
   return LBM_OK;
 }
 

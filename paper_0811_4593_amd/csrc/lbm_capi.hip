@@ -620,6 +620,14 @@ lbm_status lbm_get_launch(const lbm_lattice *L, int *block_x, int *nodes_per_thr
   return LBM_OK;
 }
 
+lbm_status lbm_get_size(const lbm_lattice *L, int *nx, int *ny, int *nz) {
+  if (!L || !nx || !ny || !nz) return fail(LBM_ERR_ARG, "NULL argument");
+  *nx = L->nx;
+  *ny = L->ny;
+  *nz = L->nz;
+  return LBM_OK;
+}
+
 lbm_status lbm_get_step(const lbm_lattice *L, unsigned long long *steps) {
   if (!L || !steps) return fail(LBM_ERR_ARG, "NULL argument");
   *steps = L->steps;

@@ -33,11 +33,11 @@ EXPORTS = (
     "lbm_moments", "lbm_totals", "lbm_get_populations", "lbm_set_populations", "lbm_state_buffer",
     "lbm_set_layout", "lbm_get_layout", "lbm_buffer_elements",
     "lbm_element_bytes", "lbm_population_pitch", "lbm_set_launch", "lbm_get_launch", "lbm_autotune", "lbm_get_step",
-    "lbm_tune_placement", "lbm_probe",
+    "lbm_tune_placement", "lbm_probe", "lbm_get_size",
     "lbm_destroy", "lbm_last_error",
     "lbm_job_bytes", "lbm_batch_create", "lbm_batch_submit", "lbm_batch_run_chunk", "lbm_batch_poll",
     "lbm_batch_result", "lbm_batch_set_shape", "lbm_batch_get_shape", "lbm_batch_autotune", "lbm_batch_set_policy",
-    "lbm_batch_memory", "lbm_batch_destroy",
+    "lbm_batch_memory", "lbm_batch_set_lanes", "lbm_batch_get_stats", "lbm_batch_destroy",
 )
 
 LBM_JOB_QUEUED, LBM_JOB_RUNNING, LBM_JOB_DONE = 0, 1, 2
@@ -61,7 +61,16 @@ class LbmJob(ctypes.Structure):
 
 class LbmJobStatus(ctypes.Structure):
     _fields_ = [("state", ctypes.c_int), ("steps", ctypes.c_int), ("delta", ctypes.c_double),
-                ("converged", ctypes.c_int)]
+                ("converged", ctypes.c_int), ("nodes", ctypes.c_longlong)]
+
+
+class LbmBatchStats(ctypes.Structure):
+    _fields_ = [("lanes", ctypes.c_int), ("chunks", ctypes.c_longlong), ("job_chunks", ctypes.c_longlong),
+                ("multi_job_chunks", ctypes.c_longlong), ("max_jobs_in_chunk", ctypes.c_int),
+                ("overlapped_chunks", ctypes.c_longlong), ("max_lanes_running", ctypes.c_int)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class LBMError(RuntimeError):
@@ -127,6 +136,7 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_get_step.argtypes = [_vp, ctypes.POINTER(ctypes.c_ulonglong)]
     lib.lbm_tune_placement.argtypes = [_vp, st, st, ctypes.POINTER(st), _dp, _dp]
     lib.lbm_probe.argtypes = [_vp, st, st]
+    lib.lbm_get_size.argtypes = [_vp, ctypes.POINTER(st), ctypes.POINTER(st), ctypes.POINTER(st)]
     lib.lbm_destroy.argtypes = [_vp]
     lib.lbm_destroy.restype = None
     lib.lbm_last_error.argtypes = []
@@ -144,6 +154,8 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_batch_get_shape.argtypes = [_vp, ip, ip, ip]
     lib.lbm_batch_autotune.argtypes = [_vp, st, ip, ip, ip]
     lib.lbm_batch_memory.argtypes = [_vp, szp, szp]
+    lib.lbm_batch_set_lanes.argtypes = [_vp, st]
+    lib.lbm_batch_get_stats.argtypes = [_vp, ctypes.POINTER(LbmBatchStats)]
     lib.lbm_batch_destroy.argtypes = [_vp]
     lib.lbm_batch_destroy.restype = None
     for name in EXPORTS:
@@ -181,6 +193,45 @@ def _vec3(u) -> ctypes.Array:
     for i, x in enumerate(u):
         a[i] = float(x)
     return a
+
+
+def _host_array(a, dtype, count: int, what: str, writable: bool = False):
+    """A C-contiguous host array of `count` elements of `dtype` for a C call;
+    raises ValueError when the size does not match (the C side reads or
+    writes exactly `count` elements)."""
+    if writable:
+        if not isinstance(a, np.ndarray) or a.dtype != dtype or not a.flags["C_CONTIGUOUS"] \
+                or not a.flags["WRITEABLE"]:
+            raise ValueError(f"{what} must be a writable C-contiguous {np.dtype(dtype).name} numpy array")
+    else:
+        a = np.ascontiguousarray(np.asarray(a, dtype=dtype))
+    if a.size != count:
+        raise ValueError(f"{what} has {a.size} elements; {count} expected")
+    return a
+
+
+def _node_types(cell, count: int, what: str):
+    """Node types 0, 1, 2 as uint8, checked before any conversion (a cast
+    would turn 256 into 0 or 0.5 into 0)."""
+    c = np.asarray(cell)
+    if c.size != count:
+        raise ValueError(f"{what} has {c.size} entries; {count} expected")
+    if c.dtype.kind not in "biu":
+        raise ValueError(f"{what} must hold integers 0, 1 or 2 (got dtype {c.dtype})")
+    if c.size and (c.min() < 0 or c.max() > 2):
+        raise ValueError(f"{what} must hold integers 0, 1 or 2 (found {c.min()}..{c.max()})")
+    return np.ascontiguousarray(c.astype(np.uint8))
+
+
+def lbm_get_size(h):
+    nx, ny, nz = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load_library().lbm_get_size(h, ctypes.byref(nx), ctypes.byref(ny), ctypes.byref(nz)))
+    return nx.value, ny.value, nz.value
+
+
+def _nodes(h) -> int:
+    nx, ny, nz = lbm_get_size(h)
+    return nx * ny * nz
 
 
 def lbm_last_error() -> str:
@@ -226,7 +277,11 @@ def lbm_set_velocity_field(h, face, v=None):
     if v is None:
         _check(load_library().lbm_set_velocity_field(h, int(face), None))
         return
-    a = np.ascontiguousarray(np.asarray(v, dtype=np.float64))
+    nx, ny, nz = lbm_get_size(h)
+    if not 0 <= int(face) <= 5:
+        raise ValueError(f"invalid face {face}")
+    n_face = (ny * nz, nx * nz, nx * ny)[int(face) // 2]
+    a = _host_array(v, np.float64, 3 * n_face, "face velocity field")
     _check(load_library().lbm_set_velocity_field(h, int(face), a.ctypes.data_as(_dp)))
 
 
@@ -235,7 +290,10 @@ def lbm_set_solid_mask(h, solid=None):
     if solid is None:
         _check(load_library().lbm_set_solid_mask(h, None))
         return
-    a = np.ascontiguousarray(np.asarray(solid).astype(np.uint8))
+    a = np.asarray(solid)
+    if a.size != _nodes(h):
+        raise ValueError(f"solid mask has {a.size} entries; {_nodes(h)} expected")
+    a = np.ascontiguousarray(a != 0).astype(np.uint8)  # any non-zero value is solid
     _check(load_library().lbm_set_solid_mask(h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))))
 
 
@@ -244,7 +302,7 @@ def lbm_set_geometry(h, cell=None):
     if cell is None:
         _check(load_library().lbm_set_geometry(h, None))
         return
-    a = np.ascontiguousarray(np.asarray(cell).astype(np.uint8))
+    a = _node_types(cell, _nodes(h), "geometry")
     _check(load_library().lbm_set_geometry(h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))))
 
 
@@ -254,8 +312,8 @@ GEO_FLUID, GEO_SOLID, GEO_PLANE_EDGE_CORNER, GEO_CONVEX_EDGE, GEO_GENERAL = rang
 def lbm_classify_geometry(cell):
     """Host-only classification of (nz, ny, nx) node types; returns (code
     array of the same shape, uint32; counts per kind)."""
-    a = np.ascontiguousarray(np.asarray(cell).astype(np.uint8))
-    nz, ny, nx = a.shape
+    nz, ny, nx = np.asarray(cell).shape
+    a = _node_types(cell, nx * ny * nz, "geometry")
     code = np.zeros(a.shape, np.uint32)
     counts = (ctypes.c_longlong * 5)()
     _check(load_library().lbm_classify_geometry(nx, ny, nz, a.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)),
@@ -285,9 +343,11 @@ def lbm_moments(h, rho=None, u=None, dst_on_device: bool = False):
     if dst_on_device:
         _check(load_library().lbm_moments(h, _dev(rho), _dev(u), 1))
         return
-    for a in (rho, u):
-        if a is not None:
-            assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    n = _nodes(h)
+    if rho is not None:
+        _host_array(rho, np.float64, n, "rho", writable=True)
+    if u is not None:
+        _host_array(u, np.float64, 3 * n, "u", writable=True)
     _check(load_library().lbm_moments(h, None if rho is None else rho.ctypes.data,
                                       None if u is None else u.ctypes.data, 0))
 
@@ -300,13 +360,13 @@ def lbm_totals(h):
 
 
 def lbm_get_populations(h, out: np.ndarray):
-    assert out.dtype == np.float64 and out.flags["C_CONTIGUOUS"]
+    _host_array(out, np.float64, 19 * _nodes(h), "populations", writable=True)
     _check(load_library().lbm_get_populations(h, out.ctypes.data_as(_dp)))
     return out
 
 
 def lbm_set_populations(h, f: np.ndarray):
-    f = np.ascontiguousarray(f, dtype=np.float64)
+    f = _host_array(f, np.float64, 19 * _nodes(h), "populations")
     _check(load_library().lbm_set_populations(h, f.ctypes.data_as(_dp)))
 
 
@@ -437,12 +497,16 @@ def lbm_batch_poll(b, job_id: int) -> LbmJobStatus:
 
 def lbm_batch_result(b, job_id: int, nodes):
     """(rho, u) of a finished job, then the job is forgotten; nodes=None
-    forgets it without copying and returns (None, None)."""
+    forgets it without copying and returns (None, None).  nodes must be the
+    job's node count."""
     if nodes is None:
         _check(load_library().lbm_batch_result(b, int(job_id), None, None))
         return None, None
-    rho = np.empty(nodes)
-    u = np.empty(3 * nodes)
+    have = lbm_batch_poll(b, job_id).nodes
+    if int(nodes) != have:
+        raise ValueError(f"job {job_id} has {have} nodes, not {nodes}")
+    rho = np.empty(have)
+    u = np.empty(3 * have)
     _check(load_library().lbm_batch_result(b, int(job_id), rho.ctypes.data, u.ctypes.data))
     return rho, u
 
@@ -472,6 +536,16 @@ def lbm_batch_memory(b):
     u, c = ctypes.c_size_t(), ctypes.c_size_t()
     _check(load_library().lbm_batch_memory(b, ctypes.byref(u), ctypes.byref(c)))
     return u.value, c.value
+
+
+def lbm_batch_set_lanes(b, lanes: int):
+    _check(load_library().lbm_batch_set_lanes(b, int(lanes)))
+
+
+def lbm_batch_get_stats(b) -> dict:
+    st = LbmBatchStats()
+    _check(load_library().lbm_batch_get_stats(b, ctypes.byref(st)))
+    return st.as_dict()
 
 
 def lbm_batch_destroy(b):

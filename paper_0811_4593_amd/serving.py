@@ -118,33 +118,45 @@ class ServeReport:
     results: dict = field(default_factory=dict)
     peak_resident: int = 0
     peak_bytes: int = 0
+    stats: dict = field(default_factory=dict)  # lbm_batch_get_stats at the end (served runs)
 
     @property
     def solves_per_s(self):
         return len(self.latencies) / self.seconds if self.seconds > 0 else float("nan")
 
     def summary(self):
-        return {"requests": len(self.latencies), "seconds": round(self.seconds, 3),
-                "solves_per_s": round(self.solves_per_s, 3),
-                "p50_s": round(percentile(self.latencies, 50), 4), "p99_s": round(percentile(self.latencies, 99), 4),
-                "converged": int(sum(self.converged)), "peak_resident": self.peak_resident,
-                "peak_bytes": self.peak_bytes}
+        out = {"requests": len(self.latencies), "seconds": round(self.seconds, 3),
+               "solves_per_s": round(self.solves_per_s, 3),
+               "p50_s": round(percentile(self.latencies, 50), 4), "p99_s": round(percentile(self.latencies, 99), 4),
+               "converged": int(sum(self.converged)), "peak_resident": self.peak_resident,
+               "peak_bytes": self.peak_bytes}
+        if self.stats:
+            out["batch_stats"] = dict(self.stats)
+        return out
+
+
+SERVE_LANES = 4  # concurrent lanes of the serving loop (the box's default of 4 hardware queues)
 
 
 def serve_trace(trace, budget_bytes, chunk=100, tol=1e-6, max_steps=20000, max_jobs=256, shape=None,
                 keep_results=(), stream=None, progress=None, policy=lbm.LBM_BATCH_SHORTEST_FIRST,
-                fill_nodes=0):
+                fill_nodes=0, lanes=SERVE_LANES):
     """Replay `trace` (workloads.Request list, sorted by arrival) in real time:
     each request is submitted at its arrival time; between submissions the
     batch runs chunks, admitting queued requests as slots and memory free up
-    (continuous batching); each chunk steps the resident requests `policy`
-    picks (shortest remaining work first by default, at least fill_nodes
-    nodes).  Latency = completion time - arrival time.  progress(done,
-    total), if given, is called after every completion."""
+    (continuous batching).  With `lanes` > 1 the chunks of up to `lanes`
+    groups of requests run on the device at the same time (lbm_batch_set_lanes),
+    so a request that arrives while others run starts at once beside them;
+    `policy` forms the groups (shortest remaining work first by default; a
+    request below fill_nodes nodes shares its lane's launches with other
+    small ones up to fill_nodes nodes).  Latency = completion time - arrival
+    time.  progress(done, total), if given, is called after every
+    completion."""
     b = lbm.lbm_batch_create(budget_bytes, chunk, max_jobs, stream)
     rep = ServeReport()
     try:
         lbm.lbm_batch_set_policy(b, policy, fill_nodes)
+        lbm.lbm_batch_set_lanes(b, lanes)
         if shape:
             lbm.lbm_batch_set_shape(b, *shape)
         nreq = len(trace)
@@ -190,6 +202,7 @@ def serve_trace(trace, budget_bytes, chunk=100, tol=1e-6, max_steps=20000, max_j
         rep.latencies = [done_at[i] - trace[i].arrival for i in range(nreq)]
         rep.steps = steps
         rep.converged = conv
+        rep.stats = lbm.lbm_batch_get_stats(b)
         return rep
     finally:
         lbm.lbm_batch_destroy(b)

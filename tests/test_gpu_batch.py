@@ -232,16 +232,111 @@ def test_fp16_and_fp32_forms_against_fp64_velocity():
     assert e16sr <= 1e-3
 
 
-def test_serving_loop_small_trace_same_alone_and_in_mix():
-    trace = workloads.serving_trace(count=12, rate=40.0, seed=3, n_min=12, n_max=28)
+@pytest.mark.parametrize("lanes,fill", [(1, 0), (4, 0), (4, 6000)])
+def test_serving_loop_small_trace_same_alone_and_in_mix(lanes, fill):
+    """The serving loop on a seeded trace of small cubes arriving faster than
+    they finish: one lane (one chunk at a time), four lanes with one request
+    per lane, and four lanes where requests below 6000 nodes share their
+    lane's launches.  Every result equals the request run alone, bit for bit;
+    with four lanes chunks run beside each other on the device, and with the
+    fill threshold single launches step several requests."""
+    trace = workloads.serving_trace(count=12, rate=400.0, seed=3, n_min=12, n_max=28)
     rep = serving.serve_trace(trace, budget_bytes=64 << 20, chunk=50, tol=1e-6, max_steps=1500,
-                              max_jobs=4, keep_results=set(range(12)))
-    say(f"serve summary {rep.summary()}")
+                              max_jobs=4, keep_results=set(range(12)), lanes=lanes, fill_nodes=fill)
+    say(f"serve summary lanes={lanes} fill={fill}: {rep.summary()}")
+    st = rep.stats
+    assert st["lanes"] == lanes
     assert all(x >= 0 for x in rep.latencies)
     assert rep.peak_resident <= 4 and rep.peak_bytes <= 64 << 20
+    if lanes > 1:
+        assert st["overlapped_chunks"] >= 1 and st["max_lanes_running"] >= 2
+    if fill:
+        assert st["multi_job_chunks"] >= 1 and st["max_jobs_in_chunk"] >= 2
     for i, r in enumerate(trace):
         _, _, u_alone = serving.run_plain(r.spec, r.storage, rep.steps[i])
         np.testing.assert_array_equal(rep.results[i][1], u_alone)
+
+
+def test_lanes_lockstep_mix_equals_alone_bitwise():
+    """Lockstep with three lanes: the eleven lattices of four storage forms
+    are spread over the lanes (several per launch), each lane's chunks run
+    beside the others', and every lattice still equals itself run alone."""
+    steps = 40
+    b = lbm.lbm_batch_create(4 << 30, 10, 16)
+    try:
+        lbm.lbm_batch_set_lanes(b, 3)
+        ids = _submit_all(b, MIX, steps)
+        while lbm.lbm_batch_run_chunk(b) != (0, 0):
+            pass
+        st = lbm.lbm_batch_get_stats(b)
+        say(f"lockstep lanes stats {st}")
+        assert st["lanes"] == 3 and st["multi_job_chunks"] >= 1
+        for jid, (spec, storage) in zip(ids, MIX):
+            assert lbm.lbm_batch_poll(b, jid).steps == steps
+            rho_b, u_b = lbm.lbm_batch_result(b, jid, spec.nodes)
+            _, rho_p, u_p = serving.run_plain(spec, storage, steps)
+            np.testing.assert_array_equal(rho_b, rho_p)
+            np.testing.assert_array_equal(u_b, u_p)
+    finally:
+        lbm.lbm_batch_destroy(b)
+
+
+def test_small_requests_run_beside_a_large_one():
+    """Three lanes, shortest remaining work first, one request per lane: two
+    small requests that arrive while a large one is running take the idle
+    lanes and finish while the large one keeps stepping (with one lane it
+    would wait for them); all three equal their runs alone."""
+    big = workloads.duct(128, 64, 64, (0.03, 0.01, 0.0), 0.8)
+    small = [workloads.duct(16, 16, 16, (0.02, 0.0, 0.01), 0.9), workloads.duct(20, 12, 14, (0.01, 0.01, 0.0), 1.1)]
+    b = lbm.lbm_batch_create(1 << 30, 100, 8)
+    try:
+        lbm.lbm_batch_set_policy(b, lbm.LBM_BATCH_SHORTEST_FIRST, 0)
+        lbm.lbm_batch_set_lanes(b, 3)
+        jb = lbm.lbm_batch_submit(b, serving.job_for(big, "f32", 0.0, 3000))
+        lbm.lbm_batch_run_chunk(b)
+        assert lbm.lbm_batch_poll(b, jb).steps == 100
+        js = [lbm.lbm_batch_submit(b, serving.job_for(s, "f16sr", 0.0, 800)) for s in small]
+        big_steps_when_small_done = None
+        while True:
+            active, queued = lbm.lbm_batch_run_chunk(b)
+            if big_steps_when_small_done is None and \
+                    all(lbm.lbm_batch_poll(b, j).state == lbm.LBM_JOB_DONE for j in js):
+                big_steps_when_small_done = lbm.lbm_batch_poll(b, jb).steps
+            if active == 0 and queued == 0:
+                break
+        st = lbm.lbm_batch_get_stats(b)
+        say(f"large job at {big_steps_when_small_done} steps when the small ones were done; stats {st}")
+        assert 200 <= big_steps_when_small_done < 3000
+        assert st["overlapped_chunks"] >= 1 and st["max_lanes_running"] >= 2
+        for jid, spec, storage, steps in [(jb, big, "f32", 3000)] + [(j, s, "f16sr", 800) for j, s in zip(js, small)]:
+            assert lbm.lbm_batch_poll(b, jid).steps == steps
+            rho_b, u_b = lbm.lbm_batch_result(b, jid, spec.nodes)
+            _, rho_p, u_p = serving.run_plain(spec, storage, steps)
+            np.testing.assert_array_equal(rho_b, rho_p)
+            np.testing.assert_array_equal(u_b, u_p)
+    finally:
+        lbm.lbm_batch_destroy(b)
+
+
+def test_lanes_argument_checks():
+    b = lbm.lbm_batch_create(16 << 20, 10, 2)
+    try:
+        for bad in (0, 9):
+            with pytest.raises(lbm.LBMError) as e:
+                lbm.lbm_batch_set_lanes(b, bad)
+            assert e.value.status == lbm.LBM_ERR_ARG
+        lbm.lbm_batch_set_lanes(b, 8)
+        lbm.lbm_batch_set_lanes(b, 2)
+        assert lbm.lbm_batch_get_stats(b)["lanes"] == 2
+        jid = lbm.lbm_batch_submit(b, serving.job_for(workloads.duct(12, 8, 8), "f32", 0.0, 20))
+        while lbm.lbm_batch_run_chunk(b) != (0, 0):
+            pass
+        with pytest.raises(ValueError):
+            lbm.lbm_batch_result(b, jid, 12 * 8 * 8 - 1)  # wrong node count: refused before the copy
+        rho, u = lbm.lbm_batch_result(b, jid, 12 * 8 * 8)
+        assert rho.shape == (768,) and u.shape == (3 * 768,)
+    finally:
+        lbm.lbm_batch_destroy(b)
 
 
 def test_large_job_is_not_starved_by_small_ones():

@@ -239,6 +239,24 @@ lbm_status lbm_moments(lbm_lattice *L, double *rho, double *u, int dst_on_device
  * Inf in the totals; the values are still written). */
 lbm_status lbm_totals(lbm_lattice *L, double *mass, double momentum[3]);
 
+/* For callers that cannot allocate device memory (work under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FP64
+ * totals of lbm_totals -- mass sum_n rho, then momentum sum_n rho u -- of a
+ * population buffer f in device memory (storage form `storage`, layout
+ * `layout` of an nx*ny*nz lattice, as lbm_state_buffer gives it), written to
+ * out_device[4] (device memory) by kernels enqueued on hip_stream (NULL: the
+ * null stream); returns without waiting.  Nothing is allocated: the partial
+ * sums of the fixed-order reduction (1024 blocks, the same order as
+ * lbm_totals, so the results are the same bits) live in a static device
+ * array of 32 KiB that each GPU the library runs on holds until the process
+ * ends, and that every call on that GPU shares: calls that overlap on one
+ * GPU (on different streams or threads) race and may return wrong totals.
+ * The caller owns f and out_device.  Errors: LBM_ERR_ARG (NULL pointer,
+ * sizes < 1, 2^31 nodes or more, unknown storage or layout), LBM_ERR_HIP
+ * (symbol lookup or launch failure). */
+lbm_status lbm_totals_static(const void *f, int nx, int ny, int nz, lbm_storage storage, int layout,
+                             void *hip_stream, double *out_device);
+
 /* Copy the stored state to / from a host array f[19*N] of populations f_k
  * in double (same layout as the device state).  get returns w_k + d_k; set
  * stores d_k = f_k - w_k evaluated in double, rounded to nearest even for

@@ -33,7 +33,7 @@ EXPORTS = (
     "lbm_moments", "lbm_totals", "lbm_get_populations", "lbm_set_populations", "lbm_state_buffer",
     "lbm_set_layout", "lbm_get_layout", "lbm_buffer_elements",
     "lbm_element_bytes", "lbm_population_pitch", "lbm_set_launch", "lbm_get_launch", "lbm_autotune", "lbm_get_step",
-    "lbm_tune_placement", "lbm_probe", "lbm_get_size",
+    "lbm_tune_placement", "lbm_probe", "lbm_get_size", "lbm_totals_static",
     "lbm_destroy", "lbm_last_error",
     "lbm_job_bytes", "lbm_batch_create", "lbm_batch_submit", "lbm_batch_run_chunk", "lbm_batch_poll",
     "lbm_batch_result", "lbm_batch_set_shape", "lbm_batch_get_shape", "lbm_batch_autotune", "lbm_batch_set_policy",

@@ -39,22 +39,25 @@ COUNTERS_FILE = os.path.join(_ROOT, "profiles", "sweep_f32_duct_1024x512x512_cou
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("d3q19.hpp", "node_update.hpp", "lbm_kernels.hip", "lbm_internal.hpp"):
+    for name in ("d3q19.hpp", "node_update.hpp", "lbm_kernels.hip", "lbm_sweep2.hip", "lbm_internal.hpp"):
         with open(os.path.join(_ROOT, "paper_0811_4593_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(launch, storage, layout):
+def measured_traffic(launch, storage, layout, steps_per_launch=1, pass_args=None):
     """HBM bytes per launch from the committed rocprofv3 counter runs, if they
-    were taken on the current kernel source and launch shape; else None."""
+    were taken on the current kernel source, launch shape and pass; else
+    None."""
     try:
         with open(COUNTERS_FILE) as fh:
             c = json.load(fh)
     except (OSError, ValueError):
         return None
     if c.get("kernel_source_hash") != kernel_source_hash() or c.get("launch") != list(launch) \
-            or c.get("storage") != storage or c.get("layout", "pop") != layout:
+            or c.get("storage") != storage or c.get("layout", "pop") != layout \
+            or c.get("steps_per_launch", 1) != steps_per_launch \
+            or (pass_args is not None and c.get("pass", [1, 0, 0]) != list(pass_args)):
         return None
     return c.get("hbm_bytes_per_launch")
 
@@ -92,8 +95,12 @@ def ingest_counters(args):
         assert len(ks) == 1, (frag, list(d))
         return ks[0], d[ks[0]]
 
-    sweep_name, f_sweep = pick(fetch, ", false, false>(")  # the full sweep (COPY = false, EXT = false)
-    _, w_sweep = pick(write, ", false, false>(")
+    # the timed kernel: the two-step pass if the run used it, else the full
+    # single sweep (COPY = false, EXT = false)
+    frag = "sweep2_kernel" if any("sweep2_kernel" in k for k in fetch) else ", false, false>("
+    steps_per_launch = 2 if frag == "sweep2_kernel" else 1
+    sweep_name, f_sweep = pick(fetch, frag)
+    _, w_sweep = pick(write, frag)
     _, f_copy = pick(fetch, "copy_probe_kernel")
     _, w_copy = pick(write, "copy_probe_kernel")
     fs, ws = copy_kib / f_copy, copy_kib / w_copy
@@ -112,8 +119,10 @@ def ingest_counters(args):
         "copy_probe_known_kib": copy_kib,
         "fetch_scale": fs,
         "write_scale": ws,
+        "steps_per_launch": steps_per_launch,
+        "pass": [args.steps_per_pass, args.zplanes, args.tile_rows],  # as given to bench.py
         "hbm_bytes_per_launch": (f_sweep * fs + w_sweep * ws) * 1024.0,
-        "algorithmic_bytes_per_launch": 2 * 19 * N * lbm.lbm_element_bytes(storage),
+        "algorithmic_bytes_per_launch": 2 * 19 * N * lbm.lbm_element_bytes(storage) * steps_per_launch,
         "command": args.counters_command,
     }
     os.makedirs(os.path.dirname(COUNTERS_FILE), exist_ok=True)
@@ -283,13 +292,15 @@ def form_serve(args, requests=40):
     with plain launches."""
     import torch
 
-    from paper_0811_4593_amd import serving, workloads
+    from paper_0811_4593_amd import lbm, serving, workloads
 
     free, total = torch.cuda.mem_get_info()
     budget = int(min(free * 0.8, 200e9))
     calib = workloads.serving_trace(count=12, rate=1e9, seed=1)
+    policy = {"shortest": lbm.LBM_BATCH_SHORTEST_FIRST, "large-in-order": lbm.LBM_BATCH_LARGE_IN_ORDER}[
+        args.serve_policy]
     rep_c = serving.serve_trace(calib, budget, chunk=100, tol=1e-6, max_steps=20000, max_jobs=512,
-                                fill_nodes=args.serve_fill, lanes=args.serve_lanes)
+                                fill_nodes=args.serve_fill, lanes=args.serve_lanes, policy=policy)
     sat = rep_c.solves_per_s
     print(f"serve form: calibration {rep_c.summary()}", file=sys.stderr, flush=True)
     rate = 0.7 * sat
@@ -301,14 +312,20 @@ def form_serve(args, requests=40):
         return report
 
     rep = serving.serve_trace(trace, budget, chunk=100, tol=1e-6, max_steps=20000, max_jobs=512,
-                              fill_nodes=args.serve_fill, lanes=args.serve_lanes, progress=progress("served"))
+                              fill_nodes=args.serve_fill, lanes=args.serve_lanes, policy=policy,
+                              progress=progress("served"))
     print(f"serve form: served {rep.summary()}", file=sys.stderr, flush=True)
     base = serving.replay_one_at_a_time(trace, rep.steps, progress=progress("one at a time"))
     print(f"serve form: one-at-a-time {base.summary()}", file=sys.stderr, flush=True)
     nodes = [r.spec.nodes for r in trace]
     sv, oa = rep.summary(), base.summary()
-    return {"form": "serve", "policy": f"{args.serve_lanes} lanes, shortest remaining work first, requests below "
-                                       f"{args.serve_fill} nodes share launches up to {args.serve_fill} nodes",
+    if args.serve_policy == "shortest":
+        pol = (f"{args.serve_lanes} lanes, shortest remaining work first, requests below {args.serve_fill} nodes "
+               f"share launches up to {args.serve_fill} nodes")
+    else:
+        pol = (f"{args.serve_lanes} lanes: requests of at least {args.serve_fill} nodes one at a time in arrival "
+               f"order, smaller ones beside them, shortest remaining work first")
+    return {"form": "serve", "policy": pol,
             "requests": len(trace), "rate_per_s": round(rate, 4),
             "calibration_solves_per_s": round(sat, 4), "budget_bytes": budget,
             "mean_nodes": float(np.mean(nodes)), "storage_f16_share": float(np.mean([r.storage == "f16sr" for r in trace])),
@@ -338,6 +355,10 @@ def main():
     ap.add_argument("--layout", default="rows", choices=["pop", "rows"],
                     help="population layout of the device buffers: population-major (k*P + n) or row-major "
                          "(the 19 populations of each x-row together)")
+    ap.add_argument("--steps-per-pass", type=int, default=1, choices=[1, 2],
+                    help="time steps per pass over HBM (lbm_set_steps_per_pass; 2: temporal blocking)")
+    ap.add_argument("--zplanes", type=int, default=0, help="z-planes per workgroup of the two-step pass (0: 64)")
+    ap.add_argument("--tile-rows", type=int, default=0, help="interior rows of the two-step tiles (0: default, 5)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -356,9 +377,11 @@ def main():
     ap.add_argument("--legs", default="precision,batch,serve",
                     help="systems forms measured after the roofline run and reported under 'forms' "
                          "(comma list of precision, batch, serve; empty: none)")
-    ap.add_argument("--serve-fill", type=int, default=0,
-                    help="serve form: requests below this many nodes share their lane's launches up to it "
-                         "(shortest remaining work first; 0: one request per lane)")
+    ap.add_argument("--serve-fill", type=int, default=1 << 18,
+                    help="serve form: with large-in-order, the node count from which a request is large; with "
+                         "shortest, requests below it share their lane's launches up to it (0: one per lane)")
+    ap.add_argument("--serve-policy", default="large-in-order", choices=["shortest", "large-in-order"],
+                    help="serve form: how the lanes are filled (lbm_batch_set_policy)")
     ap.add_argument("--serve-lanes", type=int, default=4,
                     help="serve form: lanes (concurrent chunk streams) of the batch runtime")
     args = ap.parse_args()
@@ -410,6 +433,8 @@ def main():
             lbm.lbm_autotune(h, 2)
             tuned = True
         launch = lbm.lbm_get_launch(h)
+        lbm.lbm_set_steps_per_pass(h, args.steps_per_pass, args.zplanes, args.tile_rows)
+        spp, zplanes, tile_rows = lbm.lbm_get_steps_per_pass(h)
         placement = None
         if args.placement >= 2:
             tried, ms0, ms1 = lbm.lbm_tune_placement(h, args.placement, 1)
@@ -431,7 +456,7 @@ def main():
         # Bandwidth probes on the same buffers: the pull-pattern copy (no
         # arithmetic, no boundary rule) and a plain contiguous copy.
         probes = {}
-        for kind, name in ((1, "pull_pattern_copy"), (0, "contiguous_copy")):
+        for kind, name in ((1, "pull_pattern_copy"), (0, "read_write_copy")):
             lbm.lbm_probe(h, kind, 2)
             torch.cuda.synchronize()
             e0 = torch.cuda.Event(enable_timing=True)
@@ -451,10 +476,14 @@ def main():
 
     ms_per_step = wall * 1e3 / args.steps
     value = N * args.steps / wall / 1e6
-    kernel_ms = ev_ms / args.steps
-    alg_bytes = 2 * 19 * ebytes * N  # 19 loads + 19 stores per node update
+    # launches in the timed region: one per step, or one per pair of steps
+    # (an odd count ends with one single sweep)
+    launches = args.steps // 2 + args.steps % 2 if spp == 2 else args.steps
+    kernel_ms = ev_ms / launches
+    alg_bytes = 2 * 19 * ebytes * N * args.steps / launches  # 19 loads + 19 stores per node update
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
-    traffic = measured_traffic(launch, args.storage, args.layout)
+    traffic = measured_traffic(launch, args.storage, args.layout, 2 if spp == 2 else 1,
+                               [args.steps_per_pass, args.zplanes, args.tile_rows])
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -477,6 +506,9 @@ def main():
                        "autotuned": tuned},
             "placement": placement,
             "layout": {"pop": "population-major", "rows": "row-major"}[args.layout],
+            "steps_per_pass": spp,
+            "z_planes": zplanes if spp == 2 else None,
+            "tile_rows": (tile_rows or None) if spp == 2 else None,
         },
         "roofline": {
             "bound": "hbm",
@@ -485,11 +517,19 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4),
             "traffic": traffic,
-            "kernel": "sweep_kernel",
+            "kernel": "sweep2_kernel" if spp == 2 else "sweep_kernel",
+            "steps_per_launch": 2 if spp == 2 else 1,
             "kernel_ms_avg": round(kernel_ms, 4),
             # against the measured ceiling of the same access pattern: the pull-pattern
             # copy (streaming only) on the same buffers
             "frac_of_pull_copy": round(achieved / probes["pull_pattern_copy"], 4),
+            # the best 50/50 read/write stream measured on the same buffers (a contiguous copy,
+            # one 16-byte element per thread): the practical bandwidth ceiling of the box
+            "ceiling_GBs": probes["read_write_copy"],
+            "frac_of_ceiling": round(achieved / probes["read_write_copy"], 4),
+            # the same kernel on the lattice's own two buffers, before placement tuning
+            "frac_untuned_placement": None if placement is None else
+            round(2 * 19 * ebytes * N / (placement["ms_per_step_before"] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
         },
         "probes_GBs": probes,
         "mass_after": mass,

@@ -328,6 +328,27 @@ enum { LBM_XCD_NONE = 0, LBM_XCD_SLABS = 1, LBM_XCD_ROWS = 2 };
 lbm_status lbm_set_launch(lbm_lattice *L, int block_x, int nodes_per_thread, int xcd_remap);
 lbm_status lbm_get_launch(const lbm_lattice *L, int *block_x, int *nodes_per_thread, int *xcd_remap);
 
+/* Steps per pass over HBM.  steps_per_pass = 2 (temporal blocking): lbm_step
+ * advances pairs of steps with one kernel in which a workgroup streams a
+ * tile of 64 x BY nodes (BY = 13 for FP32 and FP16, 5 for FP64) through
+ * ranges of z_planes planes, computes the first step on the tile plus a
+ * one-node halo into LDS and the second from LDS into HBM.  Per pair of
+ * steps every node's populations are read about once (the halo rows are
+ * shared with neighbouring tiles through L2) and written once, against
+ * twice each with two single sweeps; the first step's arithmetic on the
+ * halo nodes is done twice (about 1.2 times the updates).  Every node's
+ * arithmetic, rounding and random words are the single sweep's, so the state
+ * after a pair equals the state after two single sweeps bit for bit.  The
+ * pass applies to lattices in the row-major layout without a solid mask,
+ * face velocity field or geometry; for others, and for the last step of an
+ * odd count, lbm_step runs the single sweep.  z_planes >= 1 (0: 64) sets the
+ * planes per workgroup; the first step on the two planes beyond a range is
+ * done by both neighbouring ranges.  steps_per_pass = 1: one single sweep
+ * per step (the default).  Errors: LBM_ERR_ARG (NULL, steps_per_pass not 1
+ * or 2, z_planes < 0). */
+lbm_status lbm_set_steps_per_pass(lbm_lattice *L, int steps_per_pass, int z_planes, int tile_rows);
+lbm_status lbm_get_steps_per_pass(const lbm_lattice *L, int *steps_per_pass, int *z_planes, int *tile_rows);
+
 /* Number of steps the lattice has taken since creation (lbm_step,
  * lbm_autotune; lbm_set_populations does not reset it).  It also keys the
  * random numbers of the stochastic-rounding form.  Errors: LBM_ERR_ARG. */
@@ -481,13 +502,19 @@ lbm_status lbm_batch_set_shape(lbm_batch *B, int block_x, int tile_nodes, int gr
  *                             large co-resident job's; the others wait,
  *                             resident.
  * A job's results do not depend on the policy (only when its steps run).
+ *   LBM_BATCH_LARGE_IN_ORDER  meant for several lanes: jobs of at least
+ *                             fill_nodes nodes are large and run one at a
+ *                             time in submission order (a later large job
+ *                             never slows an earlier one down); small jobs
+ *                             run one per remaining lane, shortest remaining
+ *                             work first, beside the large one.
  * Set the policy before submitting: with LBM_BATCH_SHORTEST_FIRST, jobs of
  * at least fill_nodes nodes submitted afterwards are stored row-major with
- * padded rows, and a chunk that steps a single row-major job runs the
- * single-lattice sweep on it.  lbm_job_bytes gives the bytes of the lockstep
+ * padded rows, with LBM_BATCH_LARGE_IN_ORDER every job; a chunk that steps
+ * a single row-major job runs the single-lattice sweep on it.  lbm_job_bytes gives the bytes of the lockstep
  * layout.  lbm_batch_autotune steps every resident job whatever the policy.
  * Errors: LBM_ERR_ARG (NULL, unknown policy). */
-enum { LBM_BATCH_LOCKSTEP = 0, LBM_BATCH_SHORTEST_FIRST = 1 };
+enum { LBM_BATCH_LOCKSTEP = 0, LBM_BATCH_SHORTEST_FIRST = 1, LBM_BATCH_LARGE_IN_ORDER = 2 };
 lbm_status lbm_batch_set_policy(lbm_batch *B, int policy, size_t fill_nodes);
 lbm_status lbm_batch_get_shape(const lbm_batch *B, int *block_x, int *tile_nodes, int *grid_blocks);
 
@@ -514,7 +541,11 @@ lbm_status lbm_batch_memory(const lbm_batch *B, size_t *used, size_t *capacity);
  *   LBM_BATCH_SHORTEST_FIRST  in order of remaining work, one job per idle
  *                             lane; a job below fill_nodes nodes takes
  *                             further jobs below fill_nodes into its lane's
- *                             launch until it holds fill_nodes nodes.
+ *                             launch until it holds fill_nodes nodes;
+ *   LBM_BATCH_LARGE_IN_ORDER  the earliest submitted large job (at least
+ *                             fill_nodes nodes) on one lane while no large
+ *                             job is in flight, small jobs one per other
+ *                             idle lane, shortest remaining work first.
  * So a request that arrives while others are on the GPU starts at once on
  * an idle lane, and its steps overlap theirs on the device, instead of
  * waiting for them.  1 <= lanes <= 8 (1: the default, one chunk at a time;

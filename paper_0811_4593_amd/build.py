@@ -11,7 +11,8 @@ import sys
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
-SOURCES = ["csrc/lbm_kernels.hip", "csrc/lbm_capi.hip", "csrc/lbm_batch.hip", "csrc/lbm_static.hip"]
+SOURCES = ["csrc/lbm_kernels.hip", "csrc/lbm_sweep2.hip", "csrc/lbm_capi.hip", "csrc/lbm_batch.hip",
+           "csrc/lbm_static.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

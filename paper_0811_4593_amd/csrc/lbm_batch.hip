@@ -771,6 +771,11 @@ double job_nodes(const Job &J) { return double(J.nodes); }
 //   nodes.  The rest wait, resident.  Small jobs then step at their own pace
 //   instead of a large co-resident job's, and a large job waits, but not for
 //   ever.
+//   Large in order: jobs of at least fill_nodes nodes are large.  While no
+//   large job is in flight, the earliest submitted large job takes an idle
+//   lane (large jobs run one at a time, in arrival order, so a later one
+//   never slows an earlier one down); the other idle lanes take small jobs,
+//   one each, in order of remaining work (left-out ones first, as above).
 constexpr int kMaxSkipped = 50;
 std::vector<std::pair<int, std::vector<int>>> plan_chunks(lbm_batch *B) {
   std::vector<int> idle;
@@ -795,6 +800,28 @@ std::vector<std::pair<int, std::vector<int>>> plan_chunks(lbm_batch *B) {
       plan[g].second.push_back(slot);
       load[g] += job_nodes(job_at(slot));
     }
+  } else if (B->policy == LBM_BATCH_LARGE_IN_ORDER) {
+    const double big = double(B->fill_nodes);
+    bool large_running = false;
+    for (int slot = 0; slot < B->max_jobs; ++slot) {
+      const int id = B->slot_job[slot];
+      if (id >= 0 && B->jobs.at(id).lane >= 0 && job_nodes(B->jobs.at(id)) >= big) large_running = true;
+    }
+    int first_large = -1;  // earliest submitted (smallest id) large candidate
+    std::vector<std::pair<std::pair<int, double>, int>> small;  // ((not forced, work), slot)
+    for (int slot : cand) {
+      const Job &J = job_at(slot);
+      if (job_nodes(J) >= big) {
+        if (first_large < 0 || B->slot_job[slot] < B->slot_job[first_large]) first_large = slot;
+      } else {
+        const double work = job_nodes(J) * double(std::max(0, J.spec.max_steps - J.steps));
+        small.push_back({{J.skipped >= kMaxSkipped ? 0 : 1, work}, slot});
+      }
+    }
+    std::sort(small.begin(), small.end());
+    size_t g = 0, next = 0;
+    if (!large_running && first_large >= 0) plan[g++].second.push_back(first_large);
+    for (; g < plan.size() && next < small.size(); ++g) plan[g].second.push_back(small[next++].second);
   } else {
     std::vector<std::pair<std::pair<int, double>, int>> order;  // ((not forced, work), slot)
     for (int slot : cand) {
@@ -1107,9 +1134,9 @@ lbm_status lbm_batch_submit(lbm_batch *B, const lbm_job *job, int *job_id) {
   // every chunk steps alone through the single-lattice sweep (shortest
   // first, at least fill_nodes nodes), else row-major only for rows of whole
   // 128-byte lines.
-  J.layout = B->policy == LBM_BATCH_SHORTEST_FIRST && double(J.nodes) >= double(B->fill_nodes)
-                 ? LBM_LAYOUT_ROW_MAJOR
-                 : batch_layout_kind(j.nx, lbm_element_bytes(j.storage));
+  const bool alone = B->policy == LBM_BATCH_LARGE_IN_ORDER ||
+                     (B->policy == LBM_BATCH_SHORTEST_FIRST && double(J.nodes) >= double(B->fill_nodes));
+  J.layout = alone ? LBM_LAYOUT_ROW_MAJOR : batch_layout_kind(j.nx, lbm_element_bytes(j.storage));
   J.bytes = job_bytes(j, J.layout);
   if (J.bytes > B->pool.capacity())
     return bfail(LBM_ERR_OOM, "job needs %zu bytes, more than the whole budget (%zu)", J.bytes, B->pool.capacity());
@@ -1178,8 +1205,10 @@ lbm_status lbm_batch_set_shape(lbm_batch *B, int block_x, int tile_nodes, int gr
 
 lbm_status lbm_batch_set_policy(lbm_batch *B, int policy, size_t fill_nodes) {
   if (!B) return bfail(LBM_ERR_ARG, "NULL handle");
-  if (policy != LBM_BATCH_LOCKSTEP && policy != LBM_BATCH_SHORTEST_FIRST)
-    return bfail(LBM_ERR_ARG, "policy must be LBM_BATCH_LOCKSTEP or LBM_BATCH_SHORTEST_FIRST (got %d)", policy);
+  if (policy != LBM_BATCH_LOCKSTEP && policy != LBM_BATCH_SHORTEST_FIRST && policy != LBM_BATCH_LARGE_IN_ORDER)
+    return bfail(LBM_ERR_ARG,
+                 "policy must be LBM_BATCH_LOCKSTEP, LBM_BATCH_SHORTEST_FIRST or LBM_BATCH_LARGE_IN_ORDER (got %d)",
+                 policy);
   B->policy = policy;
   B->fill_nodes = fill_nodes;
   return LBM_OK;

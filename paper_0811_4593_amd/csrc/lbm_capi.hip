@@ -72,6 +72,9 @@ struct lbm_lattice {
   double *d_face_v[6];     // per-node face velocities on the device, or nullptr
   unsigned *d_geo;         // complex-geometry node codes on the device, or nullptr
   int block_x, npt, xcd;
+  int pass_steps;  // 1 or 2 steps per pass over HBM
+  int zc;          // z-planes per workgroup of the two-step pass
+  int tile_rows;   // interior rows of its tiles (0: the form's default)
   unsigned long long steps;  // steps taken since creation (its low 32 bits key the stochastic rounding)
   double *d_partials;  // [kPartialBlocks * 4]
   double *d_totals;    // [4]
@@ -114,6 +117,8 @@ static lbm_status validate_create(int nx, int ny, int nz, double tau, double rho
   return LBM_OK;
 }
 
+static constexpr int kDefaultZPlanes = 64;
+
 static void default_launch(lbm_lattice *L) {
   // One node per thread, each XCD on its own eighth of the lattice, the
   // block width by row length (256 threads is the fastest shape measured on
@@ -121,6 +126,9 @@ static void default_launch(lbm_lattice *L) {
   L->block_x = lbm::default_block_x(L->nx);
   L->npt = 1;
   L->xcd = LBM_XCD_SLABS;
+  L->pass_steps = 1;
+  L->zc = kDefaultZPlanes;
+  L->tile_rows = 0;
 }
 
 static lbm_status finish_create(lbm_lattice *L, double rho0, const double u0[3], lbm_lattice **out) {
@@ -465,12 +473,18 @@ lbm_status lbm_step(lbm_lattice *L, int nsteps) {
   if (p_axes > 1)
     return fail(LBM_ERR_STATE, "pressure faces on %d axes: edges between two pressure faces are not defined", p_axes);
   lbm::SweepConfig c = sweep_config(L);
-  for (int s = 0; s < nsteps; ++s) {
+  const bool ext = L->d_solid || L->d_geo || L->d_face_v[0] || L->d_face_v[1] || L->d_face_v[2] ||
+                   L->d_face_v[3] || L->d_face_v[4] || L->d_face_v[5];
+  const bool two = L->pass_steps == 2 && L->layout == LBM_LAYOUT_ROW_MAJOR && !ext;
+  for (int s = 0; s < nsteps;) {
     c.step = unsigned(L->steps);
-    hipError_t e = lbm::launch_sweep(c, L->buf[L->cur], L->buf[L->cur ^ 1], false, L->stream);
-    if (e != hipSuccess) return hip_fail(e, "sweep launch");
+    const bool pair = two && nsteps - s >= 2;
+    hipError_t e = pair ? lbm::launch_sweep2(c, L->zc, L->tile_rows, L->buf[L->cur], L->buf[L->cur ^ 1], L->stream)
+                        : lbm::launch_sweep(c, L->buf[L->cur], L->buf[L->cur ^ 1], false, L->stream);
+    if (e != hipSuccess) return hip_fail(e, pair ? "two-step sweep launch" : "sweep launch");
     L->cur ^= 1;
-    ++L->steps;
+    L->steps += pair ? 2 : 1;
+    s += pair ? 2 : 1;
   }
   return LBM_OK;
 }
@@ -617,6 +631,26 @@ lbm_status lbm_get_launch(const lbm_lattice *L, int *block_x, int *nodes_per_thr
   *block_x = L->block_x;
   *nodes_per_thread = L->npt;
   *xcd_remap = L->xcd;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_steps_per_pass(lbm_lattice *L, int steps_per_pass, int z_planes, int tile_rows) {
+  if (!L) return fail(LBM_ERR_ARG, "NULL handle");
+  if (steps_per_pass != 1 && steps_per_pass != 2)
+    return fail(LBM_ERR_ARG, "steps_per_pass must be 1 or 2 (got %d)", steps_per_pass);
+  if (z_planes < 0) return fail(LBM_ERR_ARG, "z_planes must be >= 0 (got %d)", z_planes);
+  if (tile_rows != 0 && tile_rows != 5) return fail(LBM_ERR_ARG, "tile_rows must be 0 or 5 (got %d)", tile_rows);
+  L->pass_steps = steps_per_pass;
+  L->zc = z_planes == 0 ? kDefaultZPlanes : z_planes;
+  L->tile_rows = tile_rows;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_steps_per_pass(const lbm_lattice *L, int *steps_per_pass, int *z_planes, int *tile_rows) {
+  if (!L || !steps_per_pass || !z_planes || !tile_rows) return fail(LBM_ERR_ARG, "NULL argument");
+  *steps_per_pass = L->pass_steps;
+  *z_planes = L->zc;
+  *tile_rows = L->tile_rows;
   return LBM_OK;
 }
 

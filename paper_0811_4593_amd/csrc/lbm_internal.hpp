@@ -93,6 +93,10 @@ struct SweepArgs {
 };
 
 hipError_t launch_sweep(const SweepConfig &c, const void *src, void *dst, bool copy_only, hipStream_t s);
+// Two steps (c.step and c.step + 1) in one pass, row-major layout, no solid
+// mask, face field or geometry; z ranges of zc planes per workgroup; tiles of
+// `rows` interior rows (5, or 0 for the form's default).
+hipError_t launch_sweep2(const SweepConfig &c, int zc, int rows, const void *src, void *dst, hipStream_t s);
 
 // Node codes of a complex geometry from node types (0 fluid, 1 wall node,
 // 2 solid interior), all axes periodic; code[n] as geo_code().  Returns the

@@ -33,7 +33,7 @@ EXPORTS = (
     "lbm_moments", "lbm_totals", "lbm_get_populations", "lbm_set_populations", "lbm_state_buffer",
     "lbm_set_layout", "lbm_get_layout", "lbm_buffer_elements",
     "lbm_element_bytes", "lbm_population_pitch", "lbm_set_launch", "lbm_get_launch", "lbm_autotune", "lbm_get_step",
-    "lbm_tune_placement", "lbm_probe", "lbm_get_size", "lbm_totals_static",
+    "lbm_tune_placement", "lbm_probe", "lbm_get_size", "lbm_totals_static", "lbm_set_steps_per_pass", "lbm_get_steps_per_pass",
     "lbm_destroy", "lbm_last_error",
     "lbm_job_bytes", "lbm_batch_create", "lbm_batch_submit", "lbm_batch_run_chunk", "lbm_batch_poll",
     "lbm_batch_result", "lbm_batch_set_shape", "lbm_batch_get_shape", "lbm_batch_autotune", "lbm_batch_set_policy",
@@ -41,7 +41,7 @@ EXPORTS = (
 )
 
 LBM_JOB_QUEUED, LBM_JOB_RUNNING, LBM_JOB_DONE = 0, 1, 2
-LBM_BATCH_LOCKSTEP, LBM_BATCH_SHORTEST_FIRST = 0, 1
+LBM_BATCH_LOCKSTEP, LBM_BATCH_SHORTEST_FIRST, LBM_BATCH_LARGE_IN_ORDER = 0, 1, 2
 LBM_RULE_NO_TRANSVERSE = 1
 LBM_XCD_NONE, LBM_XCD_SLABS, LBM_XCD_ROWS = 0, 1, 2  # sweep block placement on the XCDs
 LBM_LAYOUT_POPULATION_MAJOR, LBM_LAYOUT_ROW_MAJOR = 0, 1  # population layout of the device buffers
@@ -137,6 +137,8 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_tune_placement.argtypes = [_vp, st, st, ctypes.POINTER(st), _dp, _dp]
     lib.lbm_probe.argtypes = [_vp, st, st]
     lib.lbm_get_size.argtypes = [_vp, ctypes.POINTER(st), ctypes.POINTER(st), ctypes.POINTER(st)]
+    lib.lbm_set_steps_per_pass.argtypes = [_vp, st, st, st]
+    lib.lbm_get_steps_per_pass.argtypes = [_vp, ctypes.POINTER(st), ctypes.POINTER(st), ctypes.POINTER(st)]
     lib.lbm_destroy.argtypes = [_vp]
     lib.lbm_destroy.restype = None
     lib.lbm_last_error.argtypes = []
@@ -417,6 +419,17 @@ def lbm_tune_placement(h, max_buffers: int = 6, trial_steps: int = 1):
     _check(load_library().lbm_tune_placement(h, int(max_buffers), int(trial_steps), ctypes.byref(n),
                                              ctypes.byref(before), ctypes.byref(after)))
     return n.value, before.value, after.value
+
+
+def lbm_set_steps_per_pass(h, steps_per_pass: int, z_planes: int = 0, tile_rows: int = 0):
+    _check(load_library().lbm_set_steps_per_pass(h, int(steps_per_pass), int(z_planes), int(tile_rows)))
+
+
+def lbm_get_steps_per_pass(h):
+    """(steps_per_pass, z_planes, tile_rows)"""
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load_library().lbm_get_steps_per_pass(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
 
 
 def lbm_get_step(h) -> int:

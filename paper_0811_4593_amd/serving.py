@@ -136,20 +136,23 @@ class ServeReport:
 
 
 SERVE_LANES = 4  # concurrent lanes of the serving loop (the box's default of 4 hardware queues)
+SERVE_LARGE_NODES = 1 << 18  # requests of at least 64^3 nodes run one at a time, in arrival order
 
 
 def serve_trace(trace, budget_bytes, chunk=100, tol=1e-6, max_steps=20000, max_jobs=256, shape=None,
-                keep_results=(), stream=None, progress=None, policy=lbm.LBM_BATCH_SHORTEST_FIRST,
-                fill_nodes=0, lanes=SERVE_LANES):
+                keep_results=(), stream=None, progress=None, policy=lbm.LBM_BATCH_LARGE_IN_ORDER,
+                fill_nodes=SERVE_LARGE_NODES, lanes=SERVE_LANES):
     """Replay `trace` (workloads.Request list, sorted by arrival) in real time:
     each request is submitted at its arrival time; between submissions the
     batch runs chunks, admitting queued requests as slots and memory free up
     (continuous batching).  With `lanes` > 1 the chunks of up to `lanes`
     groups of requests run on the device at the same time (lbm_batch_set_lanes),
     so a request that arrives while others run starts at once beside them;
-    `policy` forms the groups (shortest remaining work first by default; a
-    request below fill_nodes nodes shares its lane's launches with other
-    small ones up to fill_nodes nodes).  Latency = completion time - arrival
+    `policy` forms the groups (lbm_batch_set_policy): by default large
+    requests (at least fill_nodes nodes) one at a time in arrival order and
+    small ones beside them on the other lanes; with shortest remaining work
+    first, a request below fill_nodes nodes shares its lane's launches with
+    other small ones up to fill_nodes nodes.  Latency = completion time - arrival
     time.  progress(done, total), if given, is called after every
     completion."""
     b = lbm.lbm_batch_create(budget_bytes, chunk, max_jobs, stream)

@@ -53,6 +53,7 @@ def test_counter_ingest(tmp_path, monkeypatch):
         launch = "256,1,1"
         layout = "rows"
         counters_command = "test"
+        steps_per_pass, zplanes, tile_rows = 1, 0, 0
 
     bench.ingest_counters(A)
     rec = json.loads(out.read_text())
@@ -65,3 +66,43 @@ def test_counter_ingest(tmp_path, monkeypatch):
     assert bench.measured_traffic([256, 1, 1], "f32", "rows") == rec["hbm_bytes_per_launch"]
     assert bench.measured_traffic([256, 1, 1], "f32", "pop") is None
     assert bench.measured_traffic([128, 1, 1], "f32", "rows") is None
+
+
+def test_counter_ingest_two_step_pass(tmp_path, monkeypatch):
+    """A run with two steps per pass is summarised on the two-step kernel,
+    whose algorithmic bytes per launch are those of two steps."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod2", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    out = tmp_path / "counters.json"
+    monkeypatch.setattr(bench, "COUNTERS_FILE", str(out))
+    from paper_0811_4593_amd import lbm
+    nx, ny, nz = 64, 32, 16
+    N = nx * ny * nz
+    copy_kib = lbm.lbm_buffer_elements(nx, ny, nz, lbm.LBM_STORE_F32, lbm.LBM_LAYOUT_ROW_MAJOR) * 4 / 1024.0
+    k2 = "void lbm::sweep2_kernel<lbm::FormF32, 13>(float const*, float*, args)"
+    k1 = "void lbm::sweep_kernel<lbm::FormF32, 256, 1, true, false, false>(float const*, float*, args)"
+    copy = "lbm::copy_probe_kernel(uint4 const*, uint4*, unsigned long)"
+    per_step_kib = 19 * N * 4 / 1024.0
+    # one launch of the pass reads 1.1 times and writes once the populations of the nodes
+    _csv(tmp_path / "f.csv", "FETCH_SIZE", [(k2, 1.1 * per_step_kib / 2), (k1, 1.0), (copy, copy_kib / 2)])
+    _csv(tmp_path / "w.csv", "WRITE_SIZE", [(k2, per_step_kib), (k1, 1.0), (copy, copy_kib)])
+
+    class A:
+        ingest_counters = (str(tmp_path / "f.csv"), str(tmp_path / "w.csv"))
+        storage = "f32"
+        nx, ny, nz = 64, 32, 16
+        launch = "256,1,1"
+        layout = "rows"
+        counters_command = "test"
+        steps_per_pass, zplanes, tile_rows = 2, 32, 0
+
+    bench.ingest_counters(A)
+    rec = json.loads(out.read_text())
+    assert rec["kernel"] == k2 and rec["steps_per_launch"] == 2
+    assert rec["algorithmic_bytes_per_launch"] == 2 * 2 * 19 * N * 4
+    assert rec["hbm_bytes_per_launch"] == pytest.approx(2.1 * 19 * N * 4, rel=1e-12)
+    assert bench.measured_traffic([256, 1, 1], "f32", "rows", 2, [2, 32, 0]) == rec["hbm_bytes_per_launch"]
+    assert bench.measured_traffic([256, 1, 1], "f32", "rows", 1, [1, 0, 0]) is None
+    assert bench.measured_traffic([256, 1, 1], "f32", "rows", 2, [2, 64, 0]) is None

@@ -232,17 +232,24 @@ def test_fp16_and_fp32_forms_against_fp64_velocity():
     assert e16sr <= 1e-3
 
 
-@pytest.mark.parametrize("lanes,fill", [(1, 0), (4, 0), (4, 6000)])
-def test_serving_loop_small_trace_same_alone_and_in_mix(lanes, fill):
+SF, LIO = lbm.LBM_BATCH_SHORTEST_FIRST, lbm.LBM_BATCH_LARGE_IN_ORDER
+
+
+@pytest.mark.parametrize("policy,lanes,fill", [(SF, 1, 0), (SF, 4, 0), (SF, 4, 6000), (LIO, 4, 6000)],
+                         ids=["shortest-1-lane", "shortest-4-lanes", "shortest-shared-launches", "large-in-order"])
+def test_serving_loop_small_trace_same_alone_and_in_mix(policy, lanes, fill):
     """The serving loop on a seeded trace of small cubes arriving faster than
     they finish: one lane (one chunk at a time), four lanes with one request
-    per lane, and four lanes where requests below 6000 nodes share their
-    lane's launches.  Every result equals the request run alone, bit for bit;
-    with four lanes chunks run beside each other on the device, and with the
-    fill threshold single launches step several requests."""
+    per lane, four lanes where requests below 6000 nodes share their lane's
+    launches, and the serving default (large requests one at a time in
+    arrival order, small ones beside them).  Every result equals the request
+    run alone, bit for bit; with four lanes chunks run beside each other on
+    the device, and with shared launches single launches step several
+    requests."""
     trace = workloads.serving_trace(count=12, rate=400.0, seed=3, n_min=12, n_max=28)
     rep = serving.serve_trace(trace, budget_bytes=64 << 20, chunk=50, tol=1e-6, max_steps=1500,
-                              max_jobs=4, keep_results=set(range(12)), lanes=lanes, fill_nodes=fill)
+                              max_jobs=4, keep_results=set(range(12)), lanes=lanes, fill_nodes=fill,
+                              policy=policy)
     say(f"serve summary lanes={lanes} fill={fill}: {rep.summary()}")
     st = rep.stats
     assert st["lanes"] == lanes
@@ -250,7 +257,7 @@ def test_serving_loop_small_trace_same_alone_and_in_mix(lanes, fill):
     assert rep.peak_resident <= 4 and rep.peak_bytes <= 64 << 20
     if lanes > 1:
         assert st["overlapped_chunks"] >= 1 and st["max_lanes_running"] >= 2
-    if fill:
+    if fill and policy == SF:
         assert st["multi_job_chunks"] >= 1 and st["max_jobs_in_chunk"] >= 2
     for i, r in enumerate(trace):
         _, _, u_alone = serving.run_plain(r.spec, r.storage, rep.steps[i])
@@ -497,5 +504,41 @@ def test_single_sweep_chunks_every_storage_form(storage):
             lbm.lbm_destroy(h)
         np.testing.assert_array_equal(rho_c, rho)
         np.testing.assert_array_equal(u_c, u)
+    finally:
+        lbm.lbm_batch_destroy(b)
+
+
+def test_large_in_order_policy():
+    """LBM_BATCH_LARGE_IN_ORDER with three lanes: the two large jobs (at least
+    4000 nodes) run one after the other in submission order, the small ones
+    beside the first; every result equals the lattice run alone."""
+    large = [workloads.duct(24, 16, 14, (0.03, 0.01, 0.0), 0.8), workloads.duct(20, 18, 15, (0.02, 0.0, 0.01), 0.9)]
+    small = [workloads.duct(10, 8, 6, (0.02, 0.0, 0.01), 0.9), workloads.duct(12, 6, 7, (0.01, 0.01, 0.0), 1.1)]
+    b = lbm.lbm_batch_create(256 << 20, 10, 8)
+    try:
+        lbm.lbm_batch_set_policy(b, lbm.LBM_BATCH_LARGE_IN_ORDER, 4000)
+        lbm.lbm_batch_set_lanes(b, 3)
+        jl = [lbm.lbm_batch_submit(b, serving.job_for(s, "f32", 0.0, 200)) for s in large]
+        js = [lbm.lbm_batch_submit(b, serving.job_for(s, "f16sr", 0.0, 60)) for s in small]
+        small_done_at = None
+        while True:
+            active, queued = lbm.lbm_batch_run_chunk(b)
+            s0, s1 = (lbm.lbm_batch_poll(b, j) for j in jl)
+            if s1.steps > 0:  # the second large job starts only after the first is done
+                assert s0.state == lbm.LBM_JOB_DONE
+            if small_done_at is None and all(lbm.lbm_batch_poll(b, j).state == lbm.LBM_JOB_DONE for j in js):
+                small_done_at = s0.steps
+            if active == 0 and queued == 0:
+                break
+        st = lbm.lbm_batch_get_stats(b)
+        say(f"first large job at {small_done_at} steps when the small ones were done; stats {st}")
+        assert small_done_at < 200 and st["overlapped_chunks"] >= 1
+        for jid, spec, storage, steps in [(j, s, "f32", 200) for j, s in zip(jl, large)] + \
+                [(j, s, "f16sr", 60) for j, s in zip(js, small)]:
+            assert lbm.lbm_batch_poll(b, jid).steps == steps
+            rho_b, u_b = lbm.lbm_batch_result(b, jid, spec.nodes)
+            _, rho_p, u_p = serving.run_plain(spec, storage, steps)
+            np.testing.assert_array_equal(rho_b, rho_p)
+            np.testing.assert_array_equal(u_b, u_p)
     finally:
         lbm.lbm_batch_destroy(b)

@@ -4,18 +4,23 @@
 Workload: the 1024 x 512 x 512 duct (no-slip on-site walls on the y and z
 faces, on-site velocity inlet and outlet (0.04, 0.01, 0.01) on the x faces,
 tau = 0.8, FP32 storage), initial state at rest, synthetic.  A step is one
-launch of the fused sweep over all 2^28 nodes (pull streaming, boundary
-rules, BGK collision).  The populations are stored row-major (the 19
-populations of each x-row together; --layout pop: population-major), and
-the lattice's two buffers are chosen by lbm_tune_placement from a pool of 8
-allocations (its trial steps are real, untimed steps; --placement 0 keeps
-the lattice's own).  Then W untimed warm-up steps, then exactly K timed
-steps bracketed by device synchronisation.
+update of all 2^28 nodes (pull streaming, boundary rules, BGK collision);
+by default two steps run per pass over HBM (lbm_set_steps_per_pass: one
+launch of the two-step kernel per pair of steps, bitwise the state of two
+single sweeps; --steps-per-pass 1: one single sweep per step).  The
+populations are stored row-major (the 19 populations of each x-row
+together; --layout pop: population-major), and the lattice's two buffers
+are chosen by lbm_tune_placement from a pool of 8 allocations (its trial
+steps are real, untimed steps; --placement 0 keeps the lattice's own).  Then
+W untimed warm-up steps, then exactly K timed steps bracketed by device
+synchronisation.
 
 Printed: one JSON line with MLUPS (the value), the roofline object for the
-sweep kernel (algorithmic bytes per launch / average launch duration measured
-with HIP events on the launch stream), the bandwidth probes of the same
-buffers, and the CPU oracle timed on a bounded sample of the same workload.
+timed kernel (algorithmic bytes per launch / average launch duration
+measured with HIP events on the launch stream), the bandwidth probes of the
+same buffers, the CPU oracle timed on a bounded sample of the same workload,
+and the systems forms (storage precision, batching, serving) at their own
+configured sizes.
 """
 from __future__ import annotations
 
@@ -34,7 +39,7 @@ if _ROOT not in sys.path:
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 METRIC = "D3Q19 MLUPS & % HBM roofline; batched solves/s, p50/p99 at ≤1e-3 L2 err"
-COUNTERS_FILE = os.path.join(_ROOT, "profiles", "sweep_f32_duct_1024x512x512_counters.json")
+COUNTERS_FILE = os.path.join(_ROOT, "profiles", "sweep2_f32_duct_1024x512x512_counters.json")
 
 
 def kernel_source_hash() -> str:
@@ -355,9 +360,10 @@ def main():
     ap.add_argument("--layout", default="rows", choices=["pop", "rows"],
                     help="population layout of the device buffers: population-major (k*P + n) or row-major "
                          "(the 19 populations of each x-row together)")
-    ap.add_argument("--steps-per-pass", type=int, default=1, choices=[1, 2],
-                    help="time steps per pass over HBM (lbm_set_steps_per_pass; 2: temporal blocking)")
-    ap.add_argument("--zplanes", type=int, default=0, help="z-planes per workgroup of the two-step pass (0: 64)")
+    ap.add_argument("--steps-per-pass", type=int, default=2, choices=[1, 2],
+                    help="time steps per pass over HBM (lbm_set_steps_per_pass; 2: two steps per read and write "
+                         "of the state, the fastest measured on this workload)")
+    ap.add_argument("--zplanes", type=int, default=32, help="z-planes per workgroup of the two-step pass (0: 64)")
     ap.add_argument("--tile-rows", type=int, default=0, help="interior rows of the two-step tiles (0: default, 5)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)

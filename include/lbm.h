@@ -343,9 +343,12 @@ lbm_status lbm_get_launch(const lbm_lattice *L, int *block_x, int *nodes_per_thr
  * face velocity field or geometry; for others, and for the last step of an
  * odd count, lbm_step runs the single sweep.  z_planes >= 1 (0: 64) sets the
  * planes per workgroup; the first step on the two planes beyond a range is
- * done by both neighbouring ranges.  steps_per_pass = 1: one single sweep
- * per step (the default).  Errors: LBM_ERR_ARG (NULL, steps_per_pass not 1
- * or 2, z_planes < 0). */
+ * done by both neighbouring ranges.  tile_rows picks the tile height: 0,
+ * the form's default; 5, five-row tiles (two workgroups per compute unit;
+ * FP64 tiles have five rows either way).  Every variant gives the same
+ * bits.  steps_per_pass = 1: one single sweep per step (the default).
+ * Errors: LBM_ERR_ARG (NULL, steps_per_pass not 1 or 2, z_planes < 0,
+ * tile_rows not 0 or 5). */
 lbm_status lbm_set_steps_per_pass(lbm_lattice *L, int steps_per_pass, int z_planes, int tile_rows);
 lbm_status lbm_get_steps_per_pass(const lbm_lattice *L, int *steps_per_pass, int *z_planes, int *tile_rows);
 
@@ -355,14 +358,20 @@ lbm_status lbm_get_steps_per_pass(const lbm_lattice *L, int *steps_per_pass, int
 lbm_status lbm_get_step(const lbm_lattice *L, unsigned long long *steps);
 
 /* Pick the fastest launch shape for this lattice by timing real steps: for
- * each candidate (blocks of 64..512 threads no wider than the row rounded up
- * to a power of two, 1, 2 or 4 nodes per thread; one node per thread with a
- * solid mask, face field or geometry; each XCD placement) one untimed and
- * trial_steps >= 1 timed steps on the lattice's stream (HIP events).  The steps are part of
- * the run (the lattice advances by (1 + trial_steps) per candidate; results
- * do not depend on the shape).  Sets the winner and returns it through the
- * non-NULL pointers.  Synchronizes.  Errors: LBM_ERR_ARG, LBM_ERR_STATE (as
- * lbm_step), LBM_ERR_HIP; on error the previous shape is restored. */
+ * each candidate of the single sweep (blocks of 64..512 threads no wider
+ * than the row rounded up to a power of two, 1, 2 or 4 nodes per thread; one
+ * node per thread with a solid mask, face field or geometry; each XCD
+ * placement) one untimed and trial_steps >= 1 timed steps, and, in the
+ * row-major layout without those options, for each two-step pass
+ * (lbm_set_steps_per_pass: z ranges of 16, 32 or 64 planes, tiles of the
+ * form's default rows or 5 rows, slab or dispatch-order placement) one
+ * untimed and trial_steps timed pairs, on the lattice's stream (HIP events,
+ * compared per step).  The steps are part of the run (results do not depend
+ * on the choice).  Sets the winner -- launch shape, steps per pass, z range
+ * and tile rows -- and returns the launch shape through the non-NULL
+ * pointers (lbm_get_steps_per_pass gives the rest).  Synchronizes.  Errors:
+ * LBM_ERR_ARG, LBM_ERR_STATE (as lbm_step), LBM_ERR_HIP; on error the
+ * previous settings are restored. */
 lbm_status lbm_autotune(lbm_lattice *L, int trial_steps, int *block_x, int *nodes_per_thread, int *xcd_remap);
 
 /* Pick the physical placement of the two population buffers by timing real

@@ -673,16 +673,33 @@ lbm_status lbm_autotune(lbm_lattice *L, int trial_steps, int *block_x, int *node
   if (trial_steps < 1) return fail(LBM_ERR_ARG, "trial_steps must be >= 1");
   const lbm_status st = lbm_step(L, 0);  // the state checks of lbm_step
   if (st != LBM_OK) return st;
-  // Candidate shapes: blocks no wider than the row rounded up to a power of
-  // two (at least 64); one node per thread for the extended sweep.
+  // Candidate shapes of the single sweep: blocks no wider than the row
+  // rounded up to a power of two (at least 64); one node per thread for the
+  // extended sweep.  In the row-major layout without extended options also
+  // the two-step pass: z ranges of 16, 32 or 64 planes, tiles of the form's
+  // default rows or 5 rows, slab or dispatch-order placement.
   const bool ext = L->d_solid || L->d_geo || L->d_face_v[0] || L->d_face_v[1] || L->d_face_v[2] ||
                    L->d_face_v[3] || L->d_face_v[4] || L->d_face_v[5];
   int row = 64;
   while (row < L->nx && row < 512) row *= 2;
-  static const int cand[][2] = {{64, 1}, {128, 1}, {256, 1}, {512, 1}, {128, 2}, {256, 2}, {128, 4}, {256, 4}};
+  struct Cand {
+    int pass, bx, npt, xcd, zc, rows;
+  };
+  std::vector<Cand> cands;
+  static const int shape[][2] = {{64, 1}, {128, 1}, {256, 1}, {512, 1}, {128, 2}, {256, 2}, {128, 4}, {256, 4}};
   static const int place[] = {LBM_XCD_SLABS, LBM_XCD_NONE, LBM_XCD_ROWS};
-  constexpr int nplace = int(sizeof(place) / sizeof(place[0]));
-  const int old[3] = {L->block_x, L->npt, L->xcd};
+  for (const auto &sh : shape)
+    for (int xcd : place) {
+      if (sh[0] * sh[1] > row || (ext && sh[1] != 1)) continue;
+      // with one block per row the rows placement is the dispatch order
+      if (xcd == LBM_XCD_ROWS && sh[0] * sh[1] >= L->nx) continue;
+      cands.push_back({1, sh[0], sh[1], xcd, 0, 0});
+    }
+  if (L->layout == LBM_LAYOUT_ROW_MAJOR && !ext)
+    for (int zc : {16, 32, 64})
+      for (int rows : {0, 5})
+        for (int xcd : {LBM_XCD_SLABS, LBM_XCD_NONE}) cands.push_back({2, L->block_x, L->npt, xcd, zc, rows});
+  const int old[6] = {L->block_x, L->npt, L->xcd, L->pass_steps, L->zc, L->tile_rows};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
@@ -691,23 +708,26 @@ lbm_status lbm_autotune(lbm_lattice *L, int trial_steps, int *block_x, int *node
   float best_ms = 0.0f;
   int best = -1;
   lbm_status result = LBM_OK;
-  for (int i = 0; i < int(sizeof(cand) / sizeof(cand[0])) * nplace; ++i) {
-    const int bx = cand[i / nplace][0], npt = cand[i / nplace][1], xcd = place[i % nplace];
-    if (bx * npt > row || (ext && npt != 1)) continue;
-    // with one block per row the rows placement is the dispatch order
-    if (xcd == LBM_XCD_ROWS && bx * npt >= L->nx) continue;
-    L->block_x = bx;
-    L->npt = npt;
-    L->xcd = xcd;
-    // one untimed step, then trial_steps timed ones (all of them real steps)
-    result = lbm_step(L, 1);
+  for (int i = 0; i < int(cands.size()); ++i) {
+    const Cand &c = cands[i];
+    L->block_x = c.bx;
+    L->npt = c.npt;
+    L->xcd = c.xcd;
+    L->pass_steps = c.pass;
+    L->zc = c.pass == 2 ? c.zc : old[4];
+    L->tile_rows = c.pass == 2 ? c.rows : old[5];
+    // untimed launches, then timed ones (all of them real steps); the pass
+    // takes pairs of steps
+    const int n = c.pass == 2 ? 2 * trial_steps : trial_steps;
+    result = lbm_step(L, c.pass);
     if (result == LBM_OK && hipEventRecord(e0, L->stream) != hipSuccess) result = hip_fail(hipGetLastError(), "event");
-    if (result == LBM_OK) result = lbm_step(L, trial_steps);
+    if (result == LBM_OK) result = lbm_step(L, n);
     if (result == LBM_OK && hipEventRecord(e1, L->stream) != hipSuccess) result = hip_fail(hipGetLastError(), "event");
     float ms = 0.0f;
     if (result == LBM_OK && hipEventSynchronize(e1) != hipSuccess) result = hip_fail(hipGetLastError(), "event");
     if (result == LBM_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) result = hip_fail(hipGetLastError(), "timing");
     if (result != LBM_OK) break;
+    ms /= float(n);  // per step
     if (best < 0 || ms < best_ms) {
       best_ms = ms;
       best = i;
@@ -719,11 +739,18 @@ lbm_status lbm_autotune(lbm_lattice *L, int trial_steps, int *block_x, int *node
     L->block_x = old[0];
     L->npt = old[1];
     L->xcd = old[2];
+    L->pass_steps = old[3];
+    L->zc = old[4];
+    L->tile_rows = old[5];
     return result != LBM_OK ? result : fail(LBM_ERR_STATE, "no launch shape to try");
   }
-  L->block_x = cand[best / nplace][0];
-  L->npt = cand[best / nplace][1];
-  L->xcd = place[best % nplace];
+  const Cand &c = cands[best];
+  L->block_x = c.bx;
+  L->npt = c.npt;
+  L->xcd = c.xcd;
+  L->pass_steps = c.pass;
+  L->zc = c.pass == 2 ? c.zc : old[4];
+  L->tile_rows = c.pass == 2 ? c.rows : old[5];
   if (block_x) *block_x = L->block_x;
   if (nodes_per_thread) *nodes_per_thread = L->npt;
   if (xcd_remap) *xcd_remap = L->xcd;

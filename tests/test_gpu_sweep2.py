@@ -139,7 +139,7 @@ def test_steps_per_pass_arguments():
     h = lbm.lbm_create(8, 8, 8, 0.8)
     try:
         assert lbm.lbm_get_steps_per_pass(h) == (1, 64, 0)
-        for bad in ((0, 0, 0), (3, 0, 0), (2, -1, 0), (2, 0, 7)):
+        for bad in ((0, 0, 0), (3, 0, 0), (2, -1, 0), (2, 0, 7), (2, 0, 9)):
             with pytest.raises(lbm.LBMError) as e:
                 lbm.lbm_set_steps_per_pass(h, *bad)
             assert e.value.status == lbm.LBM_ERR_ARG

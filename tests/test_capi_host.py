@@ -134,3 +134,42 @@ def test_population_pitch(lbm):
     assert lbm.lbm_population_pitch(1) == 64
     assert lbm.lbm_population_pitch(1024 * 512 * 512) == 1024 * 512 * 512
     assert lbm.lbm_population_pitch(221 * 17 * 93) % 64 == 0
+
+
+def test_binding_checks_node_types_before_converting(lbm):
+    """A node-type array is checked before it is cast to bytes: values that a
+    cast would wrap (256 -> 0) or truncate (0.5 -> 0) are refused, and so is
+    an array of the wrong size."""
+    import numpy as np
+    ok = np.zeros((3, 4, 5), np.int64)
+    ok[0, 0, 0] = 2
+    ok[1, 1, 1] = 1
+    code, counts = lbm.lbm_classify_geometry(ok)
+    assert code.shape == (3, 4, 5) and sum(counts) == 60
+    for bad in (np.full((3, 4, 5), 256), np.full((3, 4, 5), 0.5), np.full((3, 4, 5), -1)):
+        with pytest.raises(ValueError):
+            lbm.lbm_classify_geometry(bad)
+    with pytest.raises(ValueError):
+        lbm._node_types(np.zeros(59, np.uint8), 60, "geometry")
+
+
+def test_binding_checks_host_array_sizes(lbm):
+    import numpy as np
+    a = lbm._host_array(np.zeros(12), np.float64, 12, "x")
+    assert a.size == 12
+    with pytest.raises(ValueError):
+        lbm._host_array(np.zeros(11), np.float64, 12, "x")
+    with pytest.raises(ValueError):  # an output array must be writable float64 of the exact size
+        lbm._host_array(np.zeros(12, np.float32), np.float64, 12, "x", writable=True)
+    out = np.zeros(12)
+    assert lbm._host_array(out, np.float64, 12, "x", writable=True) is out
+
+
+def test_null_handle_calls_of_the_newer_entry_points(lbm):
+    lib = lbm.load_library()
+    assert lib.lbm_get_size(None, None, None, None) == lbm.LBM_ERR_ARG
+    assert lib.lbm_set_steps_per_pass(None, 2, 0, 0) == lbm.LBM_ERR_ARG
+    assert lib.lbm_get_steps_per_pass(None, None, None, None) == lbm.LBM_ERR_ARG
+    assert lib.lbm_batch_set_lanes(None, 2) == lbm.LBM_ERR_ARG
+    assert lib.lbm_batch_get_stats(None, None) == lbm.LBM_ERR_ARG
+    assert lib.lbm_totals_static(None, 4, 4, 4, 1, 0, None, None) == lbm.LBM_ERR_ARG

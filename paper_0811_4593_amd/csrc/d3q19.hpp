@@ -110,11 +110,14 @@ __device__ __forceinline__ void face_values(unsigned m, const NodeParams<T> &p, 
 
 // ---------------------------------------------------------------------------
 // Boundary rules of one node.  m has bit f set when the node lies on boundary
-// face f (at most one bit per axis).  The rule is written once for every
-// face, edge and corner: the set of unknown populations U, the normals and
-// the edge direction are per-lane values, every population index is a
-// compile-time constant, and each update is a select -- the 19 populations
-// stay in registers and are never indexed at run time.
+// face f (at most one bit per axis).  The face rule is instantiated per face
+// (its unknowns and normal are constants); the edge and corner rule is
+// written once for all of them, with the set of unknown populations U, the
+// normals and the edge direction as per-lane values and each update a
+// select.  Every population index is a compile-time constant, so the 19
+// populations stay in registers and are never indexed at run time.  A wave
+// whose lanes lie on one or two faces (the ends of x-rows) runs only those
+// faces' rules.
 //
 // Face (one bit; Sec. IV, Appendix; general form of eq_bbshort):
 //   rho (1 - v.n) = sum_{c.n=0} f + 2 sum_{c.n<0} f                       (eq_uin)
@@ -145,13 +148,55 @@ __device__ __forceinline__ void face_values(unsigned m, const NodeParams<T> &p, 
 //   corner form): in deviations (rho0 - 1 - s) / 14 (edge) or / 18 (corner),
 //   s the sum of the other moving populations.
 // ---------------------------------------------------------------------------
-// (vx, vy, vz, r0): the face values of a face node (face_values, or a
-// per-node field); not used on edges and corners.
-// pmask: the pressure faces among m's faces (p.p_mask for box faces, 0 for the
-// walls of a complex geometry).
+// Face rule of face b (one bit of m; b a compile-time constant, so the set of
+// unknowns U, the normal n and every population index are constants and only
+// the unknowns' updates are computed).  (vx, vy, vz, r0): the face values
+// (the face's parameters, or a per-node field); pressure: b is a pressure
+// face.  The sums run in population order and skip only terms that are
+// exactly +0 in the masked form of the rule, so the result does not depend
+// on whether the face is known at compile time.
+template <class T, int b>
+__device__ __forceinline__ void face_rule(T (&d)[19], bool pressure, T keep_n, T vx, T vy, T vz, T r0) {
+  constexpr unsigned U = unknown_mask(b);
+  constexpr int sx = face_normal(b, 0), sy = face_normal(b, 1), sz = face_normal(b, 2);
+  T s_known = T(0), s_out = T(0), Mx = T(0), My = T(0), Mz = T(0);
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    const bool unk = (U >> k) & 1u;
+    const bool out = (U >> opp(k)) & 1u;  // c_k.n < 0
+    const bool in_plane = !unk && !out;
+    if (!unk) s_known += d[k];
+    if (out) s_out += d[k];
+    if (cx(k) && in_plane) Mx += T(cx(k)) * d[k];
+    if (cy(k) && in_plane) My += T(cy(k)) * d[k];
+    if (cz(k) && in_plane) Mz += T(cz(k)) * d[k];
+  }
+  const T B = T(1) + s_known + s_out;
+  T rho = r0;
+  if (pressure) {
+    const T vn_p = T(1) - B / r0;  // normal velocity from rho0
+    vx = vx + T(sx) * vn_p;
+    vy = vy + T(sy) * vn_p;
+    vz = vz + T(sz) * vn_p;
+  }
+  const T vn = T(sx) * vx + T(sy) * vy + T(sz) * vz;
+  if (!pressure) rho = B / (T(1) - vn);
+  const T rho3 = rho / T(3);
+#pragma unroll
+  for (int j = 0; j < 18; ++j) {
+    if (!((U >> j) & 1u)) continue;
+    const int i = opp(j);
+    const T civ = T(cx(i)) * vx + T(cy(i)) * vy + T(cz(i)) * vz;
+    const T ciM = T(cx(i)) * Mx + T(cy(i)) * My + T(cz(i)) * Mz;
+    d[j] = d[i] - T(6 * w36(i)) / T(36) * rho * civ + keep_n * (T(0.5) * ciM - rho3 * (civ + vn));
+  }
+}
+
+// Edge (two bits of m) or corner (three bits), no-slip; the density of a
+// bordering pressure face (pmask: the pressure faces among m's faces; at
+// most one, as pressure faces lie on one axis) when there is one.
 template <class T>
-__device__ __forceinline__ void boundary_rule(T (&d)[19], unsigned m, const NodeParams<T> &p, unsigned pmask, T vx,
-                                              T vy, T vz, T r0) {
+__device__ __forceinline__ void edge_corner_rule(T (&d)[19], unsigned m, const NodeParams<T> &p, unsigned pmask) {
   unsigned U = 0;
 #pragma unroll
   for (int b = 0; b < 6; ++b)
@@ -161,69 +206,73 @@ __device__ __forceinline__ void boundary_rule(T (&d)[19], unsigned m, const Node
   const int sy = int((m >> 2) & 1u) - int((m >> 3) & 1u);
   const int sz = int((m >> 4) & 1u) - int((m >> 5) & 1u);
   const int nb = __popc(m);
-  if (nb == 1) {
-    // Face: n = (sx, sy, sz).
-    const bool pressure = (m & pmask) != 0u;
-    const T keep_n = (p.rule_flags & kRuleNoTransverse) ? T(0) : T(1);
-    T s_known = T(0), s_out = T(0), Mx = T(0), My = T(0), Mz = T(0);
+  const unsigned pm = m & pmask;
+  T r0 = T(1);
 #pragma unroll
-    for (int k = 0; k < 19; ++k) {
-      const bool unk = (U >> k) & 1u;
-      const bool out = (U >> opp(k)) & 1u;  // c_k.n < 0
-      const bool in_plane = !unk && !out;
-      s_known += unk ? T(0) : d[k];
-      s_out += out ? d[k] : T(0);
-      if (cx(k)) Mx += in_plane ? T(cx(k)) * d[k] : T(0);
-      if (cy(k)) My += in_plane ? T(cy(k)) * d[k] : T(0);
-      if (cz(k)) Mz += in_plane ? T(cz(k)) * d[k] : T(0);
-    }
-    const T B = T(1) + s_known + s_out;
-    const T vn_p = T(1) - B / r0;  // pressure face: normal velocity from rho0
-    vx = pressure ? vx + T(sx) * vn_p : vx;
-    vy = pressure ? vy + T(sy) * vn_p : vy;
-    vz = pressure ? vz + T(sz) * vn_p : vz;
-    const T vn = T(sx) * vx + T(sy) * vy + T(sz) * vz;
-    const T rho = pressure ? r0 : B / (T(1) - vn);
-    const T rho3 = rho / T(3);
+  for (int b = 0; b < 6; ++b)
+    if (pm & (1u << b)) r0 = p.rho_p[b];
+  const int ex = (nb == 2 && sx == 0) ? 1 : 0;
+  const int ey = (nb == 2 && sy == 0) ? 1 : 0;
+  const int ez = (nb == 2 && sz == 0) ? 1 : 0;
+  const T Pq = T(0.25) * (T(ex) * (d[0] - d[1]) + T(ey) * (d[2] - d[3]) + T(ez) * (d[4] - d[5]));
+  unsigned bur = 0;
 #pragma unroll
-    for (int j = 0; j < 18; ++j) {
-      const int i = opp(j);
-      const T civ = T(cx(i)) * vx + T(cy(i)) * vy + T(cz(i)) * vz;
-      const T ciM = T(cx(i)) * Mx + T(cy(i)) * My + T(cz(i)) * Mz;
-      const T dj = d[i] - T(6 * w36(i)) / T(36) * rho * civ + keep_n * (T(0.5) * ciM - rho3 * (civ + vn));
-      d[j] = ((U >> j) & 1u) ? dj : d[j];
-    }
-  } else {
-    // Edge or corner, no-slip; density of a bordering pressure face (at most
-    // one: pressure faces lie on one axis).
-    const unsigned pm = m & pmask;
+  for (int k = 0; k < 18; ++k) bur |= ((U >> k) & (U >> opp(k)) & 1u) << k;
 #pragma unroll
-    for (int b = 0; b < 6; ++b)
-      if (pm & (1u << b)) r0 = p.rho_p[b];
-    const int ex = (nb == 2 && sx == 0) ? 1 : 0;
-    const int ey = (nb == 2 && sy == 0) ? 1 : 0;
-    const int ez = (nb == 2 && sz == 0) ? 1 : 0;
-    const T Pq = T(0.25) * (T(ex) * (d[0] - d[1]) + T(ey) * (d[2] - d[3]) + T(ez) * (d[4] - d[5]));
-    unsigned bur = 0;
-#pragma unroll
-    for (int k = 0; k < 18; ++k) bur |= ((U >> k) & (U >> opp(k)) & 1u) << k;
-#pragma unroll
-    for (int k = 0; k < 18; ++k) {
-      const bool bounced = ((U & ~bur) >> k) & 1u;
-      const int ce = cx(k) * ex + cy(k) * ey + cz(k) * ez;
-      const T dk = d[opp(k)] - T(ce) * Pq;
-      d[k] = bounced ? dk : d[k];
-    }
-    T s = T(0);
-#pragma unroll
-    for (int k = 0; k < 18; ++k) s += ((bur >> k) & 1u) ? T(0) : d[k];
-    const T db_v = s / (nb == 2 ? T(22) : T(18));
-    const T db_p = (r0 - T(1) - s) / (nb == 2 ? T(14) : T(18));
-    const T db = pm ? db_p : db_v;
-#pragma unroll
-    for (int k = 0; k < 18; ++k) d[k] = ((bur >> k) & 1u) ? db : d[k];
-    d[18] = T(12) * db;
+  for (int k = 0; k < 18; ++k) {
+    const bool bounced = ((U & ~bur) >> k) & 1u;
+    const int ce = cx(k) * ex + cy(k) * ey + cz(k) * ez;
+    const T dk = d[opp(k)] - T(ce) * Pq;
+    d[k] = bounced ? dk : d[k];
   }
+  T s = T(0);
+#pragma unroll
+  for (int k = 0; k < 18; ++k) s += ((bur >> k) & 1u) ? T(0) : d[k];
+  const T db_v = s / (nb == 2 ? T(22) : T(18));
+  const T db_p = (r0 - T(1) - s) / (nb == 2 ? T(14) : T(18));
+  const T db = pm ? db_p : db_v;
+#pragma unroll
+  for (int k = 0; k < 18; ++k) d[k] = ((bur >> k) & 1u) ? db : d[k];
+  d[18] = T(12) * db;
+}
+
+// Boundary rule of a node with face mask m and given face values (a
+// per-node velocity field, or the walls of a complex geometry): each lane
+// runs the rule of its own face, edge or corner; a wave runs only the face
+// rules its lanes need.  (vx, vy, vz, r0): the face values of a face node;
+// not used on edges and corners.  pmask: the pressure faces among m's faces
+// (p.p_mask for box faces, 0 for the walls of a complex geometry).
+template <class T>
+__device__ __forceinline__ void boundary_rule(T (&d)[19], unsigned m, const NodeParams<T> &p, unsigned pmask, T vx,
+                                              T vy, T vz, T r0) {
+  const T keep_n = (p.rule_flags & kRuleNoTransverse) ? T(0) : T(1);
+  if (m == 1u) face_rule<T, 0>(d, (pmask & 1u) != 0u, keep_n, vx, vy, vz, r0);
+  if (m == 2u) face_rule<T, 1>(d, (pmask & 2u) != 0u, keep_n, vx, vy, vz, r0);
+  if (m == 4u) face_rule<T, 2>(d, (pmask & 4u) != 0u, keep_n, vx, vy, vz, r0);
+  if (m == 8u) face_rule<T, 3>(d, (pmask & 8u) != 0u, keep_n, vx, vy, vz, r0);
+  if (m == 16u) face_rule<T, 4>(d, (pmask & 16u) != 0u, keep_n, vx, vy, vz, r0);
+  if (m == 32u) face_rule<T, 5>(d, (pmask & 32u) != 0u, keep_n, vx, vy, vz, r0);
+  if (m & (m - 1u)) edge_corner_rule<T>(d, m, p, pmask);
+}
+
+// Boundary rule of a node of a box whose faces take the lattice's face
+// parameters (velocity, or tangential velocity and density of a pressure
+// face): as boundary_rule, with the face values read directly.
+template <class T>
+__device__ __forceinline__ void box_boundary_rule(T (&d)[19], unsigned m, const NodeParams<T> &p) {
+  const T keep_n = (p.rule_flags & kRuleNoTransverse) ? T(0) : T(1);
+#define LBM_FACE(b)                                                                                        \
+  if (m == (1u << (b)))                                                                                    \
+    face_rule<T, b>(d, ((p.p_mask >> (b)) & 1u) != 0u, keep_n, p.fv.v[b][0], p.fv.v[b][1], p.fv.v[b][2], \
+                    p.rho_p[b]);
+  LBM_FACE(0)
+  LBM_FACE(1)
+  LBM_FACE(2)
+  LBM_FACE(3)
+  LBM_FACE(4)
+  LBM_FACE(5)
+#undef LBM_FACE
+  if (m & (m - 1u)) edge_corner_rule<T>(d, m, p, p.p_mask);
 }
 
 // ---------------------------------------------------------------------------

@@ -63,11 +63,7 @@ __device__ __forceinline__ unsigned box_faces(unsigned bc_mask, int x, int y, in
 // Boundary rule and collision of one node (the plain path of update_node).
 template <class T>
 __device__ __forceinline__ void rule_and_collide(T (&f)[19], unsigned m, const NodeParams<T> &p) {
-  if (m) {
-    T vx, vy, vz, r0;
-    face_values<T>(m, p, vx, vy, vz, r0);
-    boundary_rule<T>(f, m, p, p.p_mask, vx, vy, vz, r0);
-  }
+  if (m) box_boundary_rule<T>(f, m, p);
   bgk_collide<T>(f, p.omega, p.tau_f);
 }
 

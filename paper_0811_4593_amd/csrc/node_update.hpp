@@ -377,23 +377,22 @@ __device__ __forceinline__ void update_node(const Access &mem, const NodeGeom &g
         general_wall_rule<T>(f, gcode & 0x3ffffu);
       }
     }
-    if (m) {
+    if (!EXT && m) box_boundary_rule<T>(f, m, p);
+    if (EXT && m) {
       T vx, vy, vz, r0;
       face_values<T>(m, p, vx, vy, vz, r0);
-      if constexpr (EXT) {
-        const double *fld = nullptr;
-        unsigned idx = 0;
+      const double *fld = nullptr;
+      unsigned idx = 0;
 #pragma unroll
-        for (int b = 0; b < 6; ++b)
-          if (m == (1u << b)) {
-            fld = ext.face_v[b];
-            idx = b < 2 ? unsigned(y) + ny * unsigned(z) : (b < 4 ? unsigned(x) + nx * unsigned(z) : unsigned(x) + nx * unsigned(y));
-          }
-        if (fld) {
-          vx = T(fld[3 * idx]);
-          vy = T(fld[3 * idx + 1]);
-          vz = T(fld[3 * idx + 2]);
+      for (int b = 0; b < 6; ++b)
+        if (m == (1u << b)) {
+          fld = ext.face_v[b];
+          idx = b < 2 ? unsigned(y) + ny * unsigned(z) : (b < 4 ? unsigned(x) + nx * unsigned(z) : unsigned(x) + nx * unsigned(y));
         }
+      if (fld) {
+        vx = T(fld[3 * idx]);
+        vy = T(fld[3 * idx + 1]);
+        vz = T(fld[3 * idx + 2]);
       }
       boundary_rule<T>(f, m, p, p.p_mask, vx, vy, vz, r0);
     }

@@ -493,8 +493,9 @@ lbm_status lbm_batch_poll(lbm_batch *B, int job_id, lbm_job_status *st);
 lbm_status lbm_batch_result(lbm_batch *B, int job_id, double *rho, double *u);
 
 /* Launch shape of the multi-lattice sweep: block_x threads (128 or 256),
- * tile_nodes nodes per tile (>= 256), grid_blocks persistent blocks (0: 8 per
- * compute unit).  Any shape gives the same results. */
+ * tile_nodes nodes per tile (>= 256), grid_blocks 0 for one workgroup per
+ * tile (the default, with tiles of 256 nodes), or that many persistent
+ * workgroups walking the tile list.  Any shape gives the same results. */
 lbm_status lbm_batch_set_shape(lbm_batch *B, int block_x, int tile_nodes, int grid_blocks);
 
 /* Which resident jobs a chunk steps (with one lane; lbm_batch_set_lanes
@@ -528,8 +529,10 @@ lbm_status lbm_batch_set_policy(lbm_batch *B, int policy, size_t fill_nodes);
 lbm_status lbm_batch_get_shape(const lbm_batch *B, int *block_x, int *tile_nodes, int *grid_blocks);
 
 /* Admit what fits, then time trial_steps (even) steps of the resident jobs
- * for each candidate shape (block 128/256, tiles of 1024/4096/16384 nodes,
- * 4/8/16 blocks per compute unit) and keep the fastest.  The trial steps are
+ * for each candidate shape (one workgroup per tile: 256 threads and tiles of
+ * 256, 512 or 1024 nodes, 128 threads and 256 nodes; persistent: 256 threads,
+ * 1024-node tiles, 16 workgroups per compute unit, and 128 threads, 1024
+ * nodes, 8 per compute unit) and keep the fastest.  The trial steps are
  * real steps of every resident job (their step counts advance).  Results are
  * cached per process by storage mix and node-count class; a cached class is
  * not re-timed.  Outputs may be NULL.  Errors: LBM_ERR_ARG, LBM_ERR_STATE (no

@@ -456,7 +456,8 @@ typedef struct {
 } lbm_job_status;
 
 /* Device bytes a job occupies while resident: two population buffers and a
- * float velocity snapshot, each rounded up to 256 bytes.  Errors: LBM_ERR_ARG. */
+ * float velocity snapshot, each rounded up to 256 bytes -- the larger of the
+ * two layouts a batch may give it.  Errors: LBM_ERR_ARG. */
 lbm_status lbm_job_bytes(const lbm_job *job, size_t *bytes);
 
 /* Create a batch with a device pool of hbm_budget_bytes (one allocation, made
@@ -520,19 +521,47 @@ lbm_status lbm_batch_set_shape(lbm_batch *B, int block_x, int tile_nodes, int gr
  *                             work first, beside the large one.
  * Set the policy before submitting: with LBM_BATCH_SHORTEST_FIRST, jobs of
  * at least fill_nodes nodes submitted afterwards are stored row-major with
- * padded rows, with LBM_BATCH_LARGE_IN_ORDER every job; a chunk that steps
- * a single row-major job runs the single-lattice sweep on it.  lbm_job_bytes gives the bytes of the lockstep
- * layout.  lbm_batch_autotune steps every resident job whatever the policy.
+ * padded rows, with LBM_BATCH_LARGE_IN_ORDER every job (and with two steps
+ * per pass, lbm_batch_set_steps_per_pass(B, 2, ...), every job whatever the
+ * policy); a chunk that steps a single row-major job runs the single-lattice
+ * sweep (or two-step pass) on it.
+ * lbm_batch_autotune steps every resident job whatever the policy.
  * Errors: LBM_ERR_ARG (NULL, unknown policy). */
 enum { LBM_BATCH_LOCKSTEP = 0, LBM_BATCH_SHORTEST_FIRST = 1, LBM_BATCH_LARGE_IN_ORDER = 2 };
 lbm_status lbm_batch_set_policy(lbm_batch *B, int policy, size_t fill_nodes);
 lbm_status lbm_batch_get_shape(const lbm_batch *B, int *block_x, int *tile_nodes, int *grid_blocks);
 
+/* Steps per pass over HBM for the batch's chunks (Sec. II's update, two steps
+ * at a time as lbm_set_steps_per_pass does for one lattice):
+ *   1 (the default)  one step per launch;
+ *   2                every chunk by passes of two steps: one launch per
+ *                    storage form over the 64 x 13 (FP64: 64 x 5) tiles and
+ *                    z ranges of z_planes planes (0: 32) of all its jobs, or
+ *                    the single-lattice two-step kernel for a chunk of one
+ *                    job; every job is then stored row-major with padded
+ *                    rows.
+ * Single steps close a chunk whose step count needs them (chunk_steps 2 mod
+ * 4: two).  Results are the same bits in either mode.  Two steps per pass
+ * pay for batches of large FP32 and FP64 lattices (eight 256^3 cubes: FP32
+ * 37.1 -> 40.4 GLUPS, FP64 17.8 -> 23.8), not for small or narrow ones: on
+ * 64 uneven ducts of 32-256 x 16-128 x 16-128 nodes they ran 1.3x slower
+ * than one step per launch (a quarter of the tiles' lanes fall outside such
+ * lattices), and a chunk of one cube of up to 320^3 nodes has too few tiles
+ * to fill the chip (FP32 no faster, FP16 1.6x slower).
+ * Errors: LBM_ERR_ARG (steps not 1 or 2, z_planes outside [0, 4096]),
+ * LBM_ERR_STATE (a chunk in flight; 2 while a population-major job is queued
+ * or resident -- set the mode before submitting). */
+lbm_status lbm_batch_set_steps_per_pass(lbm_batch *B, int steps_per_pass, int z_planes);
+lbm_status lbm_batch_get_steps_per_pass(const lbm_batch *B, int *steps_per_pass, int *z_planes);
+
 /* Admit what fits, then time trial_steps (even) steps of the resident jobs
  * for each candidate shape (one workgroup per tile: 256 threads and tiles of
  * 256, 512 or 1024 nodes, 128 threads and 256 nodes; persistent: 256 threads,
  * 1024-node tiles, 16 workgroups per compute unit, and 128 threads, 1024
- * nodes, 8 per compute unit) and keep the fastest.  The trial steps are
+ * nodes, 8 per compute unit) and keep the fastest; with two steps per pass,
+ * z ranges of 16, 32 or 64 planes in two box orders (each XCD a contiguous
+ * share of the box list, or dispatch order), timed over trial_steps rounded
+ * up to a multiple of 4 (at least 4) after 4 warm-up steps.  The trial steps are
  * real steps of every resident job (their step counts advance).  Results are
  * cached per process by storage mix and node-count class; a cached class is
  * not re-timed.  Outputs may be NULL.  Errors: LBM_ERR_ARG, LBM_ERR_STATE (no

@@ -16,6 +16,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <tuple>
 #include <new>
 #include <mutex>
 #include <thread>
@@ -25,6 +26,7 @@
 #include "lbm_internal.hpp"
 #include "lbm_launch_defaults.hpp"
 #include "node_update.hpp"
+#include "sweep2_box.hpp"
 
 namespace lbm {
 
@@ -73,8 +75,8 @@ constexpr unsigned kTileGroup = 4;
 // workgroups).  Each lane updates the nodes of slots n0 + t, n0 + t + BX, ...
 // of its tile (the padding slots of a row-major lattice with padded rows stay
 // idle, so that its rows' waves start on cache lines as the rows do).  `s` is
-// the index of the step within the launch sequence: it selects source and
-// destination buffer (parity) and, with the lattice's step_base, the step key.
+// the index of the step within the launch sequence (with the lattice's
+// step_base, the step key); the step reads buf[parity] and writes the other.
 //
 // One workgroup per tile beat persistent workgroups by 14% on the 64 ducts
 // (1.305 against 1.510 ms per step, tiles of 256 against the persistent
@@ -82,13 +84,31 @@ constexpr unsigned kTileGroup = 4;
 // waits on the dependent loads of each new tile's descriptor and lattice
 // parameters before its first gather, where fresh workgroups start while
 // others still run.
+// Node-update parameters of a lattice in the arithmetic type T.
+template <class T>
+__device__ __forceinline__ NodeParams<T> lattice_params(const BatchLat &L) {
+  NodeParams<T> prm;
+  prm.bc_mask = L.bc_mask;
+  prm.p_mask = L.p_mask;
+  prm.rule_flags = 0u;
+  prm.omega = T(L.omega);
+#pragma unroll
+  for (int f = 0; f < 6; ++f) prm.rho_p[f] = T(L.rho_p[f]);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) prm.tau_f[d] = T(L.tau_f[d]);
+#pragma unroll
+  for (int f = 0; f < 6; ++f)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) prm.fv.v[f][d] = T(L.v[f][d]);
+  return prm;
+}
+
 template <class F, int BX>
 __global__ __launch_bounds__(BX) void batch_sweep_kernel(const BatchLat *__restrict__ lats,
                                                          const BatchTile *__restrict__ tiles,
-                                                         const int *__restrict__ ntiles, int s) {
+                                                         const int *__restrict__ ntiles, int s, int parity) {
   using S = typename F::S;
   using T = typename Codec<S>::T;
-  const int parity = s & 1;
   const int nt = *ntiles;
   const bool own_tile = int(gridDim.x) >= nt;
   for (int b = blockIdx.x; b < nt; b += gridDim.x) {
@@ -99,19 +119,7 @@ __global__ __launch_bounds__(BX) void batch_sweep_kernel(const BatchLat *__restr
     const unsigned buf_bytes = L.buf_elems * unsigned(sizeof(S));
     const BufAccess<S> mem{raw_buffer(L.buf[parity], buf_bytes), raw_buffer(L.buf[parity ^ 1], buf_bytes),
                            L.pop_stride * unsigned(sizeof(S)), buf_bytes};
-    NodeParams<T> prm;
-    prm.bc_mask = L.bc_mask;
-    prm.p_mask = L.p_mask;
-    prm.rule_flags = 0u;
-    prm.omega = T(L.omega);
-#pragma unroll
-    for (int f = 0; f < 6; ++f) prm.rho_p[f] = T(L.rho_p[f]);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) prm.tau_f[d] = T(L.tau_f[d]);
-#pragma unroll
-    for (int f = 0; f < 6; ++f)
-#pragma unroll
-      for (int d = 0; d < 3; ++d) prm.fv.v[f][d] = T(L.v[f][d]);
+    const NodeParams<T> prm = lattice_params<T>(L);
     const unsigned key = step_key(L.step_base + unsigned(s));
     // Coordinates of the lane's first slot, then advanced by BX slots per
     // iteration with carries (one division per tile instead of two per node).
@@ -197,28 +205,106 @@ __global__ __launch_bounds__(256) void batch_delta_kernel(const BatchLat *__rest
   }
 }
 
+// One box of the multi-lattice two-step pass: tile (tx, ty) of 64 x BYI
+// nodes and z range tz of lattice `lat` (row-major).
+struct BatchBox {
+  int lat;
+  unsigned tx, ty, tz;
+};
+
+// Steps s and s + 1 of every lattice of storage form F listed in `boxes`,
+// one workgroup per box (workgroups past the box count exit at once): the
+// single-lattice two-step pass's box update (sweep2_box) with the lattice's
+// parameters from its descriptor, reading buf[parity] and writing the other
+// buffer, so that each lattice gets the bits of two single sweeps.  remap:
+// the box list's order on the XCDs (logical_block).
+template <class F, int BYI>
+__global__ __launch_bounds__(64 * (BYI + 3)) void batch_pass_kernel(const BatchLat *__restrict__ lats,
+                                                                    const BatchBox *__restrict__ boxes,
+                                                                    const int *__restrict__ nboxes, int s, int parity,
+                                                                    int zc, int remap) {
+  using S = typename F::S;
+  using T = typename Codec<S>::T;
+  __shared__ S ring[kRingPlanes * Sweep2Tile<F, BYI>::kPlane];
+  const int nb = *nboxes;
+  if (int(blockIdx.x) >= nb) return;  // uniform over the workgroup
+  const BatchBox bx = boxes[logical_block(blockIdx.x, unsigned(nb), remap, 1u)];
+  const BatchLat &L = lats[bx.lat];
+  Sweep2Args<T> a;
+  a.nx = int(L.nx);
+  a.ny = int(L.ny);
+  a.nz = int(L.nz);
+  a.pop_stride = L.pop_stride;
+  a.row_stride = L.row_stride;
+  a.tiles_x = 0;  // the box is given
+  a.tiles_y = 0;
+  a.zc = zc;
+  a.xcd_remap = 0;
+  a.key0 = step_key(L.step_base + unsigned(s));
+  a.key1 = step_key(L.step_base + unsigned(s) + 1u);
+  a.p = lattice_params<T>(L);
+  // global (not flat) accesses: the addresses come from memory
+  const global_ptr<const S> src = (global_ptr<const S>)(L.buf[parity]);
+  const global_ptr<S> dst = (global_ptr<S>)(L.buf[parity ^ 1]);
+  sweep2_box<F, BYI, global_ptr<const S>, global_ptr<S>>(src, dst, a, bx.tx, bx.ty, bx.tz, ring);
+}
+
 __global__ void fill_float_kernel(float *__restrict__ p, size_t n, float v) {
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
 
 template <class F, int BX>
-static void launch_batch_sweep_t(const BatchLat *lats, const BatchTile *tiles, const int *nt, int s, int grid,
-                                 hipStream_t st) {
-  batch_sweep_kernel<F, BX><<<dim3(grid), dim3(BX), 0, st>>>(lats, tiles, nt, s);
+static void launch_batch_sweep_t(const BatchLat *lats, const BatchTile *tiles, const int *nt, int s, int parity,
+                                 int grid, hipStream_t st) {
+  batch_sweep_kernel<F, BX><<<dim3(grid), dim3(BX), 0, st>>>(lats, tiles, nt, s, parity);
 }
 
 static hipError_t launch_batch_sweep(int storage, int bx, const BatchLat *lats, const BatchTile *tiles, const int *nt,
-                                     int s, int grid, hipStream_t st) {
+                                     int s, int parity, int grid, hipStream_t st) {
   switch (storage * 1000 + bx) {
-    case kStoreF64 * 1000 + 128: launch_batch_sweep_t<FormF64, 128>(lats, tiles, nt, s, grid, st); break;
-    case kStoreF64 * 1000 + 256: launch_batch_sweep_t<FormF64, 256>(lats, tiles, nt, s, grid, st); break;
-    case kStoreF32 * 1000 + 128: launch_batch_sweep_t<FormF32, 128>(lats, tiles, nt, s, grid, st); break;
-    case kStoreF32 * 1000 + 256: launch_batch_sweep_t<FormF32, 256>(lats, tiles, nt, s, grid, st); break;
-    case kStoreF16 * 1000 + 128: launch_batch_sweep_t<FormF16, 128>(lats, tiles, nt, s, grid, st); break;
-    case kStoreF16 * 1000 + 256: launch_batch_sweep_t<FormF16, 256>(lats, tiles, nt, s, grid, st); break;
-    case kStoreF16SR * 1000 + 128: launch_batch_sweep_t<FormF16SR, 128>(lats, tiles, nt, s, grid, st); break;
-    case kStoreF16SR * 1000 + 256: launch_batch_sweep_t<FormF16SR, 256>(lats, tiles, nt, s, grid, st); break;
+    case kStoreF64 * 1000 + 128: launch_batch_sweep_t<FormF64, 128>(lats, tiles, nt, s, parity, grid, st); break;
+    case kStoreF64 * 1000 + 256: launch_batch_sweep_t<FormF64, 256>(lats, tiles, nt, s, parity, grid, st); break;
+    case kStoreF32 * 1000 + 128: launch_batch_sweep_t<FormF32, 128>(lats, tiles, nt, s, parity, grid, st); break;
+    case kStoreF32 * 1000 + 256: launch_batch_sweep_t<FormF32, 256>(lats, tiles, nt, s, parity, grid, st); break;
+    case kStoreF16 * 1000 + 128: launch_batch_sweep_t<FormF16, 128>(lats, tiles, nt, s, parity, grid, st); break;
+    case kStoreF16 * 1000 + 256: launch_batch_sweep_t<FormF16, 256>(lats, tiles, nt, s, parity, grid, st); break;
+    case kStoreF16SR * 1000 + 128:
+      launch_batch_sweep_t<FormF16SR, 128>(lats, tiles, nt, s, parity, grid, st);
+      break;
+    case kStoreF16SR * 1000 + 256:
+      launch_batch_sweep_t<FormF16SR, 256>(lats, tiles, nt, s, parity, grid, st);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Interior rows of the two-step pass's tiles for a storage form.
+static int pass_rows(int storage) {
+  switch (storage) {
+    case kStoreF64: return Sweep2Rows<FormF64>::kBYI;
+    case kStoreF32: return Sweep2Rows<FormF32>::kBYI;
+    case kStoreF16: return Sweep2Rows<FormF16>::kBYI;
+    default: return Sweep2Rows<FormF16SR>::kBYI;
+  }
+}
+
+template <class F>
+static void launch_batch_pass_t(const BatchLat *lats, const BatchBox *boxes, const int *nb, int s, int parity, int zc,
+                                int remap, int grid, hipStream_t st) {
+  constexpr int BYI = Sweep2Rows<F>::kBYI;
+  batch_pass_kernel<F, BYI><<<dim3(grid), dim3(Sweep2Tile<F, BYI>::kThreads), 0, st>>>(lats, boxes, nb, s, parity,
+                                                                                     zc, remap);
+}
+
+static hipError_t launch_batch_pass(int storage, const BatchLat *lats, const BatchBox *boxes, const int *nb, int s,
+                                    int parity, int zc, int remap, int grid, hipStream_t st) {
+  switch (storage) {
+    case kStoreF64: launch_batch_pass_t<FormF64>(lats, boxes, nb, s, parity, zc, remap, grid, st); break;
+    case kStoreF32: launch_batch_pass_t<FormF32>(lats, boxes, nb, s, parity, zc, remap, grid, st); break;
+    case kStoreF16: launch_batch_pass_t<FormF16>(lats, boxes, nb, s, parity, zc, remap, grid, st); break;
+    case kStoreF16SR: launch_batch_pass_t<FormF16SR>(lats, boxes, nb, s, parity, zc, remap, grid, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -406,10 +492,17 @@ struct Shape {
   int block_x = 256, tile_nodes = 256, grid = 0;  // grid 0: one workgroup per tile
 };
 
+// A tuned configuration: the single step's shape, and the two-step pass's z
+// planes and box order.
+struct Tuned {
+  Shape shape;
+  int zc = 32, remap = 1;
+};
+
 // Autotune results shared by every batch in the process, keyed by a coarse
-// description of the resident work (storage mix, log2 of the node count);
-// batches on different threads share it under a lock.
-std::map<long long, Shape> g_tuned;
+// description of the resident work (storage mix, log2 of the node count,
+// steps per pass); batches on different threads share it under a lock.
+std::map<long long, Tuned> g_tuned;
 std::mutex g_tuned_mutex;
 
 // One lane: a stream with its own descriptor and tile tables, so that the
@@ -425,16 +518,21 @@ struct Lane {
   std::vector<int> slots;  // slots the chunk in flight steps
   lbm::BatchLat *d_lats = nullptr;
   unsigned *d_delta = nullptr;
-  int *d_ntiles = nullptr;
+  int *d_ntiles = nullptr;  // tile counts per storage form, then box counts
   lbm::BatchTile *d_tiles[kNumStorage] = {nullptr, nullptr, nullptr, nullptr};
   size_t tile_cap[kNumStorage] = {0, 0, 0, 0};
-  HostBlock h_lats, h_delta, h_ntiles, h_tiles[kNumStorage];
+  lbm::BatchBox *d_boxes[kNumStorage] = {nullptr, nullptr, nullptr, nullptr};  // the two-step pass's boxes
+  size_t box_cap[kNumStorage] = {0, 0, 0, 0};
+  HostBlock h_lats, h_delta, h_ntiles, h_tiles[kNumStorage], h_boxes[kNumStorage];
   int ntiles[kNumStorage] = {0, 0, 0, 0};
+  int nboxes[kNumStorage] = {0, 0, 0, 0};
   // Jobs (slot, job id) the tile tables describe: a slot reused by a later
   // job has other extents, so the tables follow the job ids, not the slots.
   std::vector<std::pair<int, int>> table_jobs;
-  int table_tile_nodes = 0;
-  std::map<long long, hipGraphExec_t> graphs;
+  int table_tile_nodes = 0, table_pass = 0, table_zc = 0;
+  // captured chunks by (storage forms present, chunk steps, block_x, grid,
+  // steps per pass, z planes, box order)
+  std::map<std::tuple<unsigned, int, int, int, int, int, int>, hipGraphExec_t> graphs;
 };
 
 }  // namespace
@@ -447,6 +545,10 @@ struct lbm_batch {
   int chunk_steps = 100;
   int max_jobs = 0;
   Shape shape;
+  // Steps per pass: 1, one step per launch; 2, two steps per pass over the
+  // jobs of every chunk (every job row-major), z ranges of pass_zc planes per
+  // workgroup, box order pass_remap on the XCDs.
+  int pass_steps = 1, pass_zc = 32, pass_remap = 1;
   std::map<int, Job> jobs;
   std::deque<int> queue;
   std::vector<int> slot_job;           // slot -> job id (-1 free)
@@ -479,8 +581,10 @@ void free_lane(Lane &ln) {
   if (ln.d_lats) (void)hipFree(ln.d_lats);
   if (ln.d_delta) (void)hipFree(ln.d_delta);
   if (ln.d_ntiles) (void)hipFree(ln.d_ntiles);
-  for (int s = 0; s < kNumStorage; ++s)
+  for (int s = 0; s < kNumStorage; ++s) {
     if (ln.d_tiles[s]) (void)hipFree(ln.d_tiles[s]);
+    if (ln.d_boxes[s]) (void)hipFree(ln.d_boxes[s]);
+  }
   if (ln.done) (void)hipEventDestroy(ln.done);
   if (ln.own_stream && ln.stream) (void)hipStreamDestroy(ln.stream);
   ln = Lane();
@@ -499,37 +603,39 @@ lbm_status init_lane(lbm_batch *B, Lane &ln, hipStream_t given) {
   const size_t mj = size_t(B->max_jobs);
   bool ok = hipMalloc(&ln.d_lats, sizeof(lbm::BatchLat) * mj) == hipSuccess &&
             hipMalloc(&ln.d_delta, sizeof(unsigned) * mj) == hipSuccess &&
-            hipMalloc(&ln.d_ntiles, sizeof(int) * kNumStorage) == hipSuccess;
+            hipMalloc(&ln.d_ntiles, sizeof(int) * 2 * kNumStorage) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
     return bfail(LBM_ERR_OOM, "device tables of a lane could not be allocated");
   }
   if (!ln.h_lats.allocate(sizeof(lbm::BatchLat) * mj, true) || !ln.h_delta.allocate(sizeof(unsigned) * mj, true) ||
-      !ln.h_ntiles.allocate(sizeof(int) * kNumStorage, true))
+      !ln.h_ntiles.allocate(sizeof(int) * 2 * kNumStorage, true))
     return bfail(LBM_ERR_OOM, "page-locked staging of a lane could not be allocated");
   std::memset(ln.h_lats.as<void>(), 0, ln.h_lats.bytes());
   return LBM_OK;
 }
 
-// Room for n tiles of storage form s in a lane's tables.  A new device
-// table invalidates the lane's captured graphs (their launches hold the old
-// address).  Only called while the lane is idle.
-lbm_status ensure_tiles(Lane &ln, int s, size_t n) {
-  if (n <= ln.tile_cap[s]) return LBM_OK;
-  size_t cap = std::max<size_t>(n, 2 * ln.tile_cap[s]);
-  cap = std::max<size_t>(cap, 1024);
+// Room for n entries in one of a lane's device tables (tiles or boxes of a
+// storage form) and its page-locked staging.  A new device table invalidates
+// the lane's captured graphs (their launches hold the old address and take
+// the old capacity as their grid).  Only called while the lane is idle.
+template <class E>
+lbm_status ensure_table(Lane &ln, E *&d, size_t &cap, HostBlock &h, size_t n, const char *what) {
+  if (n <= cap) return LBM_OK;
+  size_t c = std::max<size_t>(n, 2 * cap);
+  c = std::max<size_t>(c, 1024);
   drop_graphs(ln);
-  if (ln.d_tiles[s]) (void)hipFree(ln.d_tiles[s]);
-  ln.d_tiles[s] = nullptr;
-  ln.tile_cap[s] = 0;
-  if (hipMalloc(&ln.d_tiles[s], sizeof(lbm::BatchTile) * cap) != hipSuccess) {
+  if (d) (void)hipFree(d);
+  d = nullptr;
+  cap = 0;
+  if (hipMalloc(&d, sizeof(E) * c) != hipSuccess) {
     (void)hipGetLastError();
-    ln.d_tiles[s] = nullptr;
-    return bfail(LBM_ERR_OOM, "tile table of %zu entries could not be allocated", cap);
+    d = nullptr;
+    return bfail(LBM_ERR_OOM, "%s table of %zu entries could not be allocated", what, c);
   }
-  if (!ln.h_tiles[s].allocate(sizeof(lbm::BatchTile) * cap, true))
-    return bfail(LBM_ERR_OOM, "page-locked tile staging of %zu entries could not be allocated", cap);
-  ln.tile_cap[s] = cap;
+  if (!h.allocate(sizeof(E) * c, true))
+    return bfail(LBM_ERR_OOM, "page-locked %s staging of %zu entries could not be allocated", what, c);
+  cap = c;
   return LBM_OK;
 }
 
@@ -547,31 +653,57 @@ unsigned present_mask(const Lane &ln) {
 lbm_status upload_tables(lbm_batch *B, Lane &ln, const std::vector<int> &slots) {
   std::vector<std::pair<int, int>> jobs;
   for (int slot : slots) jobs.push_back({slot, B->slot_job[slot]});
-  if (jobs != ln.table_jobs || ln.table_tile_nodes != B->shape.tile_nodes) {
+  const bool pass2 = B->pass_steps == 2;
+  if (jobs != ln.table_jobs || ln.table_tile_nodes != B->shape.tile_nodes || ln.table_pass != B->pass_steps ||
+      ln.table_zc != B->pass_zc) {
     std::vector<lbm::BatchTile> tiles[kNumStorage];
+    std::vector<lbm::BatchBox> boxes[kNumStorage];
     const unsigned tn = unsigned(B->shape.tile_nodes);
     for (int slot : slots) {
       const Job &J = B->jobs.at(B->slot_job[slot]);
+      const int st = J.spec.storage;
       const unsigned S = unsigned(size_t(B->lat[slot].slot_row) * J.spec.ny * J.spec.nz);  // slots of the job
-      for (unsigned n0 = 0; n0 < S; n0 += tn) tiles[J.spec.storage].push_back({slot, n0, std::min(S, n0 + tn)});
+      for (unsigned n0 = 0; n0 < S; n0 += tn) tiles[st].push_back({slot, n0, std::min(S, n0 + tn)});
+      if (!pass2) continue;
+      if (J.layout != LBM_LAYOUT_ROW_MAJOR)
+        return bfail(LBM_ERR_STATE, "job %d is not row-major: two steps per pass need every job row-major",
+                     B->slot_job[slot]);
+      // boxes z range by z range, row of tiles by row of tiles
+      const unsigned by = unsigned(lbm::pass_rows(st)), zc = unsigned(B->pass_zc);
+      const unsigned tx = (unsigned(J.spec.nx) + 63u) / 64u, ty = (unsigned(J.spec.ny) + by - 1u) / by;
+      const unsigned tz = (unsigned(J.spec.nz) + zc - 1u) / zc;
+      for (unsigned z = 0; z < tz; ++z)
+        for (unsigned y = 0; y < ty; ++y)
+          for (unsigned x = 0; x < tx; ++x) boxes[st].push_back({slot, x, y, z});
     }
+    int *counts = ln.h_ntiles.as<int>();
     for (int s = 0; s < kNumStorage; ++s) {
-      lbm_status st = ensure_tiles(ln, s, tiles[s].size());
+      lbm_status st = ensure_table(ln, ln.d_tiles[s], ln.tile_cap[s], ln.h_tiles[s], tiles[s].size(), "tile");
+      if (st == LBM_OK) st = ensure_table(ln, ln.d_boxes[s], ln.box_cap[s], ln.h_boxes[s], boxes[s].size(), "box");
       if (st != LBM_OK) return st;
       ln.ntiles[s] = int(tiles[s].size());
+      ln.nboxes[s] = int(boxes[s].size());
       if (!tiles[s].empty()) {
         std::memcpy(ln.h_tiles[s].as<void>(), tiles[s].data(), tiles[s].size() * sizeof(lbm::BatchTile));
         LBM_BHIP(hipMemcpyAsync(ln.d_tiles[s], ln.h_tiles[s].as<void>(), tiles[s].size() * sizeof(lbm::BatchTile),
                                 hipMemcpyHostToDevice, ln.stream),
                  "upload tiles");
       }
-      ln.h_ntiles.as<int>()[s] = ln.ntiles[s];
+      if (!boxes[s].empty()) {
+        std::memcpy(ln.h_boxes[s].as<void>(), boxes[s].data(), boxes[s].size() * sizeof(lbm::BatchBox));
+        LBM_BHIP(hipMemcpyAsync(ln.d_boxes[s], ln.h_boxes[s].as<void>(), boxes[s].size() * sizeof(lbm::BatchBox),
+                                hipMemcpyHostToDevice, ln.stream),
+                 "upload boxes");
+      }
+      counts[s] = ln.ntiles[s];
+      counts[kNumStorage + s] = ln.nboxes[s];
     }
-    LBM_BHIP(hipMemcpyAsync(ln.d_ntiles, ln.h_ntiles.as<void>(), sizeof(int) * kNumStorage, hipMemcpyHostToDevice,
-                            ln.stream),
-             "upload tile counts");
+    LBM_BHIP(hipMemcpyAsync(ln.d_ntiles, counts, sizeof(int) * 2 * kNumStorage, hipMemcpyHostToDevice, ln.stream),
+             "upload tile and box counts");
     ln.table_jobs = jobs;
     ln.table_tile_nodes = B->shape.tile_nodes;
+    ln.table_pass = B->pass_steps;
+    ln.table_zc = B->pass_zc;
   }
   lbm::BatchLat *h = ln.h_lats.as<lbm::BatchLat>();
   int lo = B->max_jobs, hi = -1;
@@ -588,21 +720,43 @@ lbm_status upload_tables(lbm_batch *B, Lane &ln, const std::vector<int> &slots) 
   return LBM_OK;
 }
 
-// Enqueue nsteps steps with indices first..first+nsteps-1 of a sequence that
-// starts at each lattice's step_base (first and nsteps even keep the state in
-// buf[0] at the end).  Grid: the shape's persistent workgroups, or (grid 0)
-// one workgroup per entry of the lane's tile table -- its capacity, which
-// only changes when the table is reallocated, and then the lane's graphs are
-// dropped; workgroups past the current tile count exit at once.
+// Passes of two steps in a sequence of nsteps (even) steps that starts and
+// ends with the state in buf[0]: each pass leaves the state in the other
+// buffer, each single step too, so the count of passes has the parity of
+// nsteps / 2 ... minus one when that is odd, and two single steps close the
+// sequence (10 steps: 4 passes and 2 single steps; 100 steps: 50 passes).
+int passes_in(int nsteps) {
+  const int m = nsteps / 2;
+  return m % 2 == 0 ? m : m - 1;
+}
+
+// Enqueue nsteps (even) steps with indices first..first+nsteps-1 of a
+// sequence that starts at each lattice's step_base, the state in buf[0]
+// before and after.  With two steps per pass: passes_in(nsteps) passes over
+// the lane's boxes, then single steps; else single steps.  Grid of a single
+// step: the shape's persistent workgroups, or (grid 0) one workgroup per
+// entry of the lane's tile table -- its capacity, which only changes when
+// the table is reallocated, and then the lane's graphs are dropped;
+// workgroups past the current tile count exit at once.  A pass launches one
+// workgroup per entry of the box table in the same way.
 lbm_status launch_steps(lbm_batch *B, Lane &ln, int nsteps, int first) {
-  for (int st = first; st < first + nsteps; ++st)
+  const int P = B->pass_steps == 2 ? passes_in(nsteps) : 0;
+  for (int i = 0; i < P; ++i)
+    for (int s = 0; s < kNumStorage; ++s)
+      if (ln.nboxes[s] > 0)
+        LBM_BHIP(lbm::launch_batch_pass(s, ln.d_lats, ln.d_boxes[s], ln.d_ntiles + kNumStorage + s, first + 2 * i,
+                                        i & 1, B->pass_zc, B->pass_remap, int(ln.box_cap[s]), ln.stream),
+                 "batch pass launch");
+  for (int j = 2 * P; j < nsteps; ++j) {
+    const int parity = (j - P) & 1;  // buffer flips so far: P passes and j - 2P single steps
     for (int s = 0; s < kNumStorage; ++s)
       if (ln.ntiles[s] > 0) {
         const int grid = B->shape.grid > 0 ? B->shape.grid : int(ln.tile_cap[s]);
-        LBM_BHIP(lbm::launch_batch_sweep(s, B->shape.block_x, ln.d_lats, ln.d_tiles[s], ln.d_ntiles + s, st, grid,
-                                         ln.stream),
+        LBM_BHIP(lbm::launch_batch_sweep(s, B->shape.block_x, ln.d_lats, ln.d_tiles[s], ln.d_ntiles + s, first + j,
+                                         parity, grid, ln.stream),
                  "batch sweep launch");
       }
+  }
   return LBM_OK;
 }
 
@@ -613,9 +767,17 @@ lbm_status run_solo_chunk(lbm_batch *B, Lane &ln, int slot) {
   const Job &J = B->jobs.at(B->slot_job[slot]);
   const lbm::BatchLat &L = B->lat[slot];
   lbm::SweepConfig c = J.cfg;
-  for (int s = 0; s < B->chunk_steps; ++s) {
+  // with two steps per pass, passes of the single-lattice two-step kernel
+  // first (the same order of buffers as launch_steps; the job is row-major)
+  const int P = B->pass_steps == 2 ? passes_in(B->chunk_steps) : 0;
+  for (int i = 0; i < P; ++i) {
+    c.step = unsigned(J.steps + 2 * i);
+    LBM_BHIP(lbm::launch_sweep2(c, B->pass_zc, 0, L.buf[i & 1], L.buf[(i & 1) ^ 1], ln.stream), "pass launch");
+  }
+  for (int s = 2 * P; s < B->chunk_steps; ++s) {
+    const int q = (s - P) & 1;
     c.step = unsigned(J.steps + s);
-    LBM_BHIP(lbm::launch_sweep(c, L.buf[s & 1], L.buf[(s & 1) ^ 1], false, ln.stream), "sweep launch");
+    LBM_BHIP(lbm::launch_sweep(c, L.buf[q], L.buf[q ^ 1], false, ln.stream), "sweep launch");
   }
   return LBM_OK;
 }
@@ -623,8 +785,8 @@ lbm_status run_solo_chunk(lbm_batch *B, Lane &ln, int slot) {
 lbm_status run_graph_chunk(lbm_batch *B, Lane &ln) {
   const unsigned mask = present_mask(ln);
   if (!mask) return LBM_OK;
-  const long long key = (long long)mask | ((long long)B->chunk_steps << 8) | ((long long)B->shape.block_x << 24) |
-                        ((long long)B->shape.grid << 36);
+  const auto key = std::make_tuple(mask, B->chunk_steps, B->shape.block_x, B->shape.grid, B->pass_steps, B->pass_zc,
+                                   B->pass_remap);
   auto it = ln.graphs.find(key);
   if (it == ln.graphs.end()) {
     hipGraph_t graph;
@@ -1016,7 +1178,7 @@ long long tune_key(const lbm_batch *B, const Lane &ln) {
     if (id >= 0) nodes += B->jobs.at(id).nodes;
   int lg = 0;
   while ((size_t(1) << lg) < nodes) ++lg;
-  return (long long)present_mask(ln) | ((long long)lg << 4);
+  return (long long)present_mask(ln) | ((long long)lg << 4) | ((long long)B->pass_steps << 12);
 }
 
 }  // namespace
@@ -1026,7 +1188,9 @@ extern "C" {
 lbm_status lbm_job_bytes(const lbm_job *job, size_t *bytes) {
   if (!job || !bytes) return bfail(LBM_ERR_ARG, "NULL argument");
   if (lbm_element_bytes(job->storage) == 0) return bfail(LBM_ERR_ARG, "invalid storage");
-  *bytes = job_bytes(*job, batch_layout_kind(job->nx, lbm_element_bytes(job->storage)));
+  // either layout a batch may give the job
+  *bytes = std::max(job_bytes(*job, LBM_LAYOUT_ROW_MAJOR),
+                    job_bytes(*job, batch_layout_kind(job->nx, lbm_element_bytes(job->storage))));
   return LBM_OK;
 }
 
@@ -1154,13 +1318,15 @@ lbm_status lbm_batch_submit(lbm_batch *B, const lbm_job *job, int *job_id) {
   Job J;
   J.spec = j;
   J.nodes = size_t(j.nx) * j.ny * j.nz;
-  // The layout is fixed here: row-major with padded rows for a job that
-  // every chunk steps alone through the single-lattice sweep (shortest
-  // first, at least fill_nodes nodes), else row-major only for rows of whole
-  // 128-byte lines.
+  // The layout is fixed here: row-major with padded rows for every job with
+  // two steps per pass (the pass's tiles are rows of one population) and
+  // for a job that every chunk steps alone through the single-lattice sweep
+  // (shortest first, at least fill_nodes nodes), else row-major only for
+  // rows of whole 128-byte lines.
   const bool alone = B->policy == LBM_BATCH_LARGE_IN_ORDER ||
                      (B->policy == LBM_BATCH_SHORTEST_FIRST && double(J.nodes) >= double(B->fill_nodes));
-  J.layout = alone ? LBM_LAYOUT_ROW_MAJOR : batch_layout_kind(j.nx, lbm_element_bytes(j.storage));
+  J.layout = (alone || B->pass_steps == 2) ? LBM_LAYOUT_ROW_MAJOR
+                                           : batch_layout_kind(j.nx, lbm_element_bytes(j.storage));
   J.bytes = job_bytes(j, J.layout);
   if (J.bytes > B->pool.capacity())
     return bfail(LBM_ERR_OOM, "job needs %zu bytes, more than the whole budget (%zu)", J.bytes, B->pool.capacity());
@@ -1227,6 +1393,31 @@ lbm_status lbm_batch_set_shape(lbm_batch *B, int block_x, int tile_nodes, int gr
   return LBM_OK;
 }
 
+lbm_status lbm_batch_set_steps_per_pass(lbm_batch *B, int steps_per_pass, int z_planes) {
+  if (!B) return bfail(LBM_ERR_ARG, "NULL handle");
+  if (steps_per_pass != 1 && steps_per_pass != 2)
+    return bfail(LBM_ERR_ARG, "steps_per_pass must be 1 or 2 (got %d)", steps_per_pass);
+  if (z_planes < 0 || z_planes > 4096) return bfail(LBM_ERR_ARG, "z_planes must be in [0, 4096] (got %d)", z_planes);
+  for (const Lane &ln : B->lanes)
+    if (ln.busy) return bfail(LBM_ERR_STATE, "a chunk is in flight");
+  if (steps_per_pass == 2)
+    for (const auto &kv : B->jobs)
+      if ((kv.second.state == LBM_JOB_QUEUED || kv.second.state == LBM_JOB_RUNNING) &&
+          kv.second.layout != LBM_LAYOUT_ROW_MAJOR)
+        return bfail(LBM_ERR_STATE, "job %d is stored population-major: two steps per pass need row-major jobs "
+                     "(set the mode before submitting)", kv.first);
+  B->pass_steps = steps_per_pass;
+  B->pass_zc = z_planes == 0 ? 32 : z_planes;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_get_steps_per_pass(const lbm_batch *B, int *steps_per_pass, int *z_planes) {
+  if (!B || !steps_per_pass || !z_planes) return bfail(LBM_ERR_ARG, "NULL argument");
+  *steps_per_pass = B->pass_steps;
+  *z_planes = B->pass_zc;
+  return LBM_OK;
+}
+
 lbm_status lbm_batch_set_policy(lbm_batch *B, int policy, size_t fill_nodes) {
   if (!B) return bfail(LBM_ERR_ARG, "NULL handle");
   if (policy != LBM_BATCH_LOCKSTEP && policy != LBM_BATCH_SHORTEST_FIRST && policy != LBM_BATCH_LARGE_IN_ORDER)
@@ -1263,35 +1454,53 @@ lbm_status lbm_batch_autotune(lbm_batch *B, int trial_steps, int *block_x, int *
   st = upload_tables(B, ln, all);
   if (st != LBM_OK) return st;
   const long long key = tune_key(B, ln);
-  Shape cached_shape;
+  Tuned cached;
   bool have_cached = false;
   {
     std::lock_guard<std::mutex> lock(g_tuned_mutex);
-    auto cached = g_tuned.find(key);
-    if (cached != g_tuned.end()) {
-      cached_shape = cached->second;
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+      cached = it->second;
       have_cached = true;
     }
   }
+  const bool pass2 = B->pass_steps == 2;
   if (have_cached) {
-    st = lbm_batch_set_shape(B, cached_shape.block_x, cached_shape.tile_nodes, cached_shape.grid);
+    st = lbm_batch_set_shape(B, cached.shape.block_x, cached.shape.tile_nodes, cached.shape.grid);
+    B->pass_zc = cached.zc;
+    B->pass_remap = cached.remap;
   } else {
     // Every trial step is a real step of every resident lattice (results do
     // not depend on the launch shape); the step counters advance with them.
+    // With two steps per pass the candidates are the pass's z ranges and box
+    // orders (the single step's shape stays the default: chunks of a
+    // multiple of 4 steps take no single step), timed over at least 4 steps
+    // (2 passes), a multiple of 4, after 2 warm-up passes.
+    const int warm = pass2 ? 4 : 2;
+    const int timed = pass2 ? (std::max(trial_steps, 4) + 3) / 4 * 4 : trial_steps;
+    std::vector<Tuned> cands;
+    if (pass2) {
+      for (int zc : {16, 32, 64})
+        for (int remap : {1, 0}) cands.push_back({Shape(), zc, remap});
+    } else {
+      // one workgroup per tile of 256-1024 nodes, and two persistent grids
+      for (const Shape &c : {Shape{256, 256, 0}, Shape{256, 512, 0}, Shape{256, 1024, 0}, Shape{128, 256, 0},
+                             Shape{256, 1024, 16 * B->num_cu}, Shape{128, 1024, 8 * B->num_cu}})
+        cands.push_back({c, B->pass_zc, B->pass_remap});
+    }
     hipEvent_t e0, e1;
     LBM_BHIP(hipEventCreate(&e0), "event");
     LBM_BHIP(hipEventCreate(&e1), "event");
-    Shape best;
+    Tuned best;
     float best_ms = INFINITY;
-    // one workgroup per tile of 256-1024 nodes, and two persistent grids
-    const Shape cands[] = {{256, 256, 0},  {256, 512, 0},  {256, 1024, 0},
-                           {128, 256, 0},  {256, 1024, 16 * B->num_cu}, {128, 1024, 8 * B->num_cu}};
-    for (const Shape &c : cands) {
-      st = lbm_batch_set_shape(B, c.block_x, c.tile_nodes, c.grid);
+    for (const Tuned &c : cands) {
+      st = lbm_batch_set_shape(B, c.shape.block_x, c.shape.tile_nodes, c.shape.grid);
+      B->pass_zc = c.zc;
+      B->pass_remap = c.remap;
       if (st == LBM_OK) st = upload_tables(B, ln, all);
-      if (st == LBM_OK) st = launch_steps(B, ln, 2, 0);  // warm-up
+      if (st == LBM_OK) st = launch_steps(B, ln, warm, 0);
       hipError_t e = st == LBM_OK ? hipEventRecord(e0, ln.stream) : hipSuccess;
-      if (st == LBM_OK && e == hipSuccess) st = launch_steps(B, ln, trial_steps, 2);
+      if (st == LBM_OK && e == hipSuccess) st = launch_steps(B, ln, timed, warm);
       if (st == LBM_OK && e == hipSuccess) e = hipEventRecord(e1, ln.stream);
       if (st == LBM_OK && e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;
@@ -1301,10 +1510,10 @@ lbm_status lbm_batch_autotune(lbm_batch *B, int trial_steps, int *block_x, int *
         (void)hipEventDestroy(e1);
         return st != LBM_OK ? st : bfail(LBM_ERR_HIP, "autotune timing: %s", hipGetErrorString(e));
       }
-      for (int slot : all) B->jobs.at(B->slot_job[slot]).steps += 2 + trial_steps;
+      for (int slot : all) B->jobs.at(B->slot_job[slot]).steps += warm + timed;
       if (ms < best_ms) {
         best_ms = ms;
-        best = B->shape;
+        best = c;
       }
     }
     (void)hipEventDestroy(e0);
@@ -1313,7 +1522,9 @@ lbm_status lbm_batch_autotune(lbm_batch *B, int trial_steps, int *block_x, int *
       std::lock_guard<std::mutex> lock(g_tuned_mutex);
       g_tuned[key] = best;
     }
-    st = lbm_batch_set_shape(B, best.block_x, best.tile_nodes, best.grid);
+    st = lbm_batch_set_shape(B, best.shape.block_x, best.shape.tile_nodes, best.shape.grid);
+    B->pass_zc = best.zc;
+    B->pass_remap = best.remap;
   }
   if (st != LBM_OK) return st;
   if (block_x) *block_x = B->shape.block_x;

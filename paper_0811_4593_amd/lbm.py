@@ -37,7 +37,8 @@ EXPORTS = (
     "lbm_destroy", "lbm_last_error",
     "lbm_job_bytes", "lbm_batch_create", "lbm_batch_submit", "lbm_batch_run_chunk", "lbm_batch_poll",
     "lbm_batch_result", "lbm_batch_set_shape", "lbm_batch_get_shape", "lbm_batch_autotune", "lbm_batch_set_policy",
-    "lbm_batch_memory", "lbm_batch_set_lanes", "lbm_batch_get_stats", "lbm_batch_destroy",
+    "lbm_batch_memory", "lbm_batch_set_lanes", "lbm_batch_get_stats", "lbm_batch_set_steps_per_pass",
+    "lbm_batch_get_steps_per_pass", "lbm_batch_destroy",
 )
 
 LBM_JOB_QUEUED, LBM_JOB_RUNNING, LBM_JOB_DONE = 0, 1, 2
@@ -157,6 +158,8 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_batch_autotune.argtypes = [_vp, st, ip, ip, ip]
     lib.lbm_batch_memory.argtypes = [_vp, szp, szp]
     lib.lbm_batch_set_lanes.argtypes = [_vp, st]
+    lib.lbm_batch_set_steps_per_pass.argtypes = [_vp, st, st]
+    lib.lbm_batch_get_steps_per_pass.argtypes = [_vp, ctypes.POINTER(st), ctypes.POINTER(st)]
     lib.lbm_batch_get_stats.argtypes = [_vp, ctypes.POINTER(LbmBatchStats)]
     lib.lbm_batch_destroy.argtypes = [_vp]
     lib.lbm_batch_destroy.restype = None
@@ -553,6 +556,18 @@ def lbm_batch_memory(b):
 
 def lbm_batch_set_lanes(b, lanes: int):
     _check(load_library().lbm_batch_set_lanes(b, int(lanes)))
+
+
+def lbm_batch_set_steps_per_pass(b, steps_per_pass: int, z_planes: int = 0):
+    """1 (the default): one step per launch; 2: passes of two steps over
+    every job (row-major jobs; set before submitting)."""
+    _check(load_library().lbm_batch_set_steps_per_pass(b, int(steps_per_pass), int(z_planes)))
+
+
+def lbm_batch_get_steps_per_pass(b):
+    sp, zc = ctypes.c_int(), ctypes.c_int()
+    _check(load_library().lbm_batch_get_steps_per_pass(b, ctypes.byref(sp), ctypes.byref(zc)))
+    return sp.value, zc.value
 
 
 def lbm_batch_get_stats(b) -> dict:

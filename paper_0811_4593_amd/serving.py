@@ -37,7 +37,7 @@ class BatchRun:
 
 
 def run_batch(specs, storage="f32", steps=2000, chunk=100, budget_bytes=None, autotune=True, trial_steps=4,
-              stream=None, keep_results=True):
+              stream=None, keep_results=True, steps_per_pass=None):
     """Run every spec as one job of a batch for `steps` steps (no early stop).
     Returns the wall time from the first chunk to the last retirement."""
     jobs = [job_for(s, storage, 0.0, steps) for s in specs]
@@ -45,6 +45,8 @@ def run_batch(specs, storage="f32", steps=2000, chunk=100, budget_bytes=None, au
     budget = budget_bytes or int(need * 1.05) + (64 << 20)
     b = lbm.lbm_batch_create(budget, chunk, max(len(jobs), 1), stream)
     try:
+        if steps_per_pass is not None:
+            lbm.lbm_batch_set_steps_per_pass(b, steps_per_pass, 0)
         ids = [lbm.lbm_batch_submit(b, j) for j in jobs]
         t0 = time.perf_counter()
         shape = lbm.lbm_batch_autotune(b, trial_steps) if autotune else lbm.lbm_batch_get_shape(b)

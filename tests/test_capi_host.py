@@ -173,3 +173,24 @@ def test_null_handle_calls_of_the_newer_entry_points(lbm):
     assert lib.lbm_batch_set_lanes(None, 2) == lbm.LBM_ERR_ARG
     assert lib.lbm_batch_get_stats(None, None) == lbm.LBM_ERR_ARG
     assert lib.lbm_totals_static(None, 4, 4, 4, 1, 0, None, None) == lbm.LBM_ERR_ARG
+    assert lib.lbm_batch_set_steps_per_pass(None, 2, 0) == lbm.LBM_ERR_ARG
+    assert lib.lbm_batch_get_steps_per_pass(None, None, None) == lbm.LBM_ERR_ARG
+
+
+@pytest.mark.parametrize("nx,ny,nz,storage", [(37, 12, 9, "f32"), (32, 10, 7, "f32"), (70, 9, 5, "f16dev"),
+                                              (21, 11, 13, "f64"), (1, 1, 1, "f32")])
+def test_job_bytes_cover_either_batch_layout(lbm, nx, ny, nz, storage):
+    """A batch stores a job row-major with padded rows (two steps per pass)
+    or, with one step per pass, population-major where its rows are not whole
+    128-byte lines: lbm_job_bytes is the larger of the two."""
+    from paper_0811_4593_amd import serving, workloads
+    st = serving.STORAGE[storage]
+    esize = lbm.lbm_element_bytes(st)
+
+    def need(layout):
+        buf = lbm.lbm_buffer_elements(nx, ny, nz, st, layout) * esize
+        return 2 * ((buf + 255) // 256 * 256) + (3 * nx * ny * nz * 4 + 255) // 256 * 256
+
+    spec = workloads.LatticeSpec(nx, ny, nz, 0.8, {}, name="box")
+    got = lbm.lbm_job_bytes(serving.job_for(spec, storage, 0.0, 10))
+    assert got == max(need(lbm.LBM_LAYOUT_ROW_MAJOR), need(lbm.LBM_LAYOUT_POPULATION_MAJOR))

@@ -81,6 +81,7 @@ def test_every_launch_shape_gives_the_same_bits(shape):
     steps = 20
     b = lbm.lbm_batch_create(4 << 30, 10, 16)
     try:
+        lbm.lbm_batch_set_steps_per_pass(b, 1, 0)  # every step a launch of this shape
         lbm.lbm_batch_set_shape(b, *shape)
         assert lbm.lbm_batch_get_shape(b) == shape
         ids = _submit_all(b, MIX, steps)
@@ -112,7 +113,9 @@ def test_batch_fp64_job_matches_oracle():
 
 
 def test_admission_respects_budget_and_results_unchanged():
-    items = [(workloads.duct(40, 20, 20, (0.03, 0.01, 0.0), 0.9), "f32") for _ in range(5)]
+    # rows of whole 128-byte lines and a node count that is a multiple of 64:
+    # both layouts take the same bytes, so lbm_job_bytes is the job's size
+    items = [(workloads.duct(64, 20, 20, (0.03, 0.01, 0.0), 0.9), "f32") for _ in range(5)]
     job_bytes = lbm.lbm_job_bytes(serving.job_for(items[0][0], "f32", 0.0, 20))
     budget = 2 * job_bytes + job_bytes // 2  # room for two jobs at a time
     b = lbm.lbm_batch_create(budget, 10, 8)
@@ -374,8 +377,10 @@ def test_large_job_is_not_starved_by_small_ones():
     # small jobs fit together.  Small jobs may pass the waiting large job
     # during its first four chunks at the head of the queue, then queue
     # behind it.
-    small = workloads.duct(24, 12, 12)
-    large = workloads.duct(48, 24, 18)
+    # rows of whole lines and node counts that are multiples of 64: both
+    # layouts take the same bytes, so lbm_job_bytes is each job's size
+    small = workloads.duct(32, 12, 12)
+    large = workloads.duct(64, 24, 18)
     sb = lbm.lbm_job_bytes(serving.job_for(small, "f32", 0.0, 10))
     lb = lbm.lbm_job_bytes(serving.job_for(large, "f32", 0.0, 10))
     assert lb > 3 * sb

@@ -44,7 +44,8 @@ COUNTERS_FILE = os.path.join(_ROOT, "profiles", "sweep2_f32_duct_1024x512x512_co
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("d3q19.hpp", "node_update.hpp", "lbm_kernels.hip", "lbm_sweep2.hip", "lbm_internal.hpp"):
+    for name in ("d3q19.hpp", "node_update.hpp", "lbm_kernels.hip", "lbm_sweep2.hip", "sweep2_box.hpp",
+                 "lbm_internal.hpp"):
         with open(os.path.join(_ROOT, "paper_0811_4593_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

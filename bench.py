@@ -131,8 +131,9 @@ def ingest_counters(args):
         "algorithmic_bytes_per_launch": 2 * 19 * N * lbm.lbm_element_bytes(storage) * steps_per_launch,
         "command": args.counters_command,
     }
-    os.makedirs(os.path.dirname(COUNTERS_FILE), exist_ok=True)
-    with open(COUNTERS_FILE, "w") as fh:
+    out = args.counters_out or COUNTERS_FILE
+    os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
+    with open(out, "w") as fh:
         json.dump(rec, fh, indent=1)
         fh.write("\n")
     print(json.dumps(rec))
@@ -372,6 +373,8 @@ def main():
                     help="summarise two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE) "
                          "into the committed counters file and exit")
     ap.add_argument("--counters-command", default="", help="the rocprofv3 command lines, for the record")
+    ap.add_argument("--counters-out", default="",
+                    help="file the summary goes to (default: the counters file the bench line reads)")
     ap.add_argument("--form", choices=["precision", "batch", "serve"], default=None,
                     help="measure one of the systems forms instead of the roofline run (see form_* below)")
     ap.add_argument("--requests", type=int, default=40, help="--form serve: requests in the timed trace")

@@ -131,7 +131,7 @@ def ingest_counters(args):
         "algorithmic_bytes_per_launch": 2 * 19 * N * lbm.lbm_element_bytes(storage) * steps_per_launch,
         "command": args.counters_command,
     }
-    out = args.counters_out or COUNTERS_FILE
+    out = getattr(args, "counters_out", "") or COUNTERS_FILE
     os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
     with open(out, "w") as fh:
         json.dump(rec, fh, indent=1)

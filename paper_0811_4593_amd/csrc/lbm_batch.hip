@@ -103,10 +103,16 @@ __device__ __forceinline__ NodeParams<T> lattice_params(const BatchLat &L) {
   return prm;
 }
 
-template <class F, int BX>
+//
+// DELTA (one workgroup per tile only): the step ends a chunk and also takes
+// the convergence measure of the state it writes; each wave's maximum goes
+// to partials[tile * BX / 64 + wave] (tile_partials_kernel then combines
+// them per lattice).
+template <class F, int BX, bool DELTA>
 __global__ __launch_bounds__(BX) void batch_sweep_kernel(const BatchLat *__restrict__ lats,
                                                          const BatchTile *__restrict__ tiles,
-                                                         const int *__restrict__ ntiles, int s, int parity) {
+                                                         const int *__restrict__ ntiles, int s, int parity,
+                                                         float *__restrict__ partials) {
   using S = typename F::S;
   using T = typename Codec<S>::T;
   const int nt = *ntiles;
@@ -133,8 +139,13 @@ __global__ __launch_bounds__(BX) void batch_sweep_kernel(const BatchLat *__restr
     const unsigned dx = unsigned(BX) - rows * sr;
     const unsigned dz = rows / g.ny;
     const unsigned dy = rows - dz * g.ny;
+    DeltaArgs dl{};
+    float dmax = 0.0f;
+    if constexpr (DELTA) dl = DeltaArgs{(global_ptr<float>)(L.snap), size_t(L.N), L.inv_uref};
     for (; n < tile.n1; n += BX) {
-      if (x < g.nx) update_node<F, false, false>(mem, g, int(x), int(y), int(z), prm, key, NodeExt{});
+      if (x < g.nx)
+        update_node<F, false, false, T, BufAccess<S>, DELTA>(mem, g, int(x), int(y), int(z), prm, key, NodeExt{}, dl,
+                                                             &dmax);
       x += dx;
       const unsigned cxr = x >= sr;
       x -= cxr ? sr : 0u;
@@ -143,6 +154,10 @@ __global__ __launch_bounds__(BX) void batch_sweep_kernel(const BatchLat *__restr
       y -= cyr ? g.ny : 0u;
       z += dz + cyr;
     }
+    if constexpr (DELTA) {
+      dmax = wave_max(dmax);
+      if ((threadIdx.x & 63) == 0) partials[size_t(t) * (BX / 64) + (threadIdx.x >> 6)] = dmax;
+    }
   }
 }
 
@@ -150,13 +165,29 @@ __global__ __launch_bounds__(BX) void batch_sweep_kernel(const BatchLat *__restr
 // |u(t) - u(t_prev)| / u_ref (u from the stored state, eq_vel), then the
 // snapshot is replaced by u(t).  Maxima are combined with an atomic max on
 // the bit pattern of non-negative floats: order-independent, so the stop step
-// of every lattice is deterministic.  NaN counts as +inf.
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-  return v;
+// of every lattice is deterministic.  NaN counts as +inf.  The sweep that
+// ends a chunk takes the measure of the state it writes (update_node with
+// DELTA); with two steps per pass this kernel takes it afterwards.
+
+// The workgroup's maximum of v into delta_bits[lat] (every thread calls it).
+__device__ __forceinline__ void flush_max(float v, unsigned *delta_bits, int lat, float *lds) {
+  v = wave_max(v);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float m = fmaxf(fmaxf(lds[0], lds[1]), fmaxf(lds[2], lds[3]));
+    atomicMax(delta_bits + lat, __float_as_uint(m));
+  }
+  __syncthreads();
 }
 
+// Each persistent workgroup takes one contiguous share of the tile list and
+// keeps each lane's maximum across the consecutive tiles of one lattice,
+// flushing it with one atomic when the lattice changes: a launch issues
+// about one atomic per workgroup and lattice instead of one per tile (a
+// 256^3 lattice has 65536 tiles of 256 nodes; their atomics on one address
+// serialised the launch), and the next tile's nodes follow the last one's
+// in memory.
 template <class S>
 __global__ __launch_bounds__(256) void batch_delta_kernel(const BatchLat *__restrict__ lats,
                                                           const BatchTile *__restrict__ tiles,
@@ -164,45 +195,80 @@ __global__ __launch_bounds__(256) void batch_delta_kernel(const BatchLat *__rest
                                                           unsigned *__restrict__ delta_bits) {
   __shared__ float lds[4];
   const int nt = *ntiles;
-  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+  const int t0 = int((long long)nt * blockIdx.x / gridDim.x);
+  const int t1 = int((long long)nt * (blockIdx.x + 1) / gridDim.x);
+  int cur = -1;  // lattice of the running maximum (uniform over the workgroup)
+  float dmax = 0.0f;
+  for (int t = t0; t < t1; ++t) {
     const BatchTile tile = tiles[t];
+    if (tile.lat != cur) {
+      if (cur >= 0) flush_max(dmax, delta_bits, cur, lds);
+      cur = tile.lat;
+      dmax = 0.0f;
+    }
     const BatchLat &L = lats[tile.lat];
     const global_ptr<const S> f = (global_ptr<const S>)(L.buf[0]);
     const global_ptr<float> snap = (global_ptr<float>)(L.snap);
-    float dmax = 0.0f;
     for (unsigned sl = tile.n0 + threadIdx.x; sl < tile.n1; sl += 256) {
       const unsigned r = sl / L.slot_row, x = sl - r * L.slot_row;
       if (x >= L.nx) continue;  // padding slot
-      const unsigned n = r * L.nx + x;
-      double dr = 0.0, j[3] = {0.0, 0.0, 0.0};
+      S raw[19];
       const size_t at = size_t(r) * L.row_stride + x;
 #pragma unroll
-      for (int k = 0; k < 19; ++k) {
-        const double v = double(Codec<S>::decode(f[at + size_t(k) * L.pop_stride]));
-        dr += v;
-        if (cx(k)) j[0] += double(cx(k)) * v;
-        if (cy(k)) j[1] += double(cy(k)) * v;
-        if (cz(k)) j[2] += double(cz(k)) * v;
-      }
-      const double ir = 1.0 / (1.0 + dr);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const double u = j[a] * ir;
-        const global_ptr<float> sp = snap + size_t(a) * L.N + n;
-        const float du = float(fabs(u - double(*sp)) * L.inv_uref);
-        dmax = (du != du) ? INFINITY : fmaxf(dmax, du);
-        *sp = float(u);
-      }
+      for (int k = 0; k < 19; ++k) raw[k] = f[at + size_t(k) * L.pop_stride];
+      dmax = fmaxf(dmax, velocity_change<S>(raw, snap, L.N, r * L.nx + x, L.inv_uref));
     }
-    dmax = wave_max(dmax);
-    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = dmax;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const float m = fmaxf(fmaxf(lds[0], lds[1]), fmaxf(lds[2], lds[3]));
-      atomicMax(delta_bits + tile.lat, __float_as_uint(m));
-    }
-    __syncthreads();
   }
+  if (cur >= 0) flush_max(dmax, delta_bits, cur, lds);
+}
+
+// The per-wave maxima of a chunk's last batch sweep (DELTA), per lattice:
+// as batch_delta_kernel, each persistent workgroup takes a contiguous share
+// of the tile list and flushes once per lattice; it reads `waves` partials
+// per tile instead of the state.  A round covers 256 / waves tiles of one
+// lattice (the tiles of a lattice are contiguous, so a round whose first
+// and last tile share a lattice lies in it); a round across a lattice's
+// end goes tile by tile.
+__global__ __launch_bounds__(256) void tile_partials_kernel(const BatchTile *__restrict__ tiles,
+                                                            const int *__restrict__ ntiles,
+                                                            const float *__restrict__ partials, int waves,
+                                                            unsigned *__restrict__ delta_bits) {
+  __shared__ float lds[4];
+  const int nt = *ntiles;
+  const int t0 = int((long long)nt * blockIdx.x / gridDim.x);
+  const int t1 = int((long long)nt * (blockIdx.x + 1) / gridDim.x);
+  const int per_round = 256 / waves, tid = int(threadIdx.x);
+  int cur = -1;  // lattice of the running maximum (uniform over the workgroup)
+  float dmax = 0.0f;
+  for (int base = t0; base < t1; base += per_round) {
+    const int last = min(base + per_round, t1) - 1;
+    const int la = tiles[base].lat, lb = tiles[last].lat;
+    if (la == lb) {
+      if (la != cur) {
+        if (cur >= 0) flush_max(dmax, delta_bits, cur, lds);
+        cur = la;
+        dmax = 0.0f;
+      }
+      const int t = base + tid / waves;
+      if (t <= last) dmax = fmaxf(dmax, partials[size_t(t) * waves + tid % waves]);
+    } else {
+      for (int u = base; u <= last; ++u) {
+        const int l = tiles[u].lat;
+        if (l != cur) {
+          if (cur >= 0) flush_max(dmax, delta_bits, cur, lds);
+          cur = l;
+          dmax = 0.0f;
+        }
+        if (tid < waves) dmax = fmaxf(dmax, partials[size_t(u) * waves + tid]);
+      }
+    }
+  }
+  if (cur >= 0) flush_max(dmax, delta_bits, cur, lds);
+}
+
+__global__ void fill_float_kernel(float *__restrict__ p, size_t n, float v) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 // One box of the multi-lattice two-step pass: tile (tx, ty) of 64 x BYI
@@ -249,34 +315,35 @@ __global__ __launch_bounds__(64 * (BYI + 3)) void batch_pass_kernel(const BatchL
   sweep2_box<F, BYI, global_ptr<const S>, global_ptr<S>>(src, dst, a, bx.tx, bx.ty, bx.tz, ring);
 }
 
-__global__ void fill_float_kernel(float *__restrict__ p, size_t n, float v) {
-  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
 template <class F, int BX>
 static void launch_batch_sweep_t(const BatchLat *lats, const BatchTile *tiles, const int *nt, int s, int parity,
-                                 int grid, hipStream_t st) {
-  batch_sweep_kernel<F, BX><<<dim3(grid), dim3(BX), 0, st>>>(lats, tiles, nt, s, parity);
+                                 float *partials, int grid, hipStream_t st) {
+  if (partials)
+    batch_sweep_kernel<F, BX, true><<<dim3(grid), dim3(BX), 0, st>>>(lats, tiles, nt, s, parity, partials);
+  else
+    batch_sweep_kernel<F, BX, false><<<dim3(grid), dim3(BX), 0, st>>>(lats, tiles, nt, s, parity, nullptr);
 }
 
+// partials: non-null for the step that ends a chunk, with one workgroup per
+// tile (the per-wave maxima of the convergence measure, bx / 64 per tile).
 static hipError_t launch_batch_sweep(int storage, int bx, const BatchLat *lats, const BatchTile *tiles, const int *nt,
-                                     int s, int parity, int grid, hipStream_t st) {
+                                     int s, int parity, float *partials, int grid, hipStream_t st) {
+#define LBM_CASE(ST, F, B)                                                                 \
+  case ST * 1000 + B:                                                                      \
+    launch_batch_sweep_t<F, B>(lats, tiles, nt, s, parity, partials, grid, st);            \
+    break;
   switch (storage * 1000 + bx) {
-    case kStoreF64 * 1000 + 128: launch_batch_sweep_t<FormF64, 128>(lats, tiles, nt, s, parity, grid, st); break;
-    case kStoreF64 * 1000 + 256: launch_batch_sweep_t<FormF64, 256>(lats, tiles, nt, s, parity, grid, st); break;
-    case kStoreF32 * 1000 + 128: launch_batch_sweep_t<FormF32, 128>(lats, tiles, nt, s, parity, grid, st); break;
-    case kStoreF32 * 1000 + 256: launch_batch_sweep_t<FormF32, 256>(lats, tiles, nt, s, parity, grid, st); break;
-    case kStoreF16 * 1000 + 128: launch_batch_sweep_t<FormF16, 128>(lats, tiles, nt, s, parity, grid, st); break;
-    case kStoreF16 * 1000 + 256: launch_batch_sweep_t<FormF16, 256>(lats, tiles, nt, s, parity, grid, st); break;
-    case kStoreF16SR * 1000 + 128:
-      launch_batch_sweep_t<FormF16SR, 128>(lats, tiles, nt, s, parity, grid, st);
-      break;
-    case kStoreF16SR * 1000 + 256:
-      launch_batch_sweep_t<FormF16SR, 256>(lats, tiles, nt, s, parity, grid, st);
-      break;
+    LBM_CASE(kStoreF64, FormF64, 128)
+    LBM_CASE(kStoreF64, FormF64, 256)
+    LBM_CASE(kStoreF32, FormF32, 128)
+    LBM_CASE(kStoreF32, FormF32, 256)
+    LBM_CASE(kStoreF16, FormF16, 128)
+    LBM_CASE(kStoreF16, FormF16, 256)
+    LBM_CASE(kStoreF16SR, FormF16SR, 128)
+    LBM_CASE(kStoreF16SR, FormF16SR, 256)
     default: return hipErrorInvalidValue;
   }
+#undef LBM_CASE
   return hipGetLastError();
 }
 
@@ -526,6 +593,11 @@ struct Lane {
   HostBlock h_lats, h_delta, h_ntiles, h_tiles[kNumStorage], h_boxes[kNumStorage];
   int ntiles[kNumStorage] = {0, 0, 0, 0};
   int nboxes[kNumStorage] = {0, 0, 0, 0};
+  // per-wave maxima of the convergence measure taken by a chunk's last step:
+  // for a graph chunk 4 per tile-table entry of each storage form (form s
+  // from part_off[s]), for a chunk of one job its single sweep's
+  float *d_part = nullptr;
+  size_t part_cap = 0, part_off[kNumStorage] = {0, 0, 0, 0};
   // Jobs (slot, job id) the tile tables describe: a slot reused by a later
   // job has other extents, so the tables follow the job ids, not the slots.
   std::vector<std::pair<int, int>> table_jobs;
@@ -585,6 +657,7 @@ void free_lane(Lane &ln) {
     if (ln.d_tiles[s]) (void)hipFree(ln.d_tiles[s]);
     if (ln.d_boxes[s]) (void)hipFree(ln.d_boxes[s]);
   }
+  if (ln.d_part) (void)hipFree(ln.d_part);
   if (ln.done) (void)hipEventDestroy(ln.done);
   if (ln.own_stream && ln.stream) (void)hipStreamDestroy(ln.stream);
   ln = Lane();
@@ -636,6 +709,24 @@ lbm_status ensure_table(Lane &ln, E *&d, size_t &cap, HostBlock &h, size_t n, co
   if (!h.allocate(sizeof(E) * c, true))
     return bfail(LBM_ERR_OOM, "page-locked %s staging of %zu entries could not be allocated", what, c);
   cap = c;
+  return LBM_OK;
+}
+
+// Room for n per-wave maxima in a lane's partials (reallocation drops the
+// lane's graphs).  Only called while the lane is idle.
+lbm_status ensure_partials(Lane &ln, size_t n) {
+  if (n <= ln.part_cap) return LBM_OK;
+  const size_t c = std::max<size_t>(n, 2 * ln.part_cap);
+  drop_graphs(ln);
+  if (ln.d_part) (void)hipFree(ln.d_part);
+  ln.d_part = nullptr;
+  ln.part_cap = 0;
+  if (hipMalloc(&ln.d_part, sizeof(float) * c) != hipSuccess) {
+    (void)hipGetLastError();
+    ln.d_part = nullptr;
+    return bfail(LBM_ERR_OOM, "partials of %zu entries could not be allocated", c);
+  }
+  ln.part_cap = c;
   return LBM_OK;
 }
 
@@ -700,6 +791,13 @@ lbm_status upload_tables(lbm_batch *B, Lane &ln, const std::vector<int> &slots) 
     }
     LBM_BHIP(hipMemcpyAsync(ln.d_ntiles, counts, sizeof(int) * 2 * kNumStorage, hipMemcpyHostToDevice, ln.stream),
              "upload tile and box counts");
+    size_t np = 0;
+    for (int s = 0; s < kNumStorage; ++s) {
+      ln.part_off[s] = np;
+      np += 4 * ln.tile_cap[s];
+    }
+    lbm_status st = ensure_partials(ln, np);
+    if (st != LBM_OK) return st;
     ln.table_jobs = jobs;
     ln.table_tile_nodes = B->shape.tile_nodes;
     ln.table_pass = B->pass_steps;
@@ -738,8 +836,10 @@ int passes_in(int nsteps) {
 // entry of the lane's tile table -- its capacity, which only changes when
 // the table is reallocated, and then the lane's graphs are dropped;
 // workgroups past the current tile count exit at once.  A pass launches one
-// workgroup per entry of the box table in the same way.
-lbm_status launch_steps(lbm_batch *B, Lane &ln, int nsteps, int first) {
+// workgroup per entry of the box table in the same way.  measure: the
+// sequence ends a chunk and its last step (a single step with one workgroup
+// per tile) also takes the convergence measure into the lane's partials.
+lbm_status launch_steps(lbm_batch *B, Lane &ln, int nsteps, int first, bool measure) {
   const int P = B->pass_steps == 2 ? passes_in(nsteps) : 0;
   for (int i = 0; i < P; ++i)
     for (int s = 0; s < kNumStorage; ++s)
@@ -753,16 +853,24 @@ lbm_status launch_steps(lbm_batch *B, Lane &ln, int nsteps, int first) {
       if (ln.ntiles[s] > 0) {
         const int grid = B->shape.grid > 0 ? B->shape.grid : int(ln.tile_cap[s]);
         LBM_BHIP(lbm::launch_batch_sweep(s, B->shape.block_x, ln.d_lats, ln.d_tiles[s], ln.d_ntiles + s, first + j,
-                                         parity, grid, ln.stream),
+                                         parity, measure && j == nsteps - 1 ? ln.d_part + ln.part_off[s] : nullptr,
+                                         grid, ln.stream),
                  "batch sweep launch");
       }
   }
   return LBM_OK;
 }
 
+// Whether a chunk's last step takes the convergence measure: it is a single
+// step (not a pass of two), of one job alone or with one workgroup per tile.
+bool measured_in_last_step(const lbm_batch *B, bool solo) {
+  return (B->pass_steps != 2 || B->chunk_steps > 2 * passes_in(B->chunk_steps)) && (solo || B->shape.grid == 0);
+}
+
 // A chunk that steps a single job: plain launches of the single-lattice
 // sweep on the job's buffers (row-aligned blocks; bitwise the batch sweep's
-// results), one per step, each with the job's own step index.
+// results), one per step, each with the job's own step index; the last one
+// also takes the convergence measure.
 lbm_status run_solo_chunk(lbm_batch *B, Lane &ln, int slot) {
   const Job &J = B->jobs.at(B->slot_job[slot]);
   const lbm::BatchLat &L = B->lat[slot];
@@ -777,7 +885,15 @@ lbm_status run_solo_chunk(lbm_batch *B, Lane &ln, int slot) {
   for (int s = 2 * P; s < B->chunk_steps; ++s) {
     const int q = (s - P) & 1;
     c.step = unsigned(J.steps + s);
-    LBM_BHIP(lbm::launch_sweep(c, L.buf[q], L.buf[q ^ 1], false, ln.stream), "sweep launch");
+    if (s == B->chunk_steps - 1 && measured_in_last_step(B, true)) {
+      lbm_status st = ensure_partials(ln, lbm::sweep_delta_partials(c));
+      if (st != LBM_OK) return st;
+      LBM_BHIP(lbm::launch_sweep_delta(c, L.buf[q], L.buf[q ^ 1], L.snap, L.inv_uref, ln.d_part, ln.d_delta + slot,
+                                       ln.stream),
+               "sweep launch");
+    }
+    else
+      LBM_BHIP(lbm::launch_sweep(c, L.buf[q], L.buf[q ^ 1], false, ln.stream), "sweep launch");
   }
   return LBM_OK;
 }
@@ -791,7 +907,7 @@ lbm_status run_graph_chunk(lbm_batch *B, Lane &ln) {
   if (it == ln.graphs.end()) {
     hipGraph_t graph;
     LBM_BHIP(hipStreamBeginCapture(ln.stream, hipStreamCaptureModeThreadLocal), "begin capture");
-    lbm_status st = launch_steps(B, ln, B->chunk_steps, 0);
+    lbm_status st = launch_steps(B, ln, B->chunk_steps, 0, measured_in_last_step(B, false));
     hipError_t e = hipStreamEndCapture(ln.stream, &graph);
     if (st != LBM_OK) return st;
     if (e != hipSuccess) return bfail(LBM_ERR_HIP, "end capture: %s", hipGetErrorString(e));
@@ -1071,20 +1187,34 @@ lbm_status start_chunk(lbm_batch *B, int l, const std::vector<int> &slots) {
   // one row-major job alone: the single-lattice sweep (population-major
   // rows that are not whole lines run faster in the batch's flat walk)
   const bool solo = slots.size() == 1 && B->jobs.at(B->slot_job[slots[0]]).layout == LBM_LAYOUT_ROW_MAJOR;
+  // The convergence maxima start at zero (a fill kernel rather than a
+  // memset: they are the bit patterns of non-negative floats, and 0.0f is
+  // all zero bits); the chunk's last step takes the measure, or, when the
+  // chunk ends with a pass of two steps, the measure kernel afterwards.
+  const size_t nd = size_t(B->max_jobs);
+  lbm::fill_float_kernel<<<dim3(unsigned((nd + 255) / 256)), dim3(256), 0, ln.stream>>>(
+      reinterpret_cast<float *>(ln.d_delta), nd, 0.0f);
+  LBM_BHIP(hipGetLastError(), "reset deltas");
   st = solo ? run_solo_chunk(B, ln, slots[0]) : run_graph_chunk(B, ln);
   if (st != LBM_OK) return st;
-  // (a fill kernel rather than a memset node: the convergence maxima are
-  // the bit patterns of non-negative floats, and 0.0f is all zero bits)
-  lbm::fill_float_kernel<<<dim3(unsigned((B->max_jobs + 255) / 256)), dim3(256), 0, ln.stream>>>(
-      reinterpret_cast<float *>(ln.d_delta), size_t(B->max_jobs), 0.0f);
-  LBM_BHIP(hipGetLastError(), "reset deltas");
-  for (int s = 0; s < kNumStorage; ++s)
-    if (ln.ntiles[s] > 0)
-      // one workgroup per tile-table entry (workgroups past the tile count exit)
-      LBM_BHIP(lbm::launch_batch_delta(s, ln.d_lats, ln.d_tiles[s], ln.d_ntiles + s, ln.d_delta, int(ln.tile_cap[s]),
+  // the measure: combined from the last step's per-wave maxima, or (after
+  // a pass, or with persistent workgroups) taken from the state; persistent
+  // workgroups, 8 per compute unit (a chunk of one job alone combined its
+  // own in launch_sweep_delta)
+  const bool measured = measured_in_last_step(B, solo);
+  for (int s = 0; s < kNumStorage; ++s) {
+    if (ln.ntiles[s] == 0 || (measured && solo)) continue;
+    if (measured) {
+      lbm::tile_partials_kernel<<<dim3(unsigned(8 * B->num_cu)), dim3(256), 0, ln.stream>>>(
+          ln.d_tiles[s], ln.d_ntiles + s, ln.d_part + ln.part_off[s], B->shape.block_x / 64, ln.d_delta);
+      LBM_BHIP(hipGetLastError(), "measure launch");
+    } else {
+      LBM_BHIP(lbm::launch_batch_delta(s, ln.d_lats, ln.d_tiles[s], ln.d_ntiles + s, ln.d_delta, 8 * B->num_cu,
                                        ln.stream),
-               "delta launch");
-  LBM_BHIP(hipMemcpyAsync(ln.h_delta.as<void>(), ln.d_delta, sizeof(unsigned) * B->max_jobs, hipMemcpyDeviceToHost,
+               "measure launch");
+    }
+  }
+  LBM_BHIP(hipMemcpyAsync(ln.h_delta.as<void>(), ln.d_delta, sizeof(unsigned) * nd, hipMemcpyDeviceToHost,
                           ln.stream),
            "copy deltas");
   LBM_BHIP(hipEventRecord(ln.done, ln.stream), "event");
@@ -1498,9 +1628,9 @@ lbm_status lbm_batch_autotune(lbm_batch *B, int trial_steps, int *block_x, int *
       B->pass_zc = c.zc;
       B->pass_remap = c.remap;
       if (st == LBM_OK) st = upload_tables(B, ln, all);
-      if (st == LBM_OK) st = launch_steps(B, ln, warm, 0);
+      if (st == LBM_OK) st = launch_steps(B, ln, warm, 0, false);
       hipError_t e = st == LBM_OK ? hipEventRecord(e0, ln.stream) : hipSuccess;
-      if (st == LBM_OK && e == hipSuccess) st = launch_steps(B, ln, timed, warm);
+      if (st == LBM_OK && e == hipSuccess) st = launch_steps(B, ln, timed, warm, false);
       if (st == LBM_OK && e == hipSuccess) e = hipEventRecord(e1, ln.stream);
       if (st == LBM_OK && e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;

@@ -93,6 +93,15 @@ struct SweepArgs {
 };
 
 hipError_t launch_sweep(const SweepConfig &c, const void *src, void *dst, bool copy_only, hipStream_t s);
+// One step (c.step) with one node per thread and block width c.block_x (64,
+// 128, 256 or 512), no solid mask, face field or geometry, that also takes
+// the convergence measure of the state it writes against snap ([3][N]
+// floats, replaced): the wave maxima of velocity_change go to partials
+// (sweep_delta_partials(c) floats, scratch), then their maximum to
+// *delta_bits (zero before the call) as the bit pattern of the float.
+hipError_t launch_sweep_delta(const SweepConfig &c, const void *src, void *dst, float *snap, double inv_uref,
+                              float *partials, unsigned *delta_bits, hipStream_t s);
+size_t sweep_delta_partials(const SweepConfig &c);
 // Two steps (c.step and c.step + 1) in one pass, row-major layout, no solid
 // mask, face field or geometry; z ranges of zc planes per workgroup; tiles of
 // `rows` interior rows (5, or 0 for the form's default).

@@ -121,6 +121,51 @@ __device__ __forceinline__ void store_elem(P p, S v) {
     *p = v;
 }
 
+// Maximum over the 64 lanes of a wave (every lane active).
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Convergence measure of one node: the velocity of the stored state,
+// u = sum_k c_k d_k / (1 + sum_k d_k) in double from the stored deviations
+// (eq_vel), against the snapshot of the previous check.  Returns
+// max_a |u_a - snap_a| / u_ref (+inf for NaN) and replaces the snapshot.
+// snap: [3][N] floats; n: the node's index x + nx (y + ny z).
+template <class S, class SnapP>
+__device__ __forceinline__ float velocity_change(const S (&raw)[19], SnapP snap, size_t N, unsigned n,
+                                                 double inv_uref) {
+  double dr = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    const double v = double(Codec<S>::decode(raw[k]));
+    dr += v;
+    if (cx(k)) j[0] += double(cx(k)) * v;
+    if (cy(k)) j[1] += double(cy(k)) * v;
+    if (cz(k)) j[2] += double(cz(k)) * v;
+  }
+  const double ir = 1.0 / (1.0 + dr);
+  float dmax = 0.0f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double u = j[a] * ir;
+    const auto sp = snap + size_t(a) * N + n;
+    const float du = float(fabs(u - double(*sp)) * inv_uref);
+    dmax = (du != du) ? INFINITY : fmaxf(dmax, du);
+    *sp = float(u);
+  }
+  return dmax;
+}
+
+// Where the sweep that ends a chunk of the batch runtime takes the
+// convergence measure of the state it writes.
+struct DeltaArgs {
+  global_ptr<float> snap;  // [3][N] velocity of the previous check
+  size_t N;
+  double inv_uref;  // 1 / velocity scale
+};
+
 // Logical block index.  The dispatcher hands workgroups to the 8 XCDs
 // round-robin (workgroup b runs on XCD b % 8).  remap 1 (slabs): logical
 // blocks [q*i, q*(i+1)) all run on XCD i, so each XCD sweeps one contiguous
@@ -292,9 +337,13 @@ __host__ __device__ constexpr unsigned geo_code(unsigned kind, unsigned m, unsig
 // source is a solid node is bounced back (the node's own opposite
 // population of the previous step), and a face node may take its velocity
 // from a per-node field.
-template <class F, bool COPY, bool EXT, class T, class Access>
+//
+// DELTA: the node's convergence measure of the state it stores
+// (velocity_change, with dl) is folded into *dmax.
+template <class F, bool COPY, bool EXT, class T, class Access, bool DELTA = false>
 __device__ __forceinline__ void update_node(const Access &mem, const NodeGeom &g, int x, int y, int z,
-                                            const NodeParams<T> &p, unsigned key, const NodeExt &ext) {
+                                            const NodeParams<T> &p, unsigned key, const NodeExt &ext,
+                                            const DeltaArgs &dl = DeltaArgs{}, float *dmax = nullptr) {
   const unsigned bc_mask = p.bc_mask;
   using S = typename F::S;
   const unsigned nx = g.nx, ny = g.ny, nz = g.nz;
@@ -406,6 +455,7 @@ __device__ __forceinline__ void update_node(const Access &mem, const NodeGeom &g
   }
 #pragma unroll
   for (int k = 0; k < 19; ++k) mem.store_at(k, row, unsigned(x), raw[k]);
+  if constexpr (DELTA) *dmax = fmaxf(*dmax, velocity_change<S>(raw, dl.snap, dl.N, n, dl.inv_uref));
 }
 
 }  // namespace lbm

@@ -143,3 +143,63 @@ def test_pass_batch_of_uneven_ducts_equals_plain():
     for i, s in enumerate(specs):
         _, _, u = serving.run_plain(s, "f32", run.steps[i])
         np.testing.assert_array_equal(run.results[i][1], u, err_msg=s.name)
+
+
+def _deltas(spec, storage, chunk, chunks, steps_per_pass, policy=None, shape=None):
+    b = lbm.lbm_batch_create(1 << 30, chunk, 4)
+    out = []
+    try:
+        lbm.lbm_batch_set_steps_per_pass(b, steps_per_pass, 0)
+        if shape is not None:
+            lbm.lbm_batch_set_shape(b, *shape)
+        if policy is not None:
+            lbm.lbm_batch_set_policy(b, policy, 1)
+        jid = lbm.lbm_batch_submit(b, serving.job_for(spec, storage, 0.0, chunk * chunks))
+        for _ in range(chunks):
+            lbm.lbm_batch_run_chunk(b)
+            st = lbm.lbm_batch_poll(b, jid)
+            out.append((st.steps, st.delta))
+    finally:
+        lbm.lbm_batch_destroy(b)
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16sr", "f64"])
+def test_convergence_measure_same_bits_in_every_path(storage):
+    """The chunk's last batch sweep (lockstep, one step per launch), the last
+    single-lattice sweep of a chunk of one job, and the measure kernel (after
+    a chunk that ends with a pass, or with persistent workgroups) all take
+    the same measure of the same state."""
+    spec = workloads.duct(20, 10, 10, (0.04, 0.01, 0.01), 0.8)
+    fused_batch = _deltas(spec, storage, 20, 4, 1)
+    persistent = _deltas(spec, storage, 20, 4, 1, shape=(256, 1024, 64))
+    fused_solo = _deltas(spec, storage, 20, 4, 1, lbm.LBM_BATCH_LARGE_IN_ORDER)
+    kernel = _deltas(spec, storage, 20, 4, 2)
+    say(f"{storage}: {fused_batch}")
+    assert fused_batch == fused_solo == kernel == persistent
+    assert all(d > 0 for _, d in fused_batch)
+
+
+def test_convergence_measure_of_a_mix_same_bits_fused_and_from_the_state():
+    """Eleven lattices of all storage forms in one lockstep chunk: the
+    measure combined from the last batch sweep's per-wave maxima (tiles of
+    many small lattices, lattice ends inside the combining kernel's rounds)
+    equals the measure kernel's, taken from the state (persistent grid)."""
+    def run(shape):
+        b = lbm.lbm_batch_create(4 << 30, 10, 16)
+        try:
+            lbm.lbm_batch_set_shape(b, *shape)
+            ids = _submit_all(b, MIX, 30)
+            out = []
+            for _ in range(2):
+                lbm.lbm_batch_run_chunk(b)
+                out.append([lbm.lbm_batch_poll(b, j).delta for j in ids])
+            return out
+        finally:
+            lbm.lbm_batch_destroy(b)
+    fused = run((256, 256, 0))
+    fused128 = run((128, 256, 0))
+    state = run((256, 1024, 64))
+    say(f"fused {fused}")
+    assert fused == state == fused128
+    assert all(d > 0 for row in fused for d in row)

@@ -268,7 +268,9 @@ def form_batch(args, steps=2000):
     from paper_0811_4593_amd import serving, workloads
 
     specs = workloads.batch_ducts(64, seed=0)
-    run = serving.run_batch(specs, "f32", steps=steps, chunk=100, autotune=True, keep_results=True)
+    # 16 real steps per autotuner candidate: 4 left the pick between
+    # near-equal shapes to noise
+    run = serving.run_batch(specs, "f32", steps=steps, chunk=100, autotune=True, trial_steps=16, keep_results=True)
     print(f"batch form: batched run {run.seconds:.2f} s", file=sys.stderr, flush=True)
     seq_s, worst = 0.0, 0.0
     seq_updates = 0.0

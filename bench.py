@@ -416,7 +416,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the single-lattice path "
-              "does not shard across GPUs in this build.", file=sys.stderr)
+              "does not shard across GPUs.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -536,7 +536,7 @@ def main():
             # copy (streaming only) on the same buffers
             "frac_of_pull_copy": round(achieved / probes["pull_pattern_copy"], 4),
             # the best 50/50 read/write stream measured on the same buffers (a contiguous copy,
-            # one 16-byte element per thread): the practical bandwidth ceiling of the box
+            # one 16-byte element per thread): the practical bandwidth ceiling of the device
             "ceiling_GBs": probes["read_write_copy"],
             "frac_of_ceiling": round(achieved / probes["read_write_copy"], 4),
             # the same kernel on the lattice's own two buffers, before placement tuning

@@ -235,7 +235,7 @@ __global__ void relayout_kernel(const E *__restrict__ src, PopLayout from, E *__
 
 // Plain contiguous copy of nbytes (multiple of 16): one 16-byte element per
 // thread, the form of the fastest read/write stream measured on the MI355X
-// (the ceiling a 50/50 read/write kernel can reach on the box).
+// (the ceiling a 50/50 read/write kernel can reach on the device).
 __global__ __launch_bounds__(256) void copy_probe_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
                                                          size_t n16) {
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;

@@ -137,7 +137,7 @@ class ServeReport:
         return out
 
 
-SERVE_LANES = 4  # concurrent lanes of the serving loop (the box's default of 4 hardware queues)
+SERVE_LANES = 4  # concurrent lanes of the serving loop (HIP's default of 4 hardware queues per process)
 SERVE_LARGE_NODES = 1 << 18  # requests of at least 64^3 nodes run one at a time, in arrival order
 
 

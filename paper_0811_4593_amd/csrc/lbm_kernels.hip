@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <type_traits>
 
 #include "d3q19.hpp"
 #include "lbm_internal.hpp"
@@ -29,16 +30,28 @@ namespace lbm {
 // offset".  COPY: streaming only (no boundary rule, no collision, raw
 // elements) -- the bandwidth ceiling of this access pattern.  EXT: the
 // extended update with solid nodes and per-node face velocities (a.ext).
+// ROWS: the row-major layout through per-row buffer descriptors (RowAccess;
+// the row of a solid node's own populations is per lane, so not with EXT);
+// otherwise plain pointers.  Stores are non-temporal either way: the
+// destination is not read again before the next step, which streams through
+// far more data than the caches hold.
 // ---------------------------------------------------------------------------
-template <class F, int BX, int NPT, bool NT, bool COPY, bool EXT>
+template <class F, int BX, int NPT, bool ROWS, bool COPY, bool EXT>
 __global__ __launch_bounds__(BX) void sweep_kernel(const typename F::S *__restrict__ src,
                                                    typename F::S *__restrict__ dst,
                                                    SweepArgs<typename Codec<typename F::S>::T> a) {
+  static_assert(!(ROWS && EXT), "per-row descriptors need a wave-uniform row");
+  using S = typename F::S;
   const unsigned b = logical_block(blockIdx.x, gridDim.x, a.xcd_remap, unsigned(a.nxc));
   const unsigned row = a.nxc == 1 ? b : b / unsigned(a.nxc);
   const int xc = int(b - row * unsigned(a.nxc));
   const NodeGeom g{unsigned(a.nx), unsigned(a.ny), unsigned(a.nz), a.row_stride};
-  const PtrAccess<typename F::S, NT> mem{src, dst, a.pop_stride};
+  using Access = std::conditional_t<ROWS, RowAccess<S>, PtrAccess<S, true>>;
+  Access mem;
+  if constexpr (ROWS)
+    mem = Access{src, dst, unsigned(a.pop_stride * sizeof(S)), unsigned(a.row_stride * sizeof(S))};
+  else
+    mem = Access{src, dst, a.pop_stride};
   const int y = int(row % g.ny);
   const int z = int(row / g.ny);
 #pragma unroll
@@ -245,23 +258,21 @@ __global__ __launch_bounds__(256) void copy_probe_kernel(const uint4 *__restrict
 // ---------------------------------------------------------------------------
 // Host-side launchers.
 // ---------------------------------------------------------------------------
-template <class F, int BX, int NPT, bool NT, bool COPY, bool EXT>
+template <class F, int BX, int NPT, bool ROWS, bool COPY, bool EXT>
 static hipError_t launch_sweep_t(const void *src, void *dst, const SweepArgs<typename Codec<typename F::S>::T> &a,
                                  hipStream_t s) {
   using S = typename F::S;
-  sweep_kernel<F, BX, NPT, NT, COPY, EXT><<<dim3(a.nblocks), dim3(BX), 0, s>>>(static_cast<const S *>(src),
+  sweep_kernel<F, BX, NPT, ROWS, COPY, EXT><<<dim3(a.nblocks), dim3(BX), 0, s>>>(static_cast<const S *>(src),
                                                                               static_cast<S *>(dst), a);
   return hipGetLastError();
 }
 
-template <class F, bool COPY>
-static hipError_t launch_sweep_shape(const void *src, void *dst,
-                                     const SweepArgs<typename Codec<typename F::S>::T> &a, int bx, int npt,
-                                     hipStream_t s) {
-  // Non-temporal stores: the destination is not read again before the next
-  // step, which streams through far more data than the caches hold.
-#define LBM_CASE(B, P)                                                       \
-  if (bx == B && npt == P) return launch_sweep_t<F, B, P, true, COPY, false>(src, dst, a, s);
+template <class F, bool ROWS, bool COPY>
+static hipError_t launch_sweep_shape_t(const void *src, void *dst,
+                                       const SweepArgs<typename Codec<typename F::S>::T> &a, int bx, int npt,
+                                       hipStream_t s) {
+#define LBM_CASE(B, P) \
+  if (bx == B && npt == P) return launch_sweep_t<F, B, P, ROWS, COPY, false>(src, dst, a, s);
   LBM_CASE(64, 1) LBM_CASE(64, 2) LBM_CASE(64, 4)
   LBM_CASE(128, 1) LBM_CASE(128, 2) LBM_CASE(128, 4)
   LBM_CASE(256, 1) LBM_CASE(256, 2) LBM_CASE(256, 4)
@@ -270,15 +281,35 @@ static hipError_t launch_sweep_shape(const void *src, void *dst,
   return hipErrorInvalidValue;
 }
 
+template <class F, bool COPY>
+static hipError_t launch_sweep_shape(const void *src, void *dst,
+                                     const SweepArgs<typename Codec<typename F::S>::T> &a, int bx, int npt,
+                                     hipStream_t s) {
+  // The row-major layout (one row holds all 19 populations) through per-row
+  // descriptors while a row's bytes fit their 31-bit offsets, for the FP16
+  // and FP64 forms.  Measured per step on a 512x256x256 duct, the same box,
+  // against plain pointers: FP16 round-to-nearest 0.445 against 0.453 ms,
+  // FP64 1.752 against 1.769 ms, FP16 with stochastic rounding equal
+  // (0.446 / 0.444: its vector instructions fell from about 424 to 348 per
+  // node without a gain, so the sweep is bound by memory, not issue), FP32
+  // 0.894 against 0.888 ms -- so FP32 keeps the pointers.
+  if constexpr (sizeof(typename F::S) != 4) {
+    const bool rows =
+        a.row_stride >= 19 * a.pop_stride && a.row_stride * sizeof(typename F::S) < (size_t(1) << 31);
+    if (rows) return launch_sweep_shape_t<F, true, COPY>(src, dst, a, bx, npt, s);
+  }
+  return launch_sweep_shape_t<F, false, COPY>(src, dst, a, bx, npt, s);
+}
+
 // The extended sweep runs one node per thread.
 template <class F>
 static hipError_t launch_sweep_ext(const void *src, void *dst, const SweepArgs<typename Codec<typename F::S>::T> &a,
                                    int bx, hipStream_t s) {
   switch (bx) {
-    case 64: return launch_sweep_t<F, 64, 1, true, false, true>(src, dst, a, s);
-    case 128: return launch_sweep_t<F, 128, 1, true, false, true>(src, dst, a, s);
-    case 256: return launch_sweep_t<F, 256, 1, true, false, true>(src, dst, a, s);
-    case 512: return launch_sweep_t<F, 512, 1, true, false, true>(src, dst, a, s);
+    case 64: return launch_sweep_t<F, 64, 1, false, false, true>(src, dst, a, s);
+    case 128: return launch_sweep_t<F, 128, 1, false, false, true>(src, dst, a, s);
+    case 256: return launch_sweep_t<F, 256, 1, false, false, true>(src, dst, a, s);
+    case 512: return launch_sweep_t<F, 512, 1, false, false, true>(src, dst, a, s);
   }
   return hipErrorInvalidValue;
 }

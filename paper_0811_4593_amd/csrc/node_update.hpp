@@ -94,7 +94,10 @@ __host__ __device__ __forceinline__ unsigned step_key(unsigned t) { return fmix3
 // rounded the same way.
 __device__ __forceinline__ _Float16 encode_half_sr(float d, unsigned r) {
   typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
-  half2_t v = {static_cast<_Float16>(0.0f), static_cast<_Float16>(0.0f)};
+  // The conversion writes the low half and keeps the high half of its
+  // destination; only the low half is used, so the destination starts as
+  // the random word itself rather than a zeroed register.
+  half2_t v = __builtin_bit_cast(half2_t, r);
   v = __builtin_amdgcn_cvt_sr_f16_f32(v, d * 256.0f, r, false);
   return v[0];
 }
@@ -213,10 +216,10 @@ struct PtrAccess {
   // Element x of the row that starts at element `row` of population k.  For
   // 2-byte storage, with the row uniform over the wave, the address is a
   // scalar 64-bit base plus a 32-bit lane byte offset (x * 2 < 2^32), so the
-  // loads need no 64-bit vector arithmetic: the FP16 forms, bound by vector
-  // instructions as much as by HBM, run 1-2% faster.  The wider forms keep
-  // the 64-bit vector address: they compute in double, already spill scalar
-  // registers, and measured 0.3% slower with the scalar bases.
+  // loads need no 64-bit vector arithmetic (the FP16 forms ran 1-2% faster
+  // so).  The wider forms keep the 64-bit vector address: they compute in
+  // double, already spill scalar registers, and measured 0.3% slower with
+  // the scalar bases.
   __device__ __forceinline__ S load_at(int k, size_t row, unsigned x) const {
     if constexpr (sizeof(S) == 2) {
       const char *base = reinterpret_cast<const char *>(src + (size_t(k) * pop_stride + row));
@@ -290,6 +293,27 @@ struct BufAccess {
     return buf_load<S>(src, voff, unsigned(k) * pop_bytes);
   }
   __device__ __forceinline__ void store_at(int k, size_t row, unsigned x, S v) const { store(k, unsigned(row) + x, v); }
+};
+
+// RowAccess: the row-major layout, where one x-row of row_stride elements
+// holds all 19 populations of its nodes.  Each access goes through a
+// descriptor of its row (base at the row's start, so the offsets stay small
+// for any lattice size), the lane's byte offset x * sizeof(S) and the
+// population's start k * pop_stride * sizeof(S) as scalar offset: no 64-bit
+// vector address arithmetic and no 19 + 19 64-bit population bases in scalar
+// registers (whose spills cost vector instructions).  The row must be
+// uniform over the wave.
+template <class S>
+struct RowAccess {
+  const S *src;
+  S *dst;
+  unsigned pop_bytes, row_bytes;  // pop_stride and row_stride in bytes (row_bytes < 2^31)
+  __device__ __forceinline__ S load_at(int k, size_t row, unsigned x) const {
+    return buf_load<S>(raw_buffer(src + row, row_bytes), x * unsigned(sizeof(S)), unsigned(k) * pop_bytes);
+  }
+  __device__ __forceinline__ void store_at(int k, size_t row, unsigned x, S v) const {
+    buf_store_nt<S>(v, raw_buffer(dst + row, row_bytes), x * unsigned(sizeof(S)), unsigned(k) * pop_bytes);
+  }
 };
 
 // Whether an access type can skip a load whose value is not needed

@@ -368,7 +368,7 @@ def main():
                     help="time steps per pass over HBM (lbm_set_steps_per_pass; 2: two steps per read and write "
                          "of the state, the fastest measured on this workload)")
     ap.add_argument("--zplanes", type=int, default=32, help="z-planes per workgroup of the two-step pass (0: 64)")
-    ap.add_argument("--tile-rows", type=int, default=0, help="interior rows of the two-step tiles (0: default, 5)")
+    ap.add_argument("--tile-rows", type=int, default=0, help="interior rows of the two-step tiles (0: the form's default, 5 or 12)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),

@@ -344,11 +344,13 @@ lbm_status lbm_get_launch(const lbm_lattice *L, int *block_x, int *nodes_per_thr
  * odd count, lbm_step runs the single sweep.  z_planes >= 1 (0: 64) sets the
  * planes per workgroup; the first step on the two planes beyond a range is
  * done by both neighbouring ranges.  tile_rows picks the tile height: 0,
- * the form's default; 5, five-row tiles (two workgroups per compute unit;
- * FP64 tiles have five rows either way).  Every variant gives the same
- * bits.  steps_per_pass = 1: one single sweep per step (the default).
- * Errors: LBM_ERR_ARG (NULL, steps_per_pass not 1 or 2, z_planes < 0,
- * tile_rows not 0 or 5). */
+ * the form's default; 5, five-row tiles (two workgroups per compute unit);
+ * 12, twelve-row tiles (15 waves, three of step 2's 12 on each SIMD;
+ * measured faster than 13 rows on 512 x 256 x 256 FP32, slower on
+ * 1024 x 512 x 512); FP64 tiles have five rows either way.  Every variant
+ * gives the same bits.  steps_per_pass = 1: one single sweep per step (the
+ * default).  Errors: LBM_ERR_ARG (NULL, steps_per_pass not 1 or 2,
+ * z_planes < 0, tile_rows not 0, 5 or 12). */
 lbm_status lbm_set_steps_per_pass(lbm_lattice *L, int steps_per_pass, int z_planes, int tile_rows);
 lbm_status lbm_get_steps_per_pass(const lbm_lattice *L, int *steps_per_pass, int *z_planes, int *tile_rows);
 

@@ -639,7 +639,8 @@ lbm_status lbm_set_steps_per_pass(lbm_lattice *L, int steps_per_pass, int z_plan
   if (steps_per_pass != 1 && steps_per_pass != 2)
     return fail(LBM_ERR_ARG, "steps_per_pass must be 1 or 2 (got %d)", steps_per_pass);
   if (z_planes < 0) return fail(LBM_ERR_ARG, "z_planes must be >= 0 (got %d)", z_planes);
-  if (tile_rows != 0 && tile_rows != 5) return fail(LBM_ERR_ARG, "tile_rows must be 0 or 5 (got %d)", tile_rows);
+  if (tile_rows != 0 && tile_rows != 5 && tile_rows != 12)
+    return fail(LBM_ERR_ARG, "tile_rows must be 0, 5 or 12 (got %d)", tile_rows);
   L->pass_steps = steps_per_pass;
   L->zc = z_planes == 0 ? kDefaultZPlanes : z_planes;
   L->tile_rows = tile_rows;
@@ -677,7 +678,7 @@ lbm_status lbm_autotune(lbm_lattice *L, int trial_steps, int *block_x, int *node
   // rounded up to a power of two (at least 64); one node per thread for the
   // extended sweep.  In the row-major layout without extended options also
   // the two-step pass: z ranges of 16, 32 or 64 planes, tiles of the form's
-  // default rows or 5 rows, slab or dispatch-order placement.
+  // default rows, 5 or 12 rows, slab or dispatch-order placement.
   const bool ext = L->d_solid || L->d_geo || L->d_face_v[0] || L->d_face_v[1] || L->d_face_v[2] ||
                    L->d_face_v[3] || L->d_face_v[4] || L->d_face_v[5];
   int row = 64;
@@ -697,8 +698,10 @@ lbm_status lbm_autotune(lbm_lattice *L, int trial_steps, int *block_x, int *node
     }
   if (L->layout == LBM_LAYOUT_ROW_MAJOR && !ext)
     for (int zc : {16, 32, 64})
-      for (int rows : {0, 5})
+      for (int rows : {0, 5, 12}) {
+        if (rows != 0 && L->storage == LBM_STORE_F64) continue;  // FP64 tiles have 5 rows either way
         for (int xcd : {LBM_XCD_SLABS, LBM_XCD_NONE}) cands.push_back({2, L->block_x, L->npt, xcd, zc, rows});
+      }
   const int old[6] = {L->block_x, L->npt, L->xcd, L->pass_steps, L->zc, L->tile_rows};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {

@@ -78,12 +78,15 @@ hipError_t launch_sweep2(const SweepConfig &c, int zc, int rows, const void *src
     case kStoreF64: return launch_sweep2_t<FormF64, Sweep2Rows<FormF64>::kBYI>(c, zc, src, dst, s);
     case kStoreF32:
       if (rows == 5) return launch_sweep2_t<FormF32, 5>(c, zc, src, dst, s);
+      if (rows == 12) return launch_sweep2_t<FormF32, 12>(c, zc, src, dst, s);
       return launch_sweep2_t<FormF32, Sweep2Rows<FormF32>::kBYI>(c, zc, src, dst, s);
     case kStoreF16:
       if (rows == 5) return launch_sweep2_t<FormF16, 5>(c, zc, src, dst, s);
+      if (rows == 12) return launch_sweep2_t<FormF16, 12>(c, zc, src, dst, s);
       return launch_sweep2_t<FormF16, Sweep2Rows<FormF16>::kBYI>(c, zc, src, dst, s);
     case kStoreF16SR:
       if (rows == 5) return launch_sweep2_t<FormF16SR, 5>(c, zc, src, dst, s);
+      if (rows == 12) return launch_sweep2_t<FormF16SR, 12>(c, zc, src, dst, s);
       return launch_sweep2_t<FormF16SR, Sweep2Rows<FormF16SR>::kBYI>(c, zc, src, dst, s);
   }
   return hipErrorInvalidValue;

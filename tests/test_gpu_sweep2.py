@@ -69,7 +69,7 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("rows", [0, 5], ids=["default-tiles", "5-row-tiles"])
+@pytest.mark.parametrize("rows", [0, 5, 12], ids=["default-tiles", "5-row-tiles", "12-row-tiles"])
 @pytest.mark.parametrize("storage", STORAGES, ids=lambda s: lbm.STORAGE_NAMES[s])
 @pytest.mark.parametrize("case", range(len(CASES)), ids=lambda i: CASES[i][0].name)
 def test_two_steps_per_pass_equal_two_single_sweeps(case, storage, rows):
@@ -112,7 +112,7 @@ def test_two_step_pass_fp64_against_oracle():
         lbm.lbm_destroy(h)
 
 
-@pytest.mark.parametrize("rows", [0, 5], ids=["default-tiles", "5-row-tiles"])
+@pytest.mark.parametrize("rows", [0, 5, 12], ids=["default-tiles", "5-row-tiles", "12-row-tiles"])
 def test_two_step_pass_full_size_duct_equals_single_sweeps(rows):
     """The bench's workload and launch (1024 x 512 x 512 FP32 duct, row-major,
     default z ranges): after six steps from rest, every element of the state
@@ -145,5 +145,7 @@ def test_steps_per_pass_arguments():
             assert e.value.status == lbm.LBM_ERR_ARG
         lbm.lbm_set_steps_per_pass(h, 2, 16, 5)
         assert lbm.lbm_get_steps_per_pass(h) == (2, 16, 5)
+        lbm.lbm_set_steps_per_pass(h, 2, 16, 12)
+        assert lbm.lbm_get_steps_per_pass(h) == (2, 16, 12)
     finally:
         lbm.lbm_destroy(h)

@@ -366,7 +366,8 @@ lbm_status lbm_get_step(const lbm_lattice *L, unsigned long long *steps);
  * placement) one untimed and trial_steps >= 1 timed steps, and, in the
  * row-major layout without those options, for each two-step pass
  * (lbm_set_steps_per_pass: z ranges of 16, 32 or 64 planes, tiles of the
- * form's default rows or 5 rows, slab or dispatch-order placement) one
+ * form's default rows, 5 or 12 rows (FP64: its 5 only), slab or
+ * dispatch-order placement) one
  * untimed and trial_steps timed pairs, on the lattice's stream (HIP events,
  * compared per step).  The steps are part of the run (results do not depend
  * on the choice).  Sets the winner -- launch shape, steps per pass, z range

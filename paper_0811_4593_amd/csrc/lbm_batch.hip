@@ -68,11 +68,11 @@ struct BatchTile {
 // 0.99x): the fewest re-reads do not make the fastest order.
 constexpr unsigned kTileGroup = 4;
 
-// One step of every lattice of storage form F listed in `tiles`.  A grid of
-// at least as many workgroups as tiles (the default) gives every tile a
-// workgroup of its own, tiles dealt to the XCDs in groups of kTileGroup
-// (logical_block); a smaller grid walks the list round-robin (persistent
-// workgroups).  Each lane updates the nodes of slots n0 + t, n0 + t + BX, ...
+// One step of every lattice of storage form F listed in `tiles`.  With own
+// (the default shape: a grid of one workgroup per entry of the tile table)
+// every tile has a workgroup of its own, tiles dealt to the XCDs in groups
+// of kTileGroup (logical_block); otherwise the grid's workgroups walk the
+// list round-robin (persistent workgroups).  Each lane updates the nodes of slots n0 + t, n0 + t + BX, ...
 // of its tile (the padding slots of a row-major lattice with padded rows stay
 // idle, so that its rows' waves start on cache lines as the rows do).  `s` is
 // the index of the step within the launch sequence (with the lattice's
@@ -108,18 +108,15 @@ __device__ __forceinline__ NodeParams<T> lattice_params(const BatchLat &L) {
 // the convergence measure of the state it writes; each wave's maximum goes
 // to partials[tile * BX / 64 + wave] (tile_partials_kernel then combines
 // them per lattice).
-template <class F, int BX, bool DELTA>
+template <class F, int BX, bool DELTA, bool OWN>
 __global__ __launch_bounds__(BX) void batch_sweep_kernel(const BatchLat *__restrict__ lats,
                                                          const BatchTile *__restrict__ tiles,
                                                          const int *__restrict__ ntiles, int s, int parity,
                                                          float *__restrict__ partials) {
+  static_assert(OWN || !DELTA, "the measure needs a workgroup per tile");
   using S = typename F::S;
   using T = typename Codec<S>::T;
-  const int nt = *ntiles;
-  const bool own_tile = int(gridDim.x) >= nt;
-  for (int b = blockIdx.x; b < nt; b += gridDim.x) {
-    const int t = own_tile ? int(logical_block(unsigned(b), unsigned(nt), 2, kTileGroup)) : b;
-    const BatchTile tile = tiles[t];
+  auto step_tile = [&](int t, const BatchTile &tile) {
     const BatchLat &L = lats[tile.lat];
     const NodeGeom g{L.nx, L.ny, L.nz, size_t(L.row_stride)};
     const unsigned buf_bytes = L.buf_elems * unsigned(sizeof(S));
@@ -158,6 +155,22 @@ __global__ __launch_bounds__(BX) void batch_sweep_kernel(const BatchLat *__restr
       dmax = wave_max(dmax);
       if ((threadIdx.x & 63) == 0) partials[size_t(t) * (BX / 64) + (threadIdx.x >> 6)] = dmax;
     }
+  };
+  if constexpr (OWN) {
+    // One workgroup per entry of the tile table (the grid is its capacity):
+    // the tile follows from the block index alone, so its record is loaded
+    // beside the tile count rather than after it, and workgroups past the
+    // count exit.
+    const int t = int(logical_block(blockIdx.x, gridDim.x, 2, kTileGroup));
+    BatchTile tile = tiles[t];
+    int nt = *ntiles;
+    // both loads in flight before either is waited for (the compiler would
+    // otherwise load the tile only after the count check)
+    asm volatile("" : "+s"(tile.lat), "+s"(tile.n0), "+s"(tile.n1), "+s"(nt));
+    if (t < nt) step_tile(t, tile);
+  } else {
+    const int nt = *ntiles;
+    for (int b = blockIdx.x; b < nt; b += gridDim.x) step_tile(b, tiles[b]);
   }
 }
 
@@ -315,22 +328,25 @@ __global__ __launch_bounds__(64 * (BYI + 3)) void batch_pass_kernel(const BatchL
   sweep2_box<F, BYI, global_ptr<const S>, global_ptr<S>>(src, dst, a, bx.tx, bx.ty, bx.tz, ring);
 }
 
+// own: the grid is the tile table's capacity, one workgroup per entry.
 template <class F, int BX>
 static void launch_batch_sweep_t(const BatchLat *lats, const BatchTile *tiles, const int *nt, int s, int parity,
-                                 float *partials, int grid, hipStream_t st) {
-  if (partials)
-    batch_sweep_kernel<F, BX, true><<<dim3(grid), dim3(BX), 0, st>>>(lats, tiles, nt, s, parity, partials);
+                                 float *partials, int grid, bool own, hipStream_t st) {
+  if (partials)  // the measure: one workgroup per tile
+    batch_sweep_kernel<F, BX, true, true><<<dim3(grid), dim3(BX), 0, st>>>(lats, tiles, nt, s, parity, partials);
+  else if (own)
+    batch_sweep_kernel<F, BX, false, true><<<dim3(grid), dim3(BX), 0, st>>>(lats, tiles, nt, s, parity, nullptr);
   else
-    batch_sweep_kernel<F, BX, false><<<dim3(grid), dim3(BX), 0, st>>>(lats, tiles, nt, s, parity, nullptr);
+    batch_sweep_kernel<F, BX, false, false><<<dim3(grid), dim3(BX), 0, st>>>(lats, tiles, nt, s, parity, nullptr);
 }
 
 // partials: non-null for the step that ends a chunk, with one workgroup per
 // tile (the per-wave maxima of the convergence measure, bx / 64 per tile).
 static hipError_t launch_batch_sweep(int storage, int bx, const BatchLat *lats, const BatchTile *tiles, const int *nt,
-                                     int s, int parity, float *partials, int grid, hipStream_t st) {
+                                     int s, int parity, float *partials, int grid, bool own, hipStream_t st) {
 #define LBM_CASE(ST, F, B)                                                                 \
   case ST * 1000 + B:                                                                      \
-    launch_batch_sweep_t<F, B>(lats, tiles, nt, s, parity, partials, grid, st);            \
+    launch_batch_sweep_t<F, B>(lats, tiles, nt, s, parity, partials, grid, own, st);       \
     break;
   switch (storage * 1000 + bx) {
     LBM_CASE(kStoreF64, FormF64, 128)
@@ -854,7 +870,7 @@ lbm_status launch_steps(lbm_batch *B, Lane &ln, int nsteps, int first, bool meas
         const int grid = B->shape.grid > 0 ? B->shape.grid : int(ln.tile_cap[s]);
         LBM_BHIP(lbm::launch_batch_sweep(s, B->shape.block_x, ln.d_lats, ln.d_tiles[s], ln.d_ntiles + s, first + j,
                                          parity, measure && j == nsteps - 1 ? ln.d_part + ln.part_off[s] : nullptr,
-                                         grid, ln.stream),
+                                         grid, B->shape.grid == 0, ln.stream),
                  "batch sweep launch");
       }
   }

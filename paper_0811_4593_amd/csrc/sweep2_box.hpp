@@ -162,8 +162,8 @@ __device__ __forceinline__ void sweep2_box(SrcP src, DstP dst,
   const int lane0 = int(threadIdx.x) & 63;
   // The FP32 form reads the step-1 sources of the halo rows and writes step
   // 2 through per-row descriptors (no 64-bit vector address arithmetic:
-  // 1.3-2.4% faster on 1024 x 512 x 512, 1.8% on 512 x 256 x 256, with 19%
-  // fewer vector instructions); the FP64 and FP16 forms, measured 2-5%
+  // 0.3-2.4% faster on 1024 x 512 x 512 and 1.8% on 512 x 256 x 256, with
+  // 17% fewer vector instructions); the FP64 and FP16 forms, measured 2-5%
   // slower so, keep the pointers.
   constexpr bool kRowDescriptors = sizeof(S) == 4;
 

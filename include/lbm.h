@@ -330,7 +330,7 @@ lbm_status lbm_get_launch(const lbm_lattice *L, int *block_x, int *nodes_per_thr
 
 /* Steps per pass over HBM.  steps_per_pass = 2 (temporal blocking): lbm_step
  * advances pairs of steps with one kernel in which a workgroup streams a
- * tile of 64 x BY nodes (BY = 13 for FP32 and FP16, 5 for FP64) through
+ * tile of 64 x BY nodes (by default BY = 13 for FP32 and FP16, 5 for FP64) through
  * ranges of z_planes planes, computes the first step on the tile plus a
  * one-node halo into LDS and the second from LDS into HBM.  Per pair of
  * steps every node's populations are read about once (the halo rows are

@@ -287,7 +287,7 @@ static hipError_t launch_sweep_shape(const void *src, void *dst,
                                      hipStream_t s) {
   // The row-major layout (one row holds all 19 populations) through per-row
   // descriptors while a row's bytes fit their 31-bit offsets, for the FP16
-  // and FP64 forms.  Measured per step on a 512x256x256 duct, the same box,
+  // and FP64 forms.  Measured per step on a 512x256x256 duct, both forms in turn on one device,
   // against plain pointers: FP16 round-to-nearest 0.445 against 0.453 ms,
   // FP64 1.752 against 1.769 ms, FP16 with stochastic rounding equal
   // (0.446 / 0.444: its vector instructions fell from about 424 to 348 per
